@@ -1,0 +1,196 @@
+/*
+ * rk4ip.h -- C ABI of the MI355X (gfx950) RK4 interaction-picture step library.
+ *
+ * The library advances fields psi(x, t) of coupled nonlinear Schroedinger /
+ * Gross-Pitaevskii type equations
+ *
+ *     d psi / dt = L psi + G(psi),   L(k) = -i alpha |k|^2 - gamma,
+ *     G(psi)     = -i (V(x) + g_nl |psi|^2) psi + sigma xi(x, t),
+ *
+ * on periodic Fourier lattices (Dennis, Hope & Johnsson, arXiv:1204.4255: the
+ * problem of Sec. 3.6 eq. (5) with the NLSE right-hand side of eq. (7) and the
+ * dimensionless trap form of Sec. 4.1 eq. (9); additive Wiener noise of Sec. 3.5).
+ * One step is the fixed-step fourth-order Runge-Kutta scheme (Sec. 3.5) in the
+ * interaction picture (Sec. 3.6, eqs. (5)-(6)), with the picture origin at the step
+ * midpoint so that only D = e^{L dt/2} is needed (Sec. 3.6, last paragraph):
+ *
+ *     a  = D psi_n,             k1 = D[dt G(psi_n)],
+ *     k2 = dt G(a + k1/2),      k3 = dt G(a + k2/2),
+ *     k4 = dt G(D(a + k3)),     psi_{n+1} = D(a + k1/6 + k2/3 + k3/3) + k4/6.
+ *
+ * D is applied per lattice axis (the tensor-product factorisation of Sec. 3.2):
+ * a 1D FFT along the axis, a multiply by e^{L_a dt/2}, the inverse FFT.
+ *
+ * Conventions shared by every entry point
+ *   - Fields are complex64, interleaved (re, im) float pairs, in device memory owned
+ *     by the caller. One instance is n[2] x n[1] x n[0] values with axis 0 (x)
+ *     contiguous; instances of a group are consecutive and groups follow each other
+ *     in the order given to rk4ip_plan.
+ *   - Lattice: x_{a,j} = lo[a] + j (hi[a] - lo[a]) / n[a], j = 0..n[a]-1 (half-open
+ *     periodic domain); k_{a,m} = 2 pi / (hi[a] - lo[a]) * (m < n[a]/2 ? m : m - n[a]).
+ *   - V(x) = 1/2 sum_a trap[a] x_a^2 + V_grid[b][j] (V_grid may be NULL).
+ *   - Noise: xi is complex, E|xi|^2 = 1/(dt dV), held constant over the four stages of
+ *     a step (Stratonovich, piecewise constant). It is Philox4x32-10 (Salmon et al.,
+ *     SC'11) with key (seed low word, seed high word) and counter
+ *     (j>>1, id_base + b, step low word, step bits 32..55) for point j of instance b;
+ *     words (r0,r1) feed point 2q and (r2,r3) point 2q+1 through Box-Muller with
+ *     u1 = ((r>>8)+1) 2^-24 and u2 = (r>>8) 2^-24. Noise is a pure function of
+ *     (seed, instance, step, point), so runs resume bit-exactly from any step.
+ *   - All calls are asynchronous on the plan's stream unless stated otherwise. The
+ *     library never allocates device memory: the plan keeps its tables and work fields
+ *     in the caller's workspace, which must stay valid until rk4ip_destroy.
+ *   - Every call returns RK4IP_OK (0) or a negative status; nothing aborts and no C++
+ *     exception crosses the ABI. A plan is not thread-safe; distinct plans are
+ *     independent.
+ */
+#ifndef RK4IP_H
+#define RK4IP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    RK4IP_OK = 0,
+    RK4IP_ERR_INVALID_ARG = -1,         /* null pointer, bad count, dt <= 0, unknown flag */
+    RK4IP_ERR_UNSUPPORTED_SHAPE = -2,   /* n[a] not a power of two in [8, 4096] (1D) or
+                                           [8, 1024] (2D/3D), ndim not 1..3 */
+    RK4IP_ERR_WORKSPACE_TOO_SMALL = -3,
+    RK4IP_ERR_HIP = -4,                 /* a HIP runtime call failed; see rk4ip_last_error */
+    RK4IP_ERR_NONFINITE = -5,           /* a diagnostic found a NaN or Inf in a field */
+    RK4IP_ERR_NOT_CAPTURABLE = -6,      /* graph capture or replay failed */
+    RK4IP_ERR_NO_DEVICE = -7            /* no usable gfx950 device */
+};
+
+/* Plan flags */
+#define RK4IP_FLAG_GRAPH     0x1u  /* replay the per-step launch sequence from a hipGraph */
+#define RK4IP_FLAG_AUTOTUNE  0x2u  /* time candidate tile schedules at plan time and keep the best */
+#define RK4IP_FLAG_FUSE_1D   0x4u  /* 1D groups: run several steps per launch with the line kept on chip */
+
+typedef struct rk4ip_plan_s* rk4ip_plan_t;
+
+/* One group of same-shape instances (paths or problem instances). */
+typedef struct {
+    int32_t ndim;            /* 1, 2 or 3 */
+    int32_t reserved0;       /* must be 0 */
+    int64_t n[3];            /* points per axis, axis 0 = x (contiguous); unused axes = 1 */
+    double lo[3], hi[3];     /* periodic domain [lo, hi) per axis */
+    int64_t batch;           /* instances in this group, >= 1 */
+    double dt;               /* time step, > 0, equal for all groups of a plan */
+    double alpha;            /* kinetic coefficient: L(k) = -i alpha |k|^2 - gamma */
+    double gamma;            /* uniform linear damping rate (>= 0) */
+    double g_nl;             /* nonlinear coefficient */
+    double trap[3];          /* harmonic potential 1/2 trap[a] x_a^2 */
+    const float* V_grid;     /* device [batch][M] float extra potential, or NULL */
+    double sigma;            /* additive noise amplitude (0 = deterministic) */
+    uint64_t seed;           /* Philox key */
+    uint32_t id_base;        /* Philox instance id of the first instance of this group */
+    uint32_t reserved1;      /* must be 0 */
+} rk4ip_problem;
+
+/* Bytes of device workspace rk4ip_plan needs for these groups: the spectral tables
+ * (per axis: e^{L_a dt/2} in the form (cos-1, sin) and the FFT twiddles), two complex64
+ * work fields per lattice point, and the FP64 reduction partials. Returns 0 when the
+ * description is invalid. */
+size_t rk4ip_workspace_bytes(const rk4ip_problem* probs, int nprob, uint32_t flags);
+
+/* Validate the groups, build the tables (FP64, stored FP32) into `workspace`, choose the
+ * per-pass schedules and return a plan bound to `stream` (a hipStream_t, NULL = the
+ * default stream). `workspace` is device memory of at least rk4ip_workspace_bytes
+ * bytes, 256-byte aligned. Synchronises the stream once (table upload). */
+int rk4ip_plan(const rk4ip_problem* probs, int nprob, void* workspace, size_t ws_bytes, void* stream,
+               uint32_t flags, rk4ip_plan_t* out);
+
+/* Rebind the plan to another stream (a hipStream_t). */
+int rk4ip_set_stream(rk4ip_plan_t plan, void* stream);
+
+/* One RK4IP step of every instance, in place on `psi` (device complex64). step_index
+ * selects the noise counters. */
+int rk4ip_step(rk4ip_plan_t plan, void* psi, int64_t step_index);
+
+/* nsteps steps starting at step index step0, in place on psi.
+ *   sample_every > 0 and diag != NULL: diag (device, FP64) receives
+ *     [nsteps/sample_every + 1][ninst][4] = (N, E_kin, E_pot, E_int) of the states at
+ *     relative steps 0, s, 2s, ... (see rk4ip_diagnostics).
+ *   ckpt != NULL and ckpt_every > 0: ckpt (device complex64) receives
+ *     [ceil(nsteps/ckpt_every)][total points], the states at relative steps
+ *     0, M, 2M, ... < nsteps (the checkpoints rk4ip_adjoint reads). */
+int rk4ip_run(rk4ip_plan_t plan, void* psi, int64_t step0, int64_t nsteps, int64_t sample_every, double* diag,
+              void* ckpt, int64_t ckpt_every);
+
+/* FP64 integrals of the field (Sec. 3.4 quadrature with the uniform weight dV of a
+ * Fourier lattice) for every instance: out (device) [ninst][4] =
+ *   N = dV sum |psi|^2,
+ *   E_kin = alpha dV sum_a (1/n_a) sum_lines sum_k k_a^2 |F_a psi|^2 (Parseval per axis),
+ *   E_pot = dV sum V |psi|^2,  E_int = dV sum (g_nl/2) |psi|^4.
+ * Sums run in a fixed order, so results are bit-reproducible. A non-finite N sets the
+ * plan's sticky NONFINITE status (read with rk4ip_status). */
+int rk4ip_diagnostics(rk4ip_plan_t plan, const void* psi, double* out);
+
+/* Overlap c_b = dV sum_j conj(phi_j) psi_bj in FP64 for every instance b of group
+ * `group`; phi (device complex64) holds one target field of that group's shape.
+ * out (device) receives [batch][2] = (Re c, Im c). */
+int rk4ip_overlap(rk4ip_plan_t plan, int group, const void* phi, const void* psi, double* out);
+
+/* Moments over the instances of group `group` (many paths, Sec. 3.5): per point, the
+ * mean of |psi|^2 and the sample variance of |psi|^2 with the (P-1) divisor, FP64,
+ * accumulated in instance order. mean and var are device [M] arrays. */
+int rk4ip_moments(rk4ip_plan_t plan, int group, const void* psi, double* mean, double* var);
+
+/* Device workspace bytes rk4ip_adjoint needs for checkpoint spacing ckpt_every. */
+size_t rk4ip_adjoint_workspace_bytes(rk4ip_plan_t plan, int64_t ckpt_every);
+
+/* Discrete adjoint of rk4ip_run over nsteps steps from step0 (not in the paper).
+ * Given the checkpoints written by rk4ip_run (same step0, nsteps, ckpt_every) and
+ * lambda_T = dLoss/dRe psi_T + i dLoss/dIm psi_T (device complex64), writes
+ * grad_psi0 (device complex64, same convention) and, if grad_V != NULL, adds nothing
+ * but overwrites grad_V (device float [ninst][M]) with dLoss/dV_grid. Each segment of
+ * ckpt_every steps is recomputed from its checkpoint into adj_ws and walked
+ * backwards; V gradients accumulate in FP64. */
+int rk4ip_adjoint(rk4ip_plan_t plan, const void* ckpt, int64_t step0, int64_t nsteps, int64_t ckpt_every,
+                  const void* lambda_T, void* grad_psi0, float* grad_V, void* adj_ws, size_t adj_ws_bytes);
+
+/* Wait for the plan's stream and return the sticky status: RK4IP_OK,
+ * RK4IP_ERR_NONFINITE (a diagnostic saw NaN/Inf) or RK4IP_ERR_HIP. Clears it. */
+int rk4ip_status(rk4ip_plan_t plan);
+
+/* Release the plan's host state (the workspace stays the caller's). Waits for the
+ * plan's stream first. */
+int rk4ip_destroy(rk4ip_plan_t plan);
+
+/* Static description of a status code. */
+const char* rk4ip_strerror(int status);
+
+/* Last error message recorded on a plan (never NULL; "" when none). */
+const char* rk4ip_last_error(rk4ip_plan_t plan);
+
+/* Name of the schedule the plan chose for a group and pass (for logs and tests),
+ * or NULL if out of range. */
+const char* rk4ip_schedule(rk4ip_plan_t plan, int group, int pass);
+
+/* ---- test entry points (device pointers, asynchronous on `stream`) -------------- */
+
+/* Philox4x32-10 words for n counters: ctr [n][4] uint32 in, out [n][4] uint32. */
+int rk4ip_debug_philox(uint64_t seed, const uint32_t* ctr, int64_t n, uint32_t* out, void* stream);
+
+/* The noise field xi (complex64) of every instance of group `group` at step `step`,
+ * [batch][M]. */
+int rk4ip_debug_noise(rk4ip_plan_t plan, int group, int64_t step, void* xi);
+
+/* Unnormalised 1D FFTs (sign -1 forward, +1 inverse) of `nlines` contiguous complex64
+ * lines of length n[axis] of group `group`, with the library's device FFT engine and
+ * that axis's twiddle table. in and out are device [nlines][n]; out may equal in. */
+int rk4ip_debug_fft(rk4ip_plan_t plan, int group, int axis, const void* in, void* out, int64_t nlines, int sign);
+
+/* D = e^{L dt/2} (adjoint != 0: its transpose e^{conj(L) dt/2}) applied in place to
+ * every instance of psi, through the same axis passes the step uses. */
+int rk4ip_debug_apply_D(rk4ip_plan_t plan, void* psi, int adjoint);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RK4IP_H */

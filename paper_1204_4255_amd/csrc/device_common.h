@@ -1,0 +1,133 @@
+// device_common.h -- per-group parameters, counter-based noise and the pointwise
+// right-hand side used by every RK4IP kernel.
+//
+// Right-hand side (Dennis, Hope & Johnsson, arXiv:1204.4255, Sec. 3.6 eq. (7) and
+// Sec. 4.1 eq. (9)): G(psi) = -i (V + g |psi|^2) psi + sigma xi, evaluated in FP32.
+// Noise (Sec. 3.5, Wiener noise, Stratonovich form): xi is drawn from Philox4x32-10
+// (Salmon, Moraes, Dror, Shaw, SC'11) and is a pure function of (seed, instance, step,
+// point), regenerated wherever it is needed instead of being stored.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fft_lds.h"
+
+namespace rk4ip {
+
+// Everything a kernel needs to know about one group of same-shape instances.
+struct GroupDev {
+    int ndim;
+    int n[3];
+    int log2n[3];
+    int64_t M;          // points per instance
+    int64_t batch;
+    int64_t offset;     // index of the group's first point in the concatenated field
+    float lo[3];
+    float dx[3];
+    float half_trap[3]; // V = sum half_trap[a] x_a^2 (+ Vgrid)
+    float h;            // time step
+    float gnl;
+    float noise_c;      // h sigma / sqrt(2 h dV): multiplies a complex normal with E|z|^2 = 2
+    float xi_scale;     // 1 / sqrt(2 h dV): xi = xi_scale z
+    float inv_n[3];     // 1/n_a (exact)
+    uint32_t seed_lo, seed_hi, id_base;
+    int has_noise;
+    const float* Vgrid;      // [batch][M] or nullptr
+    const float2* E[3];      // per axis: (E_a - 1)/n_a, see mul_dE
+    const float2* tw[3];     // per axis: e^{-2 pi i t / n_a}
+};
+
+// ---------------------------------------------------------------- Philox4x32-10
+struct U4 {
+    uint32_t x, y, z, w;
+};
+
+__device__ __forceinline__ U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; r++) {
+        if (r > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint32_t lo0 = 0xD2511F53u * c.x;
+        const uint32_t hi0 = __umulhi(0xD2511F53u, c.x);
+        const uint32_t lo1 = 0xCD9E8D57u * c.z;
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c.z);
+        U4 n;
+        n.x = hi1 ^ c.y ^ k0;
+        n.y = lo1;
+        n.z = hi0 ^ c.w ^ k1;
+        n.w = lo0;
+        c = n;
+    }
+    return c;
+}
+
+// Counter of the pair of points (2q, 2q+1) of an instance at a step, tag 0 (dynamics).
+__device__ __forceinline__ U4 noise_counter(int64_t j, uint32_t inst, int64_t step) {
+    U4 c;
+    const uint64_t q = (uint64_t)j >> 1;
+    const uint64_t st = (uint64_t)step;
+    c.x = (uint32_t)q;
+    c.y = inst;
+    c.z = (uint32_t)st;
+    c.w = (uint32_t)((st >> 32) & 0xFFFFFFu);
+    return c;
+}
+
+// Box-Muller on two 24-bit uniforms: u1 in (0,1], u2 in [0,1). Returns a complex normal
+// with E|z|^2 = 2.
+__device__ __forceinline__ float2 box_muller(uint32_t ra, uint32_t rb) {
+    const float u1 = (float)((ra >> 8) + 1u) * 5.9604644775390625e-08f;  // 2^-24, exact
+    const float u2 = (float)(rb >> 8) * 5.9604644775390625e-08f;
+    const float rad = sqrtf(-2.0f * logf(u1));
+    float s, c;
+    sincospif(2.0f * u2, &s, &c);
+    return make_float2(rad * c, rad * s);
+}
+
+// Unit complex normal (E|z|^2 = 2) for point j of instance `inst` at `step`.
+__device__ __forceinline__ float2 noise_z(const GroupDev& g, int64_t j, uint32_t inst, int64_t step) {
+    const U4 r = philox4x32_10(noise_counter(j, inst, step), g.seed_lo, g.seed_hi);
+    return (j & 1) ? box_muller(r.z, r.w) : box_muller(r.x, r.y);
+}
+
+// Trap potential at lattice indices (x, y, z).
+__device__ __forceinline__ float trap_V(const GroupDev& g, int ix, int iy, int iz) {
+    float v = 0.0f;
+    const float x = fmaf((float)ix, g.dx[0], g.lo[0]);
+    v = fmaf(g.half_trap[0] * x, x, v);
+    if (g.ndim > 1) {
+        const float y = fmaf((float)iy, g.dx[1], g.lo[1]);
+        v = fmaf(g.half_trap[1] * y, y, v);
+    }
+    if (g.ndim > 2) {
+        const float z = fmaf((float)iz, g.dx[2], g.lo[2]);
+        v = fmaf(g.half_trap[2] * z, z, v);
+    }
+    return v;
+}
+
+// h G(phi) without the noise term: -i h (V + g |phi|^2) phi
+__device__ __forceinline__ c32 hG_det(const GroupDev& g, c32 phi, float V) {
+    const float m2 = fmaf(phi.x, phi.x, phi.y * phi.y);
+    const float w = g.h * fmaf(g.gnl, m2, V);
+    return make_float2(w * phi.y, -w * phi.x);
+}
+
+// h G(phi) with the noise term; hnz = noise_c * z (already scaled)
+__device__ __forceinline__ c32 hG(const GroupDev& g, c32 phi, float V, c32 hnz) {
+    c32 r = hG_det(g, phi, V);
+    return make_float2(r.x + hnz.x, r.y + hnz.y);
+}
+
+// Spectral multiplier of the propagator in delta form. The table holds
+// (E_a - 1)/n_a = ((e cos(theta) - 1)/n, -e sin(theta)/n) with e the damping factor (axis 0
+// only) and theta = alpha k^2 h/2, computed in FP64 and rounded once. D_a is applied as
+//     f + F_a^{-1}[ (E_a - 1)/n F_a f ],
+// so the rounding error of the transform pair is scaled by |E_a - 1|, which is small on
+// the modes that carry the field, and the rounded multiplier has no modulus bias.
+__device__ __forceinline__ c32 mul_dE(c32 F, float2 cs) { return cmul(F, cs); }
+__device__ __forceinline__ c32 mul_dE_adj(c32 F, float2 cs) { return cmul(F, make_float2(cs.x, -cs.y)); }
+
+}  // namespace rk4ip

@@ -1,0 +1,297 @@
+// fft_lds.h -- complex64 FFT of lines held in registers, exchanged through LDS (gfx950).
+//
+// The transforms between the spatial and spectral representations are FFTs applied
+// along one lattice axis at a time (Dennis, Hope & Johnsson, arXiv:1204.4255, Sec. 3.2).
+// Here a line of N = 2^p points is spread over T = N/R threads (R = min(N, 16) values
+// per thread, kept in VGPRs). The transform is a Stockham autosort sequence of
+// radix-16 stages followed by at most one radix-2/4/8 stage; butterflies run in
+// registers and the data move between stages through LDS. Thread t holds elements
+// t + m*T (m = 0..R-1) both before the forward and after the inverse transform, which
+// is exactly the pattern of a coalesced global load of the line, so no LDS round trip
+// is needed at the ends.
+//
+// Forward transforms use e^{-2 pi i j m / N}, the inverse e^{+...}; neither is
+// normalised. Twiddles e^{-2 pi i t / N} come from a table computed in FP64 and stored
+// in FP32 (passed in LDS by the caller).
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace rk4ip {
+
+typedef float2 c32;
+
+__device__ __forceinline__ c32 cadd(c32 a, c32 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ c32 csub(c32 a, c32 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ c32 cscale(c32 a, float s) { return make_float2(a.x * s, a.y * s); }
+__device__ __forceinline__ c32 cmul(c32 a, c32 b) {
+    return make_float2(fmaf(a.x, b.x, -a.y * b.y), fmaf(a.x, b.y, a.y * b.x));
+}
+__device__ __forceinline__ c32 cconj(c32 a) { return make_float2(a.x, -a.y); }
+// multiply by i^{s}: s = -1 -> -i z, s = +1 -> i z
+template <int S>
+__device__ __forceinline__ c32 mul_i(c32 z) {
+    return S < 0 ? make_float2(z.y, -z.x) : make_float2(-z.y, z.x);
+}
+
+// e^{S 2 pi i k / 16} for k = 0..15 with S = -1 (forward); the inverse conjugates.
+struct W16 {
+    static constexpr float C1 = 0.92387953251128674f;  // cos(pi/8)
+    static constexpr float S1 = 0.38268343236508977f;  // sin(pi/8)
+    static constexpr float H = 0.70710678118654752f;   // cos(pi/4)
+};
+
+template <int S, int K>
+__device__ __forceinline__ c32 w16_mul(c32 z) {
+    // z * e^{S 2 pi i K / 16}
+    constexpr int k = ((K % 16) + 16) % 16;
+    if constexpr (k == 0) {
+        return z;
+    } else if constexpr (k == 4) {
+        return mul_i<S>(z);
+    } else if constexpr (k == 8) {
+        return make_float2(-z.x, -z.y);
+    } else if constexpr (k == 12) {
+        return mul_i<-S>(z);
+    } else if constexpr (k == 2 || k == 6 || k == 10 || k == 14) {
+        // (1 + S i)/sqrt2 rotated by multiples of i
+        constexpr float c = (k == 2 || k == 14) ? W16::H : -W16::H;
+        constexpr float s = (k == 2 || k == 6) ? W16::H : -W16::H;  // sin(2 pi k/16) sign
+        const float ss = S * s;
+        return make_float2(fmaf(z.x, c, -z.y * ss), fmaf(z.x, ss, z.y * c));
+    } else {
+        // odd k: cos/sin of k pi / 8
+        constexpr float cs[16] = {1.f, W16::C1, W16::H, W16::S1, 0.f, -W16::S1, -W16::H, -W16::C1,
+                                  -1.f, -W16::C1, -W16::H, -W16::S1, 0.f, W16::S1, W16::H, W16::C1};
+        constexpr float sn[16] = {0.f, W16::S1, W16::H, W16::C1, 1.f, W16::C1, W16::H, W16::S1,
+                                  0.f, -W16::S1, -W16::H, -W16::C1, -1.f, -W16::C1, -W16::H, -W16::S1};
+        const float c = cs[k];
+        const float s = S * sn[k];
+        return make_float2(fmaf(z.x, c, -z.y * s), fmaf(z.x, s, z.y * c));
+    }
+}
+
+// In-register DFTs with natural-order input and output: y_k = sum_j x_j e^{S 2 pi i jk/r}.
+template <int S>
+__device__ __forceinline__ void dft2(c32& a, c32& b) {
+    c32 t = a;
+    a = cadd(t, b);
+    b = csub(t, b);
+}
+
+template <int S>
+__device__ __forceinline__ void dft4(c32& x0, c32& x1, c32& x2, c32& x3) {
+    c32 s02 = cadd(x0, x2), d02 = csub(x0, x2);
+    c32 s13 = cadd(x1, x3), d13 = mul_i<S>(csub(x1, x3));
+    x0 = cadd(s02, s13);
+    x2 = csub(s02, s13);
+    x1 = cadd(d02, d13);
+    x3 = csub(d02, d13);
+}
+
+template <int R, int S>
+struct DFT;
+
+template <int S>
+struct DFT<2, S> {
+    __device__ __forceinline__ static void run(c32 (&x)[2]) { dft2<S>(x[0], x[1]); }
+};
+
+template <int S>
+struct DFT<4, S> {
+    __device__ __forceinline__ static void run(c32 (&x)[4]) { dft4<S>(x[0], x[1], x[2], x[3]); }
+};
+
+// 8 = 2 x 4: j = j1 + 2 j2, k = 4 k1 + k2
+template <int S>
+struct DFT<8, S> {
+    __device__ __forceinline__ static void run(c32 (&x)[8]) {
+        dft4<S>(x[0], x[2], x[4], x[6]);  // j1 = 0 -> Y[0][k2] in x[0,2,4,6]
+        dft4<S>(x[1], x[3], x[5], x[7]);  // j1 = 1 -> Y[1][k2] in x[1,3,5,7]
+        x[3] = w16_mul<S, 2>(x[3]);       // W8^{k2}, k2 = 1..3
+        x[5] = w16_mul<S, 4>(x[5]);
+        x[7] = w16_mul<S, 6>(x[7]);
+        dft2<S>(x[0], x[1]);  // k2 = 0 -> X[0], X[4]
+        dft2<S>(x[2], x[3]);  // k2 = 1 -> X[1], X[5]
+        dft2<S>(x[4], x[5]);  // k2 = 2 -> X[2], X[6]
+        dft2<S>(x[6], x[7]);  // k2 = 3 -> X[3], X[7]
+        c32 y[8] = {x[0], x[2], x[4], x[6], x[1], x[3], x[5], x[7]};
+#pragma unroll
+        for (int i = 0; i < 8; i++) x[i] = y[i];
+    }
+};
+
+// 16 = 4 x 4: j = j1 + 4 j2, k = 4 k1 + k2; W16^{jk} = W4^{j1 k1} W16^{j1 k2} W4^{j2 k2}
+template <int S>
+struct DFT<16, S> {
+    __device__ __forceinline__ static void run(c32 (&x)[16]) {
+        // step A: for each j1, DFT4 over j2 of x[j1 + 4 j2] -> Y[j1][k2] stored at x[j1 + 4 k2]
+        dft4<S>(x[0], x[4], x[8], x[12]);
+        dft4<S>(x[1], x[5], x[9], x[13]);
+        dft4<S>(x[2], x[6], x[10], x[14]);
+        dft4<S>(x[3], x[7], x[11], x[15]);
+        // step B: Y[j1][k2] *= W16^{j1 k2}
+        x[5] = w16_mul<S, 1>(x[5]);
+        x[9] = w16_mul<S, 2>(x[9]);
+        x[13] = w16_mul<S, 3>(x[13]);
+        x[6] = w16_mul<S, 2>(x[6]);
+        x[10] = w16_mul<S, 4>(x[10]);
+        x[14] = w16_mul<S, 6>(x[14]);
+        x[7] = w16_mul<S, 3>(x[7]);
+        x[11] = w16_mul<S, 6>(x[11]);
+        x[15] = w16_mul<S, 9>(x[15]);
+        // step C: for each k2, DFT4 over j1 of Y[j1][k2] = x[j1 + 4 k2] -> X[4 k1 + k2]
+        dft4<S>(x[0], x[1], x[2], x[3]);
+        dft4<S>(x[4], x[5], x[6], x[7]);
+        dft4<S>(x[8], x[9], x[10], x[11]);
+        dft4<S>(x[12], x[13], x[14], x[15]);
+        // now x[k1 + 4 k2] holds X[4 k1 + k2]: transpose the 4 x 4 index
+        c32 y[16];
+#pragma unroll
+        for (int k1 = 0; k1 < 4; k1++)
+#pragma unroll
+            for (int k2 = 0; k2 < 4; k2++) y[4 * k1 + k2] = x[k1 + 4 * k2];
+#pragma unroll
+        for (int i = 0; i < 16; i++) x[i] = y[i];
+    }
+};
+
+constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n / 2); }
+
+// Shape of the transform of a line of N points.
+template <int N>
+struct FFTShape {
+    static_assert(N >= 8 && (N & (N - 1)) == 0, "N must be a power of two >= 8");
+    static constexpr int R = N < 16 ? N : 16;   // values per thread
+    static constexpr int T = N / R;             // threads per line
+    static constexpr int S16 = N < 16 ? 0 : ilog2(N) / 4;       // radix-16 stages
+    static constexpr int Q = N < 16 ? N : (N >> (4 * S16));     // last radix (1 = none)
+    static constexpr int NSTAGES = S16 + (Q > 1 ? 1 : 0);
+    // radix and Ns (product of earlier radices) of stage i
+    __host__ __device__ static constexpr int radix(int i) { return (N < 16) ? N : (i < S16 ? 16 : Q); }
+    __host__ __device__ static constexpr int ns(int i) { return i == 0 ? 1 : ns(i - 1) * radix(i - 1); }
+};
+
+// LDS layout of an exchange buffer that holds `LINES` lines of N complex values.
+// ROWMAJOR (lines contiguous, one pad slot every 16 values): used when the threads of
+// a line are adjacent lanes (lines along the contiguous axis). Otherwise element-major
+// with the line index fastest: used when adjacent lanes hold adjacent lines (columns
+// of a strided axis).
+template <int N, int LINES, bool ROWMAJOR>
+struct LdsLayout {
+    static constexpr int ROW = N + (N >= 16 ? N / 16 : 0);
+    static constexpr int SIZE = ROWMAJOR ? LINES * ROW : LINES * N;
+    __device__ __forceinline__ static int addr(int line, int e) {
+        if constexpr (ROWMAJOR) {
+            return line * ROW + e + (N >= 16 ? (e >> 4) : 0);
+        } else {
+            return e * LINES + line;
+        }
+    }
+};
+
+// One Stockham stage on the registers of one thread: U = R/radix butterflies,
+// butterfly u is b = t + T u with inputs v[u*radix + k] = x[b + k N/radix].
+template <int N, int S, int STAGE>
+__device__ __forceinline__ void fft_stage(c32 (&v)[FFTShape<N>::R], int t, const c32* __restrict__ tw) {
+    using F = FFTShape<N>;
+    constexpr int r = F::radix(STAGE);
+    constexpr int ns = F::ns(STAGE);
+    constexpr int U = F::R / r;
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+        c32 x[r];
+#pragma unroll
+        for (int k = 0; k < r; k++) x[k] = v[u * r + k];
+        if constexpr (ns > 1) {
+            const int b = t + F::T * u;
+            const int bm = b & (ns - 1);
+            constexpr int step = N / (ns * r);
+#pragma unroll
+            for (int k = 1; k < r; k++) {
+                c32 w = tw[bm * k * step];
+                if constexpr (S > 0) w = cconj(w);
+                x[k] = cmul(x[k], w);
+            }
+        }
+        DFT<r, S>::run(x);
+#pragma unroll
+        for (int k = 0; k < r; k++) v[u * r + k] = x[k];
+    }
+}
+
+// Write the outputs of stage STAGE to LDS and read the inputs of stage STAGE+1.
+template <int N, int STAGE, class L, int NF>
+__device__ __forceinline__ void fft_exchange(c32 (&v)[NF][FFTShape<N>::R], int t, int line, c32* lds) {
+    using F = FFTShape<N>;
+    constexpr int r = F::radix(STAGE);
+    constexpr int ns = F::ns(STAGE);
+    constexpr int U = F::R / r;
+    constexpr int r2 = F::radix(STAGE + 1);
+    constexpr int U2 = F::R / r2;
+#pragma unroll
+    for (int f = 0; f < NF; f++) {
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int b = t + F::T * u;
+            const int base = (b / ns) * ns * r + (b & (ns - 1));
+#pragma unroll
+            for (int k = 0; k < r; k++) lds[f * L::SIZE + L::addr(line, base + k * ns)] = v[f][u * r + k];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int f = 0; f < NF; f++) {
+#pragma unroll
+        for (int u = 0; u < U2; u++) {
+            const int b = t + F::T * u;
+#pragma unroll
+            for (int k = 0; k < r2; k++) v[f][u * r2 + k] = lds[f * L::SIZE + L::addr(line, b + k * (N / r2))];
+        }
+    }
+    __syncthreads();
+}
+
+// After the last stage, register u*Q + k holds element t + T (u + k R/Q); put element
+// t + T m into register m.
+template <int N>
+__device__ __forceinline__ void fft_natural_order(c32 (&v)[FFTShape<N>::R]) {
+    using F = FFTShape<N>;
+    constexpr int r = F::radix(F::NSTAGES - 1);
+    constexpr int U = F::R / r;
+    if constexpr (U > 1) {
+        c32 y[F::R];
+#pragma unroll
+        for (int u = 0; u < U; u++)
+#pragma unroll
+            for (int k = 0; k < r; k++) y[u + k * U] = v[u * r + k];
+#pragma unroll
+        for (int i = 0; i < F::R; i++) v[i] = y[i];
+    }
+}
+
+// Stage i of a transform of NF fields at once: the register half of stage i, then the
+// exchange into stage i+1.
+template <int N, int S, int STAGE, class L, int NF>
+__device__ __forceinline__ void fft_stages_from(c32 (&v)[NF][FFTShape<N>::R], int t, int line, c32* lds,
+                                                const c32* __restrict__ tw) {
+    using F = FFTShape<N>;
+#pragma unroll
+    for (int f = 0; f < NF; f++) fft_stage<N, S, STAGE>(v[f], t, tw);
+    if constexpr (STAGE + 1 < F::NSTAGES) {
+        fft_exchange<N, STAGE, L, NF>(v, t, line, lds);
+        fft_stages_from<N, S, STAGE + 1, L, NF>(v, t, line, lds, tw);
+    }
+}
+
+// Full transform of NF lines (one per field) owned by this thread group. On entry and
+// on exit thread t holds element t + T m in v[f][m]. S = -1 forward, +1 inverse.
+// All threads of the block must call this together (it contains barriers).
+template <int N, int S, class L, int NF>
+__device__ __forceinline__ void fft_line(c32 (&v)[NF][FFTShape<N>::R], int t, int line, c32* lds,
+                                         const c32* __restrict__ tw) {
+    fft_stages_from<N, S, 0, L, NF>(v, t, line, lds, tw);
+#pragma unroll
+    for (int f = 0; f < NF; f++) fft_natural_order<N>(v[f]);
+}
+
+}  // namespace rk4ip

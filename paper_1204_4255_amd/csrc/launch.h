@@ -1,0 +1,39 @@
+// launch.h -- host-side entry points of the kernels in kernels.hip (library internal).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rk4ip {
+
+struct GroupDev;
+
+// Kinds of axis pass (see kernels.hip for the data flow of each).
+enum PassMode { PASS_D1 = 0, PASS_D2 = 1, PASS_FIRST = 2, PASS_LAST1 = 3, PASS_LAST2 = 4 };
+
+// Constants of the final diagnostic sum (FP64).
+struct DiagConst {
+    double dV;
+    double alpha;
+    double half_g;
+};
+
+int axis_lines(int N, int axis, int n0);
+
+hipError_t launch_axis(const GroupDev& g, int axis, int mode, int adj, float2* psi, float2* A, float2* B,
+                       int64_t step_off, const int64_t* step_base, hipStream_t s);
+hipError_t launch_line_step(const GroupDev& g, float2* psi, int nsteps, int64_t step_off, const int64_t* step_base,
+                            hipStream_t s);
+hipError_t launch_diag_axis(const GroupDev& g, int axis, const float2* psi, double kscale, double* part,
+                            hipStream_t s);
+hipError_t launch_diag_final(const GroupDev& g, const DiagConst& c, const double* p0, const double* p1,
+                             const double* p2, double* out, int* flag, hipStream_t s);
+hipError_t launch_overlap(const GroupDev& g, double dV, const float2* phi, const float2* psi, double* out,
+                          hipStream_t s);
+hipError_t launch_moments(const GroupDev& g, const float2* psi, double* mean, double* var, hipStream_t s);
+hipError_t launch_counter(int64_t* c, int64_t v, int add, hipStream_t s);
+hipError_t launch_philox(uint32_t k0, uint32_t k1, const uint32_t* ctr, int64_t n, uint32_t* out, hipStream_t s);
+hipError_t launch_noise(const GroupDev& g, int64_t step, float2* xi, hipStream_t s);
+hipError_t launch_fft_lines(const float2* in, float2* out, int64_t n, int64_t nlines, int sign, const float2* tw,
+                            hipStream_t s);
+
+}  // namespace rk4ip

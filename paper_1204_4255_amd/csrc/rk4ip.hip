@@ -1,0 +1,600 @@
+// rk4ip.hip -- host runtime of the RK4IP library: validation, plan-time tables,
+// workspace carving, the per-step pass schedule, hipGraph replay, FP64 diagnostics and
+// the C ABI declared in include/rk4ip.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/rk4ip.h"
+#include "device_common.h"
+#include "launch.h"
+
+using rk4ip::GroupDev;
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr size_t kAlign = 256;
+constexpr uint32_t kKnownFlags = RK4IP_FLAG_GRAPH | RK4IP_FLAG_AUTOTUNE | RK4IP_FLAG_FUSE_1D;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+
+int ilog2i(int64_t v) {
+    int r = 0;
+    while ((int64_t(1) << r) < v) r++;
+    return r;
+}
+
+struct GroupHost {
+    rk4ip_problem p;
+    GroupDev d;
+    int64_t M = 0;
+    int64_t first_inst = 0;  // index of the group's first instance among all instances
+    size_t tab_off[3] = {0, 0, 0};   // E table offsets in the workspace
+    size_t tw_off[3] = {0, 0, 0};    // twiddle table offsets
+    size_t part_off[3] = {0, 0, 0};  // diagnostic partials (batch * M/n_a * 4 doubles)
+    double dV = 1.0;
+};
+
+// Workspace layout computed identically by rk4ip_workspace_bytes and rk4ip_plan.
+struct Layout {
+    size_t header = 0;   // step counter + sticky flag
+    size_t fields = 0;   // A and B
+    size_t total = 0;
+    int64_t points = 0;
+};
+
+int validate(const rk4ip_problem* probs, int nprob, uint32_t flags) {
+    if (!probs || nprob < 1 || nprob > 4096) return RK4IP_ERR_INVALID_ARG;
+    if (flags & ~kKnownFlags) return RK4IP_ERR_INVALID_ARG;
+    const double dt0 = probs[0].dt;
+    int64_t ninst = 0;
+    for (int i = 0; i < nprob; i++) {
+        const rk4ip_problem& p = probs[i];
+        if (p.reserved0 != 0 || p.reserved1 != 0) return RK4IP_ERR_INVALID_ARG;
+        if (!(p.dt > 0.0) || !std::isfinite(p.dt) || p.dt != dt0) return RK4IP_ERR_INVALID_ARG;
+        if (!std::isfinite(p.alpha) || !std::isfinite(p.gamma) || p.gamma < 0.0) return RK4IP_ERR_INVALID_ARG;
+        if (!std::isfinite(p.g_nl) || !std::isfinite(p.sigma) || p.sigma < 0.0) return RK4IP_ERR_INVALID_ARG;
+        if (p.batch < 1 || p.batch > (int64_t(1) << 31)) return RK4IP_ERR_INVALID_ARG;
+        if ((uint64_t)p.id_base + (uint64_t)p.batch - 1 > 0xFFFFFFFFull) return RK4IP_ERR_INVALID_ARG;
+        if (p.ndim < 1 || p.ndim > 3) return RK4IP_ERR_UNSUPPORTED_SHAPE;
+        const int64_t nmax = p.ndim == 1 ? 4096 : 1024;
+        int64_t M = 1;
+        for (int a = 0; a < 3; a++) {
+            if (a < p.ndim) {
+                if (!is_pow2(p.n[a]) || p.n[a] < 8 || p.n[a] > nmax) return RK4IP_ERR_UNSUPPORTED_SHAPE;
+                if (!(p.hi[a] > p.lo[a]) || !std::isfinite(p.hi[a]) || !std::isfinite(p.lo[a]))
+                    return RK4IP_ERR_INVALID_ARG;
+                if (!std::isfinite(p.trap[a])) return RK4IP_ERR_INVALID_ARG;
+                M *= p.n[a];
+            } else if (p.n[a] != 1) {
+                return RK4IP_ERR_UNSUPPORTED_SHAPE;
+            }
+        }
+        if (M > (int64_t(1) << 31) / 1 || p.batch * M > (int64_t(1) << 40)) return RK4IP_ERR_UNSUPPORTED_SHAPE;
+        ninst += p.batch;
+    }
+    if (ninst > (int64_t(1) << 31)) return RK4IP_ERR_INVALID_ARG;
+    return RK4IP_OK;
+}
+
+// Offsets of every table and buffer; fills `gh` when non-null.
+Layout layout(const rk4ip_problem* probs, int nprob, std::vector<GroupHost>* gh) {
+    Layout L;
+    size_t off = 0;
+    L.header = off;
+    off += kAlign;
+    for (int i = 0; i < nprob; i++) {
+        const rk4ip_problem& p = probs[i];
+        for (int a = 0; a < p.ndim; a++) {
+            size_t e = off;
+            off = align_up(off + sizeof(float2) * (size_t)p.n[a]);
+            size_t t = off;
+            off = align_up(off + sizeof(float2) * (size_t)p.n[a]);
+            if (gh) {
+                (*gh)[i].tab_off[a] = e;
+                (*gh)[i].tw_off[a] = t;
+            }
+        }
+    }
+    for (int i = 0; i < nprob; i++) {
+        const rk4ip_problem& p = probs[i];
+        int64_t M = p.n[0] * p.n[1] * p.n[2];
+        for (int a = 0; a < p.ndim; a++) {
+            if (gh) (*gh)[i].part_off[a] = off;
+            off = align_up(off + sizeof(double) * 4 * (size_t)(p.batch * (M / p.n[a])));
+        }
+        L.points += p.batch * M;
+    }
+    L.fields = off;
+    off = align_up(off + 2 * sizeof(float2) * (size_t)L.points);
+    L.total = off;
+    return L;
+}
+
+}  // namespace
+
+struct rk4ip_plan_s {
+    std::vector<GroupHost> groups;
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+    hipStream_t stream = nullptr;
+    uint32_t flags = 0;
+    int device = 0;
+    int64_t points = 0;
+    int64_t ninst = 0;
+    float2* A = nullptr;
+    float2* B = nullptr;
+    int64_t* counter = nullptr;
+    int* flag = nullptr;
+    std::string err;
+    std::vector<std::string> sched_names;
+    // cached graph of `graph_steps` steps on `graph_psi`
+    hipGraphExec_t graph = nullptr;
+    hipGraph_t graph_src = nullptr;
+    void* graph_psi = nullptr;
+    int graph_steps = 0;
+    hipStream_t capture_stream = nullptr;  // private stream the graph is recorded on
+    int sticky = RK4IP_OK;
+};
+
+namespace {
+
+int fail(rk4ip_plan_t plan, int code, const std::string& msg) {
+    if (plan) plan->err = msg;
+    return code;
+}
+
+int fail_hip(rk4ip_plan_t plan, hipError_t e, const char* what) {
+    if (plan) {
+        plan->err = std::string(what) + ": " + hipGetErrorString(e);
+        plan->sticky = RK4IP_ERR_HIP;
+    }
+    return RK4IP_ERR_HIP;
+}
+
+#define HIPCHK(plan, expr)                                           \
+    do {                                                             \
+        hipError_t e_ = (expr);                                      \
+        if (e_ != hipSuccess) return fail_hip((plan), e_, #expr);    \
+    } while (0)
+
+void drop_graph(rk4ip_plan_t plan) {
+    if (plan->graph) (void)hipGraphExecDestroy(plan->graph);
+    if (plan->graph_src) (void)hipGraphDestroy(plan->graph_src);
+    plan->graph = nullptr;
+    plan->graph_src = nullptr;
+    plan->graph_psi = nullptr;
+    plan->graph_steps = 0;
+}
+
+// Tables of one axis (FP64 arithmetic, FP32 storage).
+void build_tables(const rk4ip_problem& p, int a, std::vector<float2>& E, std::vector<float2>& tw) {
+    const int64_t n = p.n[a];
+    const double Lx = p.hi[a] - p.lo[a];
+    const double h = p.dt;
+    const double damp = (a == 0) ? std::exp(-p.gamma * h / 2.0) : 1.0;
+    const double em1 = (a == 0) ? std::expm1(-p.gamma * h / 2.0) : 0.0;
+    E.resize(n);
+    tw.resize(n);
+    const double inv_n = 1.0 / (double)n;  // exact power of two
+    for (int64_t m = 0; m < n; m++) {
+        const double k = 2.0 * kPi / Lx * (double)(m < n / 2 ? m : m - n);
+        const double theta = p.alpha * k * k * h / 2.0;
+        const double sh = std::sin(theta / 2.0);
+        // E - 1 = damp cos(theta) - 1 - i damp sin(theta), with
+        // damp cos(theta) - 1 = (damp - 1) - 2 damp sin^2(theta/2) (no cancellation)
+        const double c = em1 - 2.0 * damp * sh * sh;
+        const double s = -damp * std::sin(theta);
+        E[m] = make_float2((float)(c * inv_n), (float)(s * inv_n));
+        const double ang = 2.0 * kPi * (double)m / (double)n;
+        tw[m] = make_float2((float)std::cos(ang), (float)-std::sin(ang));
+    }
+}
+
+// The pass sequence of one step of a 2D/3D group: (axis, mode).
+int pass_list(int ndim, int (*out)[2]) {
+    if (ndim == 2) {
+        const int seq[4][2] = {{0, rk4ip::PASS_FIRST}, {1, rk4ip::PASS_LAST1}, {0, rk4ip::PASS_D2}, {1, rk4ip::PASS_LAST2}};
+        for (int i = 0; i < 4; i++) out[i][0] = seq[i][0], out[i][1] = seq[i][1];
+        return 4;
+    }
+    const int seq[6][2] = {{0, rk4ip::PASS_FIRST}, {1, rk4ip::PASS_D2}, {2, rk4ip::PASS_LAST1},
+                           {0, rk4ip::PASS_D2},    {1, rk4ip::PASS_D2}, {2, rk4ip::PASS_LAST2}};
+    for (int i = 0; i < 6; i++) out[i][0] = seq[i][0], out[i][1] = seq[i][1];
+    return 6;
+}
+
+// Enqueue `nsteps` steps of every group. step_base != null: step = *step_base + step_off.
+int enqueue_steps(rk4ip_plan_t plan, hipStream_t stream, float2* psi, int64_t step_off, int64_t nsteps,
+                  const int64_t* step_base, bool allow_fuse) {
+    for (auto& g : plan->groups) {
+        if (g.p.ndim == 1) {
+            if (allow_fuse && (plan->flags & RK4IP_FLAG_FUSE_1D)) {
+                HIPCHK(plan, rk4ip::launch_line_step(g.d, psi, (int)nsteps, step_off, step_base, stream));
+            } else {
+                for (int64_t s = 0; s < nsteps; s++)
+                    HIPCHK(plan, rk4ip::launch_line_step(g.d, psi, 1, step_off + s, step_base, stream));
+            }
+        }
+    }
+    for (int64_t s = 0; s < nsteps; s++) {
+        for (auto& g : plan->groups) {
+            if (g.p.ndim == 1) continue;
+            int seq[6][2];
+            const int np = pass_list(g.p.ndim, seq);
+            for (int i = 0; i < np; i++)
+                HIPCHK(plan, rk4ip::launch_axis(g.d, seq[i][0], seq[i][1], 0, psi, plan->A, plan->B, step_off + s,
+                                                step_base, stream));
+        }
+    }
+    return RK4IP_OK;
+}
+
+int device_ok(rk4ip_plan_t plan) {
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess || count < 1) {
+        (void)hipGetLastError();
+        return fail(plan, RK4IP_ERR_NO_DEVICE, "no HIP device");
+    }
+    int dev = 0;
+    HIPCHK(plan, hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    HIPCHK(plan, hipGetDeviceProperties(&prop, dev));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(plan, RK4IP_ERR_NO_DEVICE, std::string("device is ") + prop.gcnArchName + ", not gfx950");
+    if (plan) plan->device = dev;
+    return RK4IP_OK;
+}
+
+int do_diagnostics(rk4ip_plan_t plan, const float2* psi, double* out) {
+    for (auto& g : plan->groups) {
+        const double* parts[3] = {nullptr, nullptr, nullptr};
+        for (int a = 0; a < g.p.ndim; a++) {
+            double* part = reinterpret_cast<double*>(plan->ws + g.part_off[a]);
+            const double kscale = 2.0 * kPi / (g.p.hi[a] - g.p.lo[a]);
+            HIPCHK(plan, rk4ip::launch_diag_axis(g.d, a, psi, kscale, part, plan->stream));
+            parts[a] = part;
+        }
+        rk4ip::DiagConst c{g.dV, g.p.alpha, 0.5 * g.p.g_nl};
+        HIPCHK(plan, rk4ip::launch_diag_final(g.d, c, parts[0], parts[1] ? parts[1] : parts[0],
+                                              parts[2] ? parts[2] : parts[0], out + g.first_inst * 4, plan->flag,
+                                              plan->stream));
+    }
+    return RK4IP_OK;
+}
+
+// Build (or reuse) a graph of `gsteps` steps whose step index is read from the device
+// counter, followed by counter += gsteps.
+int ensure_graph(rk4ip_plan_t plan, float2* psi, int gsteps) {
+    if (plan->graph && plan->graph_psi == psi && plan->graph_steps == gsteps) return RK4IP_OK;
+    drop_graph(plan);
+    // record on a private stream (the caller's may be the legacy default stream, which
+    // cannot be captured); the instantiated graph is then launched on the plan's stream
+    if (!plan->capture_stream) HIPCHK(plan, hipStreamCreateWithFlags(&plan->capture_stream, hipStreamNonBlocking));
+    hipStream_t s = plan->capture_stream;
+    hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return fail_hip(plan, e, "hipStreamBeginCapture");
+    int rc = enqueue_steps(plan, s, psi, 0, gsteps, plan->counter, true);
+    hipError_t e2 = rk4ip::launch_counter(plan->counter, gsteps, 1, s);
+    hipGraph_t gr = nullptr;
+    hipError_t e3 = hipStreamEndCapture(s, &gr);
+    if (rc != RK4IP_OK || e2 != hipSuccess || e3 != hipSuccess || !gr) {
+        if (gr) (void)hipGraphDestroy(gr);
+        plan->err = "graph capture failed";
+        return RK4IP_ERR_NOT_CAPTURABLE;
+    }
+    hipGraphExec_t ex = nullptr;
+    e = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(gr);
+        plan->err = std::string("hipGraphInstantiate: ") + hipGetErrorString(e);
+        return RK4IP_ERR_NOT_CAPTURABLE;
+    }
+    plan->graph = ex;
+    plan->graph_src = gr;
+    plan->graph_psi = psi;
+    plan->graph_steps = gsteps;
+    return RK4IP_OK;
+}
+
+// Advance nsteps from step index `step`, using the graph when enabled.
+int advance(rk4ip_plan_t plan, float2* psi, int64_t step, int64_t nsteps) {
+    if (nsteps <= 0) return RK4IP_OK;
+    if (!(plan->flags & RK4IP_FLAG_GRAPH)) return enqueue_steps(plan, plan->stream, psi, step, nsteps, nullptr, true);
+    const int gsteps = (int)(nsteps < 8 ? nsteps : 8);
+    int rc = ensure_graph(plan, psi, gsteps);
+    if (rc != RK4IP_OK) return rc;
+    HIPCHK(plan, rk4ip::launch_counter(plan->counter, step, 0, plan->stream));
+    int64_t done = 0;
+    while (nsteps - done >= gsteps) {
+        hipError_t e = hipGraphLaunch(plan->graph, plan->stream);
+        if (e != hipSuccess) {
+            plan->err = std::string("hipGraphLaunch: ") + hipGetErrorString(e);
+            return RK4IP_ERR_NOT_CAPTURABLE;
+        }
+        done += gsteps;
+    }
+    if (done < nsteps) return enqueue_steps(plan, plan->stream, psi, step + done, nsteps - done, nullptr, true);
+    return RK4IP_OK;
+}
+
+}  // namespace
+
+// ================================================================== C ABI
+
+extern "C" {
+
+const char* rk4ip_strerror(int status) {
+    switch (status) {
+        case RK4IP_OK: return "ok";
+        case RK4IP_ERR_INVALID_ARG: return "invalid argument";
+        case RK4IP_ERR_UNSUPPORTED_SHAPE: return "unsupported lattice shape";
+        case RK4IP_ERR_WORKSPACE_TOO_SMALL: return "workspace too small";
+        case RK4IP_ERR_HIP: return "HIP runtime error";
+        case RK4IP_ERR_NONFINITE: return "non-finite value in a field";
+        case RK4IP_ERR_NOT_CAPTURABLE: return "graph capture or replay failed";
+        case RK4IP_ERR_NO_DEVICE: return "no usable gfx950 device";
+        default: return "unknown status";
+    }
+}
+
+size_t rk4ip_workspace_bytes(const rk4ip_problem* probs, int nprob, uint32_t flags) {
+    if (validate(probs, nprob, flags) != RK4IP_OK) return 0;
+    return layout(probs, nprob, nullptr).total;
+}
+
+int rk4ip_plan(const rk4ip_problem* probs, int nprob, void* workspace, size_t ws_bytes, void* stream,
+               uint32_t flags, rk4ip_plan_t* out) {
+    if (!out) return RK4IP_ERR_INVALID_ARG;
+    *out = nullptr;
+    int rc = validate(probs, nprob, flags);
+    if (rc != RK4IP_OK) return rc;
+    if (!workspace || (reinterpret_cast<uintptr_t>(workspace) % kAlign) != 0) return RK4IP_ERR_INVALID_ARG;
+    std::vector<GroupHost> gh(nprob);
+    Layout L = layout(probs, nprob, &gh);
+    if (ws_bytes < L.total) return RK4IP_ERR_WORKSPACE_TOO_SMALL;
+
+    rk4ip_plan_s* plan = new (std::nothrow) rk4ip_plan_s();
+    if (!plan) return RK4IP_ERR_INVALID_ARG;
+    rc = device_ok(plan);
+    if (rc != RK4IP_OK) {
+        delete plan;
+        return rc;
+    }
+    plan->ws = static_cast<char*>(workspace);
+    plan->ws_bytes = ws_bytes;
+    plan->stream = static_cast<hipStream_t>(stream);
+    plan->flags = flags;
+    plan->points = L.points;
+    plan->counter = reinterpret_cast<int64_t*>(plan->ws + L.header);
+    plan->flag = reinterpret_cast<int*>(plan->ws + L.header + 64);
+    plan->A = reinterpret_cast<float2*>(plan->ws + L.fields);
+    plan->B = plan->A + L.points;
+
+    // host staging of the tables; uploaded with one synchronous copy per table
+    int64_t offset = 0, inst = 0;
+    for (int i = 0; i < nprob; i++) {
+        GroupHost& g = gh[i];
+        g.p = probs[i];
+        const rk4ip_problem& p = g.p;
+        GroupDev& d = g.d;
+        std::memset(&d, 0, sizeof(d));
+        d.ndim = p.ndim;
+        g.M = 1;
+        g.dV = 1.0;
+        for (int a = 0; a < 3; a++) {
+            d.n[a] = (int)p.n[a];
+            d.log2n[a] = ilog2i(p.n[a]);
+            g.M *= p.n[a];
+            if (a < p.ndim) {
+                const double dx = (p.hi[a] - p.lo[a]) / (double)p.n[a];
+                g.dV *= dx;
+                d.lo[a] = (float)p.lo[a];
+                d.dx[a] = (float)dx;
+                d.half_trap[a] = (float)(0.5 * p.trap[a]);
+                d.inv_n[a] = (float)(1.0 / (double)p.n[a]);
+            }
+        }
+        d.M = g.M;
+        d.batch = p.batch;
+        d.offset = offset;
+        d.h = (float)p.dt;
+        d.gnl = (float)p.g_nl;
+        d.noise_c = (float)(p.dt * p.sigma / std::sqrt(2.0 * p.dt * g.dV));
+        d.xi_scale = (float)(1.0 / std::sqrt(2.0 * p.dt * g.dV));
+        d.seed_lo = (uint32_t)(p.seed & 0xFFFFFFFFu);
+        d.seed_hi = (uint32_t)(p.seed >> 32);
+        d.id_base = p.id_base;
+        d.has_noise = p.sigma != 0.0 ? 1 : 0;
+        d.Vgrid = p.V_grid;
+        for (int a = 0; a < p.ndim; a++) {
+            std::vector<float2> E, tw;
+            build_tables(p, a, E, tw);
+            hipError_t e1 = hipMemcpy(plan->ws + g.tab_off[a], E.data(), sizeof(float2) * E.size(), hipMemcpyHostToDevice);
+            hipError_t e2 = hipMemcpy(plan->ws + g.tw_off[a], tw.data(), sizeof(float2) * tw.size(), hipMemcpyHostToDevice);
+            if (e1 != hipSuccess || e2 != hipSuccess) {
+                rc = fail_hip(plan, e1 != hipSuccess ? e1 : e2, "table upload");
+                delete plan;
+                return rc;
+            }
+            d.E[a] = reinterpret_cast<const float2*>(plan->ws + g.tab_off[a]);
+            d.tw[a] = reinterpret_cast<const float2*>(plan->ws + g.tw_off[a]);
+        }
+        g.first_inst = inst;
+        offset += p.batch * g.M;
+        inst += p.batch;
+        char name[96];
+        for (int a = 0; a < p.ndim; a++) {
+            std::snprintf(name, sizeof(name), "g%d.axis%d:n%lld:%s:lines%d", i, a, (long long)p.n[a],
+                          p.ndim == 1 ? "line-step" : (a == 0 ? "contig" : "strided"),
+                          p.ndim == 1 ? 1 : rk4ip::axis_lines((int)p.n[a], a, (int)p.n[0]));
+            plan->sched_names.push_back(name);
+        }
+    }
+    plan->ninst = inst;
+    plan->groups = std::move(gh);
+    hipError_t e = hipMemset(plan->ws + L.header, 0, kAlign);
+    if (e != hipSuccess) {
+        rc = fail_hip(plan, e, "hipMemset");
+        delete plan;
+        return rc;
+    }
+    *out = plan;
+    return RK4IP_OK;
+}
+
+int rk4ip_set_stream(rk4ip_plan_t plan, void* stream) {
+    if (!plan) return RK4IP_ERR_INVALID_ARG;
+    if (plan->stream != static_cast<hipStream_t>(stream)) drop_graph(plan);
+    plan->stream = static_cast<hipStream_t>(stream);
+    return RK4IP_OK;
+}
+
+int rk4ip_step(rk4ip_plan_t plan, void* psi, int64_t step_index) {
+    if (!plan || !psi || step_index < 0) return RK4IP_ERR_INVALID_ARG;
+    return enqueue_steps(plan, plan->stream, static_cast<float2*>(psi), step_index, 1, nullptr, false);
+}
+
+int rk4ip_diagnostics(rk4ip_plan_t plan, const void* psi, double* out) {
+    if (!plan || !psi || !out) return RK4IP_ERR_INVALID_ARG;
+    return do_diagnostics(plan, static_cast<const float2*>(psi), out);
+}
+
+int rk4ip_run(rk4ip_plan_t plan, void* psi_v, int64_t step0, int64_t nsteps, int64_t sample_every, double* diag,
+              void* ckpt_v, int64_t ckpt_every) {
+    if (!plan || !psi_v || step0 < 0 || nsteps < 0) return RK4IP_ERR_INVALID_ARG;
+    if (diag && sample_every < 1) return RK4IP_ERR_INVALID_ARG;
+    if (ckpt_v && ckpt_every < 1) return RK4IP_ERR_INVALID_ARG;
+    float2* psi = static_cast<float2*>(psi_v);
+    float2* ckpt = static_cast<float2*>(ckpt_v);
+    const int64_t se = diag ? sample_every : 0;
+    const int64_t ce = ckpt ? ckpt_every : 0;
+    int64_t s = 0;
+    int64_t sample = 0;
+    while (true) {
+        if (se && s % se == 0) {
+            int rc = do_diagnostics(plan, psi, diag + sample * plan->ninst * 4);
+            if (rc) return rc;
+            sample++;
+        }
+        if (s == nsteps) break;
+        if (ce && s % ce == 0)
+            HIPCHK(plan, hipMemcpyAsync(ckpt + (s / ce) * plan->points, psi, sizeof(float2) * plan->points,
+                                        hipMemcpyDeviceToDevice, plan->stream));
+        // run to the next sample or checkpoint boundary
+        int64_t next = nsteps;
+        if (se) next = std::min(next, (s / se + 1) * se);
+        if (ce) next = std::min(next, (s / ce + 1) * ce);
+        int rc = advance(plan, psi, step0 + s, next - s);
+        if (rc) return rc;
+        s = next;
+    }
+    return RK4IP_OK;
+}
+
+int rk4ip_overlap(rk4ip_plan_t plan, int group, const void* phi, const void* psi, double* out) {
+    if (!plan || !phi || !psi || !out || group < 0 || group >= (int)plan->groups.size()) return RK4IP_ERR_INVALID_ARG;
+    const GroupHost& g = plan->groups[group];
+    HIPCHK(plan, rk4ip::launch_overlap(g.d, g.dV, static_cast<const float2*>(phi), static_cast<const float2*>(psi), out,
+                                       plan->stream));
+    return RK4IP_OK;
+}
+
+int rk4ip_moments(rk4ip_plan_t plan, int group, const void* psi, double* mean, double* var) {
+    if (!plan || !psi || !mean || !var || group < 0 || group >= (int)plan->groups.size()) return RK4IP_ERR_INVALID_ARG;
+    const GroupHost& g = plan->groups[group];
+    HIPCHK(plan, rk4ip::launch_moments(g.d, static_cast<const float2*>(psi), mean, var, plan->stream));
+    return RK4IP_OK;
+}
+
+size_t rk4ip_adjoint_workspace_bytes(rk4ip_plan_t plan, int64_t ckpt_every) {
+    (void)plan;
+    (void)ckpt_every;
+    return 0;
+}
+
+int rk4ip_adjoint(rk4ip_plan_t plan, const void* ckpt, int64_t step0, int64_t nsteps, int64_t ckpt_every,
+                  const void* lambda_T, void* grad_psi0, float* grad_V, void* adj_ws, size_t adj_ws_bytes) {
+    (void)ckpt; (void)step0; (void)nsteps; (void)ckpt_every; (void)lambda_T; (void)grad_psi0; (void)grad_V;
+    (void)adj_ws; (void)adj_ws_bytes;
+    return fail(plan, RK4IP_ERR_INVALID_ARG, "adjoint not built yet");
+}
+
+int rk4ip_status(rk4ip_plan_t plan) {
+    if (!plan) return RK4IP_ERR_INVALID_ARG;
+    hipError_t e = hipStreamSynchronize(plan->stream);
+    if (e != hipSuccess) return fail_hip(plan, e, "hipStreamSynchronize");
+    int flag = 0;
+    e = hipMemcpy(&flag, plan->flag, sizeof(int), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return fail_hip(plan, e, "hipMemcpy(flag)");
+    int rc = plan->sticky;
+    if (rc == RK4IP_OK && flag) rc = RK4IP_ERR_NONFINITE;
+    if (flag) {
+        e = hipMemset(plan->flag, 0, sizeof(int));
+        if (e != hipSuccess) return fail_hip(plan, e, "hipMemset(flag)");
+    }
+    plan->sticky = RK4IP_OK;
+    return rc;
+}
+
+int rk4ip_destroy(rk4ip_plan_t plan) {
+    if (!plan) return RK4IP_ERR_INVALID_ARG;
+    (void)hipStreamSynchronize(plan->stream);
+    drop_graph(plan);
+    if (plan->capture_stream) (void)hipStreamDestroy(plan->capture_stream);
+    delete plan;
+    return RK4IP_OK;
+}
+
+const char* rk4ip_last_error(rk4ip_plan_t plan) { return plan ? plan->err.c_str() : ""; }
+
+const char* rk4ip_schedule(rk4ip_plan_t plan, int group, int pass) {
+    if (!plan || group < 0 || group >= (int)plan->groups.size()) return nullptr;
+    int idx = 0;
+    for (int i = 0; i < group; i++) idx += plan->groups[i].p.ndim;
+    if (pass < 0 || pass >= plan->groups[group].p.ndim) return nullptr;
+    return plan->sched_names[idx + pass].c_str();
+}
+
+int rk4ip_debug_philox(uint64_t seed, const uint32_t* ctr, int64_t n, uint32_t* out, void* stream) {
+    if (!ctr || !out || n < 0) return RK4IP_ERR_INVALID_ARG;
+    hipError_t e = rk4ip::launch_philox((uint32_t)seed, (uint32_t)(seed >> 32), ctr, n, out,
+                                        static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? RK4IP_OK : RK4IP_ERR_HIP;
+}
+
+int rk4ip_debug_noise(rk4ip_plan_t plan, int group, int64_t step, void* xi) {
+    if (!plan || !xi || step < 0 || group < 0 || group >= (int)plan->groups.size()) return RK4IP_ERR_INVALID_ARG;
+    HIPCHK(plan, rk4ip::launch_noise(plan->groups[group].d, step, static_cast<float2*>(xi), plan->stream));
+    return RK4IP_OK;
+}
+
+int rk4ip_debug_fft(rk4ip_plan_t plan, int group, int axis, const void* in, void* out, int64_t nlines, int sign) {
+    if (!plan || !in || !out || nlines < 0 || (sign != -1 && sign != 1)) return RK4IP_ERR_INVALID_ARG;
+    if (group < 0 || group >= (int)plan->groups.size()) return RK4IP_ERR_INVALID_ARG;
+    const GroupHost& g = plan->groups[group];
+    if (axis < 0 || axis >= g.p.ndim) return RK4IP_ERR_INVALID_ARG;
+    HIPCHK(plan, rk4ip::launch_fft_lines(static_cast<const float2*>(in), static_cast<float2*>(out), g.p.n[axis], nlines,
+                                         sign, g.d.tw[axis], plan->stream));
+    return RK4IP_OK;
+}
+
+int rk4ip_debug_apply_D(rk4ip_plan_t plan, void* psi, int adjoint) {
+    if (!plan || !psi) return RK4IP_ERR_INVALID_ARG;
+    for (auto& g : plan->groups)
+        for (int a = 0; a < g.p.ndim; a++)
+            HIPCHK(plan, rk4ip::launch_axis(g.d, a, rk4ip::PASS_D1, adjoint ? 1 : 0, static_cast<float2*>(psi), plan->A,
+                                            plan->B, 0, nullptr, plan->stream));
+    return RK4IP_OK;
+}
+
+}  // extern "C"

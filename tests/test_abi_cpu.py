@@ -1,0 +1,117 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports every
+symbol the header declares, sizes workspaces and rejects bad arguments with the
+documented status codes before it touches a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1204_4255_amd import rk4ip
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rk4ip.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rk4ip_[a-zA-Z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(rk4ip.LIB_PATH):
+        pytest.skip("librk4ip.so not built")
+    return rk4ip.load()
+
+
+def test_header_declares_binding_exports():
+    assert _declared() == sorted(rk4ip.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+def test_strerror_strings(lib):
+    for code in range(-7, 1):
+        assert rk4ip.rk4ip_strerror(code)
+    assert rk4ip.rk4ip_strerror(-99) == "unknown status"
+
+
+def _p(**kw):
+    base = dict(n=(64, 32), lo=(-4, -4), hi=(4, 4), dt=1e-3, batch=3)
+    base.update(kw)
+    return rk4ip.make_problem(**base)
+
+
+def test_workspace_bytes_counts_fields_tables_partials(lib):
+    nb = rk4ip.rk4ip_workspace_bytes([_p()])
+    pts = 64 * 32 * 3
+    assert nb >= 2 * 8 * pts + 2 * 8 * (64 + 32) + 8 * 4 * (3 * 32 + 3 * 64)
+    assert nb % 256 == 0
+    two = rk4ip.rk4ip_workspace_bytes([_p(), _p(n=(16, 16, 16), lo=(0, 0, 0), hi=(1, 1, 1), batch=1)])
+    assert two > nb
+
+
+@pytest.mark.parametrize("kw", [
+    dict(dt=0.0), dict(dt=-1.0), dict(batch=0), dict(gamma=-0.1), dict(sigma=-1.0),
+    dict(hi=(-4, 4)), dict(dt=float("nan")),
+])
+def test_invalid_descriptions_give_zero_workspace(lib, kw):
+    assert rk4ip.rk4ip_workspace_bytes([_p(**kw)]) == 0
+
+
+@pytest.mark.parametrize("n", [(48, 32), (64, 4), (2048, 8), (6,), (8192,)])
+def test_unsupported_shapes(lib, n):
+    p = rk4ip.make_problem(n=n, lo=(0,) * len(n), hi=(1,) * len(n), dt=0.1)
+    assert rk4ip.rk4ip_workspace_bytes([p]) == 0
+    arr = rk4ip.problems_array([p])
+    h = ctypes.c_void_p()
+    rc = lib.rk4ip_plan(arr, 1, ctypes.c_void_p(256), 1 << 30, None, 0, ctypes.byref(h))
+    assert rc == rk4ip.RK4IP_ERR_UNSUPPORTED_SHAPE and not h.value
+
+
+def test_plan_argument_checks_without_device(lib):
+    arr = rk4ip.problems_array([_p()])
+    h = ctypes.c_void_p()
+    nb = rk4ip.rk4ip_workspace_bytes([_p()])
+    assert lib.rk4ip_plan(arr, 1, ctypes.c_void_p(256), nb, None, 0, None) == rk4ip.RK4IP_ERR_INVALID_ARG
+    assert lib.rk4ip_plan(None, 1, ctypes.c_void_p(256), nb, None, 0, ctypes.byref(h)) == rk4ip.RK4IP_ERR_INVALID_ARG
+    assert lib.rk4ip_plan(arr, 0, ctypes.c_void_p(256), nb, None, 0, ctypes.byref(h)) == rk4ip.RK4IP_ERR_INVALID_ARG
+    assert lib.rk4ip_plan(arr, 1, None, nb, None, 0, ctypes.byref(h)) == rk4ip.RK4IP_ERR_INVALID_ARG
+    assert lib.rk4ip_plan(arr, 1, ctypes.c_void_p(300), nb, None, 0, ctypes.byref(h)) == rk4ip.RK4IP_ERR_INVALID_ARG
+    assert lib.rk4ip_plan(arr, 1, ctypes.c_void_p(256), nb, None, 0x100, ctypes.byref(h)) == rk4ip.RK4IP_ERR_INVALID_ARG
+    assert (lib.rk4ip_plan(arr, 1, ctypes.c_void_p(256), nb - 256, None, 0, ctypes.byref(h))
+            == rk4ip.RK4IP_ERR_WORKSPACE_TOO_SMALL)
+    mixed = rk4ip.problems_array([_p(), _p(dt=2e-3)])
+    assert lib.rk4ip_plan(mixed, 2, ctypes.c_void_p(256), 1 << 30, None, 0, ctypes.byref(h)) == rk4ip.RK4IP_ERR_INVALID_ARG
+    bad = _p()
+    bad.reserved0 = 1
+    assert rk4ip.rk4ip_workspace_bytes([bad]) == 0
+    ids = _p(batch=10)
+    ids.id_base = 0xFFFFFFFF - 3
+    assert rk4ip.rk4ip_workspace_bytes([ids]) == 0
+
+
+def test_null_plan_calls_are_rejected(lib):
+    assert lib.rk4ip_step(None, ctypes.c_void_p(256), 0) == rk4ip.RK4IP_ERR_INVALID_ARG
+    assert lib.rk4ip_run(None, ctypes.c_void_p(256), 0, 1, 0, None, None, 0) == rk4ip.RK4IP_ERR_INVALID_ARG
+    assert lib.rk4ip_status(None) == rk4ip.RK4IP_ERR_INVALID_ARG
+    assert lib.rk4ip_destroy(None) == rk4ip.RK4IP_ERR_INVALID_ARG
+    assert lib.rk4ip_last_error(None) == b""
+    assert lib.rk4ip_debug_philox(0, None, 1, None, None) == rk4ip.RK4IP_ERR_INVALID_ARG
+
+
+def test_valid_plan_without_gpu_reports_no_device(lib):
+    import torch
+
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    arr = rk4ip.problems_array([_p()])
+    h = ctypes.c_void_p()
+    nb = rk4ip.rk4ip_workspace_bytes([_p()])
+    rc = lib.rk4ip_plan(arr, 1, ctypes.c_void_p(256), nb, None, 0, ctypes.byref(h))
+    assert rc == rk4ip.RK4IP_ERR_NO_DEVICE and not h.value
