@@ -167,9 +167,22 @@ const char* rk4ip_strerror(int status);
 /* Last error message recorded on a plan (never NULL; "" when none). */
 const char* rk4ip_last_error(rk4ip_plan_t plan);
 
-/* Name of the schedule the plan chose for a group and pass (for logs and tests),
- * or NULL if out of range. */
+/* Number of kernel passes one step of group `group` runs (1 for a 1D group, 4 for 2D,
+ * 6 for 3D), or a negative status. */
+int rk4ip_num_passes(rk4ip_plan_t plan, int group);
+
+/* Name of pass `pass` of group `group` in step order: kind, axis, length and tile
+ * (for logs and profiles), or NULL if out of range. */
 const char* rk4ip_schedule(rk4ip_plan_t plan, int group, int pass);
+
+/* Per-pass timing with HIP events (tracing aid, off by default). While enabled, every
+ * kernel pass that rk4ip_step/rk4ip_run enqueue outside a graph is bracketed by an event
+ * pair on the plan's stream; enabling resets the counters. */
+int rk4ip_profile(rk4ip_plan_t plan, int enable);
+
+/* Wait for the plan's stream and return, for pass `pass` of group `group`, how many
+ * launches were timed and their mean duration in milliseconds. */
+int rk4ip_profile_read(rk4ip_plan_t plan, int group, int pass, int64_t* count, double* mean_ms);
 
 /* ---- test entry points (device pointers, asynchronous on `stream`) -------------- */
 

@@ -84,6 +84,7 @@ def _load():
         lib.ora_apply_D.restype = ctypes.c_int
         lib.ora_fft_nd.argtypes = [P, vp, ctypes.c_int]
         lib.ora_fft_nd.restype = ctypes.c_int
+        lib.ora_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -152,6 +153,11 @@ def _cfield(p: Problem, psi) -> np.ndarray:
     if a.size != p.batch * p.M:
         raise ValueError(f"field has {a.size} values, expected {p.batch * p.M}")
     return a.reshape(p.shape).copy()
+
+
+def threads() -> int:
+    """OpenMP threads the oracle runs with."""
+    return int(_load().ora_threads())
 
 
 def dft(x, sign: int = -1) -> np.ndarray:

@@ -43,6 +43,7 @@
  */
 #include <complex.h>
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -786,6 +787,9 @@ int ora_apply_D(const ora_problem* p, cplx* f, int dense, int adjoint) {
     free(E);
     return 0;
 }
+
+/* Threads the OpenMP loops of the oracle use. */
+int ora_threads(void) { return omp_get_max_threads(); }
 
 /* Multi-dimensional unnormalised transform of every instance (test entry). */
 int ora_fft_nd(const ora_problem* p, cplx* f, int sign) {

@@ -121,6 +121,25 @@ __device__ __forceinline__ c32 hG(const GroupDev& g, c32 phi, float V, c32 hnz) 
     return make_float2(r.x + hnz.x, r.y + hnz.y);
 }
 
+// Transposes for the discrete adjoint (not in the paper). G is R-linear in (phi, conj phi):
+// dG = A dphi + B conj(dphi) - i dV phi with A = -i (V + 2 g |phi|^2), B = -i g phi^2. With the
+// real inner product <x, y> = Re sum conj(x) y its transpose is conj(A) lam + B conj(lam),
+// and the potential gradient picks up Im(conj(lam) phi).
+__device__ __forceinline__ c32 hJT(const GroupDev& g, c32 phi, float V, c32 lam) {
+    const float m2 = fmaf(phi.x, phi.x, phi.y * phi.y);
+    const float ar = fmaf(2.0f * g.gnl, m2, V);
+    const float P = fmaf(phi.x, phi.x, -phi.y * phi.y);
+    const float Q = 2.0f * phi.x * phi.y;
+    const float cx = fmaf(P, lam.x, Q * lam.y);
+    const float cy = fmaf(Q, lam.x, -P * lam.y);
+    return make_float2(g.h * fmaf(g.gnl, cy, -ar * lam.y), g.h * fmaf(ar, lam.x, -g.gnl * cx));
+}
+
+// h Im(conj(lam) phi)
+__device__ __forceinline__ float hImconj(const GroupDev& g, c32 lam, c32 phi) {
+    return g.h * fmaf(lam.x, phi.y, -lam.y * phi.x);
+}
+
 // Spectral multiplier of the propagator in delta form. The table holds
 // (E_a - 1)/n_a = ((e cos(theta) - 1)/n, -e sin(theta)/n) with e the damping factor (axis 0
 // only) and theta = alpha k^2 h/2, computed in FP64 and rounded once. D_a is applied as

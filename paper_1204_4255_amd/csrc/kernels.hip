@@ -183,28 +183,32 @@ __global__ void __launch_bounds__(FFTShape<N>::T* LPB)
 // CONTIG: LINES consecutive lines along axis 0 (threads of a line are adjacent lanes).
 // strided: LINES adjacent x columns of one (instance, outer index) along axis 1 or 2
 // (adjacent lanes hold adjacent columns, so each row segment is one coalesced access).
+// Addresses are a workgroup-uniform 64-bit tile base plus 32-bit per-thread offsets,
+// shared by every field the pass touches.
 template <int N, bool CONTIG, int LINES>
 struct Tile {
-    int64_t base;      // point index (group-relative) of element 0 of line 0
-    int64_t stride;    // point stride along the axis
-    int64_t inst;      // instance of the tile (strided) / of this thread's line (contig)
-    int ix, iy, iz;    // lattice indices of element 0 of this thread's line
+    int64_t base;      // uniform: group-relative point index of the tile origin
+    uint32_t off0;     // this thread's element 0 relative to base
+    uint32_t dstep;    // offset between element t + m T and t + (m+1) T
+    int64_t inst;      // instance of this thread's line
+    int64_t jbase;     // in-instance index of this thread's element 0 (noise counter, Vgrid)
+    uint32_t jstride;  // in-instance index step per element along the axis
     bool active;
 
-    __device__ __forceinline__ Tile(const GroupDev& g, int axis, int l) {
+    __device__ __forceinline__ Tile(const GroupDev& g, int axis, int l, int t) {
+        constexpr int T = FFTShape<N>::T;
         if constexpr (CONTIG) {
             const int64_t lines_per_inst = g.M >> g.log2n[0];
             const int64_t nlines = g.batch * lines_per_inst;
             const int64_t line = (int64_t)blockIdx.x * LINES + l;
             active = line < nlines;
             const int64_t ln = active ? line : 0;
+            base = (int64_t)blockIdx.x * LINES * N;
+            off0 = (uint32_t)(l * N + t);
+            dstep = T;
             inst = ln / lines_per_inst;
-            const int64_t li = ln - inst * lines_per_inst;
-            base = ln * N;
-            stride = 1;
-            ix = 0;
-            iy = (int)(li & (g.n[1] - 1));
-            iz = (int)(li >> g.log2n[1]);
+            jbase = (ln - inst * lines_per_inst) * N + t;
+            jstride = 1;
         } else {
             const int xt_count = g.n[0] / LINES;
             const int outer_n = (axis == 1) ? g.n[2] : g.n[1];
@@ -214,141 +218,269 @@ struct Tile {
             const int outer = (int)(bid % outer_n);
             inst = bid / outer_n;
             active = true;
-            ix = xt * LINES + l;
-            if (axis == 1) {
-                stride = g.n[0];
-                iy = 0;
-                iz = outer;
-                base = inst * g.M + (int64_t)outer * g.n[0] * g.n[1] + xt * LINES;
-            } else {
-                stride = (int64_t)g.n[0] * g.n[1];
-                iy = outer;
-                iz = 0;
-                base = inst * g.M + (int64_t)outer * g.n[0] + xt * LINES;
-            }
+            const uint32_t stride = (axis == 1) ? (uint32_t)g.n[0] : (uint32_t)g.n[0] * (uint32_t)g.n[1];
+            const int64_t in_inst = (axis == 1) ? (int64_t)outer * g.n[0] * g.n[1] + xt * LINES
+                                                : (int64_t)outer * g.n[0] + xt * LINES;
+            base = inst * g.M + in_inst;
+            off0 = (uint32_t)l + (uint32_t)t * stride;
+            dstep = (uint32_t)T * stride;
+            jbase = in_inst + off0;
+            jstride = stride;
         }
     }
-    // group-relative point index of element e of this thread's line
-    __device__ __forceinline__ int64_t idx(int l, int e) const {
-        if constexpr (CONTIG)
-            return base + e;
-        else
-            return base + l + (int64_t)e * stride;
-    }
-    // lattice flat index within the instance of element e (for noise and Vgrid)
-    __device__ __forceinline__ void coords(const GroupDev& g, int axis, int e, int& x, int& y, int& z) const {
-        x = ix;
-        y = iy;
-        z = iz;
-        if (axis == 0)
-            x = e;
-        else if (axis == 1)
-            y = e;
-        else
-            z = e;
-    }
+    __device__ __forceinline__ uint32_t off(int m) const { return off0 + (uint32_t)m * dstep; }
+    __device__ __forceinline__ int64_t j(int m) const { return jbase + (int64_t)((uint32_t)m * (uint32_t)FFTShape<N>::T * jstride); }
 };
 
+// Lattice indices of in-instance point j.
+__device__ __forceinline__ void unflatten(const GroupDev& g, int64_t j, int& x, int& y, int& z) {
+    x = (int)(j & (g.n[0] - 1));
+    y = (int)((j >> g.log2n[0]) & (g.n[1] - 1));
+    z = (int)(j >> (g.log2n[0] + g.log2n[1]));
+}
+
 template <int N, int MODE, bool CONTIG, int LINES>
-__global__ void __launch_bounds__(FFTShape<N>::T* LINES)
-    k_axis(GroupDev g, int axis, int adj, float2* __restrict__ psi, float2* __restrict__ A,
-           float2* __restrict__ B, int64_t step_off, const int64_t* __restrict__ step_base) {
+__global__ void __launch_bounds__(FFTShape<N>::T* LINES) k_axis(GroupDev g, int axis, PassArgs args) {
     using F = FFTShape<N>;
     constexpr int R = F::R, T = F::T;
-    constexpr int NF = (MODE == PASS_D1) ? 1 : 2;
+    constexpr int NF = (MODE == PASS_D1 || MODE == PASS_U) ? 1 : 2;
     using L = LdsLayout<N, LINES, CONTIG>;
     __shared__ c32 lds[NF * L::SIZE];
     const int t = CONTIG ? (int)(threadIdx.x % T) : (int)(threadIdx.x / LINES);
     const int l = CONTIG ? (int)(threadIdx.x / T) : (int)(threadIdx.x % LINES);
-    const Tile<N, CONTIG, LINES> tile(g, axis, l);
+    const Tile<N, CONTIG, LINES> tile(g, axis, l, t);
     const float2* __restrict__ E = g.E[axis];
     const float2* __restrict__ tw = g.tw[axis];
-    float2* ps = psi + g.offset;
-    float2* pa = A + g.offset;
-    float2* pb = B + g.offset;
-    constexpr bool NEEDS_RHS = (MODE == PASS_FIRST || MODE == PASS_LAST1 || MODE == PASS_LAST2);
-    const int64_t step = NEEDS_RHS ? read_step(step_off, step_base) : 0;
+    const int64_t o = g.offset + tile.base;
+    float2* __restrict__ ps = args.psi ? args.psi + o : nullptr;
+    float2* __restrict__ pa = args.A ? args.A + o : nullptr;
+    float2* __restrict__ pb = args.B ? args.B + o : nullptr;
+    const float2* __restrict__ x0 = args.aux0 ? args.aux0 + o : nullptr;
+    const float2* __restrict__ x1 = args.aux1 ? args.aux1 + o : nullptr;
+    double* __restrict__ vb = args.vbar ? args.vbar + o : nullptr;
+    constexpr bool NEEDS_STEP = (MODE == PASS_FIRST || MODE == PASS_LAST1 || MODE == PASS_LAST2 ||
+                                 MODE == PASS_U || MODE == PASS_AS);
+    const int64_t step = NEEDS_STEP ? read_step(args.step_off, args.step_base) : 0;
     const uint32_t iid = g.id_base + (uint32_t)tile.inst;
+    const float* __restrict__ Vg = g.Vgrid ? g.Vgrid + tile.inst * g.M : nullptr;
 
-    // pointwise inputs of the right-hand side at element e of this thread's line
-    auto rhs_inputs = [&](int e, float& V, c32& nz) {
+    // pointwise inputs of the right-hand side at element t + m T of this thread's line
+    auto potential_at = [&](int m) {
+        const int64_t j = tile.j(m);
         int x, y, z;
-        tile.coords(g, axis, e, x, y, z);
-        V = trap_V(g, x, y, z);
-        const int64_t j = (int64_t)x + ((int64_t)y << g.log2n[0]) + ((int64_t)z << (g.log2n[0] + g.log2n[1]));
-        if (g.Vgrid) V += g.Vgrid[tile.inst * g.M + j];
-        if (g.has_noise) {
-            const float2 zz = noise_z(g, j, iid, step);
-            nz = make_float2(g.noise_c * zz.x, g.noise_c * zz.y);
-        } else {
-            nz = make_float2(0.f, 0.f);
-        }
+        unflatten(g, j, x, y, z);
+        float V = trap_V(g, x, y, z);
+        if (Vg) V += Vg[j];
+        return V;
     };
+    auto noise_at = [&](int m) {
+        if (!g.has_noise) return make_float2(0.f, 0.f);
+        const float2 zz = noise_z(g, tile.j(m), iid, step);
+        return make_float2(g.noise_c * zz.x, g.noise_c * zz.y);
+    };
+    const c32 zero = make_float2(0.f, 0.f);
 
     c32 f[NF][R];
-    if constexpr (MODE == PASS_D1) {
+    if constexpr (MODE == PASS_D1 || MODE == PASS_FIRST) {
 #pragma unroll
-        for (int m = 0; m < R; m++)
-            f[0][m] = tile.active ? ps[tile.idx(l, t + m * T)] : make_float2(0.f, 0.f);
-    } else if constexpr (MODE == PASS_FIRST) {
+        for (int m = 0; m < R; m++) f[0][m] = tile.active ? ps[tile.off(m)] : zero;
+        if constexpr (MODE == PASS_FIRST) {
 #pragma unroll
-        for (int m = 0; m < R; m++)
-            f[0][m] = tile.active ? ps[tile.idx(l, t + m * T)] : make_float2(0.f, 0.f);
+            for (int m = 0; m < R; m++) f[1][m] = hG(g, f[0][m], potential_at(m), noise_at(m));
+        }
+    } else if constexpr (MODE == PASS_U) {
+        // u = a + k3 from (a, k1)
 #pragma unroll
         for (int m = 0; m < R; m++) {
-            float V;
-            c32 nz;
-            rhs_inputs(t + m * T, V, nz);
-            f[1][m] = hG(g, f[0][m], V, nz);
+            const c32 a = tile.active ? x0[tile.off(m)] : zero;
+            const c32 k1 = tile.active ? x1[tile.off(m)] : zero;
+            const float V = potential_at(m);
+            const c32 nz = noise_at(m);
+            const c32 k2 = hG(g, make_float2(fmaf(0.5f, k1.x, a.x), fmaf(0.5f, k1.y, a.y)), V, nz);
+            const c32 k3 = hG(g, make_float2(fmaf(0.5f, k2.x, a.x), fmaf(0.5f, k2.y, a.y)), V, nz);
+            f[0][m] = cadd(a, k3);
+        }
+    } else if constexpr (MODE == PASS_AW) {
+        // adjoint of psi' = D acc + k4/6, k4 = h G(w): (lam, wbar = h J(w)^T lam/6)
+#pragma unroll
+        for (int m = 0; m < R; m++) {
+            const c32 lam = tile.active ? ps[tile.off(m)] : zero;
+            const c32 w = tile.active ? x0[tile.off(m)] : zero;
+            const c32 k4b = cscale(lam, 1.0f / 6.0f);
+            f[0][m] = lam;
+            f[1][m] = hJT(g, w, potential_at(m), k4b);
+            if (vb && tile.active) vb[tile.off(m)] += (double)hImconj(g, k4b, w);
         }
     } else {
 #pragma unroll
         for (int m = 0; m < R; m++) {
-            const int64_t i = tile.idx(l, t + m * T);
-            f[0][m] = tile.active ? pa[i] : make_float2(0.f, 0.f);
-            f[1][m] = tile.active ? pb[i] : make_float2(0.f, 0.f);
+            f[0][m] = tile.active ? pa[tile.off(m)] : zero;
+            f[1][m] = tile.active ? pb[tile.off(m)] : zero;
         }
     }
 
-    propagate<N, L, NF>(f, t, l, lds, tw, E, adj != 0);
+    propagate<N, L, NF>(f, t, l, lds, tw, E, args.adj != 0);
 
     if (!tile.active) return;  // after the last barrier
-    if constexpr (MODE == PASS_D1) {
+    if constexpr (MODE == PASS_D1 || MODE == PASS_U) {
 #pragma unroll
-        for (int m = 0; m < R; m++) ps[tile.idx(l, t + m * T)] = f[0][m];
+        for (int m = 0; m < R; m++) ps[tile.off(m)] = f[0][m];
     } else if constexpr (MODE == PASS_LAST1) {
 #pragma unroll
         for (int m = 0; m < R; m++) {
-            float V;
-            c32 nz;
-            rhs_inputs(t + m * T, V, nz);
+            const float V = potential_at(m);
+            const c32 nz = noise_at(m);
             const c32 a = f[0][m], k1 = f[1][m];
             const c32 k2 = hG(g, make_float2(fmaf(0.5f, k1.x, a.x), fmaf(0.5f, k1.y, a.y)), V, nz);
             const c32 k3 = hG(g, make_float2(fmaf(0.5f, k2.x, a.x), fmaf(0.5f, k2.y, a.y)), V, nz);
             const float sx = k1.x * (1.0f / 6.0f) + (k2.x + k3.x) * (1.0f / 3.0f);
             const float sy = k1.y * (1.0f / 6.0f) + (k2.y + k3.y) * (1.0f / 3.0f);
-            const int64_t i = tile.idx(l, t + m * T);
-            pa[i] = cadd(a, k3);
-            pb[i] = make_float2(a.x + sx, a.y + sy);
+            pa[tile.off(m)] = cadd(a, k3);
+            pb[tile.off(m)] = make_float2(a.x + sx, a.y + sy);
         }
     } else if constexpr (MODE == PASS_LAST2) {
 #pragma unroll
         for (int m = 0; m < R; m++) {
-            float V;
-            c32 nz;
-            rhs_inputs(t + m * T, V, nz);
-            const c32 k4 = hG(g, f[0][m], V, nz);
-            ps[tile.idx(l, t + m * T)] =
-                make_float2(fmaf(k4.x, 1.0f / 6.0f, f[1][m].x), fmaf(k4.y, 1.0f / 6.0f, f[1][m].y));
+            const c32 k4 = hG(g, f[0][m], potential_at(m), noise_at(m));
+            ps[tile.off(m)] = make_float2(fmaf(k4.x, 1.0f / 6.0f, f[1][m].x), fmaf(k4.y, 1.0f / 6.0f, f[1][m].y));
         }
-    } else {  // FIRST, D2
+    } else if constexpr (MODE == PASS_AS) {
+        // transposes of the stage combinations: (accbar, ubar) -> (abar, k1bar)
 #pragma unroll
         for (int m = 0; m < R; m++) {
-            const int64_t i = tile.idx(l, t + m * T);
-            pa[i] = f[0][m];
-            pb[i] = f[1][m];
+            const float V = potential_at(m);
+            const c32 nz = noise_at(m);
+            const c32 a = x0[tile.off(m)], k1 = x1[tile.off(m)];
+            const c32 p2 = make_float2(fmaf(0.5f, k1.x, a.x), fmaf(0.5f, k1.y, a.y));
+            const c32 k2 = hG(g, p2, V, nz);
+            const c32 p3 = make_float2(fmaf(0.5f, k2.x, a.x), fmaf(0.5f, k2.y, a.y));
+            const c32 accb = f[0][m], ub = f[1][m];
+            const c32 k3b = make_float2(fmaf(accb.x, 1.0f / 3.0f, ub.x), fmaf(accb.y, 1.0f / 3.0f, ub.y));
+            const c32 p3b = hJT(g, p3, V, k3b);
+            const c32 k2b = make_float2(fmaf(accb.x, 1.0f / 3.0f, 0.5f * p3b.x), fmaf(accb.y, 1.0f / 3.0f, 0.5f * p3b.y));
+            const c32 p2b = hJT(g, p2, V, k2b);
+            const c32 k1b = make_float2(fmaf(accb.x, 1.0f / 6.0f, 0.5f * p2b.x), fmaf(accb.y, 1.0f / 6.0f, 0.5f * p2b.y));
+            const c32 ab = make_float2(accb.x + ub.x + p3b.x + p2b.x, accb.y + ub.y + p3b.y + p2b.y);
+            if (vb) vb[tile.off(m)] += (double)hImconj(g, k3b, p3) + (double)hImconj(g, k2b, p2);
+            pa[tile.off(m)] = ab;
+            pb[tile.off(m)] = k1b;
+        }
+    } else if constexpr (MODE == PASS_AF) {
+        // psibar = D^T abar + h J(psi_n)^T (D^T k1bar)
+#pragma unroll
+        for (int m = 0; m < R; m++) {
+            const c32 pn = x0[tile.off(m)];
+            const c32 g0b = f[1][m];
+            const c32 r = hJT(g, pn, potential_at(m), g0b);
+            if (vb) vb[tile.off(m)] += (double)hImconj(g, g0b, pn);
+            ps[tile.off(m)] = cadd(f[0][m], r);
+        }
+    } else {  // FIRST, D2, AW
+#pragma unroll
+        for (int m = 0; m < R; m++) {
+            pa[tile.off(m)] = f[0][m];
+            pb[tile.off(m)] = f[1][m];
         }
     }
+}
+
+// ---------------------------------------------------------------------------- 1D adjoint step
+
+// Adjoint of one step of LPB whole lines: forward stages recomputed from psi_n in
+// registers, then the two transposed D-pairs; lam (in/out) is the adjoint state and vbar
+// accumulates the potential gradient.
+template <int N, int LPB>
+__global__ void __launch_bounds__(FFTShape<N>::T* LPB)
+    k_line_adjoint(GroupDev g, const float2* __restrict__ psi_n, float2* __restrict__ lam, double* __restrict__ vbar,
+                   int64_t step) {
+    using F = FFTShape<N>;
+    using L = LdsLayout<N, LPB, true>;
+    constexpr int R = F::R, T = F::T;
+    __shared__ c32 lds[2 * L::SIZE];
+    const int t = threadIdx.x % T;
+    const int l = threadIdx.x / T;
+    const int64_t inst = (int64_t)blockIdx.x * LPB + l;
+    const bool active = inst < g.batch;
+    const int64_t base = g.offset + (active ? inst : 0) * N;
+    const float2* __restrict__ E = g.E[0];
+    const float2* __restrict__ tw = g.tw[0];
+    const uint32_t iid = g.id_base + (uint32_t)inst;
+    const c32 zero = make_float2(0.f, 0.f);
+    auto V_at = [&](int m) {
+        float v = trap_V(g, t + m * T, 0, 0);
+        if (g.Vgrid && active) v += g.Vgrid[inst * N + t + m * T];
+        return v;
+    };
+    auto nz_at = [&](int m) {
+        if (!g.has_noise) return zero;
+        const float2 z = noise_z(g, t + m * T, iid, step);
+        return make_float2(g.noise_c * z.x, g.noise_c * z.y);
+    };
+    // forward: (a, k1) = D (psi, hG(psi))
+    c32 f[2][R];
+#pragma unroll
+    for (int m = 0; m < R; m++) {
+        f[0][m] = active ? psi_n[base + t + m * T] : zero;
+        f[1][m] = hG(g, f[0][m], V_at(m), nz_at(m));
+    }
+    propagate<N, L, 2>(f, t, l, lds, tw, E, false);
+    // w = D(a + k3): keep (a, k1) in f, the transform of u in w[0]
+    c32 w[1][R];
+#pragma unroll
+    for (int m = 0; m < R; m++) {
+        const c32 a = f[0][m], k1 = f[1][m];
+        const float V = V_at(m);
+        const c32 nz = nz_at(m);
+        const c32 k2 = hG(g, make_float2(fmaf(0.5f, k1.x, a.x), fmaf(0.5f, k1.y, a.y)), V, nz);
+        const c32 k3 = hG(g, make_float2(fmaf(0.5f, k2.x, a.x), fmaf(0.5f, k2.y, a.y)), V, nz);
+        w[0][m] = cadd(a, k3);
+    }
+    propagate<N, L, 1>(w, t, l, lds, tw, E, false);
+    // adjoint: (lam, wbar) -> D^T -> (accbar, ubar)
+    c32 b[2][R];
+    float vacc[R];
+#pragma unroll
+    for (int m = 0; m < R; m++) {
+        const c32 lm = active ? lam[base + t + m * T] : zero;
+        const c32 k4b = cscale(lm, 1.0f / 6.0f);
+        b[0][m] = lm;
+        b[1][m] = hJT(g, w[0][m], V_at(m), k4b);
+        vacc[m] = hImconj(g, k4b, w[0][m]);
+    }
+    propagate<N, L, 2>(b, t, l, lds, tw, E, true);
+#pragma unroll
+    for (int m = 0; m < R; m++) {
+        const float V = V_at(m);
+        const c32 nz = nz_at(m);
+        const c32 a = f[0][m], k1 = f[1][m];
+        const c32 p2 = make_float2(fmaf(0.5f, k1.x, a.x), fmaf(0.5f, k1.y, a.y));
+        const c32 k2 = hG(g, p2, V, nz);
+        const c32 p3 = make_float2(fmaf(0.5f, k2.x, a.x), fmaf(0.5f, k2.y, a.y));
+        const c32 accb = b[0][m], ub = b[1][m];
+        const c32 k3b = make_float2(fmaf(accb.x, 1.0f / 3.0f, ub.x), fmaf(accb.y, 1.0f / 3.0f, ub.y));
+        const c32 p3b = hJT(g, p3, V, k3b);
+        const c32 k2b = make_float2(fmaf(accb.x, 1.0f / 3.0f, 0.5f * p3b.x), fmaf(accb.y, 1.0f / 3.0f, 0.5f * p3b.y));
+        const c32 p2b = hJT(g, p2, V, k2b);
+        const c32 k1b = make_float2(fmaf(accb.x, 1.0f / 6.0f, 0.5f * p2b.x), fmaf(accb.y, 1.0f / 6.0f, 0.5f * p2b.y));
+        vacc[m] += hImconj(g, k3b, p3) + hImconj(g, k2b, p2);
+        b[0][m] = make_float2(accb.x + ub.x + p3b.x + p2b.x, accb.y + ub.y + p3b.y + p2b.y);
+        b[1][m] = k1b;
+    }
+    propagate<N, L, 2>(b, t, l, lds, tw, E, true);
+    if (!active) return;
+#pragma unroll
+    for (int m = 0; m < R; m++) {
+        const c32 pn = psi_n[base + t + m * T];
+        const c32 r = hJT(g, pn, V_at(m), b[1][m]);
+        vacc[m] += hImconj(g, b[1][m], pn);
+        lam[base + t + m * T] = cadd(b[0][m], r);
+        if (vbar) vbar[base + t + m * T] += (double)vacc[m];
+    }
+}
+
+__global__ void k_vbar_to_float(const double* __restrict__ v, float* __restrict__ out, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = (float)v[i];
 }
 
 // ---------------------------------------------------------------------------- FP64 reductions
@@ -366,18 +498,18 @@ __global__ void __launch_bounds__(FFTShape<N>::T* LINES)
     __shared__ double red[FFTShape<N>::T * LINES][4];
     const int t = CONTIG ? (int)(threadIdx.x % T) : (int)(threadIdx.x / LINES);
     const int l = CONTIG ? (int)(threadIdx.x / T) : (int)(threadIdx.x % LINES);
-    const Tile<N, CONTIG, LINES> tile(g, axis, l);
-    const float2* ps = psi + g.offset;
+    const Tile<N, CONTIG, LINES> tile(g, axis, l, t);
+    const float2* ps = psi + g.offset + tile.base;
     c32 f[1][R];
     double s1 = 0.0, s2 = 0.0, s3 = 0.0;
 #pragma unroll
     for (int m = 0; m < R; m++) {
-        f[0][m] = tile.active ? ps[tile.idx(l, t + m * T)] : make_float2(0.f, 0.f);
+        f[0][m] = tile.active ? ps[tile.off(m)] : make_float2(0.f, 0.f);
         if (axis == 0) {
+            const int64_t j = tile.j(m);
             int x, y, z;
-            tile.coords(g, axis, t + m * T, x, y, z);
+            unflatten(g, j, x, y, z);
             double V = (double)trap_V(g, x, y, z);
-            const int64_t j = (int64_t)x + ((int64_t)y << g.log2n[0]) + ((int64_t)z << (g.log2n[0] + g.log2n[1]));
             if (g.Vgrid && tile.active) V += (double)g.Vgrid[tile.inst * g.M + j];
             const double m2 = (double)f[0][m].x * f[0][m].x + (double)f[0][m].y * f[0][m].y;
             s1 += m2;
@@ -396,7 +528,7 @@ __global__ void __launch_bounds__(FFTShape<N>::T* LINES)
         s0 += k * k * a2;
     }
     // fixed-order reduction over the T threads of each line
-    const int slot = CONTIG ? (l * T + t) : (l * T + t);
+    const int slot = l * T + t;
     red[slot][0] = s0;
     red[slot][1] = s1;
     red[slot][2] = s2;
@@ -410,14 +542,19 @@ __global__ void __launch_bounds__(FFTShape<N>::T* LINES)
             a2 += red[l * T + i][2];
             a3 += red[l * T + i][3];
         }
+        // line number within the instance: (in-instance index of element 0) with the axis
+        // coordinate removed
+        const int64_t j0 = tile.jbase - (int64_t)t * tile.jstride;
         int64_t line;
-        if constexpr (CONTIG) {
-            line = (int64_t)blockIdx.x * LINES + l;
+        if (axis == 0) {
+            line = j0 >> g.log2n[0];
         } else {
-            // (inst, outer, x) -> inst * (M / n_axis) + outer * n0 + x
-            const int outer = (axis == 1) ? tile.iz : tile.iy;
-            line = tile.inst * (g.M >> g.log2n[axis]) + (int64_t)outer * g.n[0] + tile.ix;
+            int x, y, z;
+            unflatten(g, j0, x, y, z);
+            const int outer = (axis == 1) ? z : y;
+            line = (int64_t)outer * g.n[0] + x;
         }
+        line += tile.inst * (g.M >> g.log2n[axis]);
         double* o = part + line * 4;
         o[0] = a0 * (double)g.inv_n[axis];
         o[1] = a1;
@@ -535,78 +672,114 @@ static int contig_lines(int N) {
 int axis_lines(int N, int axis, int n0) { return axis == 0 ? contig_lines(N) : strided_lines(N, n0); }
 
 template <int N, int MODE, bool CONTIG, int LINES>
-static hipError_t go_axis(const GroupDev& g, int axis, int adj, float2* psi, float2* A, float2* B, int64_t step_off,
-                          const int64_t* step_base, hipStream_t s) {
+static hipError_t go_axis(const GroupDev& g, int axis, const PassArgs& a, hipStream_t s) {
     int64_t blocks;
     if (CONTIG)
         blocks = (g.batch * (g.M >> g.log2n[0]) + LINES - 1) / LINES;
     else
         blocks = g.batch * (g.M >> g.log2n[axis]) / LINES;
     hipLaunchKernelGGL((k_axis<N, MODE, CONTIG, LINES>), dim3((unsigned)blocks), dim3(FFTShape<N>::T * LINES), 0, s,
-                       g, axis, adj, psi, A, B, step_off, step_base);
+                       g, axis, a);
     return hipGetLastError();
 }
 
+// passes that run only on axis 0 / only on the last (strided) axis
+constexpr bool contig_only(int mode) { return mode == PASS_FIRST || mode == PASS_U || mode == PASS_AW; }
+constexpr bool strided_only(int mode) {
+    return mode == PASS_LAST1 || mode == PASS_LAST2 || mode == PASS_AS || mode == PASS_AF;
+}
+
 template <int N, int MODE>
-static hipError_t go_axis_n(const GroupDev& g, int axis, int adj, float2* psi, float2* A, float2* B, int64_t step_off,
-                            const int64_t* step_base, hipStream_t s) {
+static hipError_t go_axis_n(const GroupDev& g, int axis, const PassArgs& a, hipStream_t s) {
     constexpr int T = FFTShape<N>::T;
     constexpr int CL = (256 / T) < 1 ? 1 : 256 / T;
     if (axis == 0) {
-        if constexpr (MODE == PASS_LAST1 || MODE == PASS_LAST2) {
+        if constexpr (strided_only(MODE)) {
             return hipErrorInvalidValue;
         } else {
-            return go_axis<N, MODE, true, CL>(g, axis, adj, psi, A, B, step_off, step_base, s);
+            return go_axis<N, MODE, true, CL>(g, axis, a, s);
         }
     }
-    if constexpr (MODE == PASS_FIRST) {
+    if constexpr (contig_only(MODE)) {
         return hipErrorInvalidValue;
     } else {
         const int w = strided_lines(N, g.n[0]);
         switch (w) {
             case 16:
-                if constexpr (T * 16 <= 1024 && fits_lds(N, 16, 2))
-                    return go_axis<N, MODE, false, 16>(g, axis, adj, psi, A, B, step_off, step_base, s);
+                if constexpr (T * 16 <= 1024 && fits_lds(N, 16, 2)) return go_axis<N, MODE, false, 16>(g, axis, a, s);
                 break;
             case 8:
-                if constexpr (T * 8 <= 1024 && fits_lds(N, 8, 2))
-                    return go_axis<N, MODE, false, 8>(g, axis, adj, psi, A, B, step_off, step_base, s);
+                if constexpr (T * 8 <= 1024 && fits_lds(N, 8, 2)) return go_axis<N, MODE, false, 8>(g, axis, a, s);
                 break;
-            case 4:
-                return go_axis<N, MODE, false, 4>(g, axis, adj, psi, A, B, step_off, step_base, s);
-            default:
-                break;
+            case 4: return go_axis<N, MODE, false, 4>(g, axis, a, s);
+            default: break;
         }
         return hipErrorInvalidValue;
     }
 }
 
 template <int MODE>
-static hipError_t go_axis_mode(const GroupDev& g, int axis, int adj, float2* psi, float2* A, float2* B,
-                               int64_t step_off, const int64_t* step_base, hipStream_t s) {
+static hipError_t go_axis_mode(const GroupDev& g, int axis, const PassArgs& a, hipStream_t s) {
     switch (g.n[axis]) {
-        case 8: return go_axis_n<8, MODE>(g, axis, adj, psi, A, B, step_off, step_base, s);
-        case 16: return go_axis_n<16, MODE>(g, axis, adj, psi, A, B, step_off, step_base, s);
-        case 32: return go_axis_n<32, MODE>(g, axis, adj, psi, A, B, step_off, step_base, s);
-        case 64: return go_axis_n<64, MODE>(g, axis, adj, psi, A, B, step_off, step_base, s);
-        case 128: return go_axis_n<128, MODE>(g, axis, adj, psi, A, B, step_off, step_base, s);
-        case 256: return go_axis_n<256, MODE>(g, axis, adj, psi, A, B, step_off, step_base, s);
-        case 512: return go_axis_n<512, MODE>(g, axis, adj, psi, A, B, step_off, step_base, s);
-        case 1024: return go_axis_n<1024, MODE>(g, axis, adj, psi, A, B, step_off, step_base, s);
+        case 8: return go_axis_n<8, MODE>(g, axis, a, s);
+        case 16: return go_axis_n<16, MODE>(g, axis, a, s);
+        case 32: return go_axis_n<32, MODE>(g, axis, a, s);
+        case 64: return go_axis_n<64, MODE>(g, axis, a, s);
+        case 128: return go_axis_n<128, MODE>(g, axis, a, s);
+        case 256: return go_axis_n<256, MODE>(g, axis, a, s);
+        case 512: return go_axis_n<512, MODE>(g, axis, a, s);
+        case 1024: return go_axis_n<1024, MODE>(g, axis, a, s);
         default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_axis(const GroupDev& g, int axis, int mode, int adj, float2* psi, float2* A, float2* B,
-                       int64_t step_off, const int64_t* step_base, hipStream_t s) {
+hipError_t launch_axis(const GroupDev& g, int axis, int mode, const PassArgs& a, hipStream_t s) {
     switch (mode) {
-        case PASS_D1: return go_axis_mode<PASS_D1>(g, axis, adj, psi, A, B, step_off, step_base, s);
-        case PASS_D2: return go_axis_mode<PASS_D2>(g, axis, adj, psi, A, B, step_off, step_base, s);
-        case PASS_FIRST: return go_axis_mode<PASS_FIRST>(g, axis, adj, psi, A, B, step_off, step_base, s);
-        case PASS_LAST1: return go_axis_mode<PASS_LAST1>(g, axis, adj, psi, A, B, step_off, step_base, s);
-        case PASS_LAST2: return go_axis_mode<PASS_LAST2>(g, axis, adj, psi, A, B, step_off, step_base, s);
+        case PASS_D1: return go_axis_mode<PASS_D1>(g, axis, a, s);
+        case PASS_D2: return go_axis_mode<PASS_D2>(g, axis, a, s);
+        case PASS_FIRST: return go_axis_mode<PASS_FIRST>(g, axis, a, s);
+        case PASS_LAST1: return go_axis_mode<PASS_LAST1>(g, axis, a, s);
+        case PASS_LAST2: return go_axis_mode<PASS_LAST2>(g, axis, a, s);
+        case PASS_U: return go_axis_mode<PASS_U>(g, axis, a, s);
+        case PASS_AW: return go_axis_mode<PASS_AW>(g, axis, a, s);
+        case PASS_AS: return go_axis_mode<PASS_AS>(g, axis, a, s);
+        case PASS_AF: return go_axis_mode<PASS_AF>(g, axis, a, s);
         default: return hipErrorInvalidValue;
     }
+}
+
+template <int N>
+static hipError_t go_line_adj(const GroupDev& g, const float2* psi_n, float2* lam, double* vbar, int64_t step,
+                              hipStream_t s) {
+    constexpr int T = FFTShape<N>::T;
+    constexpr int LPB = T >= 64 ? 1 : 64 / T;
+    const int64_t blocks = (g.batch + LPB - 1) / LPB;
+    hipLaunchKernelGGL((k_line_adjoint<N, LPB>), dim3((unsigned)blocks), dim3(T * LPB), 0, s, g, psi_n, lam, vbar,
+                       step);
+    return hipGetLastError();
+}
+
+hipError_t launch_line_adjoint(const GroupDev& g, const float2* psi_n, float2* lam, double* vbar, int64_t step,
+                               hipStream_t s) {
+    switch (g.n[0]) {
+        case 8: return go_line_adj<8>(g, psi_n, lam, vbar, step, s);
+        case 16: return go_line_adj<16>(g, psi_n, lam, vbar, step, s);
+        case 32: return go_line_adj<32>(g, psi_n, lam, vbar, step, s);
+        case 64: return go_line_adj<64>(g, psi_n, lam, vbar, step, s);
+        case 128: return go_line_adj<128>(g, psi_n, lam, vbar, step, s);
+        case 256: return go_line_adj<256>(g, psi_n, lam, vbar, step, s);
+        case 512: return go_line_adj<512>(g, psi_n, lam, vbar, step, s);
+        case 1024: return go_line_adj<1024>(g, psi_n, lam, vbar, step, s);
+        case 2048: return go_line_adj<2048>(g, psi_n, lam, vbar, step, s);
+        case 4096: return go_line_adj<4096>(g, psi_n, lam, vbar, step, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_vbar_to_float(const double* vbar, float* out, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_vbar_to_float, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, vbar, out, n);
+    return hipGetLastError();
 }
 
 template <int N>

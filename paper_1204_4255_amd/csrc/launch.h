@@ -7,8 +7,33 @@ namespace rk4ip {
 
 struct GroupDev;
 
-// Kinds of axis pass (see kernels.hip for the data flow of each).
-enum PassMode { PASS_D1 = 0, PASS_D2 = 1, PASS_FIRST = 2, PASS_LAST1 = 3, PASS_LAST2 = 4 };
+// Kinds of axis pass (see kernels.hip for the data flow of each). The first five make
+// the forward step; U, AW, AS and AF are the extra passes of the adjoint step.
+enum PassMode {
+    PASS_D1 = 0,
+    PASS_D2 = 1,
+    PASS_FIRST = 2,
+    PASS_LAST1 = 3,
+    PASS_LAST2 = 4,
+    PASS_U = 5,
+    PASS_AW = 6,
+    PASS_AS = 7,
+    PASS_AF = 8
+};
+
+// Pointers of one pass; every field pointer addresses the concatenated field of all
+// groups (the kernel adds the group offset).
+struct PassArgs {
+    float2* psi;              // single field: D1 in/out, FIRST in, LAST2/AF/U out, AW in (lambda)
+    float2* A;                // field pair in/out
+    float2* B;
+    const float2* aux0;       // extra pointwise inputs: U (a, k1), AW (w), AS (a, k1), AF (psi_n)
+    const float2* aux1;
+    double* vbar;             // FP64 potential-gradient accumulator (concatenated), AW/AS/AF
+    int adj;                  // apply the transpose of D
+    int64_t step_off;
+    const int64_t* step_base; // step = step_off (+ *step_base when not null)
+};
 
 // Constants of the final diagnostic sum (FP64).
 struct DiagConst {
@@ -19,8 +44,10 @@ struct DiagConst {
 
 int axis_lines(int N, int axis, int n0);
 
-hipError_t launch_axis(const GroupDev& g, int axis, int mode, int adj, float2* psi, float2* A, float2* B,
-                       int64_t step_off, const int64_t* step_base, hipStream_t s);
+hipError_t launch_axis(const GroupDev& g, int axis, int mode, const PassArgs& a, hipStream_t s);
+hipError_t launch_line_adjoint(const GroupDev& g, const float2* psi_n, float2* lam, double* vbar, int64_t step,
+                               hipStream_t s);
+hipError_t launch_vbar_to_float(const double* vbar, float* out, int64_t n, hipStream_t s);
 hipError_t launch_line_step(const GroupDev& g, float2* psi, int nsteps, int64_t step_off, const int64_t* step_base,
                             hipStream_t s);
 hipError_t launch_diag_axis(const GroupDev& g, int axis, const float2* psi, double kscale, double* part,

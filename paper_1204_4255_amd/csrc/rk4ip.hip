@@ -5,6 +5,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <new>
 #include <string>
@@ -135,7 +136,7 @@ struct rk4ip_plan_s {
     int64_t* counter = nullptr;
     int* flag = nullptr;
     std::string err;
-    std::vector<std::string> sched_names;
+    std::vector<std::vector<std::string>> sched_names;  // [group][pass]
     // cached graph of `graph_steps` steps on `graph_psi`
     hipGraphExec_t graph = nullptr;
     hipGraph_t graph_src = nullptr;
@@ -143,6 +144,16 @@ struct rk4ip_plan_s {
     int graph_steps = 0;
     hipStream_t capture_stream = nullptr;  // private stream the graph is recorded on
     int sticky = RK4IP_OK;
+    // per-pass event timing
+    bool profiling = false;
+    struct Timed {
+        int group, pass;
+        hipEvent_t a, b;
+    };
+    std::vector<Timed> timed;
+    std::vector<hipEvent_t> spare;
+    std::vector<std::vector<double>> prof_ms;     // [group][pass] summed ms
+    std::vector<std::vector<int64_t>> prof_n;     // [group][pass] launches
 };
 
 namespace {
@@ -212,27 +223,87 @@ int pass_list(int ndim, int (*out)[2]) {
     return 6;
 }
 
+hipEvent_t take_event(rk4ip_plan_t plan) {
+    if (!plan->spare.empty()) {
+        hipEvent_t e = plan->spare.back();
+        plan->spare.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Run `launch` bracketed by an event pair when profiling (never inside a capture).
+template <class F>
+int timed_launch(rk4ip_plan_t plan, hipStream_t stream, int group, int pass, bool capturing, F&& launch) {
+    if (!plan->profiling || capturing) {
+        HIPCHK(plan, launch());
+        return RK4IP_OK;
+    }
+    hipEvent_t a = take_event(plan), b = take_event(plan);
+    if (!a || !b) return fail(plan, RK4IP_ERR_HIP, "hipEventCreate failed");
+    HIPCHK(plan, hipEventRecord(a, stream));
+    HIPCHK(plan, launch());
+    HIPCHK(plan, hipEventRecord(b, stream));
+    plan->timed.push_back({group, pass, a, b});
+    return RK4IP_OK;
+}
+
+// Fold recorded event pairs into the per-pass sums (waits for them).
+int collect_profile(rk4ip_plan_t plan) {
+    for (auto& t : plan->timed) {
+        HIPCHK(plan, hipEventSynchronize(t.b));
+        float ms = 0.f;
+        HIPCHK(plan, hipEventElapsedTime(&ms, t.a, t.b));
+        plan->prof_ms[t.group][t.pass] += ms;
+        plan->prof_n[t.group][t.pass] += 1;
+        plan->spare.push_back(t.a);
+        plan->spare.push_back(t.b);
+    }
+    plan->timed.clear();
+    return RK4IP_OK;
+}
+
 // Enqueue `nsteps` steps of every group. step_base != null: step = *step_base + step_off.
 int enqueue_steps(rk4ip_plan_t plan, hipStream_t stream, float2* psi, int64_t step_off, int64_t nsteps,
                   const int64_t* step_base, bool allow_fuse) {
-    for (auto& g : plan->groups) {
-        if (g.p.ndim == 1) {
-            if (allow_fuse && (plan->flags & RK4IP_FLAG_FUSE_1D)) {
-                HIPCHK(plan, rk4ip::launch_line_step(g.d, psi, (int)nsteps, step_off, step_base, stream));
-            } else {
-                for (int64_t s = 0; s < nsteps; s++)
-                    HIPCHK(plan, rk4ip::launch_line_step(g.d, psi, 1, step_off + s, step_base, stream));
+    const bool capturing = step_base != nullptr;
+    int rc;
+    for (size_t gi = 0; gi < plan->groups.size(); gi++) {
+        auto& g = plan->groups[gi];
+        if (g.p.ndim != 1) continue;
+        if (allow_fuse && (plan->flags & RK4IP_FLAG_FUSE_1D)) {
+            rc = timed_launch(plan, stream, (int)gi, 0, capturing, [&] {
+                return rk4ip::launch_line_step(g.d, psi, (int)nsteps, step_off, step_base, stream);
+            });
+            if (rc) return rc;
+        } else {
+            for (int64_t s = 0; s < nsteps; s++) {
+                rc = timed_launch(plan, stream, (int)gi, 0, capturing, [&] {
+                    return rk4ip::launch_line_step(g.d, psi, 1, step_off + s, step_base, stream);
+                });
+                if (rc) return rc;
             }
         }
     }
     for (int64_t s = 0; s < nsteps; s++) {
-        for (auto& g : plan->groups) {
+        for (size_t gi = 0; gi < plan->groups.size(); gi++) {
+            auto& g = plan->groups[gi];
             if (g.p.ndim == 1) continue;
             int seq[6][2];
             const int np = pass_list(g.p.ndim, seq);
-            for (int i = 0; i < np; i++)
-                HIPCHK(plan, rk4ip::launch_axis(g.d, seq[i][0], seq[i][1], 0, psi, plan->A, plan->B, step_off + s,
-                                                step_base, stream));
+            for (int i = 0; i < np; i++) {
+                rk4ip::PassArgs pa{};
+                pa.psi = psi;
+                pa.A = plan->A;
+                pa.B = plan->B;
+                pa.step_off = step_off + s;
+                pa.step_base = step_base;
+                rc = timed_launch(plan, stream, (int)gi, i, capturing,
+                                  [&] { return rk4ip::launch_axis(g.d, seq[i][0], seq[i][1], pa, stream); });
+                if (rc) return rc;
+            }
         }
     }
     return RK4IP_OK;
@@ -432,13 +503,24 @@ int rk4ip_plan(const rk4ip_problem* probs, int nprob, void* workspace, size_t ws
         g.first_inst = inst;
         offset += p.batch * g.M;
         inst += p.batch;
-        char name[96];
-        for (int a = 0; a < p.ndim; a++) {
-            std::snprintf(name, sizeof(name), "g%d.axis%d:n%lld:%s:lines%d", i, a, (long long)p.n[a],
-                          p.ndim == 1 ? "line-step" : (a == 0 ? "contig" : "strided"),
-                          p.ndim == 1 ? 1 : rk4ip::axis_lines((int)p.n[a], a, (int)p.n[0]));
-            plan->sched_names.push_back(name);
+        char name[128];
+        std::vector<std::string> names;
+        if (p.ndim == 1) {
+            std::snprintf(name, sizeof(name), "line_step:n%lld", (long long)p.n[0]);
+            names.push_back(name);
+        } else {
+            static const char* kinds[] = {"D1", "D2", "FIRST", "LAST1", "LAST2"};
+            int seq[6][2];
+            const int np = pass_list(p.ndim, seq);
+            for (int k = 0; k < np; k++) {
+                const int a = seq[k][0];
+                std::snprintf(name, sizeof(name), "%s:axis%d:n%lld:%s:lines%d", kinds[seq[k][1]], a,
+                              (long long)p.n[a], a == 0 ? "contig" : "strided",
+                              rk4ip::axis_lines((int)p.n[a], a, (int)p.n[0]));
+                names.push_back(name);
+            }
         }
+        plan->sched_names.push_back(names);
     }
     plan->ninst = inst;
     plan->groups = std::move(gh);
@@ -517,16 +599,104 @@ int rk4ip_moments(rk4ip_plan_t plan, int group, const void* psi, double* mean, d
 }
 
 size_t rk4ip_adjoint_workspace_bytes(rk4ip_plan_t plan, int64_t ckpt_every) {
-    (void)plan;
-    (void)ckpt_every;
-    return 0;
+    if (!plan || ckpt_every < 1) return 0;
+    // segment states, the recompute buffer, three work fields (w, and the adjoint pair)
+    // and the FP64 potential-gradient accumulator
+    const size_t field = align_up(sizeof(float2) * (size_t)plan->points);
+    return (size_t)(ckpt_every + 4) * field + align_up(sizeof(double) * (size_t)plan->points);
 }
 
-int rk4ip_adjoint(rk4ip_plan_t plan, const void* ckpt, int64_t step0, int64_t nsteps, int64_t ckpt_every,
+int rk4ip_adjoint(rk4ip_plan_t plan, const void* ckpt_v, int64_t step0, int64_t nsteps, int64_t ckpt_every,
                   const void* lambda_T, void* grad_psi0, float* grad_V, void* adj_ws, size_t adj_ws_bytes) {
-    (void)ckpt; (void)step0; (void)nsteps; (void)ckpt_every; (void)lambda_T; (void)grad_psi0; (void)grad_V;
-    (void)adj_ws; (void)adj_ws_bytes;
-    return fail(plan, RK4IP_ERR_INVALID_ARG, "adjoint not built yet");
+    if (!plan || !ckpt_v || !lambda_T || !grad_psi0 || !adj_ws || step0 < 0 || nsteps < 0 || ckpt_every < 1)
+        return RK4IP_ERR_INVALID_ARG;
+    if ((reinterpret_cast<uintptr_t>(adj_ws) % kAlign) != 0) return RK4IP_ERR_INVALID_ARG;
+    if (adj_ws_bytes < rk4ip_adjoint_workspace_bytes(plan, ckpt_every)) return RK4IP_ERR_WORKSPACE_TOO_SMALL;
+    hipStream_t st = plan->stream;
+    const size_t field = align_up(sizeof(float2) * (size_t)plan->points);
+    char* w = static_cast<char*>(adj_ws);
+    float2* store = reinterpret_cast<float2*>(w);
+    float2* cur = reinterpret_cast<float2*>(w + (size_t)ckpt_every * field);
+    float2* W = reinterpret_cast<float2*>(w + (size_t)(ckpt_every + 1) * field);
+    float2* X = reinterpret_cast<float2*>(w + (size_t)(ckpt_every + 2) * field);
+    float2* Y = reinterpret_cast<float2*>(w + (size_t)(ckpt_every + 3) * field);
+    double* vbar = reinterpret_cast<double*>(w + (size_t)(ckpt_every + 4) * field);
+    const float2* ckpt = static_cast<const float2*>(ckpt_v);
+    float2* lam = static_cast<float2*>(grad_psi0);
+    const size_t fbytes = sizeof(float2) * (size_t)plan->points;
+    if (lam != lambda_T) HIPCHK(plan, hipMemcpyAsync(lam, lambda_T, fbytes, hipMemcpyDeviceToDevice, st));
+    HIPCHK(plan, hipMemsetAsync(vbar, 0, sizeof(double) * (size_t)plan->points, st));
+
+    const int64_t nseg = (nsteps + ckpt_every - 1) / ckpt_every;
+    for (int64_t seg = nseg - 1; seg >= 0; seg--) {
+        const int64_t s0 = seg * ckpt_every;
+        const int64_t len = std::min(ckpt_every, nsteps - s0);
+        // recompute and keep the states of this segment
+        HIPCHK(plan, hipMemcpyAsync(cur, ckpt + seg * plan->points, fbytes, hipMemcpyDeviceToDevice, st));
+        for (int64_t i = 0; i < len; i++) {
+            HIPCHK(plan, hipMemcpyAsync(store + i * (int64_t)(field / sizeof(float2)), cur, fbytes,
+                                        hipMemcpyDeviceToDevice, st));
+            if (i + 1 < len) {
+                int rc = enqueue_steps(plan, st, cur, step0 + s0 + i, 1, nullptr, false);
+                if (rc) return rc;
+            }
+        }
+        // walk the segment backwards
+        for (int64_t i = len - 1; i >= 0; i--) {
+            const float2* pn = store + i * (int64_t)(field / sizeof(float2));
+            const int64_t step = step0 + s0 + i;
+            for (auto& g : plan->groups) {
+                if (g.p.ndim == 1) {
+                    HIPCHK(plan, rk4ip::launch_line_adjoint(g.d, pn, lam, vbar, step, st));
+                    continue;
+                }
+                const int last = g.p.ndim - 1;
+                rk4ip::PassArgs pa{};
+                pa.step_off = step;
+                // forward: (A, B) = D (psi_n, hG(psi_n)) = (a, k1)
+                pa.psi = const_cast<float2*>(pn);
+                pa.A = plan->A;
+                pa.B = plan->B;
+                HIPCHK(plan, rk4ip::launch_axis(g.d, 0, rk4ip::PASS_FIRST, pa, st));
+                for (int a = 1; a <= last; a++) HIPCHK(plan, rk4ip::launch_axis(g.d, a, rk4ip::PASS_D2, pa, st));
+                // forward: W = D (a + k3)
+                rk4ip::PassArgs pu{};
+                pu.step_off = step;
+                pu.psi = W;
+                pu.aux0 = plan->A;
+                pu.aux1 = plan->B;
+                HIPCHK(plan, rk4ip::launch_axis(g.d, 0, rk4ip::PASS_U, pu, st));
+                for (int a = 1; a <= last; a++) HIPCHK(plan, rk4ip::launch_axis(g.d, a, rk4ip::PASS_D1, pu, st));
+                // adjoint: (X, Y) = D^T (lam, h J(w)^T lam/6), then the stage transposes
+                rk4ip::PassArgs pw{};
+                pw.step_off = step;
+                pw.adj = 1;
+                pw.psi = lam;
+                pw.aux0 = W;
+                pw.A = X;
+                pw.B = Y;
+                pw.vbar = vbar;
+                HIPCHK(plan, rk4ip::launch_axis(g.d, 0, rk4ip::PASS_AW, pw, st));
+                for (int a = 1; a < last; a++) HIPCHK(plan, rk4ip::launch_axis(g.d, a, rk4ip::PASS_D2, pw, st));
+                pw.aux0 = plan->A;
+                pw.aux1 = plan->B;
+                HIPCHK(plan, rk4ip::launch_axis(g.d, last, rk4ip::PASS_AS, pw, st));
+                // adjoint: lam = D^T abar + h J(psi_n)^T D^T k1bar
+                rk4ip::PassArgs pf{};
+                pf.step_off = step;
+                pf.adj = 1;
+                pf.A = X;
+                pf.B = Y;
+                pf.psi = lam;
+                pf.aux0 = pn;
+                pf.vbar = vbar;
+                for (int a = 0; a < last; a++) HIPCHK(plan, rk4ip::launch_axis(g.d, a, rk4ip::PASS_D2, pf, st));
+                HIPCHK(plan, rk4ip::launch_axis(g.d, last, rk4ip::PASS_AF, pf, st));
+            }
+        }
+    }
+    if (grad_V) HIPCHK(plan, rk4ip::launch_vbar_to_float(vbar, grad_V, plan->points, st));
+    return RK4IP_OK;
 }
 
 int rk4ip_status(rk4ip_plan_t plan) {
@@ -551,18 +721,51 @@ int rk4ip_destroy(rk4ip_plan_t plan) {
     (void)hipStreamSynchronize(plan->stream);
     drop_graph(plan);
     if (plan->capture_stream) (void)hipStreamDestroy(plan->capture_stream);
+    for (auto& t : plan->timed) {
+        (void)hipEventDestroy(t.a);
+        (void)hipEventDestroy(t.b);
+    }
+    for (auto e : plan->spare) (void)hipEventDestroy(e);
     delete plan;
     return RK4IP_OK;
 }
 
 const char* rk4ip_last_error(rk4ip_plan_t plan) { return plan ? plan->err.c_str() : ""; }
 
+int rk4ip_num_passes(rk4ip_plan_t plan, int group) {
+    if (!plan || group < 0 || group >= (int)plan->groups.size()) return RK4IP_ERR_INVALID_ARG;
+    return (int)plan->sched_names[group].size();
+}
+
 const char* rk4ip_schedule(rk4ip_plan_t plan, int group, int pass) {
     if (!plan || group < 0 || group >= (int)plan->groups.size()) return nullptr;
-    int idx = 0;
-    for (int i = 0; i < group; i++) idx += plan->groups[i].p.ndim;
-    if (pass < 0 || pass >= plan->groups[group].p.ndim) return nullptr;
-    return plan->sched_names[idx + pass].c_str();
+    if (pass < 0 || pass >= (int)plan->sched_names[group].size()) return nullptr;
+    return plan->sched_names[group][pass].c_str();
+}
+
+int rk4ip_profile(rk4ip_plan_t plan, int enable) {
+    if (!plan) return RK4IP_ERR_INVALID_ARG;
+    int rc = collect_profile(plan);
+    if (rc) return rc;
+    plan->profiling = enable != 0;
+    plan->prof_ms.assign(plan->groups.size(), std::vector<double>(6, 0.0));
+    plan->prof_n.assign(plan->groups.size(), std::vector<int64_t>(6, 0));
+    return RK4IP_OK;
+}
+
+int rk4ip_profile_read(rk4ip_plan_t plan, int group, int pass, int64_t* count, double* mean_ms) {
+    if (!plan || !count || !mean_ms || group < 0 || group >= (int)plan->groups.size()) return RK4IP_ERR_INVALID_ARG;
+    if (pass < 0 || pass >= (int)plan->sched_names[group].size()) return RK4IP_ERR_INVALID_ARG;
+    int rc = collect_profile(plan);
+    if (rc) return rc;
+    if (plan->prof_n.empty()) {
+        *count = 0;
+        *mean_ms = 0.0;
+        return RK4IP_OK;
+    }
+    *count = plan->prof_n[group][pass];
+    *mean_ms = *count ? plan->prof_ms[group][pass] / (double)*count : 0.0;
+    return RK4IP_OK;
 }
 
 int rk4ip_debug_philox(uint64_t seed, const uint32_t* ctr, int64_t n, uint32_t* out, void* stream) {
@@ -590,10 +793,11 @@ int rk4ip_debug_fft(rk4ip_plan_t plan, int group, int axis, const void* in, void
 
 int rk4ip_debug_apply_D(rk4ip_plan_t plan, void* psi, int adjoint) {
     if (!plan || !psi) return RK4IP_ERR_INVALID_ARG;
+    rk4ip::PassArgs pa{};
+    pa.psi = static_cast<float2*>(psi);
+    pa.adj = adjoint ? 1 : 0;
     for (auto& g : plan->groups)
-        for (int a = 0; a < g.p.ndim; a++)
-            HIPCHK(plan, rk4ip::launch_axis(g.d, a, rk4ip::PASS_D1, adjoint ? 1 : 0, static_cast<float2*>(psi), plan->A,
-                                            plan->B, 0, nullptr, plan->stream));
+        for (int a = 0; a < g.p.ndim; a++) HIPCHK(plan, rk4ip::launch_axis(g.d, a, rk4ip::PASS_D1, pa, plan->stream));
     return RK4IP_OK;
 }
 

@@ -37,7 +37,7 @@ EXPORTS = [
     "rk4ip_workspace_bytes", "rk4ip_plan", "rk4ip_set_stream", "rk4ip_step", "rk4ip_run",
     "rk4ip_diagnostics", "rk4ip_overlap", "rk4ip_moments", "rk4ip_adjoint_workspace_bytes",
     "rk4ip_adjoint", "rk4ip_status", "rk4ip_destroy", "rk4ip_strerror", "rk4ip_last_error",
-    "rk4ip_schedule", "rk4ip_debug_philox", "rk4ip_debug_noise", "rk4ip_debug_fft",
+    "rk4ip_schedule", "rk4ip_num_passes", "rk4ip_profile", "rk4ip_profile_read", "rk4ip_debug_philox", "rk4ip_debug_noise", "rk4ip_debug_fft",
     "rk4ip_debug_apply_D",
 ]
 
@@ -88,6 +88,9 @@ def load(path: str = LIB_PATH):
         "rk4ip_strerror": (ctypes.c_char_p, [i32]),
         "rk4ip_last_error": (ctypes.c_char_p, [vp]),
         "rk4ip_schedule": (ctypes.c_char_p, [vp, i32, i32]),
+        "rk4ip_num_passes": (i32, [vp, i32]),
+        "rk4ip_profile": (i32, [vp, i32]),
+        "rk4ip_profile_read": (i32, [vp, i32, i32, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double)]),
         "rk4ip_debug_philox": (i32, [u64, vp, i64, vp, vp]),
         "rk4ip_debug_noise": (i32, [vp, i32, i64, vp]),
         "rk4ip_debug_fft": (i32, [vp, i32, i32, vp, vp, i64, i32]),
@@ -277,9 +280,23 @@ class Plan:
     def status(self) -> int:
         return int(load().rk4ip_status(self.handle))
 
-    def schedule(self, group: int, axis: int) -> str:
-        r = load().rk4ip_schedule(self.handle, group, axis)
+    def schedule(self, group: int, pass_index: int) -> str:
+        r = load().rk4ip_schedule(self.handle, group, pass_index)
         return r.decode() if r else ""
+
+    def num_passes(self, group: int) -> int:
+        return int(load().rk4ip_num_passes(self.handle, group))
+
+    def profile(self, enable: bool):
+        _check(load().rk4ip_profile(self.handle, int(bool(enable))), self.handle, "rk4ip_profile")
+
+    def profile_read(self, group: int, pass_index: int):
+        """(launch count, mean ms) of one pass since profiling was enabled."""
+        n = ctypes.c_int64()
+        ms = ctypes.c_double()
+        _check(load().rk4ip_profile_read(self.handle, group, pass_index, ctypes.byref(n), ctypes.byref(ms)),
+               self.handle, "rk4ip_profile_read")
+        return int(n.value), float(ms.value)
 
     def noise(self, group: int, step: int):
         import torch
