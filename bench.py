@@ -64,7 +64,11 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--profile-steps", type=int, default=20)
     ap.add_argument("--no-graph", action="store_true", help="launch passes eagerly instead of replaying a hipGraph")
+    ap.add_argument("--no-autotune", action="store_true", help="use the default tile schedules")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run one elementwise copy kernel of 256 MiB in + 256 MiB out (a reference for "
+                         "rocprofv3 FETCH_SIZE/WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; the multi-GPU path is a design "
@@ -77,11 +81,18 @@ def main() -> int:
     from paper_1204_4255_amd import rk4ip, workloads
 
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
     w = workloads.gpe3d(nsteps=args.steps)
     g = w.groups[0]
     pts = g.M * g.batch
     probs, _keep = rk4ip.problems_from_workload(w)
-    flags = 0 if args.no_graph else rk4ip.RK4IP_FLAG_GRAPH
+    tune = 0 if args.no_autotune else rk4ip.RK4IP_FLAG_AUTOTUNE
+    flags = (0 if args.no_graph else rk4ip.RK4IP_FLAG_GRAPH) | tune
     plan = rk4ip.Plan(probs, flags=flags)
     psi0 = rk4ip.field_to_device(w)
     psi = psi0.clone()
@@ -103,7 +114,7 @@ def main() -> int:
     value = pts * args.steps / (ms / 1e3)
 
     # per-pass launch times with HIP events on the plan's stream (eager launches)
-    prof_plan = rk4ip.Plan(probs, flags=0)
+    prof_plan = rk4ip.Plan(probs, flags=tune)
     work = psi0.clone()
     prof_plan.run(work, 3)
     prof_plan.profile(True)
@@ -116,7 +127,7 @@ def main() -> int:
     # group by kernel (same kind and axis kind share one kernel)
     kernels = {}
     for p in passes:
-        kind, axis, n_, layout, lines = p["pass"].split(":")
+        kind, axis, n_, layout = p["pass"].split(":")[:4]
         key = f"{kind}:{layout}"
         k = kernels.setdefault(key, {"launches": 0, "total_ms": 0.0, "kind": kind})
         k["launches"] += p["launches"]
@@ -143,7 +154,8 @@ def main() -> int:
         "data": "synthetic: seeded 3D GPE initial field (trap ground state x N(0,0.05^2) phase noise)",
         "config": {"workload": "gpe3d_256^3", "lattice": [256, 256, 256], "domain": [-10, 10], "dt": w.h,
                    "g": 2000.0, "trap": [1.0, 1.5, 2.0], "instances": 1,
-                   "launch": "hipGraph of 8 steps" if flags else "eager passes"},
+                   "launch": "hipGraph of 8 steps" if not args.no_graph else "eager passes",
+                   "autotune": not args.no_autotune},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "kernel": dom_name, "kernel_mean_ms": dom_mean_ms,
@@ -157,21 +169,24 @@ def main() -> int:
     if not args.no_cpu_baseline:
         import oracle
 
-        # bounded sample: one step of the same 256^3 workload from the same initial field
+        # bounded sample: the first CPU_STEPS steps of the same 256^3 workload from the
+        # same initial field (about 10 s of FP64 work on a 16-core host)
+        cpu_steps = 8
         f0 = np.asarray(w.psi0[0], dtype=np.complex64).astype(np.complex128)
         op = oracle.Problem(n=g.n, lo=g.lo, hi=g.hi, h=w.h, batch=1, alpha=g.alpha, gamma=g.gamma, gnl=g.gnl,
                             trap=g.trap)
         t0 = time.perf_counter()
-        ref = oracle.step(op, f0, 0)
+        ref, _, _ = oracle.run(op, f0, cpu_steps)
         cpu_s = time.perf_counter() - t0
         one = psi0.clone()
-        plan.step(one, 0)
+        plan.run(one, cpu_steps)
         got = one.cpu().numpy().astype(np.complex128).reshape(ref.shape)
         err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
-        result["cpu_baseline"] = {"value": pts / cpu_s, "unit": "grid-point-steps/s", "cores": oracle.threads(),
-                                  "kind": "oracle", "sample": "1 step of the 256^3 workload (FP64, radix-2 FFT)",
+        result["cpu_baseline"] = {"value": pts * cpu_steps / cpu_s, "unit": "grid-point-steps/s",
+                                  "cores": oracle.threads(), "kind": "oracle",
+                                  "sample": f"the first {cpu_steps} steps of the 256^3 workload (FP64, radix-2 FFT)",
                                   "seconds": cpu_s}
-        result["parity_1step_rel_l2"] = err
+        result[f"parity_{cpu_steps}step_rel_l2"] = err
     print(json.dumps(result))
     plan.destroy()
     prof_plan.destroy()

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librk4ip.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["kernels.hip", "rk4ip.hip"]
+SOURCES = ["kernels_fwd.hip", "kernels_adj.hip", "kernels_aux.hip", "rk4ip.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

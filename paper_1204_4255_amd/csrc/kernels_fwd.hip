@@ -1,0 +1,148 @@
+// kernels_fwd.hip -- forward-step kernels: the per-axis passes (D1, D2, FIRST, LAST1,
+// LAST2) and the 1D whole-line step. See pass_common.h for the data flow of a step.
+#include "pass_common.h"
+
+namespace rk4ip {
+
+// ---------------------------------------------------------------------------- 1D step
+
+// One workgroup runs LPB whole lines (instances). Every value of the step stays in
+// registers; LDS only carries the FFT exchanges.
+template <int N, int LPB, bool NOISE>
+__global__ void __launch_bounds__(FFTShape<N>::T* LPB)
+    k_line_step(GroupDev g, float2* __restrict__ psi, int nsteps, int64_t step_off,
+                const int64_t* __restrict__ step_base) {
+    using F = FFTShape<N>;
+    using L = LdsLayout<N, LPB, true>;
+    constexpr int R = F::R, T = F::T;
+    __shared__ c32 lds[2 * L::SIZE];
+    __shared__ c32 tw[N];
+    __shared__ float2 E[N];
+    stage_tables<N>(tw, E, g.tw[0], g.E[0]);
+    const int t = threadIdx.x % T;
+    const int l = threadIdx.x / T;
+    const int64_t inst = (int64_t)blockIdx.x * LPB + l;
+    const bool active = inst < g.batch;
+    float2* p = psi + g.offset + inst * N;
+
+    c32 f[2][R];
+    float V[R];
+#pragma unroll
+    for (int m = 0; m < R; m++) {
+        const int e = t + m * T;
+        f[0][m] = active ? p[e] : make_float2(0.f, 0.f);
+        float v = trap_V(g, e, 0, 0);
+        if (g.Vgrid && active) v += g.Vgrid[inst * N + e];
+        V[m] = v;
+    }
+    const uint32_t iid = g.id_base + (uint32_t)inst;
+    int64_t step = read_step(step_off, step_base);
+    __syncthreads();  // tables staged
+    for (int s = 0; s < nsteps; s++, step++) {
+        c32 nz[R];
+#pragma unroll
+        for (int m = 0; m < R; m++) {
+            if constexpr (NOISE) {
+                const float2 z = noise_z(g, t + m * T, iid, step);
+                nz[m] = make_float2(g.noise_c * z.x, g.noise_c * z.y);
+            } else {
+                nz[m] = make_float2(0.f, 0.f);
+            }
+        }
+        // first pair: D psi and D[h G(psi)]
+#pragma unroll
+        for (int m = 0; m < R; m++) f[1][m] = hG(g, f[0][m], V[m], nz[m]);
+        propagate<N, L, 2>(f, t, l, lds, tw, E, false);
+        // stages at the midpoint picture
+#pragma unroll
+        for (int m = 0; m < R; m++) {
+            const c32 a = f[0][m], k1 = f[1][m];
+            const c32 k2 = hG(g, make_float2(fmaf(0.5f, k1.x, a.x), fmaf(0.5f, k1.y, a.y)), V[m], nz[m]);
+            const c32 k3 = hG(g, make_float2(fmaf(0.5f, k2.x, a.x), fmaf(0.5f, k2.y, a.y)), V[m], nz[m]);
+            f[0][m] = cadd(a, k3);
+            const float sx = k1.x * (1.0f / 6.0f) + (k2.x + k3.x) * (1.0f / 3.0f);
+            const float sy = k1.y * (1.0f / 6.0f) + (k2.y + k3.y) * (1.0f / 3.0f);
+            f[1][m] = make_float2(a.x + sx, a.y + sy);
+        }
+        // second pair: D u and D acc
+        propagate<N, L, 2>(f, t, l, lds, tw, E, false);
+#pragma unroll
+        for (int m = 0; m < R; m++) {
+            const c32 k4 = hG(g, f[0][m], V[m], nz[m]);
+            f[0][m] = make_float2(fmaf(k4.x, 1.0f / 6.0f, f[1][m].x), fmaf(k4.y, 1.0f / 6.0f, f[1][m].y));
+        }
+    }
+    if (active) {
+#pragma unroll
+        for (int m = 0; m < R; m++) p[t + m * T] = f[0][m];
+    }
+}
+
+// ---------------------------------------------------------------------------- launchers
+
+int axis_lines(int N, int axis, int n0) { return axis == 0 ? contig_lines(N) : strided_lines(N, n0); }
+
+bool axis_schedule_ok(int N, int mode, int axis, int n0, int lines, int seq) {
+    const bool contig = axis == 0;
+    if (!contig && lines > n0) return false;
+    switch (N) {
+        case 8: return schedule_ok_n<8>(mode, contig, lines, seq);
+        case 16: return schedule_ok_n<16>(mode, contig, lines, seq);
+        case 32: return schedule_ok_n<32>(mode, contig, lines, seq);
+        case 64: return schedule_ok_n<64>(mode, contig, lines, seq);
+        case 128: return schedule_ok_n<128>(mode, contig, lines, seq);
+        case 256: return schedule_ok_n<256>(mode, contig, lines, seq);
+        case 512: return schedule_ok_n<512>(mode, contig, lines, seq);
+        case 1024: return schedule_ok_n<1024>(mode, contig, lines, seq);
+        default: return false;
+    }
+}
+
+hipError_t launch_axis(const GroupDev& g, int axis, int mode, const PassArgs& a, hipStream_t s) {
+    switch (mode) {
+        case PASS_D1: return go_axis_mode<PASS_D1>(g, axis, a, s);
+        case PASS_D2: return go_axis_mode<PASS_D2>(g, axis, a, s);
+        case PASS_FIRST: return go_axis_mode<PASS_FIRST>(g, axis, a, s);
+        case PASS_LAST1: return go_axis_mode<PASS_LAST1>(g, axis, a, s);
+        case PASS_LAST2: return go_axis_mode<PASS_LAST2>(g, axis, a, s);
+        case PASS_U:
+        case PASS_AW:
+        case PASS_AS:
+        case PASS_AF: return launch_axis_adjoint(g, axis, mode, a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int N>
+static hipError_t go_line(const GroupDev& g, float2* psi, int nsteps, int64_t step_off, const int64_t* step_base,
+                          hipStream_t s) {
+    constexpr int T = FFTShape<N>::T;
+    constexpr int LPB = T >= 64 ? 1 : 64 / T;
+    const int64_t blocks = (g.batch + LPB - 1) / LPB;
+    if (g.has_noise)
+        hipLaunchKernelGGL((k_line_step<N, LPB, true>), dim3((unsigned)blocks), dim3(T * LPB), 0, s, g, psi, nsteps,
+                           step_off, step_base);
+    else
+        hipLaunchKernelGGL((k_line_step<N, LPB, false>), dim3((unsigned)blocks), dim3(T * LPB), 0, s, g, psi, nsteps,
+                           step_off, step_base);
+    return hipGetLastError();
+}
+
+hipError_t launch_line_step(const GroupDev& g, float2* psi, int nsteps, int64_t step_off, const int64_t* step_base,
+                            hipStream_t s) {
+    switch (g.n[0]) {
+        case 8: return go_line<8>(g, psi, nsteps, step_off, step_base, s);
+        case 16: return go_line<16>(g, psi, nsteps, step_off, step_base, s);
+        case 32: return go_line<32>(g, psi, nsteps, step_off, step_base, s);
+        case 64: return go_line<64>(g, psi, nsteps, step_off, step_base, s);
+        case 128: return go_line<128>(g, psi, nsteps, step_off, step_base, s);
+        case 256: return go_line<256>(g, psi, nsteps, step_off, step_base, s);
+        case 512: return go_line<512>(g, psi, nsteps, step_off, step_base, s);
+        case 1024: return go_line<1024>(g, psi, nsteps, step_off, step_base, s);
+        case 2048: return go_line<2048>(g, psi, nsteps, step_off, step_base, s);
+        case 4096: return go_line<4096>(g, psi, nsteps, step_off, step_base, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace rk4ip

@@ -31,6 +31,9 @@ struct PassArgs {
     const float2* aux1;
     double* vbar;             // FP64 potential-gradient accumulator (concatenated), AW/AS/AF
     int adj;                  // apply the transpose of D
+    int lines;                // tile schedule: lines (contiguous axis) or columns (strided) per
+                              // workgroup, 0 = default
+    int seq;                  // 1: transform the two fields one after the other (half the LDS)
     int64_t step_off;
     const int64_t* step_base; // step = step_off (+ *step_base when not null)
 };
@@ -43,8 +46,11 @@ struct DiagConst {
 };
 
 int axis_lines(int N, int axis, int n0);
+// Whether a (lines, seq) schedule of a pass is compiled for this length and axis.
+bool axis_schedule_ok(int N, int mode, int axis, int n0, int lines, int seq);
 
 hipError_t launch_axis(const GroupDev& g, int axis, int mode, const PassArgs& a, hipStream_t s);
+hipError_t launch_axis_adjoint(const GroupDev& g, int axis, int mode, const PassArgs& a, hipStream_t s);
 hipError_t launch_line_adjoint(const GroupDev& g, const float2* psi_n, float2* lam, double* vbar, int64_t step,
                                hipStream_t s);
 hipError_t launch_vbar_to_float(const double* vbar, float* out, int64_t n, hipStream_t s);

@@ -1,0 +1,446 @@
+// pass_common.h -- the per-axis pass kernel of the RK4IP step, its tile mapping and the
+// launch templates shared by the forward and adjoint kernel files.
+//
+// The step (Dennis, Hope & Johnsson, arXiv:1204.4255: classic RK4, Sec. 3.5, in the
+// interaction picture of Sec. 3.6 with the picture origin at the step midpoint) is
+//   a  = D psi,   k1 = D[h G(psi)],   k2 = h G(a + k1/2),   k3 = h G(a + k2/2),
+//   k4 = h G(D(a + k3)),   psi' = D(a + k1/6 + k2/3 + k3/3) + k4/6,
+// with D = e^{L h/2} applied per lattice axis (Sec. 3.2 factorisation): FFT along the
+// axis, multiply by e^{L_a h/2}, inverse FFT. The four D applications come in two pairs
+// of two fields, so on a 2D/3D lattice a step is two sweeps over the axes, each pass
+// reading and writing two complex64 fields once:
+//   FIRST (axis 0):   psi            -> (psi, hG(psi)) -> D_0 -> (A, B)
+//   D2    (middle):   (A, B)         -> D_a            -> (A, B)
+//   LAST1 (last axis):(A, B)         -> D_a -> a, k1; k2, k3; u = a + k3,
+//                                        acc = a + k1/6 + k2/3 + k3/3 -> (A, B) = (u, acc)
+//   D2    (axis 0, middle axes)
+//   LAST2 (last axis):(A, B)         -> D_a -> psi' = D acc + hG(D u)/6 -> psi
+// A 1D line fits one workgroup, so the whole step (eight transforms) runs in registers
+// and LDS with one read and one write of psi (k_line_step), optionally for several
+// steps per launch.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "device_common.h"
+#include "launch.h"
+
+namespace rk4ip {
+
+__device__ __forceinline__ int64_t read_step(int64_t step_off, const int64_t* step_base) {
+    return step_off + (step_base ? *step_base : 0);
+}
+
+// Copy an axis's twiddle and (E - 1)/n tables into LDS (the caller synchronises).
+template <int N>
+__device__ __forceinline__ void stage_tables(c32* s_tw, float2* s_E, const float2* __restrict__ tw,
+                                             const float2* __restrict__ E) {
+    for (int i = threadIdx.x; i < N; i += blockDim.x) {
+        s_tw[i] = tw[i];
+        if (s_E) s_E[i] = E[i];
+    }
+}
+
+// D_a on NF lines held in registers, in delta form: f <- f + F^{-1}[(E_a - 1)/n F f]
+// (adj: the transpose, with the conjugate multiplier). tw and E point to LDS copies of
+// the tables. All threads of the block call it.
+template <int N, class L, int NF>
+__device__ __forceinline__ void propagate(c32 (&f)[NF][FFTShape<N>::R], int t, int l, c32* lds,
+                                          const c32* tw, const float2* E, bool adj) {
+    using F = FFTShape<N>;
+    c32 o[NF][F::R];
+#pragma unroll
+    for (int q = 0; q < NF; q++)
+#pragma unroll
+        for (int m = 0; m < F::R; m++) o[q][m] = f[q][m];
+    fft_line<N, -1, L, NF>(f, t, l, lds, tw);
+#pragma unroll
+    for (int m = 0; m < F::R; m++) {
+        float2 cs = E[t + m * F::T];
+        if (adj) cs.y = -cs.y;
+#pragma unroll
+        for (int q = 0; q < NF; q++) f[q][m] = cmul(f[q][m], cs);
+    }
+    fft_line<N, +1, L, NF>(f, t, l, lds, tw);
+#pragma unroll
+    for (int q = 0; q < NF; q++)
+#pragma unroll
+        for (int m = 0; m < F::R; m++) f[q][m] = cadd(f[q][m], o[q][m]);
+}
+
+// Which lines a workgroup owns and where element e of its line l lives.
+// CONTIG: LINES consecutive lines along axis 0 (threads of a line are adjacent lanes).
+// strided: LINES adjacent x columns of one (instance, outer index) along axis 1 or 2
+// (adjacent lanes hold adjacent columns, so each row segment is one coalesced access).
+// Addresses are a workgroup-uniform 64-bit tile base plus 32-bit per-thread offsets,
+// shared by every field the pass touches.
+template <int N, bool CONTIG, int LINES>
+struct Tile {
+    int64_t base;      // uniform: group-relative point index of the tile origin
+    uint32_t off0;     // this thread's element 0 relative to base
+    uint32_t dstep;    // offset between element t + m T and t + (m+1) T
+    int64_t inst;      // instance of this thread's line
+    int64_t jbase;     // in-instance index of this thread's element 0 (noise counter, Vgrid)
+    uint32_t jstride;  // in-instance index step per element along the axis
+    bool active;
+
+    __device__ __forceinline__ Tile(const GroupDev& g, int axis, int l, int t) {
+        constexpr int T = FFTShape<N>::T;
+        if constexpr (CONTIG) {
+            const int64_t lines_per_inst = g.M >> g.log2n[0];
+            const int64_t nlines = g.batch * lines_per_inst;
+            const int64_t line = (int64_t)blockIdx.x * LINES + l;
+            active = line < nlines;
+            const int64_t ln = active ? line : 0;
+            base = (int64_t)blockIdx.x * LINES * N;
+            off0 = (uint32_t)(l * N + t);
+            dstep = T;
+            inst = ln / lines_per_inst;
+            jbase = (ln - inst * lines_per_inst) * N + t;
+            jstride = 1;
+        } else {
+            const int xt_count = g.n[0] / LINES;
+            const int outer_n = (axis == 1) ? g.n[2] : g.n[1];
+            int64_t bid = blockIdx.x;
+            const int xt = (int)(bid % xt_count);
+            bid /= xt_count;
+            const int outer = (int)(bid % outer_n);
+            inst = bid / outer_n;
+            active = true;
+            const uint32_t stride = (axis == 1) ? (uint32_t)g.n[0] : (uint32_t)g.n[0] * (uint32_t)g.n[1];
+            const int64_t in_inst = (axis == 1) ? (int64_t)outer * g.n[0] * g.n[1] + xt * LINES
+                                                : (int64_t)outer * g.n[0] + xt * LINES;
+            base = inst * g.M + in_inst;
+            off0 = (uint32_t)l + (uint32_t)t * stride;
+            dstep = (uint32_t)T * stride;
+            jbase = in_inst + off0;
+            jstride = stride;
+        }
+    }
+    __device__ __forceinline__ uint32_t off(int m) const { return off0 + (uint32_t)m * dstep; }
+    // byte offset of element t + m T for a field of float2 (the tile spans < 4 GiB)
+    __device__ __forceinline__ uint32_t b8(int m) const { return (off0 + (uint32_t)m * dstep) * 8u; }
+    __device__ __forceinline__ int64_t j(int m) const { return jbase + (int64_t)((uint32_t)m * (uint32_t)FFTShape<N>::T * jstride); }
+};
+
+// Access at a 32-bit byte offset from a workgroup-uniform base: lets the compiler use the
+// scalar-base form of the global load/store instead of a 64-bit address per element.
+__device__ __forceinline__ float2 ld2(const float2* base, uint32_t boff) {
+    return *reinterpret_cast<const float2*>(reinterpret_cast<const char*>(base) + boff);
+}
+__device__ __forceinline__ void st2(float2* base, uint32_t boff, float2 v) {
+    *reinterpret_cast<float2*>(reinterpret_cast<char*>(base) + boff) = v;
+}
+__device__ __forceinline__ double ldd(const double* base, uint32_t boff) {
+    return *reinterpret_cast<const double*>(reinterpret_cast<const char*>(base) + boff);
+}
+__device__ __forceinline__ void std_(double* base, uint32_t boff, double v) {
+    *reinterpret_cast<double*>(reinterpret_cast<char*>(base) + boff) = v;
+}
+
+// Lattice indices of in-instance point j.
+__device__ __forceinline__ void unflatten(const GroupDev& g, int64_t j, int& x, int& y, int& z) {
+    x = (int)(j & (g.n[0] - 1));
+    y = (int)((j >> g.log2n[0]) & (g.n[1] - 1));
+    z = (int)(j >> (g.log2n[0] + g.log2n[1]));
+}
+
+constexpr int fields_of(int mode) { return (mode == PASS_D1 || mode == PASS_U) ? 1 : 2; }
+
+// SEQ: the two fields share one exchange buffer and go through the transform one after
+// the other (lower LDS and register peak, twice the barriers).
+template <int N, int MODE, bool CONTIG, int LINES, bool NOISE, bool SEQ>
+__global__ void __launch_bounds__(FFTShape<N>::T* LINES) k_axis(GroupDev g, int axis, PassArgs args) {
+    using F = FFTShape<N>;
+    constexpr int R = F::R, T = F::T;
+    constexpr int NF = fields_of(MODE);
+    using L = LdsLayout<N, LINES, CONTIG>;
+    __shared__ c32 lds[(SEQ ? 1 : NF) * L::SIZE];
+    __shared__ c32 tw[N];
+    __shared__ float2 E[N];
+    stage_tables<N>(tw, E, g.tw[axis], g.E[axis]);
+    const int t = CONTIG ? (int)(threadIdx.x % T) : (int)(threadIdx.x / LINES);
+    const int l = CONTIG ? (int)(threadIdx.x / T) : (int)(threadIdx.x % LINES);
+    const Tile<N, CONTIG, LINES> tile(g, axis, l, t);
+    const int64_t o = g.offset + tile.base;
+    float2* __restrict__ ps = args.psi ? args.psi + o : nullptr;
+    float2* __restrict__ pa = args.A ? args.A + o : nullptr;
+    float2* __restrict__ pb = args.B ? args.B + o : nullptr;
+    const float2* __restrict__ x0 = args.aux0 ? args.aux0 + o : nullptr;
+    const float2* __restrict__ x1 = args.aux1 ? args.aux1 + o : nullptr;
+    double* __restrict__ vb = args.vbar ? args.vbar + o : nullptr;
+    constexpr bool NEEDS_STEP = (MODE == PASS_FIRST || MODE == PASS_LAST1 || MODE == PASS_LAST2 ||
+                                 MODE == PASS_U || MODE == PASS_AS);
+    const int64_t step = NEEDS_STEP ? read_step(args.step_off, args.step_base) : 0;
+    const uint32_t iid = g.id_base + (uint32_t)tile.inst;
+    const float* __restrict__ Vg = g.Vgrid ? g.Vgrid + tile.inst * g.M : nullptr;
+
+    // pointwise inputs of the right-hand side at element t + m T of this thread's line
+    auto potential_at = [&](int m) {
+        const int64_t j = tile.j(m);
+        int x, y, z;
+        unflatten(g, j, x, y, z);
+        float V = trap_V(g, x, y, z);
+        if (Vg) V += Vg[j];
+        return V;
+    };
+    auto noise_at = [&](int m) {
+        if constexpr (!NOISE) {
+            return make_float2(0.f, 0.f);
+        } else {
+            const float2 zz = noise_z(g, tile.j(m), iid, step);
+            return make_float2(g.noise_c * zz.x, g.noise_c * zz.y);
+        }
+    };
+    const c32 zero = make_float2(0.f, 0.f);
+
+    c32 f[NF][R];
+    if constexpr (MODE == PASS_D1 || MODE == PASS_FIRST) {
+#pragma unroll
+        for (int m = 0; m < R; m++) f[0][m] = tile.active ? ld2(ps, tile.b8(m)) : zero;
+        if constexpr (MODE == PASS_FIRST) {
+#pragma unroll
+            for (int m = 0; m < R; m++) f[1][m] = hG(g, f[0][m], potential_at(m), noise_at(m));
+        }
+    } else if constexpr (MODE == PASS_U) {
+        // u = a + k3 from (a, k1)
+#pragma unroll
+        for (int m = 0; m < R; m++) {
+            const c32 a = tile.active ? ld2(x0, tile.b8(m)) : zero;
+            const c32 k1 = tile.active ? ld2(x1, tile.b8(m)) : zero;
+            const float V = potential_at(m);
+            const c32 nz = noise_at(m);
+            const c32 k2 = hG(g, make_float2(fmaf(0.5f, k1.x, a.x), fmaf(0.5f, k1.y, a.y)), V, nz);
+            const c32 k3 = hG(g, make_float2(fmaf(0.5f, k2.x, a.x), fmaf(0.5f, k2.y, a.y)), V, nz);
+            f[0][m] = cadd(a, k3);
+        }
+    } else if constexpr (MODE == PASS_AW) {
+        // adjoint of psi' = D acc + k4/6, k4 = h G(w): (lam, wbar = h J(w)^T lam/6)
+#pragma unroll
+        for (int m = 0; m < R; m++) {
+            const c32 lam = tile.active ? ld2(ps, tile.b8(m)) : zero;
+            const c32 w = tile.active ? ld2(x0, tile.b8(m)) : zero;
+            const c32 k4b = cscale(lam, 1.0f / 6.0f);
+            f[0][m] = lam;
+            f[1][m] = hJT(g, w, potential_at(m), k4b);
+            if (vb && tile.active) std_(vb, tile.b8(m), ldd(vb, tile.b8(m)) + (double)hImconj(g, k4b, w));
+        }
+    } else {
+#pragma unroll
+        for (int m = 0; m < R; m++) {
+            f[0][m] = tile.active ? ld2(pa, tile.b8(m)) : zero;
+            f[1][m] = tile.active ? ld2(pb, tile.b8(m)) : zero;
+        }
+    }
+
+    __syncthreads();  // tables staged (the loads above overlap the copy)
+    if constexpr (SEQ && NF == 2) {
+        c32(&f0)[1][R] = *reinterpret_cast<c32(*)[1][R]>(&f[0]);
+        c32(&f1)[1][R] = *reinterpret_cast<c32(*)[1][R]>(&f[1]);
+        propagate<N, L, 1>(f0, t, l, lds, tw, E, args.adj != 0);
+        propagate<N, L, 1>(f1, t, l, lds, tw, E, args.adj != 0);
+    } else {
+        propagate<N, L, NF>(f, t, l, lds, tw, E, args.adj != 0);
+    }
+
+    if (!tile.active) return;  // after the last barrier
+    if constexpr (MODE == PASS_D1 || MODE == PASS_U) {
+#pragma unroll
+        for (int m = 0; m < R; m++) st2(ps, tile.b8(m), f[0][m]);
+    } else if constexpr (MODE == PASS_LAST1) {
+#pragma unroll
+        for (int m = 0; m < R; m++) {
+            const float V = potential_at(m);
+            const c32 nz = noise_at(m);
+            const c32 a = f[0][m], k1 = f[1][m];
+            const c32 k2 = hG(g, make_float2(fmaf(0.5f, k1.x, a.x), fmaf(0.5f, k1.y, a.y)), V, nz);
+            const c32 k3 = hG(g, make_float2(fmaf(0.5f, k2.x, a.x), fmaf(0.5f, k2.y, a.y)), V, nz);
+            const float sx = k1.x * (1.0f / 6.0f) + (k2.x + k3.x) * (1.0f / 3.0f);
+            const float sy = k1.y * (1.0f / 6.0f) + (k2.y + k3.y) * (1.0f / 3.0f);
+            st2(pa, tile.b8(m), cadd(a, k3));
+            st2(pb, tile.b8(m), make_float2(a.x + sx, a.y + sy));
+        }
+    } else if constexpr (MODE == PASS_LAST2) {
+#pragma unroll
+        for (int m = 0; m < R; m++) {
+            const c32 k4 = hG(g, f[0][m], potential_at(m), noise_at(m));
+            st2(ps, tile.b8(m), make_float2(fmaf(k4.x, 1.0f / 6.0f, f[1][m].x), fmaf(k4.y, 1.0f / 6.0f, f[1][m].y)));
+        }
+    } else if constexpr (MODE == PASS_AS) {
+        // transposes of the stage combinations: (accbar, ubar) -> (abar, k1bar)
+#pragma unroll
+        for (int m = 0; m < R; m++) {
+            const float V = potential_at(m);
+            const c32 nz = noise_at(m);
+            const c32 a = ld2(x0, tile.b8(m)), k1 = ld2(x1, tile.b8(m));
+            const c32 p2 = make_float2(fmaf(0.5f, k1.x, a.x), fmaf(0.5f, k1.y, a.y));
+            const c32 k2 = hG(g, p2, V, nz);
+            const c32 p3 = make_float2(fmaf(0.5f, k2.x, a.x), fmaf(0.5f, k2.y, a.y));
+            const c32 accb = f[0][m], ub = f[1][m];
+            const c32 k3b = make_float2(fmaf(accb.x, 1.0f / 3.0f, ub.x), fmaf(accb.y, 1.0f / 3.0f, ub.y));
+            const c32 p3b = hJT(g, p3, V, k3b);
+            const c32 k2b = make_float2(fmaf(accb.x, 1.0f / 3.0f, 0.5f * p3b.x), fmaf(accb.y, 1.0f / 3.0f, 0.5f * p3b.y));
+            const c32 p2b = hJT(g, p2, V, k2b);
+            const c32 k1b = make_float2(fmaf(accb.x, 1.0f / 6.0f, 0.5f * p2b.x), fmaf(accb.y, 1.0f / 6.0f, 0.5f * p2b.y));
+            const c32 ab = make_float2(accb.x + ub.x + p3b.x + p2b.x, accb.y + ub.y + p3b.y + p2b.y);
+            if (vb) std_(vb, tile.b8(m), ldd(vb, tile.b8(m)) + (double)hImconj(g, k3b, p3) + (double)hImconj(g, k2b, p2));
+            st2(pa, tile.b8(m), ab);
+            st2(pb, tile.b8(m), k1b);
+        }
+    } else if constexpr (MODE == PASS_AF) {
+        // psibar = D^T abar + h J(psi_n)^T (D^T k1bar)
+#pragma unroll
+        for (int m = 0; m < R; m++) {
+            const c32 pn = ld2(x0, tile.b8(m));
+            const c32 g0b = f[1][m];
+            const c32 r = hJT(g, pn, potential_at(m), g0b);
+            if (vb) std_(vb, tile.b8(m), ldd(vb, tile.b8(m)) + (double)hImconj(g, g0b, pn));
+            st2(ps, tile.b8(m), cadd(f[0][m], r));
+        }
+    } else {  // FIRST, D2, AW
+#pragma unroll
+        for (int m = 0; m < R; m++) {
+            st2(pa, tile.b8(m), f[0][m]);
+            st2(pb, tile.b8(m), f[1][m]);
+        }
+    }
+}
+
+// LDS of a strided tile of w columns and nf fields must fit the 160 KiB of a CU.
+constexpr bool fits_lds(int N, int w, int nf) { return (long)nf * N * w * 8 <= 128 * 1024; }
+
+static inline int strided_lines(int N, int n0) {
+    int w = N <= 256 ? 16 : (N == 512 ? 8 : 4);
+    return w < n0 ? w : n0;
+}
+
+static inline int contig_lines(int N) {
+    const int T = N < 16 ? 1 : N / 16;
+    int l = 256 / T;
+    return l < 1 ? 1 : l;
+}
+
+
+// passes whose pointwise work evaluates G (and so may draw noise)
+constexpr bool uses_rhs(int mode) {
+    return mode == PASS_FIRST || mode == PASS_LAST1 || mode == PASS_LAST2 || mode == PASS_U || mode == PASS_AS;
+}
+
+template <int N, int MODE, bool CONTIG, int LINES, bool SEQ>
+static hipError_t go_axis(const GroupDev& g, int axis, const PassArgs& a, hipStream_t s) {
+    int64_t blocks;
+    if (CONTIG)
+        blocks = (g.batch * (g.M >> g.log2n[0]) + LINES - 1) / LINES;
+    else
+        blocks = g.batch * (g.M >> g.log2n[axis]) / LINES;
+    const dim3 grid((unsigned)blocks), block(FFTShape<N>::T * LINES);
+    if constexpr (uses_rhs(MODE)) {
+        if (g.has_noise) {
+            hipLaunchKernelGGL((k_axis<N, MODE, CONTIG, LINES, true, SEQ>), grid, block, 0, s, g, axis, a);
+            return hipGetLastError();
+        }
+    }
+    hipLaunchKernelGGL((k_axis<N, MODE, CONTIG, LINES, false, SEQ>), grid, block, 0, s, g, axis, a);
+    return hipGetLastError();
+}
+
+// passes that run only on axis 0 / only on the last (strided) axis
+constexpr bool contig_only(int mode) { return mode == PASS_FIRST || mode == PASS_U || mode == PASS_AW; }
+constexpr bool strided_only(int mode) {
+    return mode == PASS_LAST1 || mode == PASS_LAST2 || mode == PASS_AS || mode == PASS_AF;
+}
+// lengths with more than the default schedule compiled (the ones the workloads use)
+constexpr bool tuned_length(int N) { return N >= 128 && N <= 512; }
+// forward-step passes get the schedule variants; the adjoint passes use the default
+constexpr bool tuned_mode(int mode) { return mode <= PASS_LAST2; }
+
+constexpr int default_contig_lines(int N) { return N < 16 ? 256 : ((256 / (N / 16)) < 1 ? 1 : 256 / (N / 16)); }
+
+// Is schedule (lines, seq) of pass MODE compiled for length N on the contiguous or a
+// strided axis? Mirrors the instantiations in go_axis_n.
+template <int N, int MODE>
+constexpr bool schedule_compiled(bool contig, int lines, int seq) {
+    constexpr int T = FFTShape<N>::T;
+    constexpr int NF = fields_of(MODE);
+    if (seq && (NF != 2 || !tuned_length(N) || !tuned_mode(MODE))) return false;
+    const int nf = seq ? 1 : NF;
+    if (contig) {
+        const int dl = default_contig_lines(N);
+        if (lines == dl) return true;
+        return tuned_length(N) && tuned_mode(MODE) && lines == dl / 2 && lines >= 1;
+    }
+    if (lines != 4 && lines != 8 && lines != 16 && lines != 32) return false;
+    if (T * lines > 1024 || !fits_lds(N, lines, nf)) return false;
+    if (lines == 32 && !(tuned_length(N) && tuned_mode(MODE))) return false;
+    return true;
+}
+
+template <int N, int MODE, bool CONTIG, int LINES>
+static hipError_t go_axis_sched(const GroupDev& g, int axis, const PassArgs& a, hipStream_t s) {
+    if constexpr (schedule_compiled<N, MODE>(CONTIG, LINES, 1)) {
+        if (a.seq) return go_axis<N, MODE, CONTIG, LINES, true>(g, axis, a, s);
+    }
+    if constexpr (schedule_compiled<N, MODE>(CONTIG, LINES, 0)) {
+        if (!a.seq) return go_axis<N, MODE, CONTIG, LINES, false>(g, axis, a, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <int N, int MODE>
+static hipError_t go_axis_n(const GroupDev& g, int axis, const PassArgs& a, hipStream_t s) {
+    constexpr int CL = default_contig_lines(N);
+    if (axis == 0) {
+        if constexpr (strided_only(MODE)) {
+            return hipErrorInvalidValue;
+        } else {
+            const int lines = a.lines ? a.lines : CL;
+            if (lines == CL) return go_axis_sched<N, MODE, true, CL>(g, axis, a, s);
+            if constexpr (CL / 2 >= 1) {
+                if (lines == CL / 2) return go_axis_sched<N, MODE, true, (CL / 2 >= 1 ? CL / 2 : 1)>(g, axis, a, s);
+            }
+            return hipErrorInvalidValue;
+        }
+    }
+    if constexpr (contig_only(MODE)) {
+        return hipErrorInvalidValue;
+    } else {
+        const int w = a.lines ? a.lines : strided_lines(N, g.n[0]);
+        if (w > g.n[0]) return hipErrorInvalidValue;
+        switch (w) {
+            case 32: return go_axis_sched<N, MODE, false, 32>(g, axis, a, s);
+            case 16: return go_axis_sched<N, MODE, false, 16>(g, axis, a, s);
+            case 8: return go_axis_sched<N, MODE, false, 8>(g, axis, a, s);
+            case 4: return go_axis_sched<N, MODE, false, 4>(g, axis, a, s);
+            default: return hipErrorInvalidValue;
+        }
+    }
+}
+
+template <int N>
+static bool schedule_ok_n(int mode, bool contig, int lines, int seq) {
+    switch (mode) {
+        case PASS_D1: return schedule_compiled<N, PASS_D1>(contig, lines, seq);
+        case PASS_D2: return schedule_compiled<N, PASS_D2>(contig, lines, seq);
+        case PASS_FIRST: return contig && schedule_compiled<N, PASS_FIRST>(contig, lines, seq);
+        case PASS_LAST1: return !contig && schedule_compiled<N, PASS_LAST1>(contig, lines, seq);
+        case PASS_LAST2: return !contig && schedule_compiled<N, PASS_LAST2>(contig, lines, seq);
+        default: return false;
+    }
+}
+
+template <int MODE>
+static hipError_t go_axis_mode(const GroupDev& g, int axis, const PassArgs& a, hipStream_t s) {
+    switch (g.n[axis]) {
+        case 8: return go_axis_n<8, MODE>(g, axis, a, s);
+        case 16: return go_axis_n<16, MODE>(g, axis, a, s);
+        case 32: return go_axis_n<32, MODE>(g, axis, a, s);
+        case 64: return go_axis_n<64, MODE>(g, axis, a, s);
+        case 128: return go_axis_n<128, MODE>(g, axis, a, s);
+        case 256: return go_axis_n<256, MODE>(g, axis, a, s);
+        case 512: return go_axis_n<512, MODE>(g, axis, a, s);
+        case 1024: return go_axis_n<1024, MODE>(g, axis, a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace rk4ip

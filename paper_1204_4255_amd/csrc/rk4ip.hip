@@ -5,6 +5,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <algorithm>
 #include <cstring>
 #include <new>
@@ -137,6 +138,7 @@ struct rk4ip_plan_s {
     int* flag = nullptr;
     std::string err;
     std::vector<std::vector<std::string>> sched_names;  // [group][pass]
+    std::vector<std::vector<std::pair<int, int>>> sched;  // [group][pass] = (lines, seq); (0, 0) = default
     // cached graph of `graph_steps` steps on `graph_psi`
     hipGraphExec_t graph = nullptr;
     hipGraph_t graph_src = nullptr;
@@ -265,6 +267,116 @@ int collect_profile(rk4ip_plan_t plan) {
     return RK4IP_OK;
 }
 
+// Mean time (ms) of `reps` launches of one pass with a given schedule, on the work fields.
+int time_pass(rk4ip_plan_t plan, const GroupHost& g, int axis, int mode, int lines, int seq, int reps, float* ms) {
+    rk4ip::PassArgs pa{};
+    pa.A = plan->A;
+    pa.B = plan->B;
+    pa.psi = (mode == rk4ip::PASS_FIRST) ? plan->B : plan->A;  // same tiles are read before written
+    pa.lines = lines;
+    pa.seq = seq;
+    hipStream_t st = plan->stream;
+    for (int i = 0; i < 2; i++) HIPCHK(plan, rk4ip::launch_axis(g.d, axis, mode, pa, st));
+    hipEvent_t a = take_event(plan), b = take_event(plan);
+    if (!a || !b) return fail(plan, RK4IP_ERR_HIP, "hipEventCreate failed");
+    HIPCHK(plan, hipEventRecord(a, st));
+    for (int i = 0; i < reps; i++) HIPCHK(plan, rk4ip::launch_axis(g.d, axis, mode, pa, st));
+    HIPCHK(plan, hipEventRecord(b, st));
+    HIPCHK(plan, hipEventSynchronize(b));
+    HIPCHK(plan, hipEventElapsedTime(ms, a, b));
+    *ms /= (float)reps;
+    plan->spare.push_back(a);
+    plan->spare.push_back(b);
+    return RK4IP_OK;
+}
+
+// Tuning cache: a flat JSON object {"key": [lines, seq], ...} in the file named by
+// RK4IP_TUNE_CACHE (optional).
+std::string tune_key(const GroupHost& g, int pass) {
+    char k[160];
+    std::snprintf(k, sizeof(k), "gfx950|n=%lld,%lld,%lld|b=%lld|pass=%d", (long long)g.p.n[0], (long long)g.p.n[1],
+                  (long long)g.p.n[2], (long long)g.p.batch, pass);
+    return k;
+}
+
+bool cache_lookup(const std::string& text, const std::string& key, int* lines, int* seq) {
+    const std::string q = "\"" + key + "\"";
+    size_t p = text.find(q);
+    if (p == std::string::npos) return false;
+    p = text.find('[', p);
+    if (p == std::string::npos) return false;
+    return std::sscanf(text.c_str() + p, "[%d , %d]", lines, seq) == 2 ||
+           std::sscanf(text.c_str() + p, "[%d,%d]", lines, seq) == 2;
+}
+
+// Choose the fastest compiled schedule of every pass (RK4IP_FLAG_AUTOTUNE).
+int autotune(rk4ip_plan_t plan) {
+    const char* path = std::getenv("RK4IP_TUNE_CACHE");
+    std::string text;
+    if (path) {
+        if (FILE* fh = std::fopen(path, "r")) {
+            char buf[4096];
+            size_t n;
+            while ((n = std::fread(buf, 1, sizeof(buf), fh)) > 0) text.append(buf, n);
+            std::fclose(fh);
+        }
+    }
+    std::vector<std::pair<std::string, std::pair<int, int>>> fresh;
+    HIPCHK(plan, hipMemsetAsync(plan->A, 0, 2 * sizeof(float2) * (size_t)plan->points, plan->stream));
+    for (size_t gi = 0; gi < plan->groups.size(); gi++) {
+        const GroupHost& g = plan->groups[gi];
+        if (g.p.ndim == 1) continue;
+        int seq_list[6][2];
+        const int np = pass_list(g.p.ndim, seq_list);
+        for (int i = 0; i < np; i++) {
+            const int axis = seq_list[i][0], mode = seq_list[i][1];
+            const int N = (int)g.p.n[axis], n0 = (int)g.p.n[0];
+            int cl = 0, cs = 0;
+            if (cache_lookup(text, tune_key(g, i), &cl, &cs) && rk4ip::axis_schedule_ok(N, mode, axis, n0, cl, cs)) {
+                plan->sched[gi][i] = {cl, cs};
+                continue;
+            }
+            float best = 1e30f;
+            std::pair<int, int> pick{0, 0};
+            const int cand_lines[] = {1, 2, 4, 8, 16, 32, 64, 128, 256};
+            for (int lines : cand_lines)
+                for (int sq = 0; sq < 2; sq++) {
+                    if (!rk4ip::axis_schedule_ok(N, mode, axis, n0, lines, sq)) continue;
+                    float ms = 0.f;
+                    int rc = time_pass(plan, g, axis, mode, lines, sq, 5, &ms);
+                    if (rc) return rc;
+                    if (ms < best) {
+                        best = ms;
+                        pick = {lines, sq};
+                    }
+                }
+            plan->sched[gi][i] = pick;
+            fresh.push_back({tune_key(g, i), pick});
+        }
+    }
+    if (path && !fresh.empty()) {
+        // rewrite the cache: old entries kept verbatim, new ones appended
+        std::string body = text;
+        size_t close = body.rfind('}');
+        if (close == std::string::npos) body = "{\n", close = body.size();
+        else body = body.substr(0, close);
+        bool has_entry = body.find('[') != std::string::npos;
+        for (auto& f : fresh) {
+            char line[256];
+            std::snprintf(line, sizeof(line), "%s \"%s\": [%d, %d]\n", has_entry ? "," : " ", f.first.c_str(),
+                          f.second.first, f.second.second);
+            body += line;
+            has_entry = true;
+        }
+        body += "}\n";
+        if (FILE* fh = std::fopen(path, "w")) {
+            std::fwrite(body.data(), 1, body.size(), fh);
+            std::fclose(fh);
+        }
+    }
+    return RK4IP_OK;
+}
+
 // Enqueue `nsteps` steps of every group. step_base != null: step = *step_base + step_off.
 int enqueue_steps(rk4ip_plan_t plan, hipStream_t stream, float2* psi, int64_t step_off, int64_t nsteps,
                   const int64_t* step_base, bool allow_fuse) {
@@ -300,6 +412,8 @@ int enqueue_steps(rk4ip_plan_t plan, hipStream_t stream, float2* psi, int64_t st
                 pa.B = plan->B;
                 pa.step_off = step_off + s;
                 pa.step_base = step_base;
+                pa.lines = plan->sched[gi][i].first;
+                pa.seq = plan->sched[gi][i].second;
                 rc = timed_launch(plan, stream, (int)gi, i, capturing,
                                   [&] { return rk4ip::launch_axis(g.d, seq[i][0], seq[i][1], pa, stream); });
                 if (rc) return rc;
@@ -503,7 +617,21 @@ int rk4ip_plan(const rk4ip_problem* probs, int nprob, void* workspace, size_t ws
         g.first_inst = inst;
         offset += p.batch * g.M;
         inst += p.batch;
-        char name[128];
+        plan->sched.push_back(std::vector<std::pair<int, int>>(p.ndim == 1 ? 1 : (p.ndim == 2 ? 4 : 6), {0, 0}));
+    }
+    plan->ninst = inst;
+    plan->groups = std::move(gh);
+    if (flags & RK4IP_FLAG_AUTOTUNE) {
+        rc = autotune(plan);
+        if (rc != RK4IP_OK) {
+            delete plan;
+            return rc;
+        }
+    }
+    // names of the chosen schedules
+    for (size_t gi = 0; gi < plan->groups.size(); gi++) {
+        const rk4ip_problem& p = plan->groups[gi].p;
+        char name[160];
         std::vector<std::string> names;
         if (p.ndim == 1) {
             std::snprintf(name, sizeof(name), "line_step:n%lld", (long long)p.n[0]);
@@ -514,16 +642,15 @@ int rk4ip_plan(const rk4ip_problem* probs, int nprob, void* workspace, size_t ws
             const int np = pass_list(p.ndim, seq);
             for (int k = 0; k < np; k++) {
                 const int a = seq[k][0];
-                std::snprintf(name, sizeof(name), "%s:axis%d:n%lld:%s:lines%d", kinds[seq[k][1]], a,
-                              (long long)p.n[a], a == 0 ? "contig" : "strided",
-                              rk4ip::axis_lines((int)p.n[a], a, (int)p.n[0]));
+                const auto sc = plan->sched[gi][k];
+                const int lines = sc.first ? sc.first : rk4ip::axis_lines((int)p.n[a], a, (int)p.n[0]);
+                std::snprintf(name, sizeof(name), "%s:axis%d:n%lld:%s:lines%d:%s", kinds[seq[k][1]], a,
+                              (long long)p.n[a], a == 0 ? "contig" : "strided", lines, sc.second ? "seq" : "joint");
                 names.push_back(name);
             }
         }
         plan->sched_names.push_back(names);
     }
-    plan->ninst = inst;
-    plan->groups = std::move(gh);
     hipError_t e = hipMemset(plan->ws + L.header, 0, kAlign);
     if (e != hipSuccess) {
         rc = fail_hip(plan, e, "hipMemset");

@@ -270,6 +270,25 @@ def test_graph_replays_match_eager_with_work_between(torch):
         assert torch.equal(a, b), rep
 
 
+def test_autotuned_schedules_match_default_bitwise(torch):
+    log("autotuned schedules vs default (3D 256x32x64 and 2D 512x128)")
+    for n in ((256, 32, 64), (512, 128)):
+        nd = len(n)
+        g = W.Group(n=n, lo=(-5.0,) * nd, hi=(5.0,) * nd, batch=1, gnl=10.0, trap=(1, 1, 1), sigma=0.01, seed=2)
+        f = quantised(random_field(g, 50))
+        w = W.Workload("t", [g], 1e-3, 3, [f])
+        base = plan_for(w, 0)
+        tuned = plan_for(w, rk4ip.RK4IP_FLAG_AUTOTUNE)
+        names = [tuned.schedule(0, i) for i in range(tuned.num_passes(0))]
+        log("  " + " ".join(names))
+        a = _dev(torch, f)
+        b = _dev(torch, f)
+        base.run(a, 3)
+        tuned.run(b, 3)
+        torch.cuda.synchronize()
+        assert torch.equal(a, b)
+
+
 # ----------------------------------------------------------------------------- the workloads
 
 
