@@ -66,7 +66,7 @@ enum {
 };
 
 /* Plan flags */
-#define RK4IP_FLAG_GRAPH     0x1u  /* replay the per-step launch sequence from a hipGraph */
+#define RK4IP_FLAG_GRAPH     0x1u  /* replay the steady-state steps of a run from a hipGraph */
 #define RK4IP_FLAG_AUTOTUNE  0x2u  /* time candidate tile schedules at plan time and keep the best */
 #define RK4IP_FLAG_FUSE_1D   0x4u  /* 1D groups: run several steps per launch with the line kept on chip */
 
@@ -167,11 +167,14 @@ const char* rk4ip_strerror(int status);
 /* Last error message recorded on a plan (never NULL; "" when none). */
 const char* rk4ip_last_error(rk4ip_plan_t plan);
 
-/* Number of kernel passes one step of group `group` runs (1 for a 1D group, 4 for 2D,
- * 6 for 3D), or a negative status. */
+/* Number of kernel pass kinds of group `group`, or a negative status: 1 for a 1D group
+ * (the whole step in one launch); 4 for 2D (FIRST x, LF y, XF x, LAST2 x) and 6 for 3D
+ * (FIRST x, D2 y, LF z, D2 y, XF x, LAST2 x). A run of n steps on a 2D/3D group launches
+ * FIRST once, the middle passes n times, XF n - 1 times (it ends one step and starts the
+ * next) and LAST2 once. */
 int rk4ip_num_passes(rk4ip_plan_t plan, int group);
 
-/* Name of pass `pass` of group `group` in step order: kind, axis, length and tile
+/* Name of pass `pass` of group `group` in the order above: kind, axis, length and tile
  * (for logs and profiles), or NULL if out of range. */
 const char* rk4ip_schedule(rk4ip_plan_t plan, int group, int pass);
 

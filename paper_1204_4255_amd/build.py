@@ -10,7 +10,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librk4ip.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["kernels_fwd.hip", "kernels_adj.hip", "kernels_aux.hip", "rk4ip.hip"]
+SOURCES = [
+    "kernels_fwd.hip", "kernels_pass_d.hip", "kernels_pass_first.hip", "kernels_pass_last.hip", "kernels_pass_xf.hip",
+    "kernels_adj.hip", "kernels_aux.hip", "rk4ip.hip",
+]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -2,9 +2,9 @@
 //
 // The transforms between the spatial and spectral representations are FFTs applied
 // along one lattice axis at a time (Dennis, Hope & Johnsson, arXiv:1204.4255, Sec. 3.2).
-// Here a line of N = 2^p points is spread over T = N/R threads (R = min(N, 16) values
-// per thread, kept in VGPRs). The transform is a Stockham autosort sequence of
-// radix-16 stages followed by at most one radix-2/4/8 stage; butterflies run in
+// Here a line of N = 2^p points is spread over T = N/R threads (R = min(N, 16) or
+// min(N, 8) values per thread, kept in VGPRs). The transform is a Stockham autosort
+// sequence of radix-R stages followed by at most one smaller stage; butterflies run in
 // registers and the data move between stages through LDS. Thread t holds elements
 // t + m*T (m = 0..R-1) both before the forward and after the inverse transform, which
 // is exactly the pattern of a coalesced global load of the line, so no LDS round trip
@@ -157,17 +157,21 @@ struct DFT<16, S> {
 
 constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n / 2); }
 
-// Shape of the transform of a line of N points.
-template <int N>
+// Shape of the transform of a line of N points with at most RR values per thread: a
+// sequence of radix-R stages (R = min(N, RR)) and at most one smaller last stage.
+template <int N, int RR = 16>
 struct FFTShape {
     static_assert(N >= 8 && (N & (N - 1)) == 0, "N must be a power of two >= 8");
-    static constexpr int R = N < 16 ? N : 16;   // values per thread
+    static_assert(RR == 8 || RR == 16, "8 or 16 values per thread");
+    static constexpr int NN = N;
+    static constexpr int R = N < RR ? N : RR;   // values per thread
     static constexpr int T = N / R;             // threads per line
-    static constexpr int S16 = N < 16 ? 0 : ilog2(N) / 4;       // radix-16 stages
-    static constexpr int Q = N < 16 ? N : (N >> (4 * S16));     // last radix (1 = none)
-    static constexpr int NSTAGES = S16 + (Q > 1 ? 1 : 0);
+    static constexpr int LR = ilog2(R);
+    static constexpr int S = N < RR ? 0 : ilog2(N) / LR;        // full radix-R stages
+    static constexpr int Q = N < RR ? N : (N >> (LR * S));      // last radix (1 = none)
+    static constexpr int NSTAGES = S + (Q > 1 ? 1 : 0);
     // radix and Ns (product of earlier radices) of stage i
-    __host__ __device__ static constexpr int radix(int i) { return (N < 16) ? N : (i < S16 ? 16 : Q); }
+    __host__ __device__ static constexpr int radix(int i) { return (N < RR) ? N : (i < S ? R : Q); }
     __host__ __device__ static constexpr int ns(int i) { return i == 0 ? 1 : ns(i - 1) * radix(i - 1); }
 };
 
@@ -191,9 +195,9 @@ struct LdsLayout {
 
 // One Stockham stage on the registers of one thread: U = R/radix butterflies,
 // butterfly u is b = t + T u with inputs v[u*radix + k] = x[b + k N/radix].
-template <int N, int S, int STAGE>
-__device__ __forceinline__ void fft_stage(c32 (&v)[FFTShape<N>::R], int t, const c32* __restrict__ tw) {
-    using F = FFTShape<N>;
+template <class F, int S, int STAGE>
+__device__ __forceinline__ void fft_stage(c32 (&v)[F::R], int t, const c32* __restrict__ tw) {
+    constexpr int N = F::NN;
     constexpr int r = F::radix(STAGE);
     constexpr int ns = F::ns(STAGE);
     constexpr int U = F::R / r;
@@ -220,9 +224,9 @@ __device__ __forceinline__ void fft_stage(c32 (&v)[FFTShape<N>::R], int t, const
 }
 
 // Write the outputs of stage STAGE to LDS and read the inputs of stage STAGE+1.
-template <int N, int STAGE, class L, int NF>
-__device__ __forceinline__ void fft_exchange(c32 (&v)[NF][FFTShape<N>::R], int t, int line, c32* lds) {
-    using F = FFTShape<N>;
+template <class F, int STAGE, class L, int NF>
+__device__ __forceinline__ void fft_exchange(c32 (&v)[NF][F::R], int t, int line, c32* lds) {
+    constexpr int N = F::NN;
     constexpr int r = F::radix(STAGE);
     constexpr int ns = F::ns(STAGE);
     constexpr int U = F::R / r;
@@ -253,9 +257,8 @@ __device__ __forceinline__ void fft_exchange(c32 (&v)[NF][FFTShape<N>::R], int t
 
 // After the last stage, register u*Q + k holds element t + T (u + k R/Q); put element
 // t + T m into register m.
-template <int N>
-__device__ __forceinline__ void fft_natural_order(c32 (&v)[FFTShape<N>::R]) {
-    using F = FFTShape<N>;
+template <class F>
+__device__ __forceinline__ void fft_natural_order(c32 (&v)[F::R]) {
     constexpr int r = F::radix(F::NSTAGES - 1);
     constexpr int U = F::R / r;
     if constexpr (U > 1) {
@@ -271,27 +274,27 @@ __device__ __forceinline__ void fft_natural_order(c32 (&v)[FFTShape<N>::R]) {
 
 // Stage i of a transform of NF fields at once: the register half of stage i, then the
 // exchange into stage i+1.
-template <int N, int S, int STAGE, class L, int NF>
-__device__ __forceinline__ void fft_stages_from(c32 (&v)[NF][FFTShape<N>::R], int t, int line, c32* lds,
+template <class F, int S, int STAGE, class L, int NF>
+__device__ __forceinline__ void fft_stages_from(c32 (&v)[NF][F::R], int t, int line, c32* lds,
                                                 const c32* __restrict__ tw) {
-    using F = FFTShape<N>;
 #pragma unroll
-    for (int f = 0; f < NF; f++) fft_stage<N, S, STAGE>(v[f], t, tw);
+    for (int f = 0; f < NF; f++) fft_stage<F, S, STAGE>(v[f], t, tw);
     if constexpr (STAGE + 1 < F::NSTAGES) {
-        fft_exchange<N, STAGE, L, NF>(v, t, line, lds);
-        fft_stages_from<N, S, STAGE + 1, L, NF>(v, t, line, lds, tw);
+        fft_exchange<F, STAGE, L, NF>(v, t, line, lds);
+        fft_stages_from<F, S, STAGE + 1, L, NF>(v, t, line, lds, tw);
     }
 }
 
 // Full transform of NF lines (one per field) owned by this thread group. On entry and
-// on exit thread t holds element t + T m in v[f][m]. S = -1 forward, +1 inverse.
-// All threads of the block must call this together (it contains barriers).
-template <int N, int S, class L, int NF>
-__device__ __forceinline__ void fft_line(c32 (&v)[NF][FFTShape<N>::R], int t, int line, c32* lds,
+// on exit thread t holds element t + T m in v[f][m]. S = -1 forward, +1 inverse. F is the
+// FFTShape (length and values per thread). All threads of the block must call this
+// together (it contains barriers).
+template <class F, int S, class L, int NF>
+__device__ __forceinline__ void fft_line(c32 (&v)[NF][F::R], int t, int line, c32* lds,
                                          const c32* __restrict__ tw) {
-    fft_stages_from<N, S, 0, L, NF>(v, t, line, lds, tw);
+    fft_stages_from<F, S, 0, L, NF>(v, t, line, lds, tw);
 #pragma unroll
-    for (int f = 0; f < NF; f++) fft_natural_order<N>(v[f]);
+    for (int f = 0; f < NF; f++) fft_natural_order<F>(v[f]);
 }
 
 }  // namespace rk4ip

@@ -45,7 +45,7 @@ __global__ void __launch_bounds__(FFTShape<N>::T* LPB)
         f[0][m] = active ? psi_n[base + t + m * T] : zero;
         f[1][m] = hG(g, f[0][m], V_at(m), nz_at(m));
     }
-    propagate<N, L, 2>(f, t, l, lds, tw, E, false);
+    propagate<F, L, 2>(f, t, l, lds, tw, E, false);
     // w = D(a + k3): keep (a, k1) in f, the transform of u in w[0]
     c32 w[1][R];
 #pragma unroll
@@ -57,7 +57,7 @@ __global__ void __launch_bounds__(FFTShape<N>::T* LPB)
         const c32 k3 = hG(g, make_float2(fmaf(0.5f, k2.x, a.x), fmaf(0.5f, k2.y, a.y)), V, nz);
         w[0][m] = cadd(a, k3);
     }
-    propagate<N, L, 1>(w, t, l, lds, tw, E, false);
+    propagate<F, L, 1>(w, t, l, lds, tw, E, false);
     // adjoint: (lam, wbar) -> D^T -> (accbar, ubar)
     c32 b[2][R];
     float vacc[R];
@@ -69,7 +69,7 @@ __global__ void __launch_bounds__(FFTShape<N>::T* LPB)
         b[1][m] = hJT(g, w[0][m], V_at(m), k4b);
         vacc[m] = hImconj(g, k4b, w[0][m]);
     }
-    propagate<N, L, 2>(b, t, l, lds, tw, E, true);
+    propagate<F, L, 2>(b, t, l, lds, tw, E, true);
 #pragma unroll
     for (int m = 0; m < R; m++) {
         const float V = V_at(m);
@@ -88,7 +88,7 @@ __global__ void __launch_bounds__(FFTShape<N>::T* LPB)
         b[0][m] = make_float2(accb.x + ub.x + p3b.x + p2b.x, accb.y + ub.y + p3b.y + p2b.y);
         b[1][m] = k1b;
     }
-    propagate<N, L, 2>(b, t, l, lds, tw, E, true);
+    propagate<F, L, 2>(b, t, l, lds, tw, E, true);
     if (!active) return;
 #pragma unroll
     for (int m = 0; m < R; m++) {

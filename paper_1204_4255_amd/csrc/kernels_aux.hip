@@ -43,9 +43,9 @@ __global__ void __launch_bounds__(FFTShape<N>::T* LINES)
 #pragma unroll
     for (int m = 0; m < F::R; m++) v[0][m] = active ? in[line * N + t + m * F::T] : make_float2(0.f, 0.f);
     if (sign < 0)
-        fft_line<N, -1, L, 1>(v, t, l, lds, tw);
+        fft_line<F, -1, L, 1>(v, t, l, lds, tw);
     else
-        fft_line<N, +1, L, 1>(v, t, l, lds, tw);
+        fft_line<F, +1, L, 1>(v, t, l, lds, tw);
     if (active) {
 #pragma unroll
         for (int m = 0; m < F::R; m++) out[line * N + t + m * F::T] = v[0][m];
@@ -69,7 +69,7 @@ __global__ void __launch_bounds__(FFTShape<N>::T* LINES)
     stage_tables<N>(tw, nullptr, g.tw[axis], nullptr);
     const int t = CONTIG ? (int)(threadIdx.x % T) : (int)(threadIdx.x / LINES);
     const int l = CONTIG ? (int)(threadIdx.x / T) : (int)(threadIdx.x % LINES);
-    const Tile<N, CONTIG, LINES> tile(g, axis, l, t);
+    const Tile<F, CONTIG, LINES> tile(g, axis, l, t);
     const float2* ps = psi + g.offset + tile.base;
     c32 f[1][R];
     double s1 = 0.0, s2 = 0.0, s3 = 0.0;
@@ -89,7 +89,7 @@ __global__ void __launch_bounds__(FFTShape<N>::T* LINES)
         }
     }
     __syncthreads();  // twiddles staged
-    fft_line<N, -1, L, 1>(f, t, l, lds, tw);
+    fft_line<F, -1, L, 1>(f, t, l, lds, tw);
     double s0 = 0.0;
 #pragma unroll
     for (int m = 0; m < R; m++) {

@@ -1,5 +1,5 @@
-// kernels_fwd.hip -- forward-step kernels: the per-axis passes (D1, D2, FIRST, LAST1,
-// LAST2) and the 1D whole-line step. See pass_common.h for the data flow of a step.
+// kernels_fwd.hip -- the 1D whole-line step kernel and the dispatch of the per-axis
+// passes (compiled in kernels_pass_*.hip). See pass_common.h for the data flow of a step.
 #include "pass_common.h"
 
 namespace rk4ip {
@@ -52,7 +52,7 @@ __global__ void __launch_bounds__(FFTShape<N>::T* LPB)
         // first pair: D psi and D[h G(psi)]
 #pragma unroll
         for (int m = 0; m < R; m++) f[1][m] = hG(g, f[0][m], V[m], nz[m]);
-        propagate<N, L, 2>(f, t, l, lds, tw, E, false);
+        propagate<F, L, 2>(f, t, l, lds, tw, E, false);
         // stages at the midpoint picture
 #pragma unroll
         for (int m = 0; m < R; m++) {
@@ -65,7 +65,7 @@ __global__ void __launch_bounds__(FFTShape<N>::T* LPB)
             f[1][m] = make_float2(a.x + sx, a.y + sy);
         }
         // second pair: D u and D acc
-        propagate<N, L, 2>(f, t, l, lds, tw, E, false);
+        propagate<F, L, 2>(f, t, l, lds, tw, E, false);
 #pragma unroll
         for (int m = 0; m < R; m++) {
             const c32 k4 = hG(g, f[0][m], V[m], nz[m]);
@@ -82,29 +82,30 @@ __global__ void __launch_bounds__(FFTShape<N>::T* LPB)
 
 int axis_lines(int N, int axis, int n0) { return axis == 0 ? contig_lines(N) : strided_lines(N, n0); }
 
-bool axis_schedule_ok(int N, int mode, int axis, int n0, int lines, int seq) {
+bool axis_schedule_ok(int N, int mode, int axis, int n0, int lines, int seq, int radix) {
     const bool contig = axis == 0;
     if (!contig && lines > n0) return false;
     switch (N) {
-        case 8: return schedule_ok_n<8>(mode, contig, lines, seq);
-        case 16: return schedule_ok_n<16>(mode, contig, lines, seq);
-        case 32: return schedule_ok_n<32>(mode, contig, lines, seq);
-        case 64: return schedule_ok_n<64>(mode, contig, lines, seq);
-        case 128: return schedule_ok_n<128>(mode, contig, lines, seq);
-        case 256: return schedule_ok_n<256>(mode, contig, lines, seq);
-        case 512: return schedule_ok_n<512>(mode, contig, lines, seq);
-        case 1024: return schedule_ok_n<1024>(mode, contig, lines, seq);
+        case 8: return schedule_ok_n<8>(mode, contig, lines, seq, radix);
+        case 16: return schedule_ok_n<16>(mode, contig, lines, seq, radix);
+        case 32: return schedule_ok_n<32>(mode, contig, lines, seq, radix);
+        case 64: return schedule_ok_n<64>(mode, contig, lines, seq, radix);
+        case 128: return schedule_ok_n<128>(mode, contig, lines, seq, radix);
+        case 256: return schedule_ok_n<256>(mode, contig, lines, seq, radix);
+        case 512: return schedule_ok_n<512>(mode, contig, lines, seq, radix);
+        case 1024: return schedule_ok_n<1024>(mode, contig, lines, seq, radix);
         default: return false;
     }
 }
 
 hipError_t launch_axis(const GroupDev& g, int axis, int mode, const PassArgs& a, hipStream_t s) {
     switch (mode) {
-        case PASS_D1: return go_axis_mode<PASS_D1>(g, axis, a, s);
-        case PASS_D2: return go_axis_mode<PASS_D2>(g, axis, a, s);
-        case PASS_FIRST: return go_axis_mode<PASS_FIRST>(g, axis, a, s);
-        case PASS_LAST1: return go_axis_mode<PASS_LAST1>(g, axis, a, s);
-        case PASS_LAST2: return go_axis_mode<PASS_LAST2>(g, axis, a, s);
+        case PASS_D1:
+        case PASS_D2: return launch_axis_d(g, axis, mode, a, s);
+        case PASS_FIRST:
+        case PASS_LAST2: return launch_axis_first(g, axis, mode, a, s);
+        case PASS_LF: return launch_axis_last(g, axis, mode, a, s);
+        case PASS_XF: return launch_axis_xf(g, axis, a, s);
         case PASS_U:
         case PASS_AW:
         case PASS_AS:

@@ -7,18 +7,19 @@ namespace rk4ip {
 
 struct GroupDev;
 
-// Kinds of axis pass (see kernels.hip for the data flow of each). The first five make
-// the forward step; U, AW, AS and AF are the extra passes of the adjoint step.
+// Kinds of axis pass (see pass_common.h for the data flow of each). FIRST, D2, LF, XF and
+// LAST2 make the forward step; U, AW, AS and AF are the extra passes of the adjoint step.
 enum PassMode {
     PASS_D1 = 0,
     PASS_D2 = 1,
     PASS_FIRST = 2,
-    PASS_LAST1 = 3,
     PASS_LAST2 = 4,
     PASS_U = 5,
     PASS_AW = 6,
     PASS_AS = 7,
-    PASS_AF = 8
+    PASS_AF = 8,
+    PASS_LF = 9,   // last axis: D, the RK4 stage epilogue, D again
+    PASS_XF = 10   // axis 0: D, the end of one step, the start of the next, D again
 };
 
 // Pointers of one pass; every field pointer addresses the concatenated field of all
@@ -33,7 +34,9 @@ struct PassArgs {
     int adj;                  // apply the transpose of D
     int lines;                // tile schedule: lines (contiguous axis) or columns (strided) per
                               // workgroup, 0 = default
-    int seq;                  // 1: transform the two fields one after the other (half the LDS)
+    int seq;                  // 0: fields transformed together; 1: one after the other (half the
+                              // LDS); 2: as 1 with the second field loaded after the first
+    int radix;                // values per thread in the transform: 16 (0 = default) or 8
     int64_t step_off;
     const int64_t* step_base; // step = step_off (+ *step_base when not null)
 };
@@ -47,10 +50,14 @@ struct DiagConst {
 
 int axis_lines(int N, int axis, int n0);
 // Whether a (lines, seq) schedule of a pass is compiled for this length and axis.
-bool axis_schedule_ok(int N, int mode, int axis, int n0, int lines, int seq);
+bool axis_schedule_ok(int N, int mode, int axis, int n0, int lines, int seq, int radix);
 
 hipError_t launch_axis(const GroupDev& g, int axis, int mode, const PassArgs& a, hipStream_t s);
 hipError_t launch_axis_adjoint(const GroupDev& g, int axis, int mode, const PassArgs& a, hipStream_t s);
+hipError_t launch_axis_d(const GroupDev& g, int axis, int mode, const PassArgs& a, hipStream_t s);
+hipError_t launch_axis_first(const GroupDev& g, int axis, int mode, const PassArgs& a, hipStream_t s);
+hipError_t launch_axis_xf(const GroupDev& g, int axis, const PassArgs& a, hipStream_t s);
+hipError_t launch_axis_last(const GroupDev& g, int axis, int mode, const PassArgs& a, hipStream_t s);
 hipError_t launch_line_adjoint(const GroupDev& g, const float2* psi_n, float2* lam, double* vbar, int64_t step,
                                hipStream_t s);
 hipError_t launch_vbar_to_float(const double* vbar, float* out, int64_t n, hipStream_t s);

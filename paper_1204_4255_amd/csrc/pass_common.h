@@ -7,14 +7,19 @@
 //   k4 = h G(D(a + k3)),   psi' = D(a + k1/6 + k2/3 + k3/3) + k4/6,
 // with D = e^{L h/2} applied per lattice axis (Sec. 3.2 factorisation): FFT along the
 // axis, multiply by e^{L_a h/2}, inverse FFT. The four D applications come in two pairs
-// of two fields, so on a 2D/3D lattice a step is two sweeps over the axes, each pass
-// reading and writing two complex64 fields once:
-//   FIRST (axis 0):   psi            -> (psi, hG(psi)) -> D_0 -> (A, B)
-//   D2    (middle):   (A, B)         -> D_a            -> (A, B)
-//   LAST1 (last axis):(A, B)         -> D_a -> a, k1; k2, k3; u = a + k3,
-//                                        acc = a + k1/6 + k2/3 + k3/3 -> (A, B) = (u, acc)
-//   D2    (axis 0, middle axes)
-//   LAST2 (last axis):(A, B)         -> D_a -> psi' = D acc + hG(D u)/6 -> psi
+// of two fields. D commutes across axes, so the second pair can sweep the axes in the
+// reverse order of the first; then the two passes on the last axis and the two on axis 0
+// (the end of one step and the start of the next) each fuse into one pass. On a 2D/3D
+// lattice every pass reads and writes two complex64 fields once:
+//   FIRST (axis 0):  psi    -> (psi, hG(psi)) -> D_0 -> (A, B)         opens a run of steps
+//   D2    (middle):  (A, B) -> D_a -> (A, B)
+//   LF    (last):    (A, B) -> D_a -> (a, k1); k2, k3; u = a + k3,
+//                              acc = a + k1/6 + k2/3 + k3/3 -> D_a -> (A, B)
+//   D2    (middle, second sweep)
+//   XF    (axis 0):  (A, B) -> D_0 -> psi' = D acc + hG(D u)/6; (psi', hG(psi')) -> D_0 -> (A, B)
+//   LAST2 (axis 0):  (A, B) -> D_0 -> psi' -> psi                      closes the run
+// The noise of a step is drawn wherever that step evaluates G (XF draws step n-1's for k4
+// and step n's for the next start).
 // A 1D line fits one workgroup, so the whole step (eight transforms) runs in registers
 // and LDS with one read and one write of psi (k_line_step), optionally for several
 // steps per launch.
@@ -44,16 +49,15 @@ __device__ __forceinline__ void stage_tables(c32* s_tw, float2* s_E, const float
 // D_a on NF lines held in registers, in delta form: f <- f + F^{-1}[(E_a - 1)/n F f]
 // (adj: the transpose, with the conjugate multiplier). tw and E point to LDS copies of
 // the tables. All threads of the block call it.
-template <int N, class L, int NF>
-__device__ __forceinline__ void propagate(c32 (&f)[NF][FFTShape<N>::R], int t, int l, c32* lds,
-                                          const c32* tw, const float2* E, bool adj) {
-    using F = FFTShape<N>;
+template <class F, class L, int NF>
+__device__ __forceinline__ void propagate(c32 (&f)[NF][F::R], int t, int l, c32* lds, const c32* tw,
+                                          const float2* E, bool adj) {
     c32 o[NF][F::R];
 #pragma unroll
     for (int q = 0; q < NF; q++)
 #pragma unroll
         for (int m = 0; m < F::R; m++) o[q][m] = f[q][m];
-    fft_line<N, -1, L, NF>(f, t, l, lds, tw);
+    fft_line<F, -1, L, NF>(f, t, l, lds, tw);
 #pragma unroll
     for (int m = 0; m < F::R; m++) {
         float2 cs = E[t + m * F::T];
@@ -61,7 +65,7 @@ __device__ __forceinline__ void propagate(c32 (&f)[NF][FFTShape<N>::R], int t, i
 #pragma unroll
         for (int q = 0; q < NF; q++) f[q][m] = cmul(f[q][m], cs);
     }
-    fft_line<N, +1, L, NF>(f, t, l, lds, tw);
+    fft_line<F, +1, L, NF>(f, t, l, lds, tw);
 #pragma unroll
     for (int q = 0; q < NF; q++)
 #pragma unroll
@@ -74,8 +78,9 @@ __device__ __forceinline__ void propagate(c32 (&f)[NF][FFTShape<N>::R], int t, i
 // (adjacent lanes hold adjacent columns, so each row segment is one coalesced access).
 // Addresses are a workgroup-uniform 64-bit tile base plus 32-bit per-thread offsets,
 // shared by every field the pass touches.
-template <int N, bool CONTIG, int LINES>
+template <class F, bool CONTIG, int LINES>
 struct Tile {
+    static constexpr int N = F::NN;
     int64_t base;      // uniform: group-relative point index of the tile origin
     uint32_t off0;     // this thread's element 0 relative to base
     uint32_t dstep;    // offset between element t + m T and t + (m+1) T
@@ -85,7 +90,7 @@ struct Tile {
     bool active;
 
     __device__ __forceinline__ Tile(const GroupDev& g, int axis, int l, int t) {
-        constexpr int T = FFTShape<N>::T;
+        constexpr int T = F::T;
         if constexpr (CONTIG) {
             const int64_t lines_per_inst = g.M >> g.log2n[0];
             const int64_t nlines = g.batch * lines_per_inst;
@@ -120,7 +125,7 @@ struct Tile {
     __device__ __forceinline__ uint32_t off(int m) const { return off0 + (uint32_t)m * dstep; }
     // byte offset of element t + m T for a field of float2 (the tile spans < 4 GiB)
     __device__ __forceinline__ uint32_t b8(int m) const { return (off0 + (uint32_t)m * dstep) * 8u; }
-    __device__ __forceinline__ int64_t j(int m) const { return jbase + (int64_t)((uint32_t)m * (uint32_t)FFTShape<N>::T * jstride); }
+    __device__ __forceinline__ int64_t j(int m) const { return jbase + (int64_t)((uint32_t)m * (uint32_t)F::T * jstride); }
 };
 
 // Access at a 32-bit byte offset from a workgroup-uniform base: lets the compiler use the
@@ -147,21 +152,32 @@ __device__ __forceinline__ void unflatten(const GroupDev& g, int64_t j, int& x, 
 
 constexpr int fields_of(int mode) { return (mode == PASS_D1 || mode == PASS_U) ? 1 : 2; }
 
-// SEQ: the two fields share one exchange buffer and go through the transform one after
-// the other (lower LDS and register peak, twice the barriers).
-template <int N, int MODE, bool CONTIG, int LINES, bool NOISE, bool SEQ>
-__global__ void __launch_bounds__(FFTShape<N>::T* LINES) k_axis(GroupDev g, int axis, PassArgs args) {
-    using F = FFTShape<N>;
+// passes whose pointwise work evaluates G (and so may draw noise)
+constexpr bool uses_rhs(int mode) {
+    return mode == PASS_FIRST || mode == PASS_LAST2 || mode == PASS_U || mode == PASS_AS ||
+           mode == PASS_LF || mode == PASS_XF;
+}
+
+// SEQ = 0: both fields go through the transform together (one exchange buffer each).
+// SEQ = 1: they share one buffer and go through one after the other (half the LDS, a
+//          lower register peak, twice the barriers).
+// SEQ = 2: as 1, and the second field is only loaded once the first is transformed
+//          (lowest register peak, fewer loads in flight per wave).
+// RR: values per thread in the transform (16, or 8 for half the registers and one more
+// LDS exchange per transform).
+template <int N, int MODE, bool CONTIG, int LINES, bool NOISE, int SEQ, int RR>
+__global__ void __launch_bounds__((FFTShape<N, RR>::T * LINES)) k_axis(GroupDev g, int axis, PassArgs args) {
+    using F = FFTShape<N, RR>;
     constexpr int R = F::R, T = F::T;
     constexpr int NF = fields_of(MODE);
     using L = LdsLayout<N, LINES, CONTIG>;
-    __shared__ c32 lds[(SEQ ? 1 : NF) * L::SIZE];
+    __shared__ c32 lds[(SEQ != 0 ? 1 : NF) * L::SIZE];
     __shared__ c32 tw[N];
     __shared__ float2 E[N];
     stage_tables<N>(tw, E, g.tw[axis], g.E[axis]);
     const int t = CONTIG ? (int)(threadIdx.x % T) : (int)(threadIdx.x / LINES);
     const int l = CONTIG ? (int)(threadIdx.x / T) : (int)(threadIdx.x % LINES);
-    const Tile<N, CONTIG, LINES> tile(g, axis, l, t);
+    const Tile<F, CONTIG, LINES> tile(g, axis, l, t);
     const int64_t o = g.offset + tile.base;
     float2* __restrict__ ps = args.psi ? args.psi + o : nullptr;
     float2* __restrict__ pa = args.A ? args.A + o : nullptr;
@@ -169,30 +185,52 @@ __global__ void __launch_bounds__(FFTShape<N>::T* LINES) k_axis(GroupDev g, int 
     const float2* __restrict__ x0 = args.aux0 ? args.aux0 + o : nullptr;
     const float2* __restrict__ x1 = args.aux1 ? args.aux1 + o : nullptr;
     double* __restrict__ vb = args.vbar ? args.vbar + o : nullptr;
-    constexpr bool NEEDS_STEP = (MODE == PASS_FIRST || MODE == PASS_LAST1 || MODE == PASS_LAST2 ||
-                                 MODE == PASS_U || MODE == PASS_AS);
+    constexpr bool NEEDS_STEP = uses_rhs(MODE);
     const int64_t step = NEEDS_STEP ? read_step(args.step_off, args.step_base) : 0;
     const uint32_t iid = g.id_base + (uint32_t)tile.inst;
     const float* __restrict__ Vg = g.Vgrid ? g.Vgrid + tile.inst * g.M : nullptr;
 
-    // pointwise inputs of the right-hand side at element t + m T of this thread's line
-    auto potential_at = [&](int m) {
-        const int64_t j = tile.j(m);
+    // The trap potential along the line: the other axes' part once per thread, the
+    // axis's own term per element.
+    float V_other = 0.0f;
+    {
         int x, y, z;
-        unflatten(g, j, x, y, z);
-        float V = trap_V(g, x, y, z);
-        if (Vg) V += Vg[j];
+        unflatten(g, tile.j(0), x, y, z);
+        const int c[3] = {x, y, z};
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            if (a == axis || a >= g.ndim) continue;
+            const float xa = fmaf((float)c[a], g.dx[a], g.lo[a]);
+            V_other = fmaf(g.half_trap[a] * xa, xa, V_other);
+        }
+    }
+    const float ht_axis = g.half_trap[axis], lo_axis = g.lo[axis], dx_axis = g.dx[axis];
+    auto potential_at = [&](int m) {
+        const float xa = fmaf((float)(t + m * T), dx_axis, lo_axis);
+        float V = fmaf(ht_axis * xa, xa, V_other);
+        if (Vg) V += Vg[tile.j(m)];
         return V;
     };
-    auto noise_at = [&](int m) {
+    auto noise_at = [&](int m, int64_t st) {
         if constexpr (!NOISE) {
             return make_float2(0.f, 0.f);
         } else {
-            const float2 zz = noise_z(g, tile.j(m), iid, step);
+            const float2 zz = noise_z(g, tile.j(m), iid, st);
             return make_float2(g.noise_c * zz.x, g.noise_c * zz.y);
         }
     };
     const c32 zero = make_float2(0.f, 0.f);
+
+    // RK4 stages at the midpoint picture: (a, k1) -> (u, acc) in place
+    auto stages = [&](c32& f0, c32& f1, float V, c32 nz) {
+        const c32 a = f0, k1 = f1;
+        const c32 k2 = hG(g, make_float2(fmaf(0.5f, k1.x, a.x), fmaf(0.5f, k1.y, a.y)), V, nz);
+        const c32 k3 = hG(g, make_float2(fmaf(0.5f, k2.x, a.x), fmaf(0.5f, k2.y, a.y)), V, nz);
+        const float sx = k1.x * (1.0f / 6.0f) + (k2.x + k3.x) * (1.0f / 3.0f);
+        const float sy = k1.y * (1.0f / 6.0f) + (k2.y + k3.y) * (1.0f / 3.0f);
+        f0 = cadd(a, k3);
+        f1 = make_float2(a.x + sx, a.y + sy);
+    };
 
     c32 f[NF][R];
     if constexpr (MODE == PASS_D1 || MODE == PASS_FIRST) {
@@ -200,19 +238,16 @@ __global__ void __launch_bounds__(FFTShape<N>::T* LINES) k_axis(GroupDev g, int 
         for (int m = 0; m < R; m++) f[0][m] = tile.active ? ld2(ps, tile.b8(m)) : zero;
         if constexpr (MODE == PASS_FIRST) {
 #pragma unroll
-            for (int m = 0; m < R; m++) f[1][m] = hG(g, f[0][m], potential_at(m), noise_at(m));
+            for (int m = 0; m < R; m++) f[1][m] = hG(g, f[0][m], potential_at(m), noise_at(m, step));
         }
     } else if constexpr (MODE == PASS_U) {
         // u = a + k3 from (a, k1)
 #pragma unroll
         for (int m = 0; m < R; m++) {
-            const c32 a = tile.active ? ld2(x0, tile.b8(m)) : zero;
-            const c32 k1 = tile.active ? ld2(x1, tile.b8(m)) : zero;
-            const float V = potential_at(m);
-            const c32 nz = noise_at(m);
-            const c32 k2 = hG(g, make_float2(fmaf(0.5f, k1.x, a.x), fmaf(0.5f, k1.y, a.y)), V, nz);
-            const c32 k3 = hG(g, make_float2(fmaf(0.5f, k2.x, a.x), fmaf(0.5f, k2.y, a.y)), V, nz);
-            f[0][m] = cadd(a, k3);
+            c32 a = tile.active ? ld2(x0, tile.b8(m)) : zero;
+            c32 k1 = tile.active ? ld2(x1, tile.b8(m)) : zero;
+            stages(a, k1, potential_at(m), noise_at(m, step));
+            f[0][m] = a;
         }
     } else if constexpr (MODE == PASS_AW) {
         // adjoint of psi' = D acc + k4/6, k4 = h G(w): (lam, wbar = h J(w)^T lam/6)
@@ -227,43 +262,63 @@ __global__ void __launch_bounds__(FFTShape<N>::T* LINES) k_axis(GroupDev g, int 
         }
     } else {
 #pragma unroll
-        for (int m = 0; m < R; m++) {
-            f[0][m] = tile.active ? ld2(pa, tile.b8(m)) : zero;
-            f[1][m] = tile.active ? ld2(pb, tile.b8(m)) : zero;
+        for (int m = 0; m < R; m++) f[0][m] = tile.active ? ld2(pa, tile.b8(m)) : zero;
+        if constexpr (SEQ != 2) {
+#pragma unroll
+            for (int m = 0; m < R; m++) f[1][m] = tile.active ? ld2(pb, tile.b8(m)) : zero;
         }
     }
 
+    // D_axis on the registers (the first time in a pass, the second field may still have
+    // to be loaded: SEQ == 2)
+    auto transform = [&](bool first) {
+        if constexpr (SEQ != 0 && NF == 2) {
+            c32(&f0)[1][R] = *reinterpret_cast<c32(*)[1][R]>(&f[0]);
+            c32(&f1)[1][R] = *reinterpret_cast<c32(*)[1][R]>(&f[1]);
+            propagate<F, L, 1>(f0, t, l, lds, tw, E, args.adj != 0);
+            if constexpr (SEQ == 2) {
+                if (first) {
+#pragma unroll
+                    for (int m = 0; m < R; m++) f[1][m] = tile.active ? ld2(pb, tile.b8(m)) : zero;
+                }
+            }
+            propagate<F, L, 1>(f1, t, l, lds, tw, E, args.adj != 0);
+        } else {
+            propagate<F, L, NF>(f, t, l, lds, tw, E, args.adj != 0);
+        }
+    };
+
     __syncthreads();  // tables staged (the loads above overlap the copy)
-    if constexpr (SEQ && NF == 2) {
-        c32(&f0)[1][R] = *reinterpret_cast<c32(*)[1][R]>(&f[0]);
-        c32(&f1)[1][R] = *reinterpret_cast<c32(*)[1][R]>(&f[1]);
-        propagate<N, L, 1>(f0, t, l, lds, tw, E, args.adj != 0);
-        propagate<N, L, 1>(f1, t, l, lds, tw, E, args.adj != 0);
-    } else {
-        propagate<N, L, NF>(f, t, l, lds, tw, E, args.adj != 0);
+    transform(true);
+
+    if constexpr (MODE == PASS_LF || MODE == PASS_XF) {
+        // the work between the two transforms of a fused pass (every thread takes part in
+        // the second transform's barriers, active or not)
+#pragma unroll
+        for (int m = 0; m < R; m++) {
+            const float V = potential_at(m);
+            if constexpr (MODE == PASS_LF) {
+                stages(f[0][m], f[1][m], V, noise_at(m, step));
+            } else {
+                // end of step n-1: psi_n = D acc + hG(D u)/6, then the start of step n:
+                // (psi_n, h G(psi_n))
+                const c32 k4 = hG(g, f[0][m], V, noise_at(m, step - 1));
+                const c32 psi_n = make_float2(fmaf(k4.x, 1.0f / 6.0f, f[1][m].x), fmaf(k4.y, 1.0f / 6.0f, f[1][m].y));
+                f[0][m] = psi_n;
+                f[1][m] = hG(g, psi_n, V, noise_at(m, step));
+            }
+        }
+        transform(false);
     }
 
     if (!tile.active) return;  // after the last barrier
     if constexpr (MODE == PASS_D1 || MODE == PASS_U) {
 #pragma unroll
         for (int m = 0; m < R; m++) st2(ps, tile.b8(m), f[0][m]);
-    } else if constexpr (MODE == PASS_LAST1) {
-#pragma unroll
-        for (int m = 0; m < R; m++) {
-            const float V = potential_at(m);
-            const c32 nz = noise_at(m);
-            const c32 a = f[0][m], k1 = f[1][m];
-            const c32 k2 = hG(g, make_float2(fmaf(0.5f, k1.x, a.x), fmaf(0.5f, k1.y, a.y)), V, nz);
-            const c32 k3 = hG(g, make_float2(fmaf(0.5f, k2.x, a.x), fmaf(0.5f, k2.y, a.y)), V, nz);
-            const float sx = k1.x * (1.0f / 6.0f) + (k2.x + k3.x) * (1.0f / 3.0f);
-            const float sy = k1.y * (1.0f / 6.0f) + (k2.y + k3.y) * (1.0f / 3.0f);
-            st2(pa, tile.b8(m), cadd(a, k3));
-            st2(pb, tile.b8(m), make_float2(a.x + sx, a.y + sy));
-        }
     } else if constexpr (MODE == PASS_LAST2) {
 #pragma unroll
         for (int m = 0; m < R; m++) {
-            const c32 k4 = hG(g, f[0][m], potential_at(m), noise_at(m));
+            const c32 k4 = hG(g, f[0][m], potential_at(m), noise_at(m, step));
             st2(ps, tile.b8(m), make_float2(fmaf(k4.x, 1.0f / 6.0f, f[1][m].x), fmaf(k4.y, 1.0f / 6.0f, f[1][m].y)));
         }
     } else if constexpr (MODE == PASS_AS) {
@@ -271,7 +326,7 @@ __global__ void __launch_bounds__(FFTShape<N>::T* LINES) k_axis(GroupDev g, int 
 #pragma unroll
         for (int m = 0; m < R; m++) {
             const float V = potential_at(m);
-            const c32 nz = noise_at(m);
+            const c32 nz = noise_at(m, step);
             const c32 a = ld2(x0, tile.b8(m)), k1 = ld2(x1, tile.b8(m));
             const c32 p2 = make_float2(fmaf(0.5f, k1.x, a.x), fmaf(0.5f, k1.y, a.y));
             const c32 k2 = hG(g, p2, V, nz);
@@ -297,7 +352,7 @@ __global__ void __launch_bounds__(FFTShape<N>::T* LINES) k_axis(GroupDev g, int 
             if (vb) std_(vb, tile.b8(m), ldd(vb, tile.b8(m)) + (double)hImconj(g, g0b, pn));
             st2(ps, tile.b8(m), cadd(f[0][m], r));
         }
-    } else {  // FIRST, D2, AW
+    } else {  // FIRST, D2, AW, LF, XF
 #pragma unroll
         for (int m = 0; m < R; m++) {
             st2(pa, tile.b8(m), f[0][m]);
@@ -321,68 +376,87 @@ static inline int contig_lines(int N) {
 }
 
 
-// passes whose pointwise work evaluates G (and so may draw noise)
-constexpr bool uses_rhs(int mode) {
-    return mode == PASS_FIRST || mode == PASS_LAST1 || mode == PASS_LAST2 || mode == PASS_U || mode == PASS_AS;
-}
 
-template <int N, int MODE, bool CONTIG, int LINES, bool SEQ>
+template <int N, int MODE, bool CONTIG, int LINES, int SEQ, int RR>
 static hipError_t go_axis(const GroupDev& g, int axis, const PassArgs& a, hipStream_t s) {
     int64_t blocks;
     if (CONTIG)
         blocks = (g.batch * (g.M >> g.log2n[0]) + LINES - 1) / LINES;
     else
         blocks = g.batch * (g.M >> g.log2n[axis]) / LINES;
-    const dim3 grid((unsigned)blocks), block(FFTShape<N>::T * LINES);
+    const dim3 grid((unsigned)blocks), block(FFTShape<N, RR>::T * LINES);
     if constexpr (uses_rhs(MODE)) {
         if (g.has_noise) {
-            hipLaunchKernelGGL((k_axis<N, MODE, CONTIG, LINES, true, SEQ>), grid, block, 0, s, g, axis, a);
+            hipLaunchKernelGGL((k_axis<N, MODE, CONTIG, LINES, true, SEQ, RR>), grid, block, 0, s, g, axis, a);
             return hipGetLastError();
         }
     }
-    hipLaunchKernelGGL((k_axis<N, MODE, CONTIG, LINES, false, SEQ>), grid, block, 0, s, g, axis, a);
+    hipLaunchKernelGGL((k_axis<N, MODE, CONTIG, LINES, false, SEQ, RR>), grid, block, 0, s, g, axis, a);
     return hipGetLastError();
 }
 
 // passes that run only on axis 0 / only on the last (strided) axis
-constexpr bool contig_only(int mode) { return mode == PASS_FIRST || mode == PASS_U || mode == PASS_AW; }
+constexpr bool contig_only(int mode) {
+    return mode == PASS_FIRST || mode == PASS_U || mode == PASS_AW || mode == PASS_XF || mode == PASS_LAST2;
+}
 constexpr bool strided_only(int mode) {
-    return mode == PASS_LAST1 || mode == PASS_LAST2 || mode == PASS_AS || mode == PASS_AF;
+    return mode == PASS_AS || mode == PASS_AF || mode == PASS_LF;
 }
 // lengths with more than the default schedule compiled (the ones the workloads use)
 constexpr bool tuned_length(int N) { return N >= 128 && N <= 512; }
 // forward-step passes get the schedule variants; the adjoint passes use the default
-constexpr bool tuned_mode(int mode) { return mode <= PASS_LAST2; }
+constexpr bool tuned_mode(int mode) { return mode <= PASS_LAST2 || mode == PASS_LF || mode == PASS_XF; }
+// passes that read both fields of the pair from memory
+constexpr bool loads_two_fields(int mode) {
+    return mode == PASS_D2 || mode == PASS_LAST2 || mode == PASS_AS || mode == PASS_AF ||
+           mode == PASS_LF || mode == PASS_XF;
+}
 
 constexpr int default_contig_lines(int N) { return N < 16 ? 256 : ((256 / (N / 16)) < 1 ? 1 : 256 / (N / 16)); }
 
-// Is schedule (lines, seq) of pass MODE compiled for length N on the contiguous or a
-// strided axis? Mirrors the instantiations in go_axis_n.
+// Is schedule (lines, seq, rr) of pass MODE compiled for length N on the contiguous or a
+// strided axis? Mirrors the instantiations in go_axis_n. rr = values per thread.
 template <int N, int MODE>
-constexpr bool schedule_compiled(bool contig, int lines, int seq) {
-    constexpr int T = FFTShape<N>::T;
+constexpr bool schedule_compiled(bool contig, int lines, int seq, int rr) {
     constexpr int NF = fields_of(MODE);
-    if (seq && (NF != 2 || !tuned_length(N) || !tuned_mode(MODE))) return false;
+    const bool tuned = tuned_length(N) && tuned_mode(MODE);
+    if (rr != 16 && !(rr == 8 && tuned)) return false;
+    const int T = N / (N < rr ? N : rr);
+    if (seq < 0 || seq > 2) return false;
+    if (seq && (NF != 2 || !tuned)) return false;
+    if (seq == 2 && !loads_two_fields(MODE)) return false;
     const int nf = seq ? 1 : NF;
     if (contig) {
-        const int dl = default_contig_lines(N);
-        if (lines == dl) return true;
-        return tuned_length(N) && tuned_mode(MODE) && lines == dl / 2 && lines >= 1;
+        const int dl = default_contig_lines(N);  // 256 threads with 16 values per thread
+        if (rr == 16 && lines == dl) return true;
+        if (!tuned) return false;
+        if (rr == 16) return lines == dl / 2 && lines >= 1;
+        return (lines == dl || lines == dl / 2) && lines >= 1 && T * lines <= 1024;
     }
     if (lines != 4 && lines != 8 && lines != 16 && lines != 32) return false;
     if (T * lines > 1024 || !fits_lds(N, lines, nf)) return false;
-    if (lines == 32 && !(tuned_length(N) && tuned_mode(MODE))) return false;
+    if (lines == 32 && !tuned) return false;
     return true;
+}
+
+template <int N, int MODE, bool CONTIG, int LINES, int RR>
+static hipError_t go_axis_sched_rr(const GroupDev& g, int axis, const PassArgs& a, hipStream_t s) {
+    if constexpr (schedule_compiled<N, MODE>(CONTIG, LINES, 2, RR)) {
+        if (a.seq == 2) return go_axis<N, MODE, CONTIG, LINES, 2, RR>(g, axis, a, s);
+    }
+    if constexpr (schedule_compiled<N, MODE>(CONTIG, LINES, 1, RR)) {
+        if (a.seq == 1) return go_axis<N, MODE, CONTIG, LINES, 1, RR>(g, axis, a, s);
+    }
+    if constexpr (schedule_compiled<N, MODE>(CONTIG, LINES, 0, RR)) {
+        if (a.seq == 0) return go_axis<N, MODE, CONTIG, LINES, 0, RR>(g, axis, a, s);
+    }
+    return hipErrorInvalidValue;
 }
 
 template <int N, int MODE, bool CONTIG, int LINES>
 static hipError_t go_axis_sched(const GroupDev& g, int axis, const PassArgs& a, hipStream_t s) {
-    if constexpr (schedule_compiled<N, MODE>(CONTIG, LINES, 1)) {
-        if (a.seq) return go_axis<N, MODE, CONTIG, LINES, true>(g, axis, a, s);
-    }
-    if constexpr (schedule_compiled<N, MODE>(CONTIG, LINES, 0)) {
-        if (!a.seq) return go_axis<N, MODE, CONTIG, LINES, false>(g, axis, a, s);
-    }
+    if (a.radix == 8) return go_axis_sched_rr<N, MODE, CONTIG, LINES, 8>(g, axis, a, s);
+    if (a.radix == 0 || a.radix == 16) return go_axis_sched_rr<N, MODE, CONTIG, LINES, 16>(g, axis, a, s);
     return hipErrorInvalidValue;
 }
 
@@ -417,13 +491,14 @@ static hipError_t go_axis_n(const GroupDev& g, int axis, const PassArgs& a, hipS
 }
 
 template <int N>
-static bool schedule_ok_n(int mode, bool contig, int lines, int seq) {
+static bool schedule_ok_n(int mode, bool contig, int lines, int seq, int rr) {
     switch (mode) {
-        case PASS_D1: return schedule_compiled<N, PASS_D1>(contig, lines, seq);
-        case PASS_D2: return schedule_compiled<N, PASS_D2>(contig, lines, seq);
-        case PASS_FIRST: return contig && schedule_compiled<N, PASS_FIRST>(contig, lines, seq);
-        case PASS_LAST1: return !contig && schedule_compiled<N, PASS_LAST1>(contig, lines, seq);
-        case PASS_LAST2: return !contig && schedule_compiled<N, PASS_LAST2>(contig, lines, seq);
+        case PASS_D1: return schedule_compiled<N, PASS_D1>(contig, lines, seq, rr);
+        case PASS_D2: return schedule_compiled<N, PASS_D2>(contig, lines, seq, rr);
+        case PASS_FIRST: return contig && schedule_compiled<N, PASS_FIRST>(contig, lines, seq, rr);
+        case PASS_LAST2: return contig && schedule_compiled<N, PASS_LAST2>(contig, lines, seq, rr);
+        case PASS_LF: return !contig && schedule_compiled<N, PASS_LF>(contig, lines, seq, rr);
+        case PASS_XF: return contig && schedule_compiled<N, PASS_XF>(contig, lines, seq, rr);
         default: return false;
     }
 }

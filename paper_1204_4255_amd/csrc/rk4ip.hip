@@ -34,6 +34,14 @@ int ilog2i(int64_t v) {
     return r;
 }
 
+// Tile schedule of one pass (see PassArgs): lines or columns per workgroup, joint or
+// sequential field transforms, values per thread in the transform.
+struct Sched {
+    int lines = 0;
+    int seq = 0;
+    int radix = 0;
+};
+
 struct GroupHost {
     rk4ip_problem p;
     GroupDev d;
@@ -138,7 +146,7 @@ struct rk4ip_plan_s {
     int* flag = nullptr;
     std::string err;
     std::vector<std::vector<std::string>> sched_names;  // [group][pass]
-    std::vector<std::vector<std::pair<int, int>>> sched;  // [group][pass] = (lines, seq); (0, 0) = default
+    std::vector<std::vector<Sched>> sched;  // [group][pass]; zeros = default schedule
     // cached graph of `graph_steps` steps on `graph_psi`
     hipGraphExec_t graph = nullptr;
     hipGraph_t graph_src = nullptr;
@@ -212,17 +220,41 @@ void build_tables(const rk4ip_problem& p, int a, std::vector<float2>& E, std::ve
     }
 }
 
-// The pass sequence of one step of a 2D/3D group: (axis, mode).
-int pass_list(int ndim, int (*out)[2]) {
+// The passes of a 2D/3D group. A run of steps is OPEN (at its first step), then for every
+// step but the last the MID passes and the NEXT pass (which ends the step and opens the
+// following one), and for the last step the MID passes and CLOSE.
+enum Role { ROLE_OPEN, ROLE_MID, ROLE_NEXT, ROLE_CLOSE };
+struct PassDef {
+    int axis, mode, role;
+};
+
+int pass_list(int ndim, PassDef* out) {
     if (ndim == 2) {
-        const int seq[4][2] = {{0, rk4ip::PASS_FIRST}, {1, rk4ip::PASS_LAST1}, {0, rk4ip::PASS_D2}, {1, rk4ip::PASS_LAST2}};
-        for (int i = 0; i < 4; i++) out[i][0] = seq[i][0], out[i][1] = seq[i][1];
+        const PassDef seq[4] = {{0, rk4ip::PASS_FIRST, ROLE_OPEN},
+                                {1, rk4ip::PASS_LF, ROLE_MID},
+                                {0, rk4ip::PASS_XF, ROLE_NEXT},
+                                {0, rk4ip::PASS_LAST2, ROLE_CLOSE}};
+        for (int i = 0; i < 4; i++) out[i] = seq[i];
         return 4;
     }
-    const int seq[6][2] = {{0, rk4ip::PASS_FIRST}, {1, rk4ip::PASS_D2}, {2, rk4ip::PASS_LAST1},
-                           {0, rk4ip::PASS_D2},    {1, rk4ip::PASS_D2}, {2, rk4ip::PASS_LAST2}};
-    for (int i = 0; i < 6; i++) out[i][0] = seq[i][0], out[i][1] = seq[i][1];
+    const PassDef seq[6] = {{0, rk4ip::PASS_FIRST, ROLE_OPEN}, {1, rk4ip::PASS_D2, ROLE_MID},
+                            {2, rk4ip::PASS_LF, ROLE_MID},     {1, rk4ip::PASS_D2, ROLE_MID},
+                            {0, rk4ip::PASS_XF, ROLE_NEXT},    {0, rk4ip::PASS_LAST2, ROLE_CLOSE}};
+    for (int i = 0; i < 6; i++) out[i] = seq[i];
     return 6;
+}
+constexpr int kMaxPasses = 6;
+
+const char* mode_name(int mode) {
+    switch (mode) {
+        case rk4ip::PASS_D1: return "D1";
+        case rk4ip::PASS_D2: return "D2";
+        case rk4ip::PASS_FIRST: return "FIRST";
+        case rk4ip::PASS_LAST2: return "LAST2";
+        case rk4ip::PASS_LF: return "LF";
+        case rk4ip::PASS_XF: return "XF";
+        default: return "?";
+    }
 }
 
 hipEvent_t take_event(rk4ip_plan_t plan) {
@@ -268,13 +300,15 @@ int collect_profile(rk4ip_plan_t plan) {
 }
 
 // Mean time (ms) of `reps` launches of one pass with a given schedule, on the work fields.
-int time_pass(rk4ip_plan_t plan, const GroupHost& g, int axis, int mode, int lines, int seq, int reps, float* ms) {
+int time_pass(rk4ip_plan_t plan, const GroupHost& g, int axis, int mode, const Sched& sc, int reps, float* ms) {
     rk4ip::PassArgs pa{};
     pa.A = plan->A;
     pa.B = plan->B;
     pa.psi = (mode == rk4ip::PASS_FIRST) ? plan->B : plan->A;  // same tiles are read before written
-    pa.lines = lines;
-    pa.seq = seq;
+    pa.step_off = 1;
+    pa.lines = sc.lines;
+    pa.seq = sc.seq;
+    pa.radix = sc.radix;
     hipStream_t st = plan->stream;
     for (int i = 0; i < 2; i++) HIPCHK(plan, rk4ip::launch_axis(g.d, axis, mode, pa, st));
     hipEvent_t a = take_event(plan), b = take_event(plan);
@@ -299,14 +333,14 @@ std::string tune_key(const GroupHost& g, int pass) {
     return k;
 }
 
-bool cache_lookup(const std::string& text, const std::string& key, int* lines, int* seq) {
+bool cache_lookup(const std::string& text, const std::string& key, Sched* sc) {
     const std::string q = "\"" + key + "\"";
     size_t p = text.find(q);
     if (p == std::string::npos) return false;
     p = text.find('[', p);
     if (p == std::string::npos) return false;
-    return std::sscanf(text.c_str() + p, "[%d , %d]", lines, seq) == 2 ||
-           std::sscanf(text.c_str() + p, "[%d,%d]", lines, seq) == 2;
+    return std::sscanf(text.c_str() + p, "[%d , %d , %d]", &sc->lines, &sc->seq, &sc->radix) == 3 ||
+           std::sscanf(text.c_str() + p, "[%d,%d,%d]", &sc->lines, &sc->seq, &sc->radix) == 3;
 }
 
 // Choose the fastest compiled schedule of every pass (RK4IP_FLAG_AUTOTUNE).
@@ -321,35 +355,42 @@ int autotune(rk4ip_plan_t plan) {
             std::fclose(fh);
         }
     }
-    std::vector<std::pair<std::string, std::pair<int, int>>> fresh;
+    std::vector<std::pair<std::string, Sched>> fresh;
     HIPCHK(plan, hipMemsetAsync(plan->A, 0, 2 * sizeof(float2) * (size_t)plan->points, plan->stream));
     for (size_t gi = 0; gi < plan->groups.size(); gi++) {
         const GroupHost& g = plan->groups[gi];
         if (g.p.ndim == 1) continue;
-        int seq_list[6][2];
-        const int np = pass_list(g.p.ndim, seq_list);
+        PassDef defs[kMaxPasses];
+        const int np = pass_list(g.p.ndim, defs);
         for (int i = 0; i < np; i++) {
-            const int axis = seq_list[i][0], mode = seq_list[i][1];
+            const int axis = defs[i].axis, mode = defs[i].mode;
             const int N = (int)g.p.n[axis], n0 = (int)g.p.n[0];
-            int cl = 0, cs = 0;
-            if (cache_lookup(text, tune_key(g, i), &cl, &cs) && rk4ip::axis_schedule_ok(N, mode, axis, n0, cl, cs)) {
-                plan->sched[gi][i] = {cl, cs};
+            Sched c;
+            if (cache_lookup(text, tune_key(g, i), &c) &&
+                rk4ip::axis_schedule_ok(N, mode, axis, n0, c.lines, c.seq, c.radix)) {
+                plan->sched[gi][i] = c;
                 continue;
             }
             float best = 1e30f;
-            std::pair<int, int> pick{0, 0};
+            Sched pick;
             const int cand_lines[] = {1, 2, 4, 8, 16, 32, 64, 128, 256};
-            for (int lines : cand_lines)
-                for (int sq = 0; sq < 2; sq++) {
-                    if (!rk4ip::axis_schedule_ok(N, mode, axis, n0, lines, sq)) continue;
-                    float ms = 0.f;
-                    int rc = time_pass(plan, g, axis, mode, lines, sq, 5, &ms);
-                    if (rc) return rc;
-                    if (ms < best) {
-                        best = ms;
-                        pick = {lines, sq};
+            const int cand_radix[] = {16, 8};
+            for (int rr : cand_radix)
+                for (int lines : cand_lines)
+                    for (int sq = 0; sq < 3; sq++) {
+                        if (!rk4ip::axis_schedule_ok(N, mode, axis, n0, lines, sq, rr)) continue;
+                        Sched cand;
+                        cand.lines = lines;
+                        cand.seq = sq;
+                        cand.radix = rr;
+                        float ms = 0.f;
+                        int rc = time_pass(plan, g, axis, mode, cand, 5, &ms);
+                        if (rc) return rc;
+                        if (ms < best) {
+                            best = ms;
+                            pick = cand;
+                        }
                     }
-                }
             plan->sched[gi][i] = pick;
             fresh.push_back({tune_key(g, i), pick});
         }
@@ -363,8 +404,8 @@ int autotune(rk4ip_plan_t plan) {
         bool has_entry = body.find('[') != std::string::npos;
         for (auto& f : fresh) {
             char line[256];
-            std::snprintf(line, sizeof(line), "%s \"%s\": [%d, %d]\n", has_entry ? "," : " ", f.first.c_str(),
-                          f.second.first, f.second.second);
+            std::snprintf(line, sizeof(line), "%s \"%s\": [%d, %d, %d]\n", has_entry ? "," : " ", f.first.c_str(),
+                          f.second.lines, f.second.seq, f.second.radix);
             body += line;
             has_entry = true;
         }
@@ -377,14 +418,14 @@ int autotune(rk4ip_plan_t plan) {
     return RK4IP_OK;
 }
 
-// Enqueue `nsteps` steps of every group. step_base != null: step = *step_base + step_off.
-int enqueue_steps(rk4ip_plan_t plan, hipStream_t stream, float2* psi, int64_t step_off, int64_t nsteps,
+// Enqueue `nsteps` steps of every 1D group. step_base != null: step = *step_base + step_off.
+int enqueue_lines(rk4ip_plan_t plan, hipStream_t stream, float2* psi, int64_t step_off, int64_t nsteps,
                   const int64_t* step_base, bool allow_fuse) {
     const bool capturing = step_base != nullptr;
     int rc;
     for (size_t gi = 0; gi < plan->groups.size(); gi++) {
         auto& g = plan->groups[gi];
-        if (g.p.ndim != 1) continue;
+        if (g.p.ndim != 1 || nsteps <= 0) continue;
         if (allow_fuse && (plan->flags & RK4IP_FLAG_FUSE_1D)) {
             rc = timed_launch(plan, stream, (int)gi, 0, capturing, [&] {
                 return rk4ip::launch_line_step(g.d, psi, (int)nsteps, step_off, step_base, stream);
@@ -399,28 +440,68 @@ int enqueue_steps(rk4ip_plan_t plan, hipStream_t stream, float2* psi, int64_t st
             }
         }
     }
-    for (int64_t s = 0; s < nsteps; s++) {
+    return RK4IP_OK;
+}
+
+// Enqueue part of a run on every 2D/3D group: OPEN at step_off (if `open`), then `nunits`
+// units (MID of step s, NEXT into step s + 1, for s = step_off ...), then, if `close`, MID
+// and CLOSE of step step_off + nunits. step_base != null: every step index is offset by
+// *step_base.
+int enqueue_lattice(rk4ip_plan_t plan, hipStream_t stream, float2* psi, int64_t step_off, int64_t nunits, bool open,
+                    bool close, const int64_t* step_base) {
+    const bool capturing = step_base != nullptr;
+    auto launch_role = [&](int role, int64_t step) -> int {
         for (size_t gi = 0; gi < plan->groups.size(); gi++) {
             auto& g = plan->groups[gi];
             if (g.p.ndim == 1) continue;
-            int seq[6][2];
-            const int np = pass_list(g.p.ndim, seq);
+            PassDef defs[kMaxPasses];
+            const int np = pass_list(g.p.ndim, defs);
             for (int i = 0; i < np; i++) {
+                if (defs[i].role != role) continue;
                 rk4ip::PassArgs pa{};
                 pa.psi = psi;
                 pa.A = plan->A;
                 pa.B = plan->B;
-                pa.step_off = step_off + s;
+                pa.step_off = step;
                 pa.step_base = step_base;
-                pa.lines = plan->sched[gi][i].first;
-                pa.seq = plan->sched[gi][i].second;
-                rc = timed_launch(plan, stream, (int)gi, i, capturing,
-                                  [&] { return rk4ip::launch_axis(g.d, seq[i][0], seq[i][1], pa, stream); });
+                pa.lines = plan->sched[gi][i].lines;
+                pa.seq = plan->sched[gi][i].seq;
+                pa.radix = plan->sched[gi][i].radix;
+                int rc = timed_launch(plan, stream, (int)gi, i, capturing, [&] {
+                    return rk4ip::launch_axis(g.d, defs[i].axis, defs[i].mode, pa, stream);
+                });
                 if (rc) return rc;
             }
         }
+        return RK4IP_OK;
+    };
+    int rc;
+    if (open && (rc = launch_role(ROLE_OPEN, step_off))) return rc;
+    for (int64_t u = 0; u < nunits; u++) {
+        if ((rc = launch_role(ROLE_MID, step_off + u))) return rc;
+        if ((rc = launch_role(ROLE_NEXT, step_off + u + 1))) return rc;
+    }
+    if (close) {
+        if ((rc = launch_role(ROLE_MID, step_off + nunits))) return rc;
+        if ((rc = launch_role(ROLE_CLOSE, step_off + nunits))) return rc;
     }
     return RK4IP_OK;
+}
+
+bool has_lattice(rk4ip_plan_t plan) {
+    for (auto& g : plan->groups)
+        if (g.p.ndim > 1) return true;
+    return false;
+}
+
+// Enqueue `nsteps` steps (from step index step_off) of every group, eagerly.
+int enqueue_steps(rk4ip_plan_t plan, hipStream_t stream, float2* psi, int64_t step_off, int64_t nsteps,
+                  bool allow_fuse) {
+    if (nsteps <= 0) return RK4IP_OK;
+    int rc = enqueue_lines(plan, stream, psi, step_off, nsteps, nullptr, allow_fuse);
+    if (rc) return rc;
+    if (!has_lattice(plan)) return RK4IP_OK;
+    return enqueue_lattice(plan, stream, psi, step_off, nsteps - 1, true, true, nullptr);
 }
 
 int device_ok(rk4ip_plan_t plan) {
@@ -457,8 +538,12 @@ int do_diagnostics(rk4ip_plan_t plan, const float2* psi, double* out) {
     return RK4IP_OK;
 }
 
-// Build (or reuse) a graph of `gsteps` steps whose step index is read from the device
-// counter, followed by counter += gsteps.
+// Steps per replayed graph.
+constexpr int kGraphSteps = 32;
+
+// Build (or reuse) a graph of `gsteps` steady-state steps whose step index s is read from
+// the device counter: the 1D groups' steps s ... s + gsteps - 1 and the 2D/3D groups'
+// units (MID of step s + u, NEXT into s + u + 1), followed by counter += gsteps.
 int ensure_graph(rk4ip_plan_t plan, float2* psi, int gsteps) {
     if (plan->graph && plan->graph_psi == psi && plan->graph_steps == gsteps) return RK4IP_OK;
     drop_graph(plan);
@@ -468,7 +553,8 @@ int ensure_graph(rk4ip_plan_t plan, float2* psi, int gsteps) {
     hipStream_t s = plan->capture_stream;
     hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return fail_hip(plan, e, "hipStreamBeginCapture");
-    int rc = enqueue_steps(plan, s, psi, 0, gsteps, plan->counter, true);
+    int rc = enqueue_lines(plan, s, psi, 0, gsteps, plan->counter, true);
+    if (rc == RK4IP_OK) rc = enqueue_lattice(plan, s, psi, 0, gsteps, false, false, plan->counter);
     hipError_t e2 = rk4ip::launch_counter(plan->counter, gsteps, 1, s);
     hipGraph_t gr = nullptr;
     hipError_t e3 = hipStreamEndCapture(s, &gr);
@@ -491,24 +577,31 @@ int ensure_graph(rk4ip_plan_t plan, float2* psi, int gsteps) {
     return RK4IP_OK;
 }
 
-// Advance nsteps from step index `step`, using the graph when enabled.
+// Advance nsteps from step index `step`, replaying graphs of steady-state steps when
+// enabled: OPEN, graphs, the remaining units eagerly, CLOSE.
 int advance(rk4ip_plan_t plan, float2* psi, int64_t step, int64_t nsteps) {
     if (nsteps <= 0) return RK4IP_OK;
-    if (!(plan->flags & RK4IP_FLAG_GRAPH)) return enqueue_steps(plan, plan->stream, psi, step, nsteps, nullptr, true);
-    const int gsteps = (int)(nsteps < 8 ? nsteps : 8);
-    int rc = ensure_graph(plan, psi, gsteps);
-    if (rc != RK4IP_OK) return rc;
-    HIPCHK(plan, rk4ip::launch_counter(plan->counter, step, 0, plan->stream));
+    if (!(plan->flags & RK4IP_FLAG_GRAPH)) return enqueue_steps(plan, plan->stream, psi, step, nsteps, true);
+    const bool lattice = has_lattice(plan);
+    const int64_t units = lattice ? nsteps - 1 : nsteps;
+    int rc;
+    if (lattice && (rc = enqueue_lattice(plan, plan->stream, psi, step, 0, true, false, nullptr))) return rc;
     int64_t done = 0;
-    while (nsteps - done >= gsteps) {
-        hipError_t e = hipGraphLaunch(plan->graph, plan->stream);
-        if (e != hipSuccess) {
-            plan->err = std::string("hipGraphLaunch: ") + hipGetErrorString(e);
-            return RK4IP_ERR_NOT_CAPTURABLE;
+    if (units >= 1) {
+        const int gsteps = (int)(units < kGraphSteps ? units : kGraphSteps);
+        if ((rc = ensure_graph(plan, psi, gsteps))) return rc;
+        HIPCHK(plan, rk4ip::launch_counter(plan->counter, step, 0, plan->stream));
+        while (units - done >= gsteps) {
+            hipError_t e = hipGraphLaunch(plan->graph, plan->stream);
+            if (e != hipSuccess) {
+                plan->err = std::string("hipGraphLaunch: ") + hipGetErrorString(e);
+                return RK4IP_ERR_NOT_CAPTURABLE;
+            }
+            done += gsteps;
         }
-        done += gsteps;
     }
-    if (done < nsteps) return enqueue_steps(plan, plan->stream, psi, step + done, nsteps - done, nullptr, true);
+    if ((rc = enqueue_lines(plan, plan->stream, psi, step + done, nsteps - done, nullptr, true))) return rc;
+    if (lattice) return enqueue_lattice(plan, plan->stream, psi, step + done, units - done, false, true, nullptr);
     return RK4IP_OK;
 }
 
@@ -617,7 +710,10 @@ int rk4ip_plan(const rk4ip_problem* probs, int nprob, void* workspace, size_t ws
         g.first_inst = inst;
         offset += p.batch * g.M;
         inst += p.batch;
-        plan->sched.push_back(std::vector<std::pair<int, int>>(p.ndim == 1 ? 1 : (p.ndim == 2 ? 4 : 6), {0, 0}));
+        {
+            PassDef defs[kMaxPasses];
+            plan->sched.push_back(std::vector<Sched>(p.ndim == 1 ? 1 : pass_list(p.ndim, defs)));
+        }
     }
     plan->ninst = inst;
     plan->groups = std::move(gh);
@@ -637,15 +733,15 @@ int rk4ip_plan(const rk4ip_problem* probs, int nprob, void* workspace, size_t ws
             std::snprintf(name, sizeof(name), "line_step:n%lld", (long long)p.n[0]);
             names.push_back(name);
         } else {
-            static const char* kinds[] = {"D1", "D2", "FIRST", "LAST1", "LAST2"};
-            int seq[6][2];
-            const int np = pass_list(p.ndim, seq);
+            PassDef defs[kMaxPasses];
+            const int np = pass_list(p.ndim, defs);
             for (int k = 0; k < np; k++) {
-                const int a = seq[k][0];
-                const auto sc = plan->sched[gi][k];
-                const int lines = sc.first ? sc.first : rk4ip::axis_lines((int)p.n[a], a, (int)p.n[0]);
-                std::snprintf(name, sizeof(name), "%s:axis%d:n%lld:%s:lines%d:%s", kinds[seq[k][1]], a,
-                              (long long)p.n[a], a == 0 ? "contig" : "strided", lines, sc.second ? "seq" : "joint");
+                const int a = defs[k].axis;
+                const Sched sc = plan->sched[gi][k];
+                const int lines = sc.lines ? sc.lines : rk4ip::axis_lines((int)p.n[a], a, (int)p.n[0]);
+                std::snprintf(name, sizeof(name), "%s:axis%d:n%lld:%s:lines%d:%s:r%d", mode_name(defs[k].mode), a,
+                              (long long)p.n[a], a == 0 ? "contig" : "strided", lines,
+                              sc.seq == 2 ? "seq-deferred" : (sc.seq ? "seq" : "joint"), sc.radix ? sc.radix : 16);
                 names.push_back(name);
             }
         }
@@ -670,7 +766,7 @@ int rk4ip_set_stream(rk4ip_plan_t plan, void* stream) {
 
 int rk4ip_step(rk4ip_plan_t plan, void* psi, int64_t step_index) {
     if (!plan || !psi || step_index < 0) return RK4IP_ERR_INVALID_ARG;
-    return enqueue_steps(plan, plan->stream, static_cast<float2*>(psi), step_index, 1, nullptr, false);
+    return enqueue_steps(plan, plan->stream, static_cast<float2*>(psi), step_index, 1, false);
 }
 
 int rk4ip_diagnostics(rk4ip_plan_t plan, const void* psi, double* out) {
@@ -764,7 +860,7 @@ int rk4ip_adjoint(rk4ip_plan_t plan, const void* ckpt_v, int64_t step0, int64_t 
             HIPCHK(plan, hipMemcpyAsync(store + i * (int64_t)(field / sizeof(float2)), cur, fbytes,
                                         hipMemcpyDeviceToDevice, st));
             if (i + 1 < len) {
-                int rc = enqueue_steps(plan, st, cur, step0 + s0 + i, 1, nullptr, false);
+                int rc = enqueue_steps(plan, st, cur, step0 + s0 + i, 1, false);
                 if (rc) return rc;
             }
         }

@@ -149,7 +149,10 @@ def test_gpu_gradient_central_difference(torch):
     d = torch.tensor((rng.standard_normal(psi0.numel()) + 1j * rng.standard_normal(psi0.numel())).astype(np.complex64),
                      device="cuda")
     d = d * (torch.linalg.vector_norm(psi0.detach()) / torch.linalg.vector_norm(d))   # same size as psi0
-    dv = torch.tensor(rng.standard_normal(V.numel()).astype(np.float32), device="cuda")
+    # the loss moves little with V over T = 0.02, so take a direction large enough that
+    # the difference stands well above the FP32 rounding of the forward runs (~1e-6 of
+    # the loss)
+    dv = torch.tensor(25.0 * rng.standard_normal(V.numel()).astype(np.float32), device="cuda")
     eps = 1e-2  # FP32 forward: larger steps keep the difference above rounding
     with torch.no_grad():
         lp = loss_of(psi0 + eps * d, V).item()

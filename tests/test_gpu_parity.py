@@ -256,22 +256,25 @@ def test_graph_replays_match_eager_with_work_between(torch):
     log("graph replays interleaved with eager torch work")
     g = W.Group(n=(32, 16, 8), lo=(-4, -4, -4), hi=(4, 4, 4), batch=2, gnl=3.0, trap=(1, 1, 1), sigma=0.01, seed=4)
     f = quantised(random_field(g, 40))
-    w = W.Workload("gr", [g], 1e-3, 8, [f])
+    w = W.Workload("gr", [g], 1e-3, 33, [f])
     eager = plan_for(w, 0)
     graph = plan_for(w, rk4ip.RK4IP_FLAG_GRAPH)
     a = _dev(torch, f)
     b = _dev(torch, f)
     for rep in range(4):
-        eager.run(a, 8, step0=8 * rep)
-        graph.run(b, 8, step0=8 * rep)   # one full replay of an 8-step graph
+        eager.run(a, 33, step0=33 * rep)
+        graph.run(b, 33, step0=33 * rep)   # FIRST, one replay of the 32-step graph, LAST2
         junk = torch.randn(1 << 16, device="cuda").sum()  # unrelated eager work between replays
         torch.cuda.synchronize()
         assert torch.isfinite(junk)
         assert torch.equal(a, b), rep
 
 
-def test_autotuned_schedules_match_default_bitwise(torch):
-    log("autotuned schedules vs default (3D 256x32x64 and 2D 512x128)")
+def test_autotuned_schedules_match_oracle(torch):
+    """Every schedule the autotuner may pick computes the same step: with 16 values per
+    thread the per-line arithmetic is identical (bitwise equal to the default), with 8
+    it differs only by rounding."""
+    log("autotuned schedules vs default and oracle (3D 256x32x64, 2D 512x128)")
     for n in ((256, 32, 64), (512, 128)):
         nd = len(n)
         g = W.Group(n=n, lo=(-5.0,) * nd, hi=(5.0,) * nd, batch=1, gnl=10.0, trap=(1, 1, 1), sigma=0.01, seed=2)
@@ -286,7 +289,12 @@ def test_autotuned_schedules_match_default_bitwise(torch):
         base.run(a, 3)
         tuned.run(b, 3)
         torch.cuda.synchronize()
-        assert torch.equal(a, b)
+        ref, _, _ = oracle.run(oprob(g, 1e-3), f, 3)
+        assert rel(_host(b, g.shape), ref) < 2e-6
+        if all(nm.endswith(":r16") for nm in names):
+            assert torch.equal(a, b)
+        else:
+            assert rel(_host(b, g.shape), _host(a, g.shape)) < 2e-6
 
 
 # ----------------------------------------------------------------------------- the workloads
