@@ -12,7 +12,6 @@ stream), and the FP64 CPU oracle timed on a bounded sample on this host's cores.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -33,13 +32,9 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_gpe3d_256.json")
 
 
 def kernel_source_hash() -> str:
-    h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_1204_4255_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        with open(os.path.join(csrc, name), "rb") as fh:
-            h.update(name.encode())
-            h.update(fh.read())
-    return h.hexdigest()[:16]
+    from paper_1204_4255_amd.build import source_hash
+
+    return source_hash()
 
 
 def measured_traffic(kernel: str):
@@ -58,6 +53,205 @@ def measured_traffic(kernel: str):
     return rec.get("bytes_per_launch")
 
 
+def _timed(torch, fn, reps: int = 1) -> float:
+    """Seconds per call of fn (events on the current stream, after one untimed call)."""
+    fn()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / 1e3 / reps
+
+
+def _single(w, gi: int, b: int, rk4ip, workloads):
+    """Workload of instance b of group gi alone (same instance id, so the same noise)."""
+    import numpy as np
+    from dataclasses import replace
+
+    g = w.groups[gi]
+    gg = replace(g, batch=1, id_base=g.id_base + b,
+                 Vgrid=None if g.Vgrid is None else np.asarray(g.Vgrid)[b:b + 1])
+    return workloads.Workload(w.name + "_one", [gg], w.h, w.nsteps, [np.asarray(w.psi0[gi])[b:b + 1]])
+
+
+def form_batched_paths(torch, rk4ip, workloads, steps: int = 200, sample_paths: int = 8):
+    """Many stochastic paths per launch vs the plain path (one path per plan, one at a time)."""
+    w = workloads.sgpe1d(nsteps=steps)
+    g = w.groups[0]
+    probs, _k = rk4ip.problems_from_workload(w)
+    psi0 = rk4ip.field_to_device(w)
+    out = {"workload": f"sgpe1d {g.batch} paths x {g.n[0]} (Philox noise), {steps} steps"}
+    results = {}
+    for name, flags in (("one_launch_per_step", rk4ip.RK4IP_FLAG_GRAPH),
+                        ("fused_steps", rk4ip.RK4IP_FLAG_GRAPH | rk4ip.RK4IP_FLAG_FUSE_1D)):
+        plan = rk4ip.Plan(probs, flags=flags)
+        psi = psi0.clone()
+        t = _timed(torch, lambda: (psi.copy_(psi0), plan.run(psi, steps)))
+        out[name + "_pt_steps_per_s"] = g.batch * g.M * steps / t
+        results[name] = psi
+        plan.destroy()
+    # the plain path: one path per plan, paths run one after another
+    plain_ms = 0.0
+    same = True
+    for b in range(sample_paths):
+        w1 = _single(w, 0, b, rk4ip, workloads)
+        p1, _k1 = rk4ip.problems_from_workload(w1)
+        plan = rk4ip.Plan(p1, flags=rk4ip.RK4IP_FLAG_GRAPH)
+        f0 = rk4ip.field_to_device(w1)
+        psi = f0.clone()
+        plain_ms += _timed(torch, lambda: (psi.copy_(f0), plan.run(psi, steps))) * 1e3
+        same = same and bool(torch.equal(psi, results["fused_steps"][b * g.M:(b + 1) * g.M]))
+        plan.destroy()
+    out["plain_pt_steps_per_s"] = sample_paths * g.M * steps / (plain_ms / 1e3)
+    out["plain_sample"] = f"{sample_paths} paths, one plan each, run one after another"
+    out["speedup_vs_plain"] = out["fused_steps_pt_steps_per_s"] / out["plain_pt_steps_per_s"]
+    out["speedup_fused_vs_one_launch_per_step"] = out["fused_steps_pt_steps_per_s"] / out[
+        "one_launch_per_step_pt_steps_per_s"]
+    out["bitwise_equal_to_plain"] = same
+    return out
+
+
+def form_uneven_batch(torch, rk4ip, workloads, steps: int = 100, sample: int = 2):
+    """Uneven 2D instances (32 x 128^2 + 32 x 256^2) in one plan vs one plan per instance."""
+    w = workloads.adjoint2d(nsteps=steps)
+    probs, _k = rk4ip.problems_from_workload(w)
+    pts = sum(g.batch * g.M for g in w.groups)
+    plan = rk4ip.Plan(probs, flags=rk4ip.RK4IP_FLAG_GRAPH | rk4ip.RK4IP_FLAG_AUTOTUNE)
+    psi0 = rk4ip.field_to_device(w)
+    psi = psi0.clone()
+    t = _timed(torch, lambda: (psi.copy_(psi0), plan.run(psi, steps)))
+    batched = pts * steps / t
+    plan.destroy()
+    # plain path: `sample` instances of each size, one plan each, one after another
+    tot_pts, tot_s = 0, 0.0
+    same = True
+    off = 0
+    for gi, g in enumerate(w.groups):
+        for b in range(sample):
+            w1 = _single(w, gi, b, rk4ip, workloads)
+            p1, _k1 = rk4ip.problems_from_workload(w1)
+            pl = rk4ip.Plan(p1, flags=rk4ip.RK4IP_FLAG_GRAPH | rk4ip.RK4IP_FLAG_AUTOTUNE)
+            f0 = rk4ip.field_to_device(w1)
+            x = f0.clone()
+            tot_s += _timed(torch, lambda: (x.copy_(f0), pl.run(x, steps)))
+            tot_pts += g.M * steps
+            ref = psi[off + b * g.M: off + (b + 1) * g.M]
+            same = same and float(torch.linalg.vector_norm(x - ref) / torch.linalg.vector_norm(ref)) < 1e-5
+            pl.destroy()
+        off += g.batch * g.M
+    # per-size throughputs weighted by the batch's point counts
+    plain = tot_pts / tot_s
+    return {"workload": f"adjoint2d shapes (32 x 128^2 + 32 x 256^2), forward, {steps} steps",
+            "batched_pt_steps_per_s": batched, "plain_pt_steps_per_s": plain,
+            "plain_sample": f"{sample} instances of each size, one plan each, one after another",
+            "speedup_vs_plain": batched / plain, "matches_plain_within_1e-5": same}
+
+
+def _torch_rk4ip(torch, w, psi0_list, V_list, steps):
+    """The same midpoint-origin RK4IP step written with torch.fft, for autograd timing only."""
+    import math
+
+    outs = []
+    for g, psi, V in zip(w.groups, psi0_list, V_list):
+        n = g.n
+        ks = []
+        for a in range(2):
+            m = torch.arange(n[a], dtype=torch.float64, device=psi.device)
+            ks.append(2 * math.pi / (g.hi[a] - g.lo[a]) * torch.where(m < n[a] // 2, m, m - n[a]))
+        k2 = ks[1][:, None] ** 2 + ks[0][None, :] ** 2
+        E = torch.exp((-1j * g.alpha * k2 - g.gamma) * (w.h / 2)).to(torch.complex64)
+        X, Y = [torch.tensor(c, device=psi.device) for c in g.mesh()]
+        Vt = (0.5 * (g.trap[0] * X ** 2 + g.trap[1] * Y ** 2)).to(torch.float32)[None] + V.reshape(psi.shape)
+        h = w.h
+
+        def D(f):
+            return torch.fft.ifft2(E * torch.fft.fft2(f))
+
+        def hG(f):
+            return (-1j * h) * (Vt + g.gnl * (f.real ** 2 + f.imag ** 2)) * f
+
+        for _ in range(steps):
+            a = D(psi)
+            k1 = D(hG(psi))
+            k2 = hG(a + 0.5 * k1)
+            k3 = hG(a + 0.5 * k2)
+            k4 = hG(D(a + k3))
+            psi = D(a + k1 / 6 + k2 / 3 + k3 / 3) + k4 / 6
+        outs.append(psi)
+    return outs
+
+
+def form_adjoint(torch, rk4ip, workloads, steps: int = 50, ckpt: int = 10):
+    """Gradient of 1 - |<phi|psi(T)>|^2 w.r.t. psi0 and V on the uneven 2D batch: the
+    hand-written adjoint (checkpoint every `ckpt` steps) vs the forward run alone and vs
+    torch.autograd through the same step written with torch.fft."""
+    import numpy as np
+    from paper_1204_4255_amd.autograd import RK4IPSolver
+
+    w = workloads.adjoint2d(nsteps=steps, ckpt_every=ckpt)
+    probs, _k = rk4ip.problems_from_workload(w)
+    solver = RK4IPSolver(probs, steps, ckpt)
+    psi0 = rk4ip.field_to_device(w)
+    Vall = torch.tensor(np.concatenate([g.Vgrid.reshape(-1) for g in w.groups]).astype(np.float32), device="cuda")
+    phis = [torch.tensor(p.astype(np.complex64).reshape(-1), device="cuda") for p in w.target]
+    sizes = [g.batch * g.M for g in w.groups]
+
+    def loss_flat(out):
+        tot, off = 0, 0
+        for g, phi, n in zip(w.groups, phis, sizes):
+            c = g.dV * torch.sum(torch.conj(phi)[None] * out[off:off + n].reshape(g.batch, -1), dim=1)
+            tot = tot + torch.sum(1 - torch.abs(c) ** 2)
+            off += n
+        return tot
+
+    state = {}
+
+    def ours():
+        p = psi0.clone().requires_grad_(True)
+        V = Vall.clone().requires_grad_(True)
+        loss_flat(solver(p, V)).backward()
+        state["ours"] = (p.grad, V.grad)
+
+    def fwd_only():
+        with torch.no_grad():
+            solver(psi0, Vall)
+
+    t_ours = _timed(torch, ours)
+    t_fwd = _timed(torch, fwd_only)
+
+    def plain_autograd():
+        p = psi0.clone().requires_grad_(True)
+        V = Vall.clone().requires_grad_(True)
+        ps, vs, off = [], [], 0
+        for g, n in zip(w.groups, sizes):
+            ps.append(p[off:off + n].reshape(g.shape))
+            vs.append(V[off:off + n].reshape(g.shape))
+            off += n
+        outs = _torch_rk4ip(torch, w, ps, vs, steps)
+        loss_flat(torch.cat([o.reshape(-1) for o in outs])).backward()
+        state["torch"] = (p.grad, V.grad)
+
+    t_torch = _timed(torch, plain_autograd)
+    gp, gv = state["ours"]
+    tp, tv = state["torch"]
+    rel = lambda a, b: float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
+    return {"workload": f"adjoint2d shapes (32 x 128^2 + 32 x 256^2), {steps} steps, checkpoint every {ckpt}",
+            "forward_plus_adjoint_s": t_ours, "forward_only_s": t_fwd,
+            "gradient_cost_in_forward_runs": t_ours / t_fwd,
+            "torch_autograd_s": t_torch, "speedup_vs_torch_autograd": t_torch / t_ours,
+            "rel_diff_vs_torch_autograd": {"grad_psi0": rel(gp, tp), "grad_V": rel(gv, tv)}}
+
+
+def measure_forms(torch, rk4ip, workloads):
+    return {"batched_paths": form_batched_paths(torch, rk4ip, workloads),
+            "uneven_batch": form_uneven_batch(torch, rk4ip, workloads),
+            "adjoint": form_adjoint(torch, rk4ip, workloads)}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -67,6 +261,9 @@ def main() -> int:
     ap.add_argument("--no-graph", action="store_true", help="launch passes eagerly instead of replaying a hipGraph")
     ap.add_argument("--no-autotune", action="store_true", help="use the default tile schedules")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the batched and adjoint forms (each timed against the plain path)")
+    ap.add_argument("--forms-only", action="store_true", help="measure only the batched and adjoint forms")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one elementwise copy kernel of 256 MiB in + 256 MiB out (a reference for "
                          "rocprofv3 FETCH_SIZE/WRITE_SIZE counters)")
@@ -82,6 +279,9 @@ def main() -> int:
     from paper_1204_4255_amd import rk4ip, workloads
 
     torch.cuda.set_device(0)
+    if args.forms_only:
+        print(json.dumps({"forms": measure_forms(torch, rk4ip, workloads)}))
+        return 0
     if args.calibrate_copy:
         src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
@@ -193,6 +393,8 @@ def main() -> int:
                                   "sample": f"the first {cpu_steps} steps of the 256^3 workload (FP64, radix-2 FFT)",
                                   "seconds": cpu_s}
         result[f"parity_{cpu_steps}step_rel_l2"] = err
+    if not args.no_forms:
+        result["forms"] = measure_forms(torch, rk4ip, workloads)
     print(json.dumps(result))
     plan.destroy()
     prof_plan.destroy()

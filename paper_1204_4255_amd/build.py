@@ -23,6 +23,18 @@ FLAGS = [
 ]
 
 
+def source_hash() -> str:
+    """Short hash of every kernel source file (ties measured counters to the code)."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        with open(os.path.join(CSRC, name), "rb") as fh:
+            h.update(name.encode())
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 def _stale(obj: str, src: str) -> bool:
     if not os.path.exists(obj):
         return True

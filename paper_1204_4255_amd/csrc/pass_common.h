@@ -78,6 +78,16 @@ __device__ __forceinline__ void propagate(c32 (&f)[NF][F::R], int t, int l, c32*
 // (adjacent lanes hold adjacent columns, so each row segment is one coalesced access).
 // Addresses are a workgroup-uniform 64-bit tile base plus 32-bit per-thread offsets,
 // shared by every field the pass touches.
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2. Give every
+// XCD a contiguous run of tiles instead, so that neighbouring strided tiles (which share
+// 128-byte lines when a tile row is narrower than a line) run on the same L2 at about the
+// same time. A bijection of [0, G).
+__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t G) {
+    constexpr int64_t X = 8;
+    const int64_t q = G / X, r = G % X, x = b % X;
+    return x * q + (x < r ? x : r) + b / X;
+}
+
 template <class F, bool CONTIG, int LINES>
 struct Tile {
     static constexpr int N = F::NN;
@@ -106,7 +116,8 @@ struct Tile {
         } else {
             const int xt_count = g.n[0] / LINES;
             const int outer_n = (axis == 1) ? g.n[2] : g.n[1];
-            int64_t bid = blockIdx.x;
+            // tiles whose rows are narrower than a 128-byte line share lines with a neighbour
+            int64_t bid = (LINES * 8 < 128) ? xcd_tile(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
             const int xt = (int)(bid % xt_count);
             bid /= xt_count;
             const int outer = (int)(bid % outer_n);

@@ -1,0 +1,145 @@
+"""Summaries of rocprofv3 runs of ``bench.py`` on the 256^3 workload.
+
+Reads the CSV output of three rocprofv3 runs from one directory:
+  kt_kernel_stats.csv           --kernel-trace --stats   (per-kernel durations)
+  fetch_counter_collection.csv  --pmc FETCH_SIZE         (KiB read per dispatch)
+  write_counter_collection.csv  --pmc WRITE_SIZE         (KiB written per dispatch)
+and optionally
+  valu_counter_collection.csv   --pmc SQ_INSTS_VALU SQ_INSTS_LDS SQ_LDS_BANK_CONFLICT SQ_WAVES
+and writes ``traffic_gpe3d_256.json`` (read by bench.py) plus markdown tables.
+
+The counters are scaled to bytes with the same counters read for one elementwise copy of
+known size (bench.py --calibrate-copy: 256 MiB in, 256 MiB out).
+
+    python -m paper_1204_4255_amd.rocprof_summary <csv dir> <out dir> "<command lines>"
+"""
+from __future__ import annotations
+
+import csv
+import json
+import os
+import re
+import sys
+from collections import defaultdict
+
+from .build import source_hash
+
+POINTS = 256 ** 3
+KINDS = {0: "D1", 1: "D2", 2: "FIRST", 4: "LAST2", 5: "U", 6: "AW", 7: "AS", 8: "AF", 9: "LF", 10: "XF"}
+# algorithmic HBM bytes per lattice point of each pass kind (complex64 = 8 B)
+PASS_BYTES = {"FIRST": 24, "D2": 32, "LF": 32, "XF": 32, "LAST2": 24}
+COPY_BYTES = 256 << 20
+AXIS_RE = re.compile(r"k_axis<(\d+), (\d+), (true|false), (\d+), (true|false), (\d), (\d+)>")
+
+
+def _short(name: str) -> str:
+    return name.split("(")[0].replace("void ", "").strip()
+
+
+def pass_of(name: str):
+    """('LF:strided', template text) for a k_axis kernel name, else None."""
+    m = AXIS_RE.search(name)
+    if not m:
+        return None
+    kind = KINDS.get(int(m.group(2)), "?")
+    layout = "contig" if m.group(3) == "true" else "strided"
+    return f"{kind}:{layout}", m.group(0)
+
+
+def _counters(path: str):
+    """{kernel name: {counter: [values per dispatch]}}"""
+    out = defaultdict(lambda: defaultdict(list))
+    if not os.path.exists(path):
+        return out
+    with open(path) as fh:
+        for r in csv.DictReader(fh):
+            out[r["Kernel_Name"]][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    return out
+
+
+def _copy_kernel(cnt, counter: str):
+    """The calibration copy: the elementwise kernel with the largest reading."""
+    best = None
+    for name, c in cnt.items():
+        if "elementwise" in name and counter in c:
+            v = max(c[counter])
+            if best is None or v > best:
+                best = v
+    return best
+
+
+def summarise(src: str, dst: str, commands: str) -> dict:
+    fetch = _counters(os.path.join(src, "fetch_counter_collection.csv"))
+    write = _counters(os.path.join(src, "write_counter_collection.csv"))
+    valu = _counters(os.path.join(src, "valu_counter_collection.csv"))
+    stats = {}
+    with open(os.path.join(src, "kt_kernel_stats.csv")) as fh:
+        for r in csv.DictReader(fh):
+            stats[r["Name"]] = r
+    cf = _copy_kernel(fetch, "FETCH_SIZE")
+    cw = _copy_kernel(write, "WRITE_SIZE")
+    fetch_factor = COPY_BYTES / 1024 / cf
+    write_factor = COPY_BYTES / 1024 / cw
+    kernels = {}
+    rows = []
+    for name in sorted(set(fetch) | set(stats)):
+        p = pass_of(name)
+        if not p or p[0].split(":")[0] not in PASS_BYTES:
+            continue
+        key, templ = p
+        f = fetch.get(name, {}).get("FETCH_SIZE")
+        w = write.get(name, {}).get("WRITE_SIZE")
+        st = stats.get(name)
+        alg = PASS_BYTES[key.split(":")[0]] * POINTS
+        rec = {"kernel": templ, "algorithmic_bytes": alg}
+        if f and w:
+            fb = sum(f) / len(f) * 1024 * fetch_factor
+            wb = sum(w) / len(w) * 1024 * write_factor
+            rec.update({"fetch_bytes": fb, "write_bytes": wb, "bytes_per_launch": fb + wb, "ratio": (fb + wb) / alg,
+                        "dispatches": len(f)})
+        if st:
+            rec.update({"calls": int(st["Calls"]), "average_ns": float(st["AverageNs"]),
+                        "min_ns": float(st["MinNs"]), "max_ns": float(st["MaxNs"]),
+                        "percent": float(st["Percentage"])})
+            rec["achieved_GBps"] = alg / float(st["AverageNs"])
+        v = valu.get(name)
+        if v and "SQ_INSTS_VALU" in v:
+            mean = lambda c: sum(v[c]) / len(v[c]) if c in v else None
+            rec["valu_insts"] = mean("SQ_INSTS_VALU")
+            rec["lds_insts"] = mean("SQ_INSTS_LDS")
+            rec["lds_bank_conflict_cycles"] = mean("SQ_LDS_BANK_CONFLICT")
+            rec["waves"] = mean("SQ_WAVES")
+            rec["valu_lane_insts_per_point"] = rec["valu_insts"] * 64 / POINTS
+            if st:
+                # one wave64 VALU instruction per CU per clock: 256 CUs at 2.4 GHz
+                rec["valu_issue_frac"] = rec["valu_insts"] / (256 * 2.4e9 * float(st["AverageNs"]) * 1e-9)
+        # several template instances can map to one pass kind: keep the one with most calls
+        if key in kernels and kernels[key].get("calls", 0) >= rec.get("calls", 0):
+            continue
+        kernels[key] = rec
+    out = {"source_hash": source_hash(), "workload": "gpe3d_256^3",
+           "calibration": {"kernel": "torch elementwise x*1.0, 256 MiB in + 256 MiB out", "FETCH_SIZE_KiB": cf,
+                           "WRITE_SIZE_KiB": cw, "fetch_factor": fetch_factor, "write_factor": write_factor},
+           "commands": commands, "kernels": kernels}
+    os.makedirs(dst, exist_ok=True)
+    with open(os.path.join(dst, "traffic_gpe3d_256.json"), "w") as fh:
+        json.dump(out, fh, indent=1)
+    return out
+
+
+def markdown(out: dict) -> str:
+    lines = ["| pass | kernel | calls | average us | min us | max us | % GPU time | algorithmic GB/s | "
+             "measured / algorithmic bytes | VALU lane-instr per point | VALU issue | LDS bank-conflict cycles |",
+             "|---|---|---|---|---|---|---|---|---|---|---|---|"]
+    for key, r in sorted(out["kernels"].items(), key=lambda kv: -kv[1].get("percent", 0)):
+        f = lambda k, fmt: (fmt % r[k]) if r.get(k) is not None else "-"
+        lines.append(f"| {key} | `{r['kernel']}` | {f('calls', '%d')} | {r.get('average_ns', 0) / 1e3:.1f} | "
+                     f"{r.get('min_ns', 0) / 1e3:.1f} | {r.get('max_ns', 0) / 1e3:.1f} | {f('percent', '%.2f')} | "
+                     f"{f('achieved_GBps', '%.0f')} | {f('ratio', '%.4f')} | {f('valu_lane_insts_per_point', '%.0f')} | "
+                     f"{f('valu_issue_frac', '%.2f')} | {f('lds_bank_conflict_cycles', '%.3g')} |")
+    return "\n".join(lines)
+
+
+if __name__ == "__main__":
+    res = summarise(sys.argv[1], sys.argv[2], sys.argv[3] if len(sys.argv) > 3 else "")
+    print(markdown(res))
