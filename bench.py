@@ -37,9 +37,9 @@ def kernel_source_hash() -> str:
     return source_hash()
 
 
-def measured_traffic(kernel: str):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary, or
-    None when it is missing or the kernels changed since the counters were taken."""
+def measured_counters(kernel: str):
+    """Counter record of `kernel` from the committed rocprofv3 summary, or None when it is
+    missing or the kernels changed since the counters were taken."""
     try:
         with open(TRAFFIC_FILE) as fh:
             t = json.load(fh)
@@ -47,11 +47,13 @@ def measured_traffic(kernel: str):
         return None
     if t.get("source_hash") != kernel_source_hash():
         return None
-    rec = t.get("kernels", {}).get(kernel)
-    if not rec:
-        return None
-    return rec.get("bytes_per_launch")
+    return t.get("kernels", {}).get(kernel)
 
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` (scaled FETCH_SIZE + WRITE_SIZE), or None."""
+    rec = measured_counters(kernel)
+    return rec.get("bytes_per_launch") if rec else None
 
 def _timed(torch, fn, reps: int = 1) -> float:
     """Seconds per call of fn (events on the current stream, after one untimed call)."""
@@ -246,10 +248,33 @@ def form_adjoint(torch, rk4ip, workloads, steps: int = 50, ckpt: int = 10):
             "rel_diff_vs_torch_autograd": {"grad_psi0": rel(gp, tp), "grad_V": rel(gv, tv)}}
 
 
+def form_fp64_transforms(torch, rk4ip, workloads, steps: int = 100):
+    """Throughput of the FP64-transform precision form next to the complex64 form on the
+    3D 256^3 and the batched 1D workloads (accuracy of both forms: the GPU parity tests)."""
+    out = {}
+    for name, w, base in (("gpe3d_256^3", workloads.gpe3d(nsteps=steps), rk4ip.RK4IP_FLAG_AUTOTUNE),
+                          ("sgpe1d_2048x1024", workloads.sgpe1d(nsteps=steps), rk4ip.RK4IP_FLAG_FUSE_1D)):
+        probs, _k = rk4ip.problems_from_workload(w)
+        pts = sum(g.batch * g.M for g in w.groups)
+        psi0 = rk4ip.field_to_device(w)
+        rates = {}
+        for form, extra in (("c64", 0), ("fp64_transforms", rk4ip.RK4IP_FLAG_FP64_TRANSFORMS)):
+            plan = rk4ip.Plan(probs, flags=rk4ip.RK4IP_FLAG_GRAPH | base | extra)
+            psi = psi0.clone()
+            plan.run(psi, 40)  # records the replay graph
+            t = _timed(torch, lambda: (psi.copy_(psi0), plan.run(psi, steps)))
+            rates[form] = pts * steps / t
+            plan.destroy()
+        out[name] = {"c64_pt_steps_per_s": rates["c64"], "fp64_transforms_pt_steps_per_s": rates["fp64_transforms"],
+                     "fp64_cost": rates["c64"] / rates["fp64_transforms"]}
+    return out
+
+
 def measure_forms(torch, rk4ip, workloads):
     return {"batched_paths": form_batched_paths(torch, rk4ip, workloads),
             "uneven_batch": form_uneven_batch(torch, rk4ip, workloads),
-            "adjoint": form_adjoint(torch, rk4ip, workloads)}
+            "adjoint": form_adjoint(torch, rk4ip, workloads),
+            "fp64_transforms": form_fp64_transforms(torch, rk4ip, workloads)}
 
 
 def main() -> int:
@@ -342,6 +367,15 @@ def main() -> int:
     bytes_per_launch = PASS_BYTES[dom["kind"]] * pts
     achieved = bytes_per_launch / (dom_mean_ms / 1e3) / 1e9
     traffic = measured_traffic(dom_name)
+    counters = measured_counters(dom_name) or {}
+    per_kernel = []
+    for name, k in sorted(kernels.items(), key=lambda kv: -kv[1]["total_ms"]):
+        mean = k["total_ms"] / k["launches"]
+        gbs = PASS_BYTES[k["kind"]] * pts / (mean / 1e3) / 1e9
+        c = measured_counters(name) or {}
+        per_kernel.append({"kernel": name, "mean_ms": mean, "launches": k["launches"], "achieved_GBps": gbs,
+                           "hbm_frac": gbs / HBM_PEAK_GBS, "valu_issue_frac_profiled": c.get("valu_issue_frac"),
+                           "traffic_ratio_profiled": c.get("ratio")})
     # bytes per step averaged over the profiled run (each pass weighted by its launches)
     step_bytes = sum(PASS_BYTES[p["pass"].split(":")[0]] * p["launches"] for p in passes) * pts / args.profile_steps
 
@@ -365,7 +399,9 @@ def main() -> int:
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "kernel": dom_name, "kernel_mean_ms": dom_mean_ms,
-                     "bytes_per_launch": bytes_per_launch},
+                     "bytes_per_launch": bytes_per_launch,
+                     "valu_issue_frac_profiled": counters.get("valu_issue_frac")},
+        "kernels": per_kernel,
         "step_roofline": {"bytes_per_step": step_bytes, "achieved_GBps": step_bytes / (ms_per_step / 1e3) / 1e9,
                           "frac": step_bytes / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS},
         "passes": passes,

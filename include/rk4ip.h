@@ -69,6 +69,13 @@ enum {
 #define RK4IP_FLAG_GRAPH     0x1u  /* replay the steady-state steps of a run from a hipGraph */
 #define RK4IP_FLAG_AUTOTUNE  0x2u  /* time candidate tile schedules at plan time and keep the best */
 #define RK4IP_FLAG_FUSE_1D   0x4u  /* 1D groups: run several steps per launch with the line kept on chip */
+/* The FP64-transform precision form: the forward step's FFTs, propagator multiply and
+ * delta add run in FP64 inside the kernels (fields stay complex64 in memory, the pointwise
+ * RK4 arithmetic stays FP32; tables are computed in FP64 and kept in FP64). It removes
+ * most of the FP32 transform rounding that accumulates over long runs whose fields carry
+ * high-k content (noise). Radix-8 schedules only; 1D lines up to 2048 points. The adjoint
+ * passes keep FP32 transforms (their recomputed forward steps use this form). */
+#define RK4IP_FLAG_FP64_TRANSFORMS 0x8u
 
 typedef struct rk4ip_plan_s* rk4ip_plan_t;
 

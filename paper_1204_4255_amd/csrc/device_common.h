@@ -35,6 +35,8 @@ struct GroupDev {
     const float* Vgrid;      // [batch][M] or nullptr
     const float2* E[3];      // per axis: (E_a - 1)/n_a, see mul_dE
     const float2* tw[3];     // per axis: e^{-2 pi i t / n_a}
+    const double2* E64[3];   // the same tables in FP64 (FP64-transform plans, else null)
+    const double2* tw64[3];
 };
 
 // ---------------------------------------------------------------- Philox4x32-10

@@ -1,4 +1,4 @@
-// fft_lds.h -- complex64 FFT of lines held in registers, exchanged through LDS (gfx950).
+// fft_lds.h -- FFT of lines held in registers, exchanged through LDS (gfx950).
 //
 // The transforms between the spatial and spectral representations are FFTs applied
 // along one lattice axis at a time (Dennis, Hope & Johnsson, arXiv:1204.4255, Sec. 3.2).
@@ -11,14 +11,17 @@
 // is needed at the ends.
 //
 // Forward transforms use e^{-2 pi i j m / N}, the inverse e^{+...}; neither is
-// normalised. Twiddles e^{-2 pi i t / N} come from a table computed in FP64 and stored
-// in FP32 (passed in LDS by the caller).
+// normalised. Twiddles e^{-2 pi i t / N} come from a table computed in FP64 (passed in
+// LDS by the caller). Every function is generic over the complex type: float2 for the
+// complex64 transforms, double2 for the FP64-transform precision form (same code, the
+// table and the LDS buffer in the same type).
 #pragma once
 #include <hip/hip_runtime.h>
 
 namespace rk4ip {
 
 typedef float2 c32;
+typedef double2 c64;
 
 __device__ __forceinline__ c32 cadd(c32 a, c32 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ c32 csub(c32 a, c32 b) { return make_float2(a.x - b.x, a.y - b.y); }
@@ -27,61 +30,85 @@ __device__ __forceinline__ c32 cmul(c32 a, c32 b) {
     return make_float2(fmaf(a.x, b.x, -a.y * b.y), fmaf(a.x, b.y, a.y * b.x));
 }
 __device__ __forceinline__ c32 cconj(c32 a) { return make_float2(a.x, -a.y); }
+
+// The same operations in FP64 (the transforms of the FP64-transform precision form).
+__device__ __forceinline__ c64 cadd(c64 a, c64 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ c64 csub(c64 a, c64 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ c64 cmul(c64 a, c64 b) {
+    return make_double2(fma(a.x, b.x, -a.y * b.y), fma(a.x, b.y, a.y * b.x));
+}
+__device__ __forceinline__ c64 cconj(c64 a) { return make_double2(a.x, -a.y); }
+
+__device__ __forceinline__ c32 mk(float x, float y, c32) { return make_float2(x, y); }
+__device__ __forceinline__ c64 mk(double x, double y, c64) { return make_double2(x, y); }
+
 // multiply by i^{s}: s = -1 -> -i z, s = +1 -> i z
-template <int S>
-__device__ __forceinline__ c32 mul_i(c32 z) {
-    return S < 0 ? make_float2(z.y, -z.x) : make_float2(-z.y, z.x);
+template <int S, class V>
+__device__ __forceinline__ V mul_i(V z) {
+    return S < 0 ? mk(z.y, -z.x, z) : mk(-z.y, z.x, z);
 }
 
-// e^{S 2 pi i k / 16} for k = 0..15 with S = -1 (forward); the inverse conjugates.
-struct W16 {
+// cos and sin of pi/8 and cos(pi/4) in the working precision: the FP32 constants are the
+// correctly rounded values, the FP64 ones carry 17 significant digits.
+template <class Sc>
+struct W16;
+template <>
+struct W16<float> {
     static constexpr float C1 = 0.92387953251128674f;  // cos(pi/8)
     static constexpr float S1 = 0.38268343236508977f;  // sin(pi/8)
     static constexpr float H = 0.70710678118654752f;   // cos(pi/4)
 };
+template <>
+struct W16<double> {
+    static constexpr double C1 = 0.92387953251128674;
+    static constexpr double S1 = 0.38268343236508977;
+    static constexpr double H = 0.70710678118654752;
+};
 
-template <int S, int K>
-__device__ __forceinline__ c32 w16_mul(c32 z) {
+template <int S, int K, class V>
+__device__ __forceinline__ V w16_mul(V z) {
     // z * e^{S 2 pi i K / 16}
+    using Sc = decltype(z.x);
+    using C = W16<Sc>;
     constexpr int k = ((K % 16) + 16) % 16;
     if constexpr (k == 0) {
         return z;
     } else if constexpr (k == 4) {
         return mul_i<S>(z);
     } else if constexpr (k == 8) {
-        return make_float2(-z.x, -z.y);
+        return mk(-z.x, -z.y, z);
     } else if constexpr (k == 12) {
         return mul_i<-S>(z);
     } else if constexpr (k == 2 || k == 6 || k == 10 || k == 14) {
         // (1 + S i)/sqrt2 rotated by multiples of i
-        constexpr float c = (k == 2 || k == 14) ? W16::H : -W16::H;
-        constexpr float s = (k == 2 || k == 6) ? W16::H : -W16::H;  // sin(2 pi k/16) sign
-        const float ss = S * s;
-        return make_float2(fmaf(z.x, c, -z.y * ss), fmaf(z.x, ss, z.y * c));
+        constexpr Sc c = (k == 2 || k == 14) ? C::H : -C::H;
+        constexpr Sc s = (k == 2 || k == 6) ? C::H : -C::H;  // sin(2 pi k/16) sign
+        const Sc ss = S * s;
+        return mk(fma(z.x, c, -z.y * ss), fma(z.x, ss, z.y * c), z);
     } else {
         // odd k: cos/sin of k pi / 8
-        constexpr float cs[16] = {1.f, W16::C1, W16::H, W16::S1, 0.f, -W16::S1, -W16::H, -W16::C1,
-                                  -1.f, -W16::C1, -W16::H, -W16::S1, 0.f, W16::S1, W16::H, W16::C1};
-        constexpr float sn[16] = {0.f, W16::S1, W16::H, W16::C1, 1.f, W16::C1, W16::H, W16::S1,
-                                  0.f, -W16::S1, -W16::H, -W16::C1, -1.f, -W16::C1, -W16::H, -W16::S1};
-        const float c = cs[k];
-        const float s = S * sn[k];
-        return make_float2(fmaf(z.x, c, -z.y * s), fmaf(z.x, s, z.y * c));
+        constexpr Sc cs[16] = {1, C::C1, C::H, C::S1, 0, -C::S1, -C::H, -C::C1,
+                               -1, -C::C1, -C::H, -C::S1, 0, C::S1, C::H, C::C1};
+        constexpr Sc sn[16] = {0, C::S1, C::H, C::C1, 1, C::C1, C::H, C::S1,
+                               0, -C::S1, -C::H, -C::C1, -1, -C::C1, -C::H, -C::S1};
+        const Sc c = cs[k];
+        const Sc s = S * sn[k];
+        return mk(fma(z.x, c, -z.y * s), fma(z.x, s, z.y * c), z);
     }
 }
 
 // In-register DFTs with natural-order input and output: y_k = sum_j x_j e^{S 2 pi i jk/r}.
-template <int S>
-__device__ __forceinline__ void dft2(c32& a, c32& b) {
-    c32 t = a;
+template <int S, class V>
+__device__ __forceinline__ void dft2(V& a, V& b) {
+    V t = a;
     a = cadd(t, b);
     b = csub(t, b);
 }
 
-template <int S>
-__device__ __forceinline__ void dft4(c32& x0, c32& x1, c32& x2, c32& x3) {
-    c32 s02 = cadd(x0, x2), d02 = csub(x0, x2);
-    c32 s13 = cadd(x1, x3), d13 = mul_i<S>(csub(x1, x3));
+template <int S, class V>
+__device__ __forceinline__ void dft4(V& x0, V& x1, V& x2, V& x3) {
+    V s02 = cadd(x0, x2), d02 = csub(x0, x2);
+    V s13 = cadd(x1, x3), d13 = mul_i<S>(csub(x1, x3));
     x0 = cadd(s02, s13);
     x2 = csub(s02, s13);
     x1 = cadd(d02, d13);
@@ -93,18 +120,21 @@ struct DFT;
 
 template <int S>
 struct DFT<2, S> {
-    __device__ __forceinline__ static void run(c32 (&x)[2]) { dft2<S>(x[0], x[1]); }
+    template <class V>
+    __device__ __forceinline__ static void run(V (&x)[2]) { dft2<S>(x[0], x[1]); }
 };
 
 template <int S>
 struct DFT<4, S> {
-    __device__ __forceinline__ static void run(c32 (&x)[4]) { dft4<S>(x[0], x[1], x[2], x[3]); }
+    template <class V>
+    __device__ __forceinline__ static void run(V (&x)[4]) { dft4<S>(x[0], x[1], x[2], x[3]); }
 };
 
 // 8 = 2 x 4: j = j1 + 2 j2, k = 4 k1 + k2
 template <int S>
 struct DFT<8, S> {
-    __device__ __forceinline__ static void run(c32 (&x)[8]) {
+    template <class V>
+    __device__ __forceinline__ static void run(V (&x)[8]) {
         dft4<S>(x[0], x[2], x[4], x[6]);  // j1 = 0 -> Y[0][k2] in x[0,2,4,6]
         dft4<S>(x[1], x[3], x[5], x[7]);  // j1 = 1 -> Y[1][k2] in x[1,3,5,7]
         x[3] = w16_mul<S, 2>(x[3]);       // W8^{k2}, k2 = 1..3
@@ -114,7 +144,7 @@ struct DFT<8, S> {
         dft2<S>(x[2], x[3]);  // k2 = 1 -> X[1], X[5]
         dft2<S>(x[4], x[5]);  // k2 = 2 -> X[2], X[6]
         dft2<S>(x[6], x[7]);  // k2 = 3 -> X[3], X[7]
-        c32 y[8] = {x[0], x[2], x[4], x[6], x[1], x[3], x[5], x[7]};
+        V y[8] = {x[0], x[2], x[4], x[6], x[1], x[3], x[5], x[7]};
 #pragma unroll
         for (int i = 0; i < 8; i++) x[i] = y[i];
     }
@@ -123,7 +153,8 @@ struct DFT<8, S> {
 // 16 = 4 x 4: j = j1 + 4 j2, k = 4 k1 + k2; W16^{jk} = W4^{j1 k1} W16^{j1 k2} W4^{j2 k2}
 template <int S>
 struct DFT<16, S> {
-    __device__ __forceinline__ static void run(c32 (&x)[16]) {
+    template <class V>
+    __device__ __forceinline__ static void run(V (&x)[16]) {
         // step A: for each j1, DFT4 over j2 of x[j1 + 4 j2] -> Y[j1][k2] stored at x[j1 + 4 k2]
         dft4<S>(x[0], x[4], x[8], x[12]);
         dft4<S>(x[1], x[5], x[9], x[13]);
@@ -145,7 +176,7 @@ struct DFT<16, S> {
         dft4<S>(x[8], x[9], x[10], x[11]);
         dft4<S>(x[12], x[13], x[14], x[15]);
         // now x[k1 + 4 k2] holds X[4 k1 + k2]: transpose the 4 x 4 index
-        c32 y[16];
+        V y[16];
 #pragma unroll
         for (int k1 = 0; k1 < 4; k1++)
 #pragma unroll
@@ -195,15 +226,15 @@ struct LdsLayout {
 
 // One Stockham stage on the registers of one thread: U = R/radix butterflies,
 // butterfly u is b = t + T u with inputs v[u*radix + k] = x[b + k N/radix].
-template <class F, int S, int STAGE>
-__device__ __forceinline__ void fft_stage(c32 (&v)[F::R], int t, const c32* __restrict__ tw) {
+template <class F, int S, int STAGE, class V>
+__device__ __forceinline__ void fft_stage(V (&v)[F::R], int t, const V* __restrict__ tw) {
     constexpr int N = F::NN;
     constexpr int r = F::radix(STAGE);
     constexpr int ns = F::ns(STAGE);
     constexpr int U = F::R / r;
 #pragma unroll
     for (int u = 0; u < U; u++) {
-        c32 x[r];
+        V x[r];
 #pragma unroll
         for (int k = 0; k < r; k++) x[k] = v[u * r + k];
         if constexpr (ns > 1) {
@@ -212,7 +243,7 @@ __device__ __forceinline__ void fft_stage(c32 (&v)[F::R], int t, const c32* __re
             constexpr int step = N / (ns * r);
 #pragma unroll
             for (int k = 1; k < r; k++) {
-                c32 w = tw[bm * k * step];
+                V w = tw[bm * k * step];
                 if constexpr (S > 0) w = cconj(w);
                 x[k] = cmul(x[k], w);
             }
@@ -224,8 +255,8 @@ __device__ __forceinline__ void fft_stage(c32 (&v)[F::R], int t, const c32* __re
 }
 
 // Write the outputs of stage STAGE to LDS and read the inputs of stage STAGE+1.
-template <class F, int STAGE, class L, int NF>
-__device__ __forceinline__ void fft_exchange(c32 (&v)[NF][F::R], int t, int line, c32* lds) {
+template <class F, int STAGE, class L, int NF, class V>
+__device__ __forceinline__ void fft_exchange(V (&v)[NF][F::R], int t, int line, V* lds) {
     constexpr int N = F::NN;
     constexpr int r = F::radix(STAGE);
     constexpr int ns = F::ns(STAGE);
@@ -257,12 +288,12 @@ __device__ __forceinline__ void fft_exchange(c32 (&v)[NF][F::R], int t, int line
 
 // After the last stage, register u*Q + k holds element t + T (u + k R/Q); put element
 // t + T m into register m.
-template <class F>
-__device__ __forceinline__ void fft_natural_order(c32 (&v)[F::R]) {
+template <class F, class V>
+__device__ __forceinline__ void fft_natural_order(V (&v)[F::R]) {
     constexpr int r = F::radix(F::NSTAGES - 1);
     constexpr int U = F::R / r;
     if constexpr (U > 1) {
-        c32 y[F::R];
+        V y[F::R];
 #pragma unroll
         for (int u = 0; u < U; u++)
 #pragma unroll
@@ -274,9 +305,9 @@ __device__ __forceinline__ void fft_natural_order(c32 (&v)[F::R]) {
 
 // Stage i of a transform of NF fields at once: the register half of stage i, then the
 // exchange into stage i+1.
-template <class F, int S, int STAGE, class L, int NF>
-__device__ __forceinline__ void fft_stages_from(c32 (&v)[NF][F::R], int t, int line, c32* lds,
-                                                const c32* __restrict__ tw) {
+template <class F, int S, int STAGE, class L, int NF, class V>
+__device__ __forceinline__ void fft_stages_from(V (&v)[NF][F::R], int t, int line, V* lds,
+                                                const V* __restrict__ tw) {
 #pragma unroll
     for (int f = 0; f < NF; f++) fft_stage<F, S, STAGE>(v[f], t, tw);
     if constexpr (STAGE + 1 < F::NSTAGES) {
@@ -289,9 +320,9 @@ __device__ __forceinline__ void fft_stages_from(c32 (&v)[NF][F::R], int t, int l
 // on exit thread t holds element t + T m in v[f][m]. S = -1 forward, +1 inverse. F is the
 // FFTShape (length and values per thread). All threads of the block must call this
 // together (it contains barriers).
-template <class F, int S, class L, int NF>
-__device__ __forceinline__ void fft_line(c32 (&v)[NF][F::R], int t, int line, c32* lds,
-                                         const c32* __restrict__ tw) {
+template <class F, int S, class L, int NF, class V>
+__device__ __forceinline__ void fft_line(V (&v)[NF][F::R], int t, int line, V* lds,
+                                         const V* __restrict__ tw) {
     fft_stages_from<F, S, 0, L, NF>(v, t, line, lds, tw);
 #pragma unroll
     for (int f = 0; f < NF; f++) fft_natural_order<F>(v[f]);

@@ -66,7 +66,7 @@ __global__ void __launch_bounds__(FFTShape<N>::T* LINES)
     __shared__ c32 lds[L::SIZE];
     __shared__ c32 tw[N];
     __shared__ double red[FFTShape<N>::T * LINES][4];
-    stage_tables<N>(tw, nullptr, g.tw[axis], nullptr);
+    stage_tables<N, c32>(tw, nullptr, g.tw[axis], nullptr);
     const int t = CONTIG ? (int)(threadIdx.x % T) : (int)(threadIdx.x / LINES);
     const int l = CONTIG ? (int)(threadIdx.x / T) : (int)(threadIdx.x % LINES);
     const Tile<F, CONTIG, LINES> tile(g, axis, l, t);

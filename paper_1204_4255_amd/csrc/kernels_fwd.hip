@@ -7,18 +7,23 @@ namespace rk4ip {
 // ---------------------------------------------------------------------------- 1D step
 
 // One workgroup runs LPB whole lines (instances). Every value of the step stays in
-// registers; LDS only carries the FFT exchanges.
-template <int N, int LPB, bool NOISE>
-__global__ void __launch_bounds__(FFTShape<N>::T* LPB)
+// registers; LDS only carries the FFT exchanges. P64: transforms in FP64 (8 values per
+// thread), everything else as in the complex64 form.
+template <int N, int LPB, bool NOISE, bool P64>
+__global__ void __launch_bounds__((FFTShape<N, (P64 ? 8 : 16)>::T * LPB))
     k_line_step(GroupDev g, float2* __restrict__ psi, int nsteps, int64_t step_off,
                 const int64_t* __restrict__ step_base) {
-    using F = FFTShape<N>;
+    using F = FFTShape<N, (P64 ? 8 : 16)>;
     using L = LdsLayout<N, LPB, true>;
+    using W = typename std::conditional<P64, c64, c32>::type;  // transform working type
     constexpr int R = F::R, T = F::T;
-    __shared__ c32 lds[2 * L::SIZE];
-    __shared__ c32 tw[N];
-    __shared__ float2 E[N];
-    stage_tables<N>(tw, E, g.tw[0], g.E[0]);
+    __shared__ W lds[2 * L::SIZE];
+    __shared__ W tw[N];
+    __shared__ W E[N];
+    if constexpr (P64)
+        stage_tables<N>(tw, E, g.tw64[0], g.E64[0]);
+    else
+        stage_tables<N>(tw, E, g.tw[0], g.E[0]);
     const int t = threadIdx.x % T;
     const int l = threadIdx.x / T;
     const int64_t inst = (int64_t)blockIdx.x * LPB + l;
@@ -82,18 +87,18 @@ __global__ void __launch_bounds__(FFTShape<N>::T* LPB)
 
 int axis_lines(int N, int axis, int n0) { return axis == 0 ? contig_lines(N) : strided_lines(N, n0); }
 
-bool axis_schedule_ok(int N, int mode, int axis, int n0, int lines, int seq, int radix) {
+bool axis_schedule_ok(int N, int mode, int axis, int n0, int lines, int seq, int radix, bool f64) {
     const bool contig = axis == 0;
     if (!contig && lines > n0) return false;
     switch (N) {
-        case 8: return schedule_ok_n<8>(mode, contig, lines, seq, radix);
-        case 16: return schedule_ok_n<16>(mode, contig, lines, seq, radix);
-        case 32: return schedule_ok_n<32>(mode, contig, lines, seq, radix);
-        case 64: return schedule_ok_n<64>(mode, contig, lines, seq, radix);
-        case 128: return schedule_ok_n<128>(mode, contig, lines, seq, radix);
-        case 256: return schedule_ok_n<256>(mode, contig, lines, seq, radix);
-        case 512: return schedule_ok_n<512>(mode, contig, lines, seq, radix);
-        case 1024: return schedule_ok_n<1024>(mode, contig, lines, seq, radix);
+        case 8: return schedule_ok_n<8>(mode, contig, lines, seq, radix, f64);
+        case 16: return schedule_ok_n<16>(mode, contig, lines, seq, radix, f64);
+        case 32: return schedule_ok_n<32>(mode, contig, lines, seq, radix, f64);
+        case 64: return schedule_ok_n<64>(mode, contig, lines, seq, radix, f64);
+        case 128: return schedule_ok_n<128>(mode, contig, lines, seq, radix, f64);
+        case 256: return schedule_ok_n<256>(mode, contig, lines, seq, radix, f64);
+        case 512: return schedule_ok_n<512>(mode, contig, lines, seq, radix, f64);
+        case 1024: return schedule_ok_n<1024>(mode, contig, lines, seq, radix, f64);
         default: return false;
     }
 }
@@ -114,34 +119,44 @@ hipError_t launch_axis(const GroupDev& g, int axis, int mode, const PassArgs& a,
     }
 }
 
-template <int N>
+template <int N, bool P64>
 static hipError_t go_line(const GroupDev& g, float2* psi, int nsteps, int64_t step_off, const int64_t* step_base,
                           hipStream_t s) {
-    constexpr int T = FFTShape<N>::T;
+    constexpr int T = FFTShape<N, (P64 ? 8 : 16)>::T;
     constexpr int LPB = T >= 64 ? 1 : 64 / T;
     const int64_t blocks = (g.batch + LPB - 1) / LPB;
     if (g.has_noise)
-        hipLaunchKernelGGL((k_line_step<N, LPB, true>), dim3((unsigned)blocks), dim3(T * LPB), 0, s, g, psi, nsteps,
-                           step_off, step_base);
+        hipLaunchKernelGGL((k_line_step<N, LPB, true, P64>), dim3((unsigned)blocks), dim3(T * LPB), 0, s, g, psi,
+                           nsteps, step_off, step_base);
     else
-        hipLaunchKernelGGL((k_line_step<N, LPB, false>), dim3((unsigned)blocks), dim3(T * LPB), 0, s, g, psi, nsteps,
-                           step_off, step_base);
+        hipLaunchKernelGGL((k_line_step<N, LPB, false, P64>), dim3((unsigned)blocks), dim3(T * LPB), 0, s, g, psi,
+                           nsteps, step_off, step_base);
     return hipGetLastError();
 }
 
+template <int N>
+static hipError_t go_line_p(const GroupDev& g, float2* psi, int nsteps, int64_t step_off, const int64_t* step_base,
+                            bool f64, hipStream_t s) {
+    if (f64) {
+        if constexpr (N <= 2048) return go_line<N, true>(g, psi, nsteps, step_off, step_base, s);
+        return hipErrorInvalidValue;  // FP64 tables and exchange buffers exceed the LDS
+    }
+    return go_line<N, false>(g, psi, nsteps, step_off, step_base, s);
+}
+
 hipError_t launch_line_step(const GroupDev& g, float2* psi, int nsteps, int64_t step_off, const int64_t* step_base,
-                            hipStream_t s) {
+                            bool f64, hipStream_t s) {
     switch (g.n[0]) {
-        case 8: return go_line<8>(g, psi, nsteps, step_off, step_base, s);
-        case 16: return go_line<16>(g, psi, nsteps, step_off, step_base, s);
-        case 32: return go_line<32>(g, psi, nsteps, step_off, step_base, s);
-        case 64: return go_line<64>(g, psi, nsteps, step_off, step_base, s);
-        case 128: return go_line<128>(g, psi, nsteps, step_off, step_base, s);
-        case 256: return go_line<256>(g, psi, nsteps, step_off, step_base, s);
-        case 512: return go_line<512>(g, psi, nsteps, step_off, step_base, s);
-        case 1024: return go_line<1024>(g, psi, nsteps, step_off, step_base, s);
-        case 2048: return go_line<2048>(g, psi, nsteps, step_off, step_base, s);
-        case 4096: return go_line<4096>(g, psi, nsteps, step_off, step_base, s);
+        case 8: return go_line_p<8>(g, psi, nsteps, step_off, step_base, f64, s);
+        case 16: return go_line_p<16>(g, psi, nsteps, step_off, step_base, f64, s);
+        case 32: return go_line_p<32>(g, psi, nsteps, step_off, step_base, f64, s);
+        case 64: return go_line_p<64>(g, psi, nsteps, step_off, step_base, f64, s);
+        case 128: return go_line_p<128>(g, psi, nsteps, step_off, step_base, f64, s);
+        case 256: return go_line_p<256>(g, psi, nsteps, step_off, step_base, f64, s);
+        case 512: return go_line_p<512>(g, psi, nsteps, step_off, step_base, f64, s);
+        case 1024: return go_line_p<1024>(g, psi, nsteps, step_off, step_base, f64, s);
+        case 2048: return go_line_p<2048>(g, psi, nsteps, step_off, step_base, f64, s);
+        case 4096: return go_line_p<4096>(g, psi, nsteps, step_off, step_base, f64, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -37,6 +37,7 @@ struct PassArgs {
     int seq;                  // 0: fields transformed together; 1: one after the other (half the
                               // LDS); 2: as 1 with the second field loaded after the first
     int radix;                // values per thread in the transform: 16 (0 = default) or 8
+    int f64;                  // transforms, propagator multiply and delta add in FP64 (radix 8)
     int64_t step_off;
     const int64_t* step_base; // step = step_off (+ *step_base when not null)
 };
@@ -50,7 +51,7 @@ struct DiagConst {
 
 int axis_lines(int N, int axis, int n0);
 // Whether a (lines, seq) schedule of a pass is compiled for this length and axis.
-bool axis_schedule_ok(int N, int mode, int axis, int n0, int lines, int seq, int radix);
+bool axis_schedule_ok(int N, int mode, int axis, int n0, int lines, int seq, int radix, bool f64);
 
 hipError_t launch_axis(const GroupDev& g, int axis, int mode, const PassArgs& a, hipStream_t s);
 hipError_t launch_axis_adjoint(const GroupDev& g, int axis, int mode, const PassArgs& a, hipStream_t s);
@@ -61,7 +62,7 @@ hipError_t launch_axis_last(const GroupDev& g, int axis, int mode, const PassArg
 hipError_t launch_line_adjoint(const GroupDev& g, const float2* psi_n, float2* lam, double* vbar, int64_t step,
                                hipStream_t s);
 hipError_t launch_vbar_to_float(const double* vbar, float* out, int64_t n, hipStream_t s);
-hipError_t launch_line_step(const GroupDev& g, float2* psi, int nsteps, int64_t step_off, const int64_t* step_base,
+hipError_t launch_line_step(const GroupDev& g, float2* psi, int nsteps, int64_t step_off, const int64_t* step_base, bool f64,
                             hipStream_t s);
 hipError_t launch_diag_axis(const GroupDev& g, int axis, const float2* psi, double kscale, double* part,
                             hipStream_t s);

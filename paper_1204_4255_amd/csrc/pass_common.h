@@ -27,6 +27,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "device_common.h"
 #include "launch.h"
 
@@ -37,9 +39,8 @@ __device__ __forceinline__ int64_t read_step(int64_t step_off, const int64_t* st
 }
 
 // Copy an axis's twiddle and (E - 1)/n tables into LDS (the caller synchronises).
-template <int N>
-__device__ __forceinline__ void stage_tables(c32* s_tw, float2* s_E, const float2* __restrict__ tw,
-                                             const float2* __restrict__ E) {
+template <int N, class V>
+__device__ __forceinline__ void stage_tables(V* s_tw, V* s_E, const V* __restrict__ tw, const V* __restrict__ E) {
     for (int i = threadIdx.x; i < N; i += blockDim.x) {
         s_tw[i] = tw[i];
         if (s_E) s_E[i] = E[i];
@@ -48,28 +49,35 @@ __device__ __forceinline__ void stage_tables(c32* s_tw, float2* s_E, const float
 
 // D_a on NF lines held in registers, in delta form: f <- f + F^{-1}[(E_a - 1)/n F f]
 // (adj: the transpose, with the conjugate multiplier). tw and E point to LDS copies of
-// the tables. All threads of the block call it.
-template <class F, class L, int NF>
-__device__ __forceinline__ void propagate(c32 (&f)[NF][F::R], int t, int l, c32* lds, const c32* tw,
-                                          const float2* E, bool adj) {
-    c32 o[NF][F::R];
+// the tables. V is the working type of the transform: float2, or double2 for the
+// FP64-transform form (the correction is formed and added to f in FP64 and rounded to
+// FP32 once). All threads of the block call it.
+__device__ __forceinline__ c32 widen(c32 a, c32) { return a; }
+__device__ __forceinline__ c64 widen(c32 a, c64) { return make_double2((double)a.x, (double)a.y); }
+__device__ __forceinline__ c32 narrow(c32 a) { return a; }
+__device__ __forceinline__ c32 narrow(c64 a) { return make_float2((float)a.x, (float)a.y); }
+
+template <class F, class L, int NF, class V>
+__device__ __forceinline__ void propagate(c32 (&f)[NF][F::R], int t, int l, V* lds, const V* tw, const V* E,
+                                          bool adj) {
+    V d[NF][F::R];
 #pragma unroll
     for (int q = 0; q < NF; q++)
 #pragma unroll
-        for (int m = 0; m < F::R; m++) o[q][m] = f[q][m];
-    fft_line<F, -1, L, NF>(f, t, l, lds, tw);
+        for (int m = 0; m < F::R; m++) d[q][m] = widen(f[q][m], V{});
+    fft_line<F, -1, L, NF>(d, t, l, lds, tw);
 #pragma unroll
     for (int m = 0; m < F::R; m++) {
-        float2 cs = E[t + m * F::T];
+        V cs = E[t + m * F::T];
         if (adj) cs.y = -cs.y;
 #pragma unroll
-        for (int q = 0; q < NF; q++) f[q][m] = cmul(f[q][m], cs);
+        for (int q = 0; q < NF; q++) d[q][m] = cmul(d[q][m], cs);
     }
-    fft_line<F, +1, L, NF>(f, t, l, lds, tw);
+    fft_line<F, +1, L, NF>(d, t, l, lds, tw);
 #pragma unroll
     for (int q = 0; q < NF; q++)
 #pragma unroll
-        for (int m = 0; m < F::R; m++) f[q][m] = cadd(f[q][m], o[q][m]);
+        for (int m = 0; m < F::R; m++) f[q][m] = narrow(cadd(widen(f[q][m], V{}), d[q][m]));
 }
 
 // Which lines a workgroup owns and where element e of its line l lives.
@@ -176,16 +184,20 @@ constexpr bool uses_rhs(int mode) {
 //          (lowest register peak, fewer loads in flight per wave).
 // RR: values per thread in the transform (16, or 8 for half the registers and one more
 // LDS exchange per transform).
-template <int N, int MODE, bool CONTIG, int LINES, bool NOISE, int SEQ, int RR>
+template <int N, int MODE, bool CONTIG, int LINES, bool NOISE, int SEQ, int RR, bool P64>
 __global__ void __launch_bounds__((FFTShape<N, RR>::T * LINES)) k_axis(GroupDev g, int axis, PassArgs args) {
     using F = FFTShape<N, RR>;
+    using V = typename std::conditional<P64, c64, c32>::type;  // transform working type
     constexpr int R = F::R, T = F::T;
     constexpr int NF = fields_of(MODE);
     using L = LdsLayout<N, LINES, CONTIG>;
-    __shared__ c32 lds[(SEQ != 0 ? 1 : NF) * L::SIZE];
-    __shared__ c32 tw[N];
-    __shared__ float2 E[N];
-    stage_tables<N>(tw, E, g.tw[axis], g.E[axis]);
+    __shared__ V lds[(SEQ != 0 ? 1 : NF) * L::SIZE];
+    __shared__ V tw[N];
+    __shared__ V E[N];
+    if constexpr (P64)
+        stage_tables<N>(tw, E, g.tw64[axis], g.E64[axis]);
+    else
+        stage_tables<N>(tw, E, g.tw[axis], g.E[axis]);
     const int t = CONTIG ? (int)(threadIdx.x % T) : (int)(threadIdx.x / LINES);
     const int l = CONTIG ? (int)(threadIdx.x / T) : (int)(threadIdx.x % LINES);
     const Tile<F, CONTIG, LINES> tile(g, axis, l, t);
@@ -388,7 +400,7 @@ static inline int contig_lines(int N) {
 
 
 
-template <int N, int MODE, bool CONTIG, int LINES, int SEQ, int RR>
+template <int N, int MODE, bool CONTIG, int LINES, int SEQ, int RR, bool P64>
 static hipError_t go_axis(const GroupDev& g, int axis, const PassArgs& a, hipStream_t s) {
     int64_t blocks;
     if (CONTIG)
@@ -398,11 +410,11 @@ static hipError_t go_axis(const GroupDev& g, int axis, const PassArgs& a, hipStr
     const dim3 grid((unsigned)blocks), block(FFTShape<N, RR>::T * LINES);
     if constexpr (uses_rhs(MODE)) {
         if (g.has_noise) {
-            hipLaunchKernelGGL((k_axis<N, MODE, CONTIG, LINES, true, SEQ, RR>), grid, block, 0, s, g, axis, a);
+            hipLaunchKernelGGL((k_axis<N, MODE, CONTIG, LINES, true, SEQ, RR, P64>), grid, block, 0, s, g, axis, a);
             return hipGetLastError();
         }
     }
-    hipLaunchKernelGGL((k_axis<N, MODE, CONTIG, LINES, false, SEQ, RR>), grid, block, 0, s, g, axis, a);
+    hipLaunchKernelGGL((k_axis<N, MODE, CONTIG, LINES, false, SEQ, RR, P64>), grid, block, 0, s, g, axis, a);
     return hipGetLastError();
 }
 
@@ -417,6 +429,8 @@ constexpr bool strided_only(int mode) {
 constexpr bool tuned_length(int N) { return N >= 128 && N <= 512; }
 // forward-step passes get the schedule variants; the adjoint passes use the default
 constexpr bool tuned_mode(int mode) { return mode <= PASS_LAST2 || mode == PASS_LF || mode == PASS_XF; }
+// passes compiled with FP64 transforms (the forward step and the plain propagator)
+constexpr bool f64_mode(int mode) { return tuned_mode(mode); }
 // passes that read both fields of the pair from memory
 constexpr bool loads_two_fields(int mode) {
     return mode == PASS_D2 || mode == PASS_LAST2 || mode == PASS_AS || mode == PASS_AF ||
@@ -425,15 +439,37 @@ constexpr bool loads_two_fields(int mode) {
 
 constexpr int default_contig_lines(int N) { return N < 16 ? 256 : ((256 / (N / 16)) < 1 ? 1 : 256 / (N / 16)); }
 
+// LDS bytes of a pass with FP64 transforms: nf exchange buffers plus the two tables.
+constexpr bool fits_lds64(int N, int lines, int nf, bool contig) {
+    const long row = contig ? (long)N + (N >= 16 ? N / 16 : 0) : (long)N;
+    return ((long)nf * row * lines + 2L * N) * 16 <= 160L * 1024;
+}
+
 // Is schedule (lines, seq, rr) of pass MODE compiled for length N on the contiguous or a
-// strided axis? Mirrors the instantiations in go_axis_n. rr = values per thread.
+// strided axis, with FP32 or FP64 transforms? Mirrors the instantiations in go_axis_n.
+// rr = values per thread.
 template <int N, int MODE>
-constexpr bool schedule_compiled(bool contig, int lines, int seq, int rr) {
+constexpr bool schedule_compiled(bool contig, int lines, int seq, int rr, bool p64) {
     constexpr int NF = fields_of(MODE);
     const bool tuned = tuned_length(N) && tuned_mode(MODE);
+    if (seq < 0 || seq > 2) return false;
+    if (p64) {
+        // radix 8 only (FP64 values take twice the registers), at most 512 threads
+        if (!f64_mode(MODE) || rr != 8 || lines < 1) return false;
+        if (seq && NF != 2) return false;
+        if (seq == 2 && (!tuned || !loads_two_fields(MODE))) return false;
+        const int nf = seq ? 1 : NF;
+        const int T = N / (N < 8 ? N : 8);
+        if (T * lines > 512 || !fits_lds64(N, lines, nf, contig)) return false;
+        if (contig) {
+            const int dl = default_contig_lines(N);
+            if (tuned) return lines == dl || lines == dl / 2 || lines == dl / 4;
+            return lines == (dl / 2 >= 1 ? dl / 2 : 1);
+        }
+        return lines == 4 || lines == 8 || lines == 16;
+    }
     if (rr != 16 && !(rr == 8 && tuned)) return false;
     const int T = N / (N < rr ? N : rr);
-    if (seq < 0 || seq > 2) return false;
     if (seq && (NF != 2 || !tuned)) return false;
     if (seq == 2 && !loads_two_fields(MODE)) return false;
     const int nf = seq ? 1 : NF;
@@ -450,38 +486,46 @@ constexpr bool schedule_compiled(bool contig, int lines, int seq, int rr) {
     return true;
 }
 
-template <int N, int MODE, bool CONTIG, int LINES, int RR>
+template <int N, int MODE, bool CONTIG, int LINES, int RR, bool P64>
 static hipError_t go_axis_sched_rr(const GroupDev& g, int axis, const PassArgs& a, hipStream_t s) {
-    if constexpr (schedule_compiled<N, MODE>(CONTIG, LINES, 2, RR)) {
-        if (a.seq == 2) return go_axis<N, MODE, CONTIG, LINES, 2, RR>(g, axis, a, s);
+    if constexpr (schedule_compiled<N, MODE>(CONTIG, LINES, 2, RR, P64)) {
+        if (a.seq == 2) return go_axis<N, MODE, CONTIG, LINES, 2, RR, P64>(g, axis, a, s);
     }
-    if constexpr (schedule_compiled<N, MODE>(CONTIG, LINES, 1, RR)) {
-        if (a.seq == 1) return go_axis<N, MODE, CONTIG, LINES, 1, RR>(g, axis, a, s);
+    if constexpr (schedule_compiled<N, MODE>(CONTIG, LINES, 1, RR, P64)) {
+        if (a.seq == 1) return go_axis<N, MODE, CONTIG, LINES, 1, RR, P64>(g, axis, a, s);
     }
-    if constexpr (schedule_compiled<N, MODE>(CONTIG, LINES, 0, RR)) {
-        if (a.seq == 0) return go_axis<N, MODE, CONTIG, LINES, 0, RR>(g, axis, a, s);
+    if constexpr (schedule_compiled<N, MODE>(CONTIG, LINES, 0, RR, P64)) {
+        if (a.seq == 0) return go_axis<N, MODE, CONTIG, LINES, 0, RR, P64>(g, axis, a, s);
     }
     return hipErrorInvalidValue;
 }
 
-template <int N, int MODE, bool CONTIG, int LINES>
+template <int N, int MODE, bool CONTIG, int LINES, bool P64>
 static hipError_t go_axis_sched(const GroupDev& g, int axis, const PassArgs& a, hipStream_t s) {
-    if (a.radix == 8) return go_axis_sched_rr<N, MODE, CONTIG, LINES, 8>(g, axis, a, s);
-    if (a.radix == 0 || a.radix == 16) return go_axis_sched_rr<N, MODE, CONTIG, LINES, 16>(g, axis, a, s);
-    return hipErrorInvalidValue;
+    if constexpr (P64) {
+        if (a.radix == 8) return go_axis_sched_rr<N, MODE, CONTIG, LINES, 8, true>(g, axis, a, s);
+        return hipErrorInvalidValue;
+    } else {
+        if (a.radix == 8) return go_axis_sched_rr<N, MODE, CONTIG, LINES, 8, false>(g, axis, a, s);
+        if (a.radix == 0 || a.radix == 16) return go_axis_sched_rr<N, MODE, CONTIG, LINES, 16, false>(g, axis, a, s);
+        return hipErrorInvalidValue;
+    }
 }
 
-template <int N, int MODE>
-static hipError_t go_axis_n(const GroupDev& g, int axis, const PassArgs& a, hipStream_t s) {
+template <int N, int MODE, bool P64>
+static hipError_t go_axis_np(const GroupDev& g, int axis, const PassArgs& a, hipStream_t s) {
     constexpr int CL = default_contig_lines(N);
     if (axis == 0) {
         if constexpr (strided_only(MODE)) {
             return hipErrorInvalidValue;
         } else {
             const int lines = a.lines ? a.lines : CL;
-            if (lines == CL) return go_axis_sched<N, MODE, true, CL>(g, axis, a, s);
+            if (lines == CL) return go_axis_sched<N, MODE, true, CL, P64>(g, axis, a, s);
             if constexpr (CL / 2 >= 1) {
-                if (lines == CL / 2) return go_axis_sched<N, MODE, true, (CL / 2 >= 1 ? CL / 2 : 1)>(g, axis, a, s);
+                if (lines == CL / 2) return go_axis_sched<N, MODE, true, (CL / 2 >= 1 ? CL / 2 : 1), P64>(g, axis, a, s);
+            }
+            if constexpr (P64 && CL / 4 >= 1) {
+                if (lines == CL / 4) return go_axis_sched<N, MODE, true, (CL / 4 >= 1 ? CL / 4 : 1), P64>(g, axis, a, s);
             }
             return hipErrorInvalidValue;
         }
@@ -492,24 +536,34 @@ static hipError_t go_axis_n(const GroupDev& g, int axis, const PassArgs& a, hipS
         const int w = a.lines ? a.lines : strided_lines(N, g.n[0]);
         if (w > g.n[0]) return hipErrorInvalidValue;
         switch (w) {
-            case 32: return go_axis_sched<N, MODE, false, 32>(g, axis, a, s);
-            case 16: return go_axis_sched<N, MODE, false, 16>(g, axis, a, s);
-            case 8: return go_axis_sched<N, MODE, false, 8>(g, axis, a, s);
-            case 4: return go_axis_sched<N, MODE, false, 4>(g, axis, a, s);
+            case 32: return go_axis_sched<N, MODE, false, 32, P64>(g, axis, a, s);
+            case 16: return go_axis_sched<N, MODE, false, 16, P64>(g, axis, a, s);
+            case 8: return go_axis_sched<N, MODE, false, 8, P64>(g, axis, a, s);
+            case 4: return go_axis_sched<N, MODE, false, 4, P64>(g, axis, a, s);
             default: return hipErrorInvalidValue;
         }
     }
 }
 
+template <int N, int MODE>
+static hipError_t go_axis_n(const GroupDev& g, int axis, const PassArgs& a, hipStream_t s) {
+    if constexpr (f64_mode(MODE)) {
+        if (a.f64) return go_axis_np<N, MODE, true>(g, axis, a, s);
+    } else {
+        if (a.f64) return hipErrorInvalidValue;
+    }
+    return go_axis_np<N, MODE, false>(g, axis, a, s);
+}
+
 template <int N>
-static bool schedule_ok_n(int mode, bool contig, int lines, int seq, int rr) {
+static bool schedule_ok_n(int mode, bool contig, int lines, int seq, int rr, bool p64) {
     switch (mode) {
-        case PASS_D1: return schedule_compiled<N, PASS_D1>(contig, lines, seq, rr);
-        case PASS_D2: return schedule_compiled<N, PASS_D2>(contig, lines, seq, rr);
-        case PASS_FIRST: return contig && schedule_compiled<N, PASS_FIRST>(contig, lines, seq, rr);
-        case PASS_LAST2: return contig && schedule_compiled<N, PASS_LAST2>(contig, lines, seq, rr);
-        case PASS_LF: return !contig && schedule_compiled<N, PASS_LF>(contig, lines, seq, rr);
-        case PASS_XF: return contig && schedule_compiled<N, PASS_XF>(contig, lines, seq, rr);
+        case PASS_D1: return schedule_compiled<N, PASS_D1>(contig, lines, seq, rr, p64);
+        case PASS_D2: return schedule_compiled<N, PASS_D2>(contig, lines, seq, rr, p64);
+        case PASS_FIRST: return contig && schedule_compiled<N, PASS_FIRST>(contig, lines, seq, rr, p64);
+        case PASS_LAST2: return contig && schedule_compiled<N, PASS_LAST2>(contig, lines, seq, rr, p64);
+        case PASS_LF: return !contig && schedule_compiled<N, PASS_LF>(contig, lines, seq, rr, p64);
+        case PASS_XF: return contig && schedule_compiled<N, PASS_XF>(contig, lines, seq, rr, p64);
         default: return false;
     }
 }

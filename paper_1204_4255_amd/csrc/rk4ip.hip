@@ -22,7 +22,8 @@ namespace {
 
 constexpr double kPi = 3.14159265358979323846;
 constexpr size_t kAlign = 256;
-constexpr uint32_t kKnownFlags = RK4IP_FLAG_GRAPH | RK4IP_FLAG_AUTOTUNE | RK4IP_FLAG_FUSE_1D;
+constexpr uint32_t kKnownFlags =
+    RK4IP_FLAG_GRAPH | RK4IP_FLAG_AUTOTUNE | RK4IP_FLAG_FUSE_1D | RK4IP_FLAG_FP64_TRANSFORMS;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -49,6 +50,8 @@ struct GroupHost {
     int64_t first_inst = 0;  // index of the group's first instance among all instances
     size_t tab_off[3] = {0, 0, 0};   // E table offsets in the workspace
     size_t tw_off[3] = {0, 0, 0};    // twiddle table offsets
+    size_t tab64_off[3] = {0, 0, 0}; // FP64 copies (FP64-transform plans)
+    size_t tw64_off[3] = {0, 0, 0};
     size_t part_off[3] = {0, 0, 0};  // diagnostic partials (batch * M/n_a * 4 doubles)
     double dV = 1.0;
 };
@@ -75,7 +78,8 @@ int validate(const rk4ip_problem* probs, int nprob, uint32_t flags) {
         if (p.batch < 1 || p.batch > (int64_t(1) << 31)) return RK4IP_ERR_INVALID_ARG;
         if ((uint64_t)p.id_base + (uint64_t)p.batch - 1 > 0xFFFFFFFFull) return RK4IP_ERR_INVALID_ARG;
         if (p.ndim < 1 || p.ndim > 3) return RK4IP_ERR_UNSUPPORTED_SHAPE;
-        const int64_t nmax = p.ndim == 1 ? 4096 : 1024;
+        // FP64 transforms keep their tables and exchange buffers in LDS up to 2048 points
+        const int64_t nmax = p.ndim == 1 ? ((flags & RK4IP_FLAG_FP64_TRANSFORMS) ? 2048 : 4096) : 1024;
         int64_t M = 1;
         for (int a = 0; a < 3; a++) {
             if (a < p.ndim) {
@@ -96,11 +100,12 @@ int validate(const rk4ip_problem* probs, int nprob, uint32_t flags) {
 }
 
 // Offsets of every table and buffer; fills `gh` when non-null.
-Layout layout(const rk4ip_problem* probs, int nprob, std::vector<GroupHost>* gh) {
+Layout layout(const rk4ip_problem* probs, int nprob, uint32_t flags, std::vector<GroupHost>* gh) {
     Layout L;
     size_t off = 0;
     L.header = off;
     off += kAlign;
+    const bool f64 = (flags & RK4IP_FLAG_FP64_TRANSFORMS) != 0;
     for (int i = 0; i < nprob; i++) {
         const rk4ip_problem& p = probs[i];
         for (int a = 0; a < p.ndim; a++) {
@@ -108,9 +113,18 @@ Layout layout(const rk4ip_problem* probs, int nprob, std::vector<GroupHost>* gh)
             off = align_up(off + sizeof(float2) * (size_t)p.n[a]);
             size_t t = off;
             off = align_up(off + sizeof(float2) * (size_t)p.n[a]);
+            size_t e64 = 0, t64 = 0;
+            if (f64) {
+                e64 = off;
+                off = align_up(off + sizeof(double2) * (size_t)p.n[a]);
+                t64 = off;
+                off = align_up(off + sizeof(double2) * (size_t)p.n[a]);
+            }
             if (gh) {
                 (*gh)[i].tab_off[a] = e;
                 (*gh)[i].tw_off[a] = t;
+                (*gh)[i].tab64_off[a] = e64;
+                (*gh)[i].tw64_off[a] = t64;
             }
         }
     }
@@ -144,6 +158,7 @@ struct rk4ip_plan_s {
     float2* B = nullptr;
     int64_t* counter = nullptr;
     int* flag = nullptr;
+    bool f64 = false;  // FP64 transforms in the forward step
     std::string err;
     std::vector<std::vector<std::string>> sched_names;  // [group][pass]
     std::vector<std::vector<Sched>> sched;  // [group][pass]; zeros = default schedule
@@ -196,8 +211,9 @@ void drop_graph(rk4ip_plan_t plan) {
     plan->graph_steps = 0;
 }
 
-// Tables of one axis (FP64 arithmetic, FP32 storage).
-void build_tables(const rk4ip_problem& p, int a, std::vector<float2>& E, std::vector<float2>& tw) {
+// Tables of one axis (FP64 arithmetic; stored in FP32, and in FP64 for FP64-transform plans).
+void build_tables(const rk4ip_problem& p, int a, std::vector<float2>& E, std::vector<float2>& tw,
+                  std::vector<double2>* E64 = nullptr, std::vector<double2>* tw64 = nullptr) {
     const int64_t n = p.n[a];
     const double Lx = p.hi[a] - p.lo[a];
     const double h = p.dt;
@@ -205,6 +221,8 @@ void build_tables(const rk4ip_problem& p, int a, std::vector<float2>& E, std::ve
     const double em1 = (a == 0) ? std::expm1(-p.gamma * h / 2.0) : 0.0;
     E.resize(n);
     tw.resize(n);
+    if (E64) E64->resize(n);
+    if (tw64) tw64->resize(n);
     const double inv_n = 1.0 / (double)n;  // exact power of two
     for (int64_t m = 0; m < n; m++) {
         const double k = 2.0 * kPi / Lx * (double)(m < n / 2 ? m : m - n);
@@ -217,6 +235,8 @@ void build_tables(const rk4ip_problem& p, int a, std::vector<float2>& E, std::ve
         E[m] = make_float2((float)(c * inv_n), (float)(s * inv_n));
         const double ang = 2.0 * kPi * (double)m / (double)n;
         tw[m] = make_float2((float)std::cos(ang), (float)-std::sin(ang));
+        if (E64) (*E64)[m] = make_double2(c * inv_n, s * inv_n);
+        if (tw64) (*tw64)[m] = make_double2(std::cos(ang), -std::sin(ang));
     }
 }
 
@@ -306,6 +326,7 @@ int time_pass(rk4ip_plan_t plan, const GroupHost& g, int axis, int mode, const S
     pa.B = plan->B;
     pa.psi = (mode == rk4ip::PASS_FIRST) ? plan->B : plan->A;  // same tiles are read before written
     pa.step_off = 1;
+    pa.f64 = plan->f64 ? 1 : 0;
     pa.lines = sc.lines;
     pa.seq = sc.seq;
     pa.radix = sc.radix;
@@ -328,8 +349,8 @@ int time_pass(rk4ip_plan_t plan, const GroupHost& g, int axis, int mode, const S
 // RK4IP_TUNE_CACHE (optional).
 std::string tune_key(const GroupHost& g, int pass) {
     char k[160];
-    std::snprintf(k, sizeof(k), "gfx950|n=%lld,%lld,%lld|b=%lld|pass=%d", (long long)g.p.n[0], (long long)g.p.n[1],
-                  (long long)g.p.n[2], (long long)g.p.batch, pass);
+    std::snprintf(k, sizeof(k), "gfx950|n=%lld,%lld,%lld|b=%lld|pass=%d%s", (long long)g.p.n[0], (long long)g.p.n[1],
+                  (long long)g.p.n[2], (long long)g.p.batch, pass, g.d.E64[0] ? "|f64" : "");
     return k;
 }
 
@@ -341,6 +362,29 @@ bool cache_lookup(const std::string& text, const std::string& key, Sched* sc) {
     if (p == std::string::npos) return false;
     return std::sscanf(text.c_str() + p, "[%d , %d , %d]", &sc->lines, &sc->seq, &sc->radix) == 3 ||
            std::sscanf(text.c_str() + p, "[%d,%d,%d]", &sc->lines, &sc->seq, &sc->radix) == 3;
+}
+
+// The schedule an FP64-transform pass runs without tuning: the first compiled one in a
+// fixed order of preference (half the default lines on the contiguous axis, the default
+// columns on a strided one; both fields at once before one after the other).
+bool default_f64_sched(const GroupHost& g, int axis, int mode, Sched* out) {
+    const int N = (int)g.p.n[axis], n0 = (int)g.p.n[0];
+    const int cl = rk4ip::axis_lines(N, 0, n0);
+    const int contig_pref[] = {cl / 2, cl / 4, cl, 1};
+    const int strided_pref[] = {rk4ip::axis_lines(N, axis, n0), 8, 4, 16};
+    for (int i = 0; i < 4; i++) {
+        const int lines = axis == 0 ? contig_pref[i] : strided_pref[i];
+        if (lines < 1) continue;
+        for (int sq = 0; sq < 3; sq++) {
+            if (rk4ip::axis_schedule_ok(N, mode, axis, n0, lines, sq, 8, true)) {
+                out->lines = lines;
+                out->seq = sq;
+                out->radix = 8;
+                return true;
+            }
+        }
+    }
+    return false;
 }
 
 // Choose the fastest compiled schedule of every pass (RK4IP_FLAG_AUTOTUNE).
@@ -367,7 +411,7 @@ int autotune(rk4ip_plan_t plan) {
             const int N = (int)g.p.n[axis], n0 = (int)g.p.n[0];
             Sched c;
             if (cache_lookup(text, tune_key(g, i), &c) &&
-                rk4ip::axis_schedule_ok(N, mode, axis, n0, c.lines, c.seq, c.radix)) {
+                rk4ip::axis_schedule_ok(N, mode, axis, n0, c.lines, c.seq, c.radix, plan->f64)) {
                 plan->sched[gi][i] = c;
                 continue;
             }
@@ -378,7 +422,7 @@ int autotune(rk4ip_plan_t plan) {
             for (int rr : cand_radix)
                 for (int lines : cand_lines)
                     for (int sq = 0; sq < 3; sq++) {
-                        if (!rk4ip::axis_schedule_ok(N, mode, axis, n0, lines, sq, rr)) continue;
+                        if (!rk4ip::axis_schedule_ok(N, mode, axis, n0, lines, sq, rr, plan->f64)) continue;
                         Sched cand;
                         cand.lines = lines;
                         cand.seq = sq;
@@ -428,13 +472,13 @@ int enqueue_lines(rk4ip_plan_t plan, hipStream_t stream, float2* psi, int64_t st
         if (g.p.ndim != 1 || nsteps <= 0) continue;
         if (allow_fuse && (plan->flags & RK4IP_FLAG_FUSE_1D)) {
             rc = timed_launch(plan, stream, (int)gi, 0, capturing, [&] {
-                return rk4ip::launch_line_step(g.d, psi, (int)nsteps, step_off, step_base, stream);
+                return rk4ip::launch_line_step(g.d, psi, (int)nsteps, step_off, step_base, plan->f64, stream);
             });
             if (rc) return rc;
         } else {
             for (int64_t s = 0; s < nsteps; s++) {
                 rc = timed_launch(plan, stream, (int)gi, 0, capturing, [&] {
-                    return rk4ip::launch_line_step(g.d, psi, 1, step_off + s, step_base, stream);
+                    return rk4ip::launch_line_step(g.d, psi, 1, step_off + s, step_base, plan->f64, stream);
                 });
                 if (rc) return rc;
             }
@@ -464,6 +508,7 @@ int enqueue_lattice(rk4ip_plan_t plan, hipStream_t stream, float2* psi, int64_t 
                 pa.B = plan->B;
                 pa.step_off = step;
                 pa.step_base = step_base;
+                pa.f64 = plan->f64 ? 1 : 0;
                 pa.lines = plan->sched[gi][i].lines;
                 pa.seq = plan->sched[gi][i].seq;
                 pa.radix = plan->sched[gi][i].radix;
@@ -627,7 +672,7 @@ const char* rk4ip_strerror(int status) {
 
 size_t rk4ip_workspace_bytes(const rk4ip_problem* probs, int nprob, uint32_t flags) {
     if (validate(probs, nprob, flags) != RK4IP_OK) return 0;
-    return layout(probs, nprob, nullptr).total;
+    return layout(probs, nprob, flags, nullptr).total;
 }
 
 int rk4ip_plan(const rk4ip_problem* probs, int nprob, void* workspace, size_t ws_bytes, void* stream,
@@ -638,7 +683,7 @@ int rk4ip_plan(const rk4ip_problem* probs, int nprob, void* workspace, size_t ws
     if (rc != RK4IP_OK) return rc;
     if (!workspace || (reinterpret_cast<uintptr_t>(workspace) % kAlign) != 0) return RK4IP_ERR_INVALID_ARG;
     std::vector<GroupHost> gh(nprob);
-    Layout L = layout(probs, nprob, &gh);
+    Layout L = layout(probs, nprob, flags, &gh);
     if (ws_bytes < L.total) return RK4IP_ERR_WORKSPACE_TOO_SMALL;
 
     rk4ip_plan_s* plan = new (std::nothrow) rk4ip_plan_s();
@@ -652,6 +697,7 @@ int rk4ip_plan(const rk4ip_problem* probs, int nprob, void* workspace, size_t ws
     plan->ws_bytes = ws_bytes;
     plan->stream = static_cast<hipStream_t>(stream);
     plan->flags = flags;
+    plan->f64 = (flags & RK4IP_FLAG_FP64_TRANSFORMS) != 0;
     plan->points = L.points;
     plan->counter = reinterpret_cast<int64_t*>(plan->ws + L.header);
     plan->flag = reinterpret_cast<int*>(plan->ws + L.header + 64);
@@ -696,9 +742,16 @@ int rk4ip_plan(const rk4ip_problem* probs, int nprob, void* workspace, size_t ws
         d.Vgrid = p.V_grid;
         for (int a = 0; a < p.ndim; a++) {
             std::vector<float2> E, tw;
-            build_tables(p, a, E, tw);
+            std::vector<double2> E64, tw64;
+            build_tables(p, a, E, tw, plan->f64 ? &E64 : nullptr, plan->f64 ? &tw64 : nullptr);
             hipError_t e1 = hipMemcpy(plan->ws + g.tab_off[a], E.data(), sizeof(float2) * E.size(), hipMemcpyHostToDevice);
             hipError_t e2 = hipMemcpy(plan->ws + g.tw_off[a], tw.data(), sizeof(float2) * tw.size(), hipMemcpyHostToDevice);
+            if (e1 == hipSuccess && e2 == hipSuccess && plan->f64) {
+                e1 = hipMemcpy(plan->ws + g.tab64_off[a], E64.data(), sizeof(double2) * E64.size(),
+                               hipMemcpyHostToDevice);
+                e2 = hipMemcpy(plan->ws + g.tw64_off[a], tw64.data(), sizeof(double2) * tw64.size(),
+                               hipMemcpyHostToDevice);
+            }
             if (e1 != hipSuccess || e2 != hipSuccess) {
                 rc = fail_hip(plan, e1 != hipSuccess ? e1 : e2, "table upload");
                 delete plan;
@@ -706,6 +759,10 @@ int rk4ip_plan(const rk4ip_problem* probs, int nprob, void* workspace, size_t ws
             }
             d.E[a] = reinterpret_cast<const float2*>(plan->ws + g.tab_off[a]);
             d.tw[a] = reinterpret_cast<const float2*>(plan->ws + g.tw_off[a]);
+            if (plan->f64) {
+                d.E64[a] = reinterpret_cast<const double2*>(plan->ws + g.tab64_off[a]);
+                d.tw64[a] = reinterpret_cast<const double2*>(plan->ws + g.tw64_off[a]);
+            }
         }
         g.first_inst = inst;
         offset += p.batch * g.M;
@@ -717,6 +774,21 @@ int rk4ip_plan(const rk4ip_problem* probs, int nprob, void* workspace, size_t ws
     }
     plan->ninst = inst;
     plan->groups = std::move(gh);
+    if (plan->f64) {
+        // FP64 transforms have no implicit default tile: take the first compiled candidate
+        for (size_t gi = 0; gi < plan->groups.size(); gi++) {
+            const GroupHost& g = plan->groups[gi];
+            if (g.p.ndim == 1) continue;
+            PassDef defs[kMaxPasses];
+            const int np = pass_list(g.p.ndim, defs);
+            for (int k = 0; k < np; k++) {
+                if (!default_f64_sched(g, defs[k].axis, defs[k].mode, &plan->sched[gi][k])) {
+                    delete plan;
+                    return RK4IP_ERR_UNSUPPORTED_SHAPE;
+                }
+            }
+        }
+    }
     if (flags & RK4IP_FLAG_AUTOTUNE) {
         rc = autotune(plan);
         if (rc != RK4IP_OK) {
@@ -730,7 +802,7 @@ int rk4ip_plan(const rk4ip_problem* probs, int nprob, void* workspace, size_t ws
         char name[160];
         std::vector<std::string> names;
         if (p.ndim == 1) {
-            std::snprintf(name, sizeof(name), "line_step:n%lld", (long long)p.n[0]);
+            std::snprintf(name, sizeof(name), "line_step:n%lld%s", (long long)p.n[0], plan->f64 ? ":f64" : "");
             names.push_back(name);
         } else {
             PassDef defs[kMaxPasses];
@@ -739,9 +811,10 @@ int rk4ip_plan(const rk4ip_problem* probs, int nprob, void* workspace, size_t ws
                 const int a = defs[k].axis;
                 const Sched sc = plan->sched[gi][k];
                 const int lines = sc.lines ? sc.lines : rk4ip::axis_lines((int)p.n[a], a, (int)p.n[0]);
-                std::snprintf(name, sizeof(name), "%s:axis%d:n%lld:%s:lines%d:%s:r%d", mode_name(defs[k].mode), a,
+                std::snprintf(name, sizeof(name), "%s:axis%d:n%lld:%s:lines%d:%s:r%d%s", mode_name(defs[k].mode), a,
                               (long long)p.n[a], a == 0 ? "contig" : "strided", lines,
-                              sc.seq == 2 ? "seq-deferred" : (sc.seq ? "seq" : "joint"), sc.radix ? sc.radix : 16);
+                              sc.seq == 2 ? "seq-deferred" : (sc.seq ? "seq" : "joint"), sc.radix ? sc.radix : 16,
+                              plan->f64 ? ":f64" : "");
                 names.push_back(name);
             }
         }
@@ -1020,7 +1093,17 @@ int rk4ip_debug_apply_D(rk4ip_plan_t plan, void* psi, int adjoint) {
     pa.psi = static_cast<float2*>(psi);
     pa.adj = adjoint ? 1 : 0;
     for (auto& g : plan->groups)
-        for (int a = 0; a < g.p.ndim; a++) HIPCHK(plan, rk4ip::launch_axis(g.d, a, rk4ip::PASS_D1, pa, plan->stream));
+        for (int a = 0; a < g.p.ndim; a++) {
+            if (plan->f64) {
+                Sched sc;
+                if (!default_f64_sched(g, a, rk4ip::PASS_D1, &sc)) return RK4IP_ERR_UNSUPPORTED_SHAPE;
+                pa.f64 = 1;
+                pa.lines = sc.lines;
+                pa.seq = sc.seq;
+                pa.radix = sc.radix;
+            }
+            HIPCHK(plan, rk4ip::launch_axis(g.d, a, rk4ip::PASS_D1, pa, plan->stream));
+        }
     return RK4IP_OK;
 }
 

@@ -31,6 +31,7 @@ RK4IP_ERR_NO_DEVICE = -7
 RK4IP_FLAG_GRAPH = 0x1
 RK4IP_FLAG_AUTOTUNE = 0x2
 RK4IP_FLAG_FUSE_1D = 0x4
+RK4IP_FLAG_FP64_TRANSFORMS = 0x8
 
 # every symbol include/rk4ip.h declares
 EXPORTS = [

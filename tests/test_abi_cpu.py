@@ -115,3 +115,18 @@ def test_valid_plan_without_gpu_reports_no_device(lib):
     nb = rk4ip.rk4ip_workspace_bytes([_p()])
     rc = lib.rk4ip_plan(arr, 1, ctypes.c_void_p(256), nb, None, 0, ctypes.byref(h))
     assert rc == rk4ip.RK4IP_ERR_NO_DEVICE and not h.value
+
+
+def test_fp64_transform_flag_sizes_and_limits(lib):
+    """The FP64-transform form adds FP64 copies of the tables to the workspace and limits
+    1D lines to 2048 points (its tables and exchange buffers live in LDS)."""
+    f64 = rk4ip.RK4IP_FLAG_FP64_TRANSFORMS
+    p = _p()
+    n32 = rk4ip.rk4ip_workspace_bytes([p])
+    n64 = rk4ip.rk4ip_workspace_bytes([p], f64)
+    assert n64 > n32 > 0
+    for n, ok in (((2048,), True), ((4096,), False)):
+        q = rk4ip.make_problem(n=n, lo=(0,), hi=(1,), dt=0.1)
+        assert (rk4ip.rk4ip_workspace_bytes([q], f64) > 0) == ok
+        assert rk4ip.rk4ip_workspace_bytes([q]) > 0
+    assert rk4ip.rk4ip_workspace_bytes([p], 0x100) == 0  # unknown flag bits
