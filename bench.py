@@ -270,8 +270,27 @@ def form_fp64_transforms(torch, rk4ip, workloads, steps: int = 100):
     return out
 
 
+def other_workloads(torch, rk4ip, workloads):
+    """Throughput of the 1D NLSE (256 points, 1000 steps) and the 2D GPE (512^2, 2000 steps)
+    at their full run lengths, graph-replayed with tuned schedules."""
+    out = {}
+    for name, w, flags in (("nlse1d_256", workloads.nlse1d(), rk4ip.RK4IP_FLAG_FUSE_1D),
+                           ("gpe2d_512^2", workloads.gpe2d(), rk4ip.RK4IP_FLAG_AUTOTUNE)):
+        probs, _k = rk4ip.problems_from_workload(w)
+        pts = sum(g.batch * g.M for g in w.groups)
+        plan = rk4ip.Plan(probs, flags=rk4ip.RK4IP_FLAG_GRAPH | flags)
+        psi0 = rk4ip.field_to_device(w)
+        psi = psi0.clone()
+        t = _timed(torch, lambda: (psi.copy_(psi0), plan.run(psi, w.nsteps)))
+        out[name] = {"steps": w.nsteps, "seconds": t, "pt_steps_per_s": pts * w.nsteps / t,
+                     "us_per_step": t / w.nsteps * 1e6}
+        plan.destroy()
+    return out
+
+
 def measure_forms(torch, rk4ip, workloads):
-    return {"batched_paths": form_batched_paths(torch, rk4ip, workloads),
+    return {"other_workloads": other_workloads(torch, rk4ip, workloads),
+            "batched_paths": form_batched_paths(torch, rk4ip, workloads),
             "uneven_batch": form_uneven_batch(torch, rk4ip, workloads),
             "adjoint": form_adjoint(torch, rk4ip, workloads),
             "fp64_transforms": form_fp64_transforms(torch, rk4ip, workloads)}
