@@ -7,13 +7,14 @@ namespace rk4ip {
 // ---------------------------------------------------------------------------- 1D step
 
 // One workgroup runs LPB whole lines (instances). Every value of the step stays in
-// registers; LDS only carries the FFT exchanges. P64: transforms in FP64 (8 values per
-// thread), everything else as in the complex64 form.
-template <int N, int LPB, bool NOISE, bool P64>
-__global__ void __launch_bounds__((FFTShape<N, (P64 ? 8 : 16)>::T * LPB))
+// registers; LDS only carries the FFT exchanges. RR values per thread (16 or 8: fewer
+// registers and more threads per line). P64: transforms in FP64 (RR = 8), everything
+// else as in the complex64 form.
+template <int N, int LPB, bool NOISE, bool P64, int RR>
+__global__ void __launch_bounds__((FFTShape<N, RR>::T * LPB))
     k_line_step(GroupDev g, float2* __restrict__ psi, int nsteps, int64_t step_off,
                 const int64_t* __restrict__ step_base) {
-    using F = FFTShape<N, (P64 ? 8 : 16)>;
+    using F = FFTShape<N, RR>;
     using L = LdsLayout<N, LPB, true>;
     using W = typename std::conditional<P64, c64, c32>::type;  // transform working type
     constexpr int R = F::R, T = F::T;
@@ -119,44 +120,46 @@ hipError_t launch_axis(const GroupDev& g, int axis, int mode, const PassArgs& a,
     }
 }
 
-template <int N, bool P64>
+template <int N, bool P64, int RR>
 static hipError_t go_line(const GroupDev& g, float2* psi, int nsteps, int64_t step_off, const int64_t* step_base,
                           hipStream_t s) {
-    constexpr int T = FFTShape<N, (P64 ? 8 : 16)>::T;
+    constexpr int T = FFTShape<N, RR>::T;
     constexpr int LPB = T >= 64 ? 1 : 64 / T;
     const int64_t blocks = (g.batch + LPB - 1) / LPB;
     if (g.has_noise)
-        hipLaunchKernelGGL((k_line_step<N, LPB, true, P64>), dim3((unsigned)blocks), dim3(T * LPB), 0, s, g, psi,
+        hipLaunchKernelGGL((k_line_step<N, LPB, true, P64, RR>), dim3((unsigned)blocks), dim3(T * LPB), 0, s, g, psi,
                            nsteps, step_off, step_base);
     else
-        hipLaunchKernelGGL((k_line_step<N, LPB, false, P64>), dim3((unsigned)blocks), dim3(T * LPB), 0, s, g, psi,
+        hipLaunchKernelGGL((k_line_step<N, LPB, false, P64, RR>), dim3((unsigned)blocks), dim3(T * LPB), 0, s, g, psi,
                            nsteps, step_off, step_base);
     return hipGetLastError();
 }
 
 template <int N>
 static hipError_t go_line_p(const GroupDev& g, float2* psi, int nsteps, int64_t step_off, const int64_t* step_base,
-                            bool f64, hipStream_t s) {
+                            bool f64, int radix, hipStream_t s) {
     if (f64) {
-        if constexpr (N <= 2048) return go_line<N, true>(g, psi, nsteps, step_off, step_base, s);
+        if constexpr (N <= 2048) return go_line<N, true, 8>(g, psi, nsteps, step_off, step_base, s);
         return hipErrorInvalidValue;  // FP64 tables and exchange buffers exceed the LDS
     }
-    return go_line<N, false>(g, psi, nsteps, step_off, step_base, s);
+    if (radix == 8) return go_line<N, false, 8>(g, psi, nsteps, step_off, step_base, s);
+    if (radix == 0 || radix == 16) return go_line<N, false, 16>(g, psi, nsteps, step_off, step_base, s);
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_line_step(const GroupDev& g, float2* psi, int nsteps, int64_t step_off, const int64_t* step_base,
-                            bool f64, hipStream_t s) {
+                            bool f64, int radix, hipStream_t s) {
     switch (g.n[0]) {
-        case 8: return go_line_p<8>(g, psi, nsteps, step_off, step_base, f64, s);
-        case 16: return go_line_p<16>(g, psi, nsteps, step_off, step_base, f64, s);
-        case 32: return go_line_p<32>(g, psi, nsteps, step_off, step_base, f64, s);
-        case 64: return go_line_p<64>(g, psi, nsteps, step_off, step_base, f64, s);
-        case 128: return go_line_p<128>(g, psi, nsteps, step_off, step_base, f64, s);
-        case 256: return go_line_p<256>(g, psi, nsteps, step_off, step_base, f64, s);
-        case 512: return go_line_p<512>(g, psi, nsteps, step_off, step_base, f64, s);
-        case 1024: return go_line_p<1024>(g, psi, nsteps, step_off, step_base, f64, s);
-        case 2048: return go_line_p<2048>(g, psi, nsteps, step_off, step_base, f64, s);
-        case 4096: return go_line_p<4096>(g, psi, nsteps, step_off, step_base, f64, s);
+        case 8: return go_line_p<8>(g, psi, nsteps, step_off, step_base, f64, radix, s);
+        case 16: return go_line_p<16>(g, psi, nsteps, step_off, step_base, f64, radix, s);
+        case 32: return go_line_p<32>(g, psi, nsteps, step_off, step_base, f64, radix, s);
+        case 64: return go_line_p<64>(g, psi, nsteps, step_off, step_base, f64, radix, s);
+        case 128: return go_line_p<128>(g, psi, nsteps, step_off, step_base, f64, radix, s);
+        case 256: return go_line_p<256>(g, psi, nsteps, step_off, step_base, f64, radix, s);
+        case 512: return go_line_p<512>(g, psi, nsteps, step_off, step_base, f64, radix, s);
+        case 1024: return go_line_p<1024>(g, psi, nsteps, step_off, step_base, f64, radix, s);
+        case 2048: return go_line_p<2048>(g, psi, nsteps, step_off, step_base, f64, radix, s);
+        case 4096: return go_line_p<4096>(g, psi, nsteps, step_off, step_base, f64, radix, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -63,7 +63,7 @@ hipError_t launch_line_adjoint(const GroupDev& g, const float2* psi_n, float2* l
                                hipStream_t s);
 hipError_t launch_vbar_to_float(const double* vbar, float* out, int64_t n, hipStream_t s);
 hipError_t launch_line_step(const GroupDev& g, float2* psi, int nsteps, int64_t step_off, const int64_t* step_base, bool f64,
-                            hipStream_t s);
+                            int radix, hipStream_t s);
 hipError_t launch_diag_axis(const GroupDev& g, int axis, const float2* psi, double kscale, double* part,
                             hipStream_t s);
 hipError_t launch_diag_final(const GroupDev& g, const DiagConst& c, const double* p0, const double* p1,

@@ -345,6 +345,24 @@ int time_pass(rk4ip_plan_t plan, const GroupHost& g, int axis, int mode, const S
     return RK4IP_OK;
 }
 
+// Mean time (ms) of `reps` launches of four 1D steps with `rr` values per thread, on the
+// work field A (its contents are irrelevant).
+int time_line(rk4ip_plan_t plan, const GroupHost& g, int rr, int reps, float* ms) {
+    hipStream_t st = plan->stream;
+    for (int i = 0; i < 2; i++) HIPCHK(plan, rk4ip::launch_line_step(g.d, plan->A, 4, 1, nullptr, false, rr, st));
+    hipEvent_t a = take_event(plan), b = take_event(plan);
+    if (!a || !b) return fail(plan, RK4IP_ERR_HIP, "hipEventCreate failed");
+    HIPCHK(plan, hipEventRecord(a, st));
+    for (int i = 0; i < reps; i++) HIPCHK(plan, rk4ip::launch_line_step(g.d, plan->A, 4, 1, nullptr, false, rr, st));
+    HIPCHK(plan, hipEventRecord(b, st));
+    HIPCHK(plan, hipEventSynchronize(b));
+    HIPCHK(plan, hipEventElapsedTime(ms, a, b));
+    *ms /= (float)reps;
+    plan->spare.push_back(a);
+    plan->spare.push_back(b);
+    return RK4IP_OK;
+}
+
 // Tuning cache: a flat JSON object {"key": [lines, seq], ...} in the file named by
 // RK4IP_TUNE_CACHE (optional).
 std::string tune_key(const GroupHost& g, int pass) {
@@ -403,7 +421,30 @@ int autotune(rk4ip_plan_t plan) {
     HIPCHK(plan, hipMemsetAsync(plan->A, 0, 2 * sizeof(float2) * (size_t)plan->points, plan->stream));
     for (size_t gi = 0; gi < plan->groups.size(); gi++) {
         const GroupHost& g = plan->groups[gi];
-        if (g.p.ndim == 1) continue;
+        if (g.p.ndim == 1) {
+            // the whole-line step: 16 or 8 values per thread (FP64 transforms use 8)
+            if (plan->f64) continue;
+            Sched c;
+            if (cache_lookup(text, tune_key(g, 0), &c) && (c.radix == 8 || c.radix == 16)) {
+                plan->sched[gi][0] = c;
+                continue;
+            }
+            float best = 1e30f;
+            Sched pick;
+            for (int rr : {16, 8}) {
+                float ms = 0.f;
+                int rc = time_line(plan, g, rr, 5, &ms);
+                if (rc) return rc;
+                if (ms < best) {
+                    best = ms;
+                    pick = Sched{};
+                    pick.radix = rr;
+                }
+            }
+            plan->sched[gi][0] = pick;
+            fresh.push_back({tune_key(g, 0), pick});
+            continue;
+        }
         PassDef defs[kMaxPasses];
         const int np = pass_list(g.p.ndim, defs);
         for (int i = 0; i < np; i++) {
@@ -472,13 +513,15 @@ int enqueue_lines(rk4ip_plan_t plan, hipStream_t stream, float2* psi, int64_t st
         if (g.p.ndim != 1 || nsteps <= 0) continue;
         if (allow_fuse && (plan->flags & RK4IP_FLAG_FUSE_1D)) {
             rc = timed_launch(plan, stream, (int)gi, 0, capturing, [&] {
-                return rk4ip::launch_line_step(g.d, psi, (int)nsteps, step_off, step_base, plan->f64, stream);
+                return rk4ip::launch_line_step(g.d, psi, (int)nsteps, step_off, step_base, plan->f64,
+                                                plan->sched[gi][0].radix, stream);
             });
             if (rc) return rc;
         } else {
             for (int64_t s = 0; s < nsteps; s++) {
                 rc = timed_launch(plan, stream, (int)gi, 0, capturing, [&] {
-                    return rk4ip::launch_line_step(g.d, psi, 1, step_off + s, step_base, plan->f64, stream);
+                    return rk4ip::launch_line_step(g.d, psi, 1, step_off + s, step_base, plan->f64,
+                                                    plan->sched[gi][0].radix, stream);
                 });
                 if (rc) return rc;
             }
@@ -802,7 +845,8 @@ int rk4ip_plan(const rk4ip_problem* probs, int nprob, void* workspace, size_t ws
         char name[160];
         std::vector<std::string> names;
         if (p.ndim == 1) {
-            std::snprintf(name, sizeof(name), "line_step:n%lld%s", (long long)p.n[0], plan->f64 ? ":f64" : "");
+            const int rr = plan->f64 ? 8 : (plan->sched[gi][0].radix ? plan->sched[gi][0].radix : 16);
+            std::snprintf(name, sizeof(name), "line_step:n%lld:r%d%s", (long long)p.n[0], rr, plan->f64 ? ":f64" : "");
             names.push_back(name);
         } else {
             PassDef defs[kMaxPasses];

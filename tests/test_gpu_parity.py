@@ -369,3 +369,34 @@ def test_gpe3d_256_two_steps_full_size(torch):
     err = rel(got, ref)
     log(f"  rel L2 vs oracle after 2 steps: {err:.3e}")
     assert err < 1e-6
+
+
+@pytest.mark.parametrize("n,batch", [((8,), 5), ((64,), 3), ((256,), 4), ((1024,), 3), ((2048,), 2), ((4096,), 1)])
+def test_line_step_radix8_matches_oracle(torch, n, batch, tmp_path, monkeypatch):
+    """The 1D whole-line kernel with 8 values per thread (picked through the tune cache)
+    against the oracle: one step, and 12 steps fused per launch with noise on a rough
+    random field (about 2e-7 of FP32 rounding per step), next to the 16-value kernel."""
+    log(f"line step radix 8 n={n} batch={batch}")
+    g = W.Group(n=n, lo=(-5.0,), hi=(5.0,), batch=batch, gnl=2.5, trap=(1.0, 0, 0), gamma=0.05, sigma=0.02,
+                seed=77, id_base=3)
+    f = quantised(random_field(g, 3))
+    w = W.Workload("s", [g], 2e-3, 12, [f])
+    ref1 = oracle.step(oprob(g, 2e-3), f, 41)
+    ref12, _, _ = oracle.run(oprob(g, 2e-3), f, 12, step0=41)
+    errs = {}
+    for rr in (8, 16):
+        cache = tmp_path / f"tune{rr}.json"
+        cache.write_text('{ "gfx950|n=%d,1,1|b=%d|pass=0": [0, 0, %d] }\n' % (n[0], batch, rr))
+        monkeypatch.setenv("RK4IP_TUNE_CACHE", str(cache))
+        plan = plan_for(w, rk4ip.RK4IP_FLAG_AUTOTUNE | rk4ip.RK4IP_FLAG_FUSE_1D)
+        assert plan.schedule(0, 0).endswith(f":r{rr}"), plan.schedule(0, 0)
+        d = _dev(torch, f)
+        plan.step(d, 41)
+        e1 = np.max(rel_per_instance(_host(d, g.shape), ref1, batch))
+        d = _dev(torch, f)
+        plan.run(d, 12, step0=41)
+        e12 = np.max(rel_per_instance(_host(d, g.shape), ref12, batch))
+        errs[rr] = (e1, e12)
+    log(f"  radix 8: {errs[8][0]:.2e} / {errs[8][1]:.2e}; radix 16: {errs[16][0]:.2e} / {errs[16][1]:.2e}")
+    assert errs[8][0] < 1e-6 and errs[8][1] < 5e-6
+    assert errs[8][1] < 2 * errs[16][1] + 1e-7
