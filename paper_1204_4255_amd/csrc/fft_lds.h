@@ -11,8 +11,8 @@
 // is needed at the ends.
 //
 // Forward transforms use e^{-2 pi i j m / N}, the inverse e^{+...}; neither is
-// normalised. Twiddles e^{-2 pi i t / N} come from a table computed in FP64 (passed in
-// LDS by the caller). Every function is generic over the complex type: float2 for the
+// normalised. Twiddles e^{-2 pi i t / N} come from a table computed in FP64, staged in
+// LDS by the caller in the stage-major order of FFTShape::tw_off (stage_twiddles). Every function is generic over the complex type: float2 for the
 // complex64 transforms, double2 for the FP64-transform precision form (same code, the
 // table and the LDS buffer in the same type).
 #pragma once
@@ -204,31 +204,68 @@ struct FFTShape {
     // radix and Ns (product of earlier radices) of stage i
     __host__ __device__ static constexpr int radix(int i) { return (N < RR) ? N : (i < S ? R : Q); }
     __host__ __device__ static constexpr int ns(int i) { return i == 0 ? 1 : ns(i - 1) * radix(i - 1); }
+    // first entry of stage i's twiddles in the stage-major table (stage 0 needs none): the
+    // factor e^{-2 pi i bm k step / N} of butterfly bm and input k >= 1 of stage i sits at
+    // tw_off(i) + (k - 1) ns(i) + bm, so the butterflies of a wavefront read consecutive
+    // entries. The table has N - 1 entries.
+    __host__ __device__ static constexpr int tw_off(int i) {
+        return i <= 1 ? 0 : tw_off(i - 1) + ns(i - 1) * (radix(i - 1) - 1);
+    }
 };
 
-// LDS layout of an exchange buffer that holds `LINES` lines of N complex values.
-// ROWMAJOR (lines contiguous, one pad slot every 16 values): used when the threads of
-// a line are adjacent lanes (lines along the contiguous axis). Otherwise element-major
-// with the line index fastest: used when adjacent lanes hold adjacent lines (columns
-// of a strided axis).
-template <int N, int LINES, bool ROWMAJOR>
+// LDS layout of an exchange buffer that holds `LINES` lines of N complex values, for a
+// transform with R values per thread.
+//  * ROWMAJOR (lines contiguous; the threads of a line are adjacent lanes): with R = 8,
+//    a one-slot row pad and the element index XORed with its own bits 3-6 in bits 0-3,
+//    which removes most bank conflicts of the radix-8 exchanges (checked on the host
+//    against 32 banks x 16 lanes and 64 banks x 32 lanes per cycle for 8-byte accesses);
+//    otherwise one pad slot every 16 values.
+//  * element-major with the line index fastest (adjacent lanes hold adjacent lines, the
+//    columns of a strided axis). Padding that removes the remaining 2-way conflicts of the
+//    first exchange costs more address arithmetic than it saves in these VALU-bound
+//    passes, so there is none.
+template <int N, int LINES, bool ROWMAJOR, int R = 16>
 struct LdsLayout {
-    static constexpr int ROW = N + (N >= 16 ? N / 16 : 0);
+    static constexpr bool SWZ = ROWMAJOR && R == 8 && N >= 16;
+    static constexpr int ROW = SWZ ? N + 1 : N + (N >= 16 ? N / 16 : 0);
     static constexpr int SIZE = ROWMAJOR ? LINES * ROW : LINES * N;
     __device__ __forceinline__ static int addr(int line, int e) {
         if constexpr (ROWMAJOR) {
-            return line * ROW + e + (N >= 16 ? (e >> 4) : 0);
+            if constexpr (SWZ) {
+                return line * ROW + (e ^ ((e >> 3) & 15 & (N - 1)));
+            } else {
+                return line * ROW + e + (N >= 16 ? (e >> 4) : 0);
+            }
         } else {
             return e * LINES + line;
         }
     }
 };
 
+// Twiddles of every stage of F in the stage-major order of FFTShape::tw_off, built from
+// the canonical table tw[j] = e^{-2 pi i j / N}. All threads of the block call it; the
+// caller synchronises before the first transform.
+template <class F, int STAGE, class V>
+__device__ __forceinline__ void stage_twiddles_from(V* s_tw, const V* __restrict__ tw) {
+    if constexpr (STAGE < F::NSTAGES) {
+        constexpr int ns = F::ns(STAGE), r = F::radix(STAGE), step = F::NN / (ns * r);
+        for (int i = threadIdx.x; i < ns * (r - 1); i += blockDim.x) {
+            const int k = i / ns + 1, bm = i - (k - 1) * ns;
+            s_tw[F::tw_off(STAGE) + i] = tw[bm * k * step];
+        }
+        stage_twiddles_from<F, STAGE + 1>(s_tw, tw);
+    }
+}
+
+template <class F, class V>
+__device__ __forceinline__ void stage_twiddles(V* s_tw, const V* __restrict__ tw) {
+    stage_twiddles_from<F, 1>(s_tw, tw);
+}
+
 // One Stockham stage on the registers of one thread: U = R/radix butterflies,
 // butterfly u is b = t + T u with inputs v[u*radix + k] = x[b + k N/radix].
 template <class F, int S, int STAGE, class V>
 __device__ __forceinline__ void fft_stage(V (&v)[F::R], int t, const V* __restrict__ tw) {
-    constexpr int N = F::NN;
     constexpr int r = F::radix(STAGE);
     constexpr int ns = F::ns(STAGE);
     constexpr int U = F::R / r;
@@ -240,10 +277,9 @@ __device__ __forceinline__ void fft_stage(V (&v)[F::R], int t, const V* __restri
         if constexpr (ns > 1) {
             const int b = t + F::T * u;
             const int bm = b & (ns - 1);
-            constexpr int step = N / (ns * r);
 #pragma unroll
             for (int k = 1; k < r; k++) {
-                V w = tw[bm * k * step];
+                V w = tw[F::tw_off(STAGE) + (k - 1) * ns + bm];
                 if constexpr (S > 0) w = cconj(w);
                 x[k] = cmul(x[k], w);
             }

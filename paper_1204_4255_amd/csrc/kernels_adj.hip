@@ -14,12 +14,12 @@ __global__ void __launch_bounds__(FFTShape<N>::T* LPB)
     k_line_adjoint(GroupDev g, const float2* __restrict__ psi_n, float2* __restrict__ lam, double* __restrict__ vbar,
                    int64_t step) {
     using F = FFTShape<N>;
-    using L = LdsLayout<N, LPB, true>;
+    using L = LdsLayout<N, LPB, true, F::R>;
     constexpr int R = F::R, T = F::T;
     __shared__ c32 lds[2 * L::SIZE];
     __shared__ c32 tw[N];
     __shared__ float2 E[N];
-    stage_tables<N>(tw, E, g.tw[0], g.E[0]);
+    stage_tables<F>(tw, E, g.tw[0], g.E[0]);
     const int t = threadIdx.x % T;
     const int l = threadIdx.x / T;
     const int64_t inst = (int64_t)blockIdx.x * LPB + l;

@@ -33,8 +33,10 @@ __global__ void __launch_bounds__(FFTShape<N>::T* LINES)
     k_fft_lines(const float2* __restrict__ in, float2* __restrict__ out, int64_t nlines, int sign,
                 const float2* __restrict__ tw) {
     using F = FFTShape<N>;
-    using L = LdsLayout<N, LINES, true>;
+    using L = LdsLayout<N, LINES, true, F::R>;
     __shared__ c32 lds[L::SIZE];
+    __shared__ c32 s_tw[N];
+    stage_twiddles<F>(s_tw, tw);
     const int t = threadIdx.x % F::T;
     const int l = threadIdx.x / F::T;
     const int64_t line = (int64_t)blockIdx.x * LINES + l;
@@ -42,10 +44,11 @@ __global__ void __launch_bounds__(FFTShape<N>::T* LINES)
     c32 v[1][F::R];
 #pragma unroll
     for (int m = 0; m < F::R; m++) v[0][m] = active ? in[line * N + t + m * F::T] : make_float2(0.f, 0.f);
+    __syncthreads();  // twiddles staged
     if (sign < 0)
-        fft_line<F, -1, L, 1>(v, t, l, lds, tw);
+        fft_line<F, -1, L, 1>(v, t, l, lds, s_tw);
     else
-        fft_line<F, +1, L, 1>(v, t, l, lds, tw);
+        fft_line<F, +1, L, 1>(v, t, l, lds, s_tw);
     if (active) {
 #pragma unroll
         for (int m = 0; m < F::R; m++) out[line * N + t + m * F::T] = v[0][m];
@@ -62,11 +65,11 @@ __global__ void __launch_bounds__(FFTShape<N>::T* LINES)
     k_diag_axis(GroupDev g, int axis, const float2* __restrict__ psi, double kscale, double* __restrict__ part) {
     using F = FFTShape<N>;
     constexpr int R = F::R, T = F::T;
-    using L = LdsLayout<N, LINES, CONTIG>;
+    using L = LdsLayout<N, LINES, CONTIG, F::R>;
     __shared__ c32 lds[L::SIZE];
     __shared__ c32 tw[N];
     __shared__ double red[FFTShape<N>::T * LINES][4];
-    stage_tables<N, c32>(tw, nullptr, g.tw[axis], nullptr);
+    stage_tables<F, c32>(tw, nullptr, g.tw[axis], nullptr);
     const int t = CONTIG ? (int)(threadIdx.x % T) : (int)(threadIdx.x / LINES);
     const int l = CONTIG ? (int)(threadIdx.x / T) : (int)(threadIdx.x % LINES);
     const Tile<F, CONTIG, LINES> tile(g, axis, l, t);

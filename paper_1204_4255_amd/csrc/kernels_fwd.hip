@@ -15,16 +15,16 @@ __global__ void __launch_bounds__((FFTShape<N, RR>::T * LPB))
     k_line_step(GroupDev g, float2* __restrict__ psi, int nsteps, int64_t step_off,
                 const int64_t* __restrict__ step_base) {
     using F = FFTShape<N, RR>;
-    using L = LdsLayout<N, LPB, true>;
+    using L = LdsLayout<N, LPB, true, F::R>;
     using W = typename std::conditional<P64, c64, c32>::type;  // transform working type
     constexpr int R = F::R, T = F::T;
     __shared__ W lds[2 * L::SIZE];
     __shared__ W tw[N];
     __shared__ W E[N];
     if constexpr (P64)
-        stage_tables<N>(tw, E, g.tw64[0], g.E64[0]);
+        stage_tables<F>(tw, E, g.tw64[0], g.E64[0]);
     else
-        stage_tables<N>(tw, E, g.tw[0], g.E[0]);
+        stage_tables<F>(tw, E, g.tw[0], g.E[0]);
     const int t = threadIdx.x % T;
     const int l = threadIdx.x / T;
     const int64_t inst = (int64_t)blockIdx.x * LPB + l;

@@ -38,12 +38,13 @@ __device__ __forceinline__ int64_t read_step(int64_t step_off, const int64_t* st
     return step_off + (step_base ? *step_base : 0);
 }
 
-// Copy an axis's twiddle and (E - 1)/n tables into LDS (the caller synchronises).
-template <int N, class V>
+// Stage an axis's twiddles (in the transform's stage-major order) and its (E - 1)/n
+// table into LDS (the caller synchronises).
+template <class F, class V>
 __device__ __forceinline__ void stage_tables(V* s_tw, V* s_E, const V* __restrict__ tw, const V* __restrict__ E) {
-    for (int i = threadIdx.x; i < N; i += blockDim.x) {
-        s_tw[i] = tw[i];
-        if (s_E) s_E[i] = E[i];
+    stage_twiddles<F>(s_tw, tw);
+    if (s_E) {
+        for (int i = threadIdx.x; i < F::NN; i += blockDim.x) s_E[i] = E[i];
     }
 }
 
@@ -90,10 +91,9 @@ __device__ __forceinline__ void propagate(c32 (&f)[NF][F::R], int t, int l, V* l
 // XCD a contiguous run of tiles instead, so that neighbouring strided tiles (which share
 // 128-byte lines when a tile row is narrower than a line) run on the same L2 at about the
 // same time. A bijection of [0, G).
-__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t G) {
-    constexpr int64_t X = 8;
-    const int64_t q = G / X, r = G % X, x = b % X;
-    return x * q + (x < r ? x : r) + b / X;
+__device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t G) {
+    const uint32_t q = G >> 3, r = G & 7u, x = b & 7u;
+    return x * q + (x < r ? x : r) + (b >> 3);
 }
 
 template <class F, bool CONTIG, int LINES>
@@ -109,27 +109,28 @@ struct Tile {
 
     __device__ __forceinline__ Tile(const GroupDev& g, int axis, int l, int t) {
         constexpr int T = F::T;
+        // every count below is a power of two: shifts and masks, no division
         if constexpr (CONTIG) {
-            const int64_t lines_per_inst = g.M >> g.log2n[0];
-            const int64_t nlines = g.batch * lines_per_inst;
+            const int lpi = g.log2n[1] + g.log2n[2];  // log2 of the lines per instance
+            const int64_t nlines = g.batch << lpi;
             const int64_t line = (int64_t)blockIdx.x * LINES + l;
             active = line < nlines;
             const int64_t ln = active ? line : 0;
             base = (int64_t)blockIdx.x * LINES * N;
             off0 = (uint32_t)(l * N + t);
             dstep = T;
-            inst = ln / lines_per_inst;
-            jbase = (ln - inst * lines_per_inst) * N + t;
+            inst = ln >> lpi;
+            jbase = (ln & ((int64_t(1) << lpi) - 1)) * N + t;
             jstride = 1;
         } else {
-            const int xt_count = g.n[0] / LINES;
-            const int outer_n = (axis == 1) ? g.n[2] : g.n[1];
+            const int xt_log = g.log2n[0] - ilog2(LINES);  // column tiles per row
+            const int outer_log = (axis == 1) ? g.log2n[2] : g.log2n[1];
             // tiles whose rows are narrower than a 128-byte line share lines with a neighbour
-            int64_t bid = (LINES * 8 < 128) ? xcd_tile(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
-            const int xt = (int)(bid % xt_count);
-            bid /= xt_count;
-            const int outer = (int)(bid % outer_n);
-            inst = bid / outer_n;
+            uint32_t bid = (LINES * 8 < 128) ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x;
+            const int xt = (int)(bid & ((1u << xt_log) - 1u));
+            bid >>= xt_log;
+            const int outer = (int)(bid & ((1u << outer_log) - 1u));
+            inst = (int64_t)(bid >> outer_log);
             active = true;
             const uint32_t stride = (axis == 1) ? (uint32_t)g.n[0] : (uint32_t)g.n[0] * (uint32_t)g.n[1];
             const int64_t in_inst = (axis == 1) ? (int64_t)outer * g.n[0] * g.n[1] + xt * LINES
@@ -190,14 +191,14 @@ __global__ void __launch_bounds__((FFTShape<N, RR>::T * LINES)) k_axis(GroupDev 
     using V = typename std::conditional<P64, c64, c32>::type;  // transform working type
     constexpr int R = F::R, T = F::T;
     constexpr int NF = fields_of(MODE);
-    using L = LdsLayout<N, LINES, CONTIG>;
+    using L = LdsLayout<N, LINES, CONTIG, R>;
     __shared__ V lds[(SEQ != 0 ? 1 : NF) * L::SIZE];
     __shared__ V tw[N];
     __shared__ V E[N];
     if constexpr (P64)
-        stage_tables<N>(tw, E, g.tw64[axis], g.E64[axis]);
+        stage_tables<F>(tw, E, g.tw64[axis], g.E64[axis]);
     else
-        stage_tables<N>(tw, E, g.tw[axis], g.E[axis]);
+        stage_tables<F>(tw, E, g.tw[axis], g.E[axis]);
     const int t = CONTIG ? (int)(threadIdx.x % T) : (int)(threadIdx.x / LINES);
     const int l = CONTIG ? (int)(threadIdx.x / T) : (int)(threadIdx.x % LINES);
     const Tile<F, CONTIG, LINES> tile(g, axis, l, t);
@@ -439,10 +440,11 @@ constexpr bool loads_two_fields(int mode) {
 
 constexpr int default_contig_lines(int N) { return N < 16 ? 256 : ((256 / (N / 16)) < 1 ? 1 : 256 / (N / 16)); }
 
-// LDS bytes of a pass with FP64 transforms: nf exchange buffers plus the two tables.
+// LDS bytes of a pass with FP64 transforms (8 values per thread): nf exchange buffers
+// (LdsLayout) plus the two tables.
 constexpr bool fits_lds64(int N, int lines, int nf, bool contig) {
-    const long row = contig ? (long)N + (N >= 16 ? N / 16 : 0) : (long)N;
-    return ((long)nf * row * lines + 2L * N) * 16 <= 160L * 1024;
+    const long buf = contig ? (long)lines * (N + 1) : (long)lines * N;
+    return ((long)nf * buf + 2L * N) * 16 <= 160L * 1024;
 }
 
 // Is schedule (lines, seq, rr) of pass MODE compiled for length N on the contiguous or a
