@@ -18,6 +18,9 @@ SOURCES = [
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
+    # the four-wave schedule variants are hints: where a 512-point pass cannot meet them
+    # the compiler keeps three waves and says so
+    "-Wno-pass-failed",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", os.path.join(HERE, "..", "include"),
 ]

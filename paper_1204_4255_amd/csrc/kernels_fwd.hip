@@ -88,18 +88,18 @@ __global__ void __launch_bounds__((FFTShape<N, RR>::T * LPB))
 
 int axis_lines(int N, int axis, int n0) { return axis == 0 ? contig_lines(N) : strided_lines(N, n0); }
 
-bool axis_schedule_ok(int N, int mode, int axis, int n0, int lines, int seq, int radix, bool f64) {
+bool axis_schedule_ok(int N, int mode, int axis, int n0, int lines, int seq, int radix, bool f64, int occ) {
     const bool contig = axis == 0;
     if (!contig && lines > n0) return false;
     switch (N) {
-        case 8: return schedule_ok_n<8>(mode, contig, lines, seq, radix, f64);
-        case 16: return schedule_ok_n<16>(mode, contig, lines, seq, radix, f64);
-        case 32: return schedule_ok_n<32>(mode, contig, lines, seq, radix, f64);
-        case 64: return schedule_ok_n<64>(mode, contig, lines, seq, radix, f64);
-        case 128: return schedule_ok_n<128>(mode, contig, lines, seq, radix, f64);
-        case 256: return schedule_ok_n<256>(mode, contig, lines, seq, radix, f64);
-        case 512: return schedule_ok_n<512>(mode, contig, lines, seq, radix, f64);
-        case 1024: return schedule_ok_n<1024>(mode, contig, lines, seq, radix, f64);
+        case 8: return schedule_ok_n<8>(mode, contig, lines, seq, radix, f64, occ);
+        case 16: return schedule_ok_n<16>(mode, contig, lines, seq, radix, f64, occ);
+        case 32: return schedule_ok_n<32>(mode, contig, lines, seq, radix, f64, occ);
+        case 64: return schedule_ok_n<64>(mode, contig, lines, seq, radix, f64, occ);
+        case 128: return schedule_ok_n<128>(mode, contig, lines, seq, radix, f64, occ);
+        case 256: return schedule_ok_n<256>(mode, contig, lines, seq, radix, f64, occ);
+        case 512: return schedule_ok_n<512>(mode, contig, lines, seq, radix, f64, occ);
+        case 1024: return schedule_ok_n<1024>(mode, contig, lines, seq, radix, f64, occ);
         default: return false;
     }
 }

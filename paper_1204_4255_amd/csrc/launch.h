@@ -38,6 +38,7 @@ struct PassArgs {
                               // LDS); 2: as 1 with the second field loaded after the first
     int radix;                // values per thread in the transform: 16 (0 = default) or 8
     int f64;                  // transforms, propagator multiply and delta add in FP64 (radix 8)
+    int occ;                  // minimum waves per SIMD the kernel is compiled for (0/1 = none, 4)
     int64_t step_off;
     const int64_t* step_base; // step = step_off (+ *step_base when not null)
 };
@@ -51,7 +52,7 @@ struct DiagConst {
 
 int axis_lines(int N, int axis, int n0);
 // Whether a (lines, seq) schedule of a pass is compiled for this length and axis.
-bool axis_schedule_ok(int N, int mode, int axis, int n0, int lines, int seq, int radix, bool f64);
+bool axis_schedule_ok(int N, int mode, int axis, int n0, int lines, int seq, int radix, bool f64, int occ = 1);
 
 hipError_t launch_axis(const GroupDev& g, int axis, int mode, const PassArgs& a, hipStream_t s);
 hipError_t launch_axis_adjoint(const GroupDev& g, int axis, int mode, const PassArgs& a, hipStream_t s);

@@ -185,8 +185,12 @@ constexpr bool uses_rhs(int mode) {
 //          (lowest register peak, fewer loads in flight per wave).
 // RR: values per thread in the transform (16, or 8 for half the registers and one more
 // LDS exchange per transform).
-template <int N, int MODE, bool CONTIG, int LINES, bool NOISE, int SEQ, int RR, bool P64>
-__global__ void __launch_bounds__((FFTShape<N, RR>::T * LINES)) k_axis(GroupDev g, int axis, PassArgs args) {
+// OCC: the minimum waves per SIMD the register allocation must allow (1 = no constraint;
+// 4 is a tuned variant for the radix-8 passes, whose allocation otherwise lands just
+// above the 128 VGPRs that four waves need).
+template <int N, int MODE, bool CONTIG, int LINES, bool NOISE, int SEQ, int RR, bool P64, int OCC>
+__global__ void __launch_bounds__((FFTShape<N, RR>::T * LINES)) __attribute__((amdgpu_waves_per_eu(OCC)))
+k_axis(GroupDev g, int axis, PassArgs args) {
     using F = FFTShape<N, RR>;
     using V = typename std::conditional<P64, c64, c32>::type;  // transform working type
     constexpr int R = F::R, T = F::T;
@@ -401,7 +405,7 @@ static inline int contig_lines(int N) {
 
 
 
-template <int N, int MODE, bool CONTIG, int LINES, int SEQ, int RR, bool P64>
+template <int N, int MODE, bool CONTIG, int LINES, int SEQ, int RR, bool P64, int OCC = 1>
 static hipError_t go_axis(const GroupDev& g, int axis, const PassArgs& a, hipStream_t s) {
     int64_t blocks;
     if (CONTIG)
@@ -411,11 +415,11 @@ static hipError_t go_axis(const GroupDev& g, int axis, const PassArgs& a, hipStr
     const dim3 grid((unsigned)blocks), block(FFTShape<N, RR>::T * LINES);
     if constexpr (uses_rhs(MODE)) {
         if (g.has_noise) {
-            hipLaunchKernelGGL((k_axis<N, MODE, CONTIG, LINES, true, SEQ, RR, P64>), grid, block, 0, s, g, axis, a);
+            hipLaunchKernelGGL((k_axis<N, MODE, CONTIG, LINES, true, SEQ, RR, P64, OCC>), grid, block, 0, s, g, axis, a);
             return hipGetLastError();
         }
     }
-    hipLaunchKernelGGL((k_axis<N, MODE, CONTIG, LINES, false, SEQ, RR, P64>), grid, block, 0, s, g, axis, a);
+    hipLaunchKernelGGL((k_axis<N, MODE, CONTIG, LINES, false, SEQ, RR, P64, OCC>), grid, block, 0, s, g, axis, a);
     return hipGetLastError();
 }
 
@@ -451,10 +455,15 @@ constexpr bool fits_lds64(int N, int lines, int nf, bool contig) {
 // strided axis, with FP32 or FP64 transforms? Mirrors the instantiations in go_axis_n.
 // rr = values per thread.
 template <int N, int MODE>
-constexpr bool schedule_compiled(bool contig, int lines, int seq, int rr, bool p64) {
+constexpr bool schedule_compiled(bool contig, int lines, int seq, int rr, bool p64, int occ = 1) {
     constexpr int NF = fields_of(MODE);
     const bool tuned = tuned_length(N) && tuned_mode(MODE);
     if (seq < 0 || seq > 2) return false;
+    if (occ != 1) {
+        // the four-wave variant: FP32, radix 8, both fields at once, tuned lengths
+        if (occ != 4 || p64 || rr != 8 || seq != 0 || !tuned) return false;
+        return schedule_compiled<N, MODE>(contig, lines, 0, 8, false, 1);
+    }
     if (p64) {
         // radix 8 only (FP64 values take twice the registers), at most 512 threads
         if (!f64_mode(MODE) || rr != 8 || lines < 1) return false;
@@ -490,6 +499,10 @@ constexpr bool schedule_compiled(bool contig, int lines, int seq, int rr, bool p
 
 template <int N, int MODE, bool CONTIG, int LINES, int RR, bool P64>
 static hipError_t go_axis_sched_rr(const GroupDev& g, int axis, const PassArgs& a, hipStream_t s) {
+    if constexpr (schedule_compiled<N, MODE>(CONTIG, LINES, 0, RR, P64, 4)) {
+        if (a.occ == 4 && a.seq == 0) return go_axis<N, MODE, CONTIG, LINES, 0, RR, P64, 4>(g, axis, a, s);
+    }
+    if (a.occ != 0 && a.occ != 1) return hipErrorInvalidValue;
     if constexpr (schedule_compiled<N, MODE>(CONTIG, LINES, 2, RR, P64)) {
         if (a.seq == 2) return go_axis<N, MODE, CONTIG, LINES, 2, RR, P64>(g, axis, a, s);
     }
@@ -558,14 +571,14 @@ static hipError_t go_axis_n(const GroupDev& g, int axis, const PassArgs& a, hipS
 }
 
 template <int N>
-static bool schedule_ok_n(int mode, bool contig, int lines, int seq, int rr, bool p64) {
+static bool schedule_ok_n(int mode, bool contig, int lines, int seq, int rr, bool p64, int occ) {
     switch (mode) {
-        case PASS_D1: return schedule_compiled<N, PASS_D1>(contig, lines, seq, rr, p64);
-        case PASS_D2: return schedule_compiled<N, PASS_D2>(contig, lines, seq, rr, p64);
-        case PASS_FIRST: return contig && schedule_compiled<N, PASS_FIRST>(contig, lines, seq, rr, p64);
-        case PASS_LAST2: return contig && schedule_compiled<N, PASS_LAST2>(contig, lines, seq, rr, p64);
-        case PASS_LF: return !contig && schedule_compiled<N, PASS_LF>(contig, lines, seq, rr, p64);
-        case PASS_XF: return contig && schedule_compiled<N, PASS_XF>(contig, lines, seq, rr, p64);
+        case PASS_D1: return schedule_compiled<N, PASS_D1>(contig, lines, seq, rr, p64, occ);
+        case PASS_D2: return schedule_compiled<N, PASS_D2>(contig, lines, seq, rr, p64, occ);
+        case PASS_FIRST: return contig && schedule_compiled<N, PASS_FIRST>(contig, lines, seq, rr, p64, occ);
+        case PASS_LAST2: return contig && schedule_compiled<N, PASS_LAST2>(contig, lines, seq, rr, p64, occ);
+        case PASS_LF: return !contig && schedule_compiled<N, PASS_LF>(contig, lines, seq, rr, p64, occ);
+        case PASS_XF: return contig && schedule_compiled<N, PASS_XF>(contig, lines, seq, rr, p64, occ);
         default: return false;
     }
 }

@@ -38,6 +38,7 @@ int ilog2i(int64_t v) {
 // Tile schedule of one pass (see PassArgs): lines or columns per workgroup, joint or
 // sequential field transforms, values per thread in the transform.
 struct Sched {
+    int occ = 0;    // 4: the variant compiled for four waves per SIMD
     int lines = 0;
     int seq = 0;
     int radix = 0;
@@ -330,6 +331,7 @@ int time_pass(rk4ip_plan_t plan, const GroupHost& g, int axis, int mode, const S
     pa.lines = sc.lines;
     pa.seq = sc.seq;
     pa.radix = sc.radix;
+    pa.occ = sc.occ;
     hipStream_t st = plan->stream;
     for (int i = 0; i < 2; i++) HIPCHK(plan, rk4ip::launch_axis(g.d, axis, mode, pa, st));
     hipEvent_t a = take_event(plan), b = take_event(plan);
@@ -378,8 +380,10 @@ bool cache_lookup(const std::string& text, const std::string& key, Sched* sc) {
     if (p == std::string::npos) return false;
     p = text.find('[', p);
     if (p == std::string::npos) return false;
-    return std::sscanf(text.c_str() + p, "[%d , %d , %d]", &sc->lines, &sc->seq, &sc->radix) == 3 ||
-           std::sscanf(text.c_str() + p, "[%d,%d,%d]", &sc->lines, &sc->seq, &sc->radix) == 3;
+    // [lines, seq, radix] or [lines, seq, radix, occ]
+    sc->occ = 0;
+    const int n = std::sscanf(text.c_str() + p, "[ %d , %d , %d , %d ]", &sc->lines, &sc->seq, &sc->radix, &sc->occ);
+    return n >= 3;
 }
 
 // The schedule an FP64-transform pass runs without tuning: the first compiled one in a
@@ -452,7 +456,7 @@ int autotune(rk4ip_plan_t plan) {
             const int N = (int)g.p.n[axis], n0 = (int)g.p.n[0];
             Sched c;
             if (cache_lookup(text, tune_key(g, i), &c) &&
-                rk4ip::axis_schedule_ok(N, mode, axis, n0, c.lines, c.seq, c.radix, plan->f64)) {
+                rk4ip::axis_schedule_ok(N, mode, axis, n0, c.lines, c.seq, c.radix, plan->f64, c.occ ? c.occ : 1)) {
                 plan->sched[gi][i] = c;
                 continue;
             }
@@ -462,12 +466,14 @@ int autotune(rk4ip_plan_t plan) {
             const int cand_radix[] = {16, 8};
             for (int rr : cand_radix)
                 for (int lines : cand_lines)
-                    for (int sq = 0; sq < 3; sq++) {
-                        if (!rk4ip::axis_schedule_ok(N, mode, axis, n0, lines, sq, rr, plan->f64)) continue;
+                    for (int sq = 0; sq < 3; sq++)
+                        for (int occ : {0, 4}) {
+                        if (!rk4ip::axis_schedule_ok(N, mode, axis, n0, lines, sq, rr, plan->f64, occ ? occ : 1)) continue;
                         Sched cand;
                         cand.lines = lines;
                         cand.seq = sq;
                         cand.radix = rr;
+                        cand.occ = occ;
                         float ms = 0.f;
                         int rc = time_pass(plan, g, axis, mode, cand, 5, &ms);
                         if (rc) return rc;
@@ -489,8 +495,8 @@ int autotune(rk4ip_plan_t plan) {
         bool has_entry = body.find('[') != std::string::npos;
         for (auto& f : fresh) {
             char line[256];
-            std::snprintf(line, sizeof(line), "%s \"%s\": [%d, %d, %d]\n", has_entry ? "," : " ", f.first.c_str(),
-                          f.second.lines, f.second.seq, f.second.radix);
+            std::snprintf(line, sizeof(line), "%s \"%s\": [%d, %d, %d, %d]\n", has_entry ? "," : " ", f.first.c_str(),
+                          f.second.lines, f.second.seq, f.second.radix, f.second.occ);
             body += line;
             has_entry = true;
         }
@@ -552,6 +558,7 @@ int enqueue_lattice(rk4ip_plan_t plan, hipStream_t stream, float2* psi, int64_t 
                 pa.step_off = step;
                 pa.step_base = step_base;
                 pa.f64 = plan->f64 ? 1 : 0;
+                pa.occ = plan->sched[gi][i].occ;
                 pa.lines = plan->sched[gi][i].lines;
                 pa.seq = plan->sched[gi][i].seq;
                 pa.radix = plan->sched[gi][i].radix;
@@ -855,10 +862,10 @@ int rk4ip_plan(const rk4ip_problem* probs, int nprob, void* workspace, size_t ws
                 const int a = defs[k].axis;
                 const Sched sc = plan->sched[gi][k];
                 const int lines = sc.lines ? sc.lines : rk4ip::axis_lines((int)p.n[a], a, (int)p.n[0]);
-                std::snprintf(name, sizeof(name), "%s:axis%d:n%lld:%s:lines%d:%s:r%d%s", mode_name(defs[k].mode), a,
+                std::snprintf(name, sizeof(name), "%s:axis%d:n%lld:%s:lines%d:%s:r%d%s%s", mode_name(defs[k].mode), a,
                               (long long)p.n[a], a == 0 ? "contig" : "strided", lines,
                               sc.seq == 2 ? "seq-deferred" : (sc.seq ? "seq" : "joint"), sc.radix ? sc.radix : 16,
-                              plan->f64 ? ":f64" : "");
+                              sc.occ == 4 ? ":o4" : "", plan->f64 ? ":f64" : "");
                 names.push_back(name);
             }
         }
