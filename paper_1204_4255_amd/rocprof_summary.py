@@ -29,7 +29,7 @@ KINDS = {0: "D1", 1: "D2", 2: "FIRST", 4: "LAST2", 5: "U", 6: "AW", 7: "AS", 8: 
 # algorithmic HBM bytes per lattice point of each pass kind (complex64 = 8 B)
 PASS_BYTES = {"FIRST": 24, "D2": 32, "LF": 32, "XF": 32, "LAST2": 24}
 COPY_BYTES = 256 << 20
-AXIS_RE = re.compile(r"k_axis<(\d+), (\d+), (true|false), (\d+), (true|false), (\d), (\d+)>")
+AXIS_RE = re.compile(r"k_axis<(\d+), (\d+), (true|false), (\d+), (true|false), (\d), (\d+)(?:, (true|false), (\d+))?>")
 
 
 def _short(name: str) -> str:
@@ -140,6 +140,81 @@ def markdown(out: dict) -> str:
     return "\n".join(lines)
 
 
+COMMANDS = """    cd /tmp && export TMPDIR=/tmp
+    export RK4IP_TUNE_CACHE=/root/repo/gpurun_out/tune_gpe3d_256.json
+    python3 /root/repo/bench.py --no-cpu-baseline --no-forms --steps 20 --warmup 5
+    rocprofv3 --kernel-trace --stats --output-format csv -d /root/repo/gpurun_out/prof -o kt -- python3 /root/repo/bench.py --no-cpu-baseline --no-forms --steps 50 --warmup 5 --calibrate-copy
+    rocprofv3 --pmc FETCH_SIZE --output-format csv -d /root/repo/gpurun_out/prof -o fetch -- python3 /root/repo/bench.py --no-cpu-baseline --no-forms --steps 3 --warmup 1 --profile-steps 2 --calibrate-copy
+    rocprofv3 --pmc WRITE_SIZE --output-format csv -d /root/repo/gpurun_out/prof -o write -- python3 /root/repo/bench.py --no-cpu-baseline --no-forms --steps 3 --warmup 1 --profile-steps 2 --calibrate-copy
+    rocprofv3 --pmc SQ_INSTS_VALU SQ_INSTS_LDS SQ_LDS_BANK_CONFLICT SQ_WAVES --output-format csv -d /root/repo/gpurun_out/prof -o valu -- python3 /root/repo/bench.py --no-cpu-baseline --no-forms --steps 3 --warmup 1 --profile-steps 2
+    python3 -m paper_1204_4255_amd.rocprof_summary /root/repo/gpurun_out/prof profiles"""
+
+COPY_GBPS = 5900.0  # a plain elementwise copy of 256 MiB in and out on this GPU
+
+
+def report(out: dict, tune: str = "") -> str:
+    cal = out["calibration"]
+    lines = [
+        "# Step kernels of the 256^3 3D GPE workload: rocprofv3 kernel trace and counters",
+        "",
+        "Commands (one MI355X, repository root). `RK4IP_TUNE_CACHE` keeps the schedules the",
+        "autotuner picks in the first run, so every later run launches the same kernels:",
+        "",
+        COMMANDS,
+        "",
+        "The last command writes this file and `traffic_gpe3d_256.json`, which `bench.py` reads",
+        f"for `roofline.traffic` while the kernel sources still hash to `{out['source_hash']}`.",
+        "",
+    ]
+    if tune:
+        lines += ["Schedules picked (tune cache: lines or columns, field order, values per thread,",
+                  "minimum waves per SIMD):", "", "```", tune.strip(), "```", ""]
+    lines += [
+        "Calibration: `--calibrate-copy` runs one torch elementwise kernel that reads 256 MiB and",
+        f"writes 256 MiB. It reads FETCH_SIZE = {cal['FETCH_SIZE_KiB']:.1f} KiB and WRITE_SIZE =",
+        f"{cal['WRITE_SIZE_KiB']:.1f} KiB, so the counters are scaled by {cal['fetch_factor']:.4f} (fetch) and",
+        f"{cal['write_factor']:.4f} (write) to bytes of HBM traffic.",
+        "",
+        "Columns:",
+        "* Calls, durations and % of GPU time come from `kt_kernel_stats.csv`. That run also holds the",
+        "  profiling plan's eager steps and the autotuner's launches, so call counts are not whole steps.",
+        "* Algorithmic GB/s = the pass's algorithmic bytes (24 or 32 B per point x 256^3) / average",
+        "  duration.",
+        "* Measured / algorithmic = (scaled FETCH + WRITE) / algorithmic bytes.",
+        "* VALU lane-instructions per point = SQ_INSTS_VALU x 64 / 256^3.",
+        "* VALU issue = SQ_INSTS_VALU / (256 CUs x 2.4 GHz x duration): the fraction of the chip's wave64",
+        "  VALU issue slots (one per CU per clock without packed FP32).",
+        "",
+        markdown(out),
+        "",
+        "Template arguments of `k_axis`: (length, pass kind, contiguous axis, lines or columns per",
+        "workgroup, noise drawn, field order 0 joint / 1 one after the other / 2 the same with the",
+        "second load deferred, values per thread, FP64 transforms, minimum waves per SIMD). Pass",
+        "kinds: 1 = D2, 2 = FIRST, 4 = LAST2, 9 = LF, 10 = XF.",
+        "",
+        "Reading (thresholds: within 10% of the copy rate = HBM-bound; VALU issue above 0.6 and",
+        "under half the copy rate = VALU-bound):",
+    ]
+    for key, r in sorted(out["kernels"].items(), key=lambda kv: -kv[1].get("percent", 0)):
+        gbs = r.get("achieved_GBps")
+        issue = r.get("valu_issue_frac")
+        ratio = r.get("ratio")
+        if gbs is None:
+            continue
+        kind = "HBM-bound" if gbs > 0.9 * COPY_GBPS else ("VALU-bound" if issue and issue > 0.6 else "mixed")
+        lines.append(f"* {key}: {gbs:.0f} GB/s ({gbs / 8000:.0%} of 8 TB/s, {gbs / COPY_GBPS:.0%} of a copy), "
+                     f"VALU issue {issue:.2f}, traffic {ratio:.3f}x algorithmic: {kind}."
+                     if issue is not None and ratio is not None else f"* {key}: {gbs:.0f} GB/s: {kind}.")
+    return "\n".join(lines) + "\n"
+
+
 if __name__ == "__main__":
-    res = summarise(sys.argv[1], sys.argv[2], sys.argv[3] if len(sys.argv) > 3 else "")
-    print(markdown(res))
+    res = summarise(sys.argv[1], sys.argv[2], sys.argv[3] if len(sys.argv) > 3 else "see step_kernels_gpe3d_256.md")
+    tune = ""
+    path = os.environ.get("RK4IP_TUNE_CACHE")
+    if path and os.path.exists(path):
+        tune = open(path).read()
+    text = report(res, tune)
+    with open(os.path.join(sys.argv[2], "step_kernels_gpe3d_256.md"), "w") as fh:
+        fh.write(text)
+    print(text)
