@@ -41,12 +41,12 @@ def build(verbose: bool = False) -> str:
 
 class _Problem(ctypes.Structure):
     _fields_ = [
-        ("ndim", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+        ("ndim", ctypes.c_int32), ("integrator", ctypes.c_int32),
         ("n", ctypes.c_int64 * 3), ("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3),
         ("batch", ctypes.c_int64), ("h", ctypes.c_double), ("alpha", ctypes.c_double),
         ("gamma", ctypes.c_double), ("gnl", ctypes.c_double), ("trap", ctypes.c_double * 3),
         ("sigma", ctypes.c_double), ("seed", ctypes.c_uint64), ("id_base", ctypes.c_uint32),
-        ("reserved1", ctypes.c_uint32), ("Vgrid", ctypes.c_void_p),
+        ("noise_substeps", ctypes.c_uint32), ("Vgrid", ctypes.c_void_p),
     ]
 
 
@@ -111,6 +111,8 @@ class Problem:
     seed: int = 0
     id_base: int = 0
     Vgrid: Optional[np.ndarray] = None  # [batch][M] float64
+    integrator: int = 0        # 0: RK4IP; 1: semi-implicit in the interaction picture
+    noise_substeps: int = 1    # noise of a step = normalised sum of this many finer draws
     _keep: list = field(default_factory=list, repr=False)
 
     @property
@@ -139,6 +141,8 @@ class Problem:
         p.sigma = float(self.sigma)
         p.seed = int(self.seed) & 0xFFFFFFFFFFFFFFFF
         p.id_base = int(self.id_base) & 0xFFFFFFFF
+        p.integrator = int(self.integrator)
+        p.noise_substeps = int(self.noise_substeps)
         if self.Vgrid is not None:
             vg = np.ascontiguousarray(self.Vgrid, dtype=np.float64).reshape(self.batch, self.M)
             self._keep = [vg]

@@ -37,6 +37,16 @@
  *       u1 = ((r>>8)+1) 2^-24 in (0,1], u2 = (r>>8) 2^-24 in [0,1).
  *   R5  Lattice x_{a,j} = lo_a + j dx_a, dx_a = (hi_a - lo_a)/n_a, half-open domain;
  *       k_{a,m} = 2 pi / (hi_a - lo_a) * (m < n_a/2 ? m : m - n_a).
+ *   R6  The semi-implicit method (Sec. 3.5, deterministic order 2, stochastic order 1)
+ *       is the implicit midpoint rule solved by fixed-point iteration, here with three
+ *       iterations and in the interaction picture with its origin at the midpoint, so
+ *       that D = e^{L h/2} is again the only exponential:
+ *         a = D psi_n;  m <- a + (h/2) G(m) three times, starting from m = a;
+ *         psi_{n+1} = D(2 m - a).
+ *   R7  Sampling one Wiener path with several step sizes (the strong-convergence test of
+ *       Sec. 3.5): with S = 2^L substeps the noise of step n is the mean of the S draws of
+ *       a run with step h/S at steps nS ... nS + S - 1, i.e. xi = (sum_s z_s / sqrt(S)) /
+ *       sqrt(2 h dV) with z_s the complex normals of those finer steps.
  *
  * Memory layout: one instance is n[0]*n[1]*n[2] complex values with axis 0 (x)
  * contiguous; instances are concatenated. Unused axes have n = 1.
@@ -52,7 +62,7 @@ typedef double complex cplx;
 
 typedef struct {
     int32_t ndim;
-    int32_t reserved0;
+    int32_t integrator; /* 0: RK4IP (R1); 1: semi-implicit in the interaction picture (R6) */
     int64_t n[3];
     double lo[3];
     double hi[3];
@@ -65,7 +75,7 @@ typedef struct {
     double sigma;
     uint64_t seed;
     uint32_t id_base;
-    uint32_t reserved1;
+    uint32_t noise_substeps; /* 0 or 1: one draw per step; 2^L: the sum of 2^L finer draws (R7) */
     const double* Vgrid; /* [batch][M] or NULL */
 } ora_problem;
 
@@ -257,8 +267,14 @@ static void noise_field(const ora_problem* p, int64_t b, int64_t step, cplx* xi)
     int64_t M = npts(p);
     double scale = 1.0 / sqrt(2.0 * p->h * dV_of(p));
     uint32_t inst = p->id_base + (uint32_t)b;
+    int64_t S = p->noise_substeps > 1 ? (int64_t)p->noise_substeps : 1;
+    double inv_sqrt_S = 1.0 / sqrt((double)S);
 #pragma omp parallel for schedule(static)
-    for (int64_t j = 0; j < M; j++) xi[j] = scale * noise_z(p->seed, inst, step, 0u, j);
+    for (int64_t j = 0; j < M; j++) {
+        cplx z = 0.0;
+        for (int64_t q = 0; q < S; q++) z += noise_z(p->seed, inst, step * S + q, 0u, j);
+        xi[j] = scale * inv_sqrt_S * z;
+    }
 }
 
 void ora_noise(const ora_problem* p, int64_t step, cplx* xi /* [batch][M] */) {
@@ -345,10 +361,40 @@ static void step_one_x(const ora_problem* p, const cplx* E, const double* V, con
     free(t);
 }
 
+/* One semi-implicit step of one instance in the interaction picture (reading R6). */
+static void si_step_one_x(const ora_problem* p, const cplx* E, const double* V, const cplx* xi, cplx* psi,
+                          int dense) {
+    int64_t M = npts(p);
+    size_t bytes = sizeof(cplx) * (size_t)M;
+    cplx* a = (cplx*)malloc(bytes);
+    cplx* m = (cplx*)malloc(bytes);
+    cplx* t = (cplx*)malloc(bytes);
+    /* a = D psi_n: the state in the picture of the midpoint */
+    memcpy(a, psi, bytes);
+    DAPPLY(a);
+    /* the midpoint value m = a + (h/2) G(m), by three fixed-point iterations from m = a
+     * (at the midpoint the picture change is the identity) */
+    memcpy(m, a, bytes);
+    for (int it = 0; it < 3; it++) {
+        hG(p, V, xi, m, t);
+        for (int64_t j = 0; j < M; j++) m[j] = a[j] + 0.5 * t[j];
+    }
+    /* end of the step in the midpoint picture, 2 m - a, mapped back through D */
+    for (int64_t j = 0; j < M; j++) t[j] = 2.0 * m[j] - a[j];
+    DAPPLY(t);
+    memcpy(psi, t, bytes);
+    free(a);
+    free(m);
+    free(t);
+}
+
 #undef DAPPLY
 
 static void step_one(const ora_problem* p, const cplx* E, const double* V, const cplx* xi, cplx* psi) {
-    step_one_x(p, E, V, xi, psi, 0);
+    if (p->integrator == 1)
+        si_step_one_x(p, E, V, xi, psi, 0);
+    else
+        step_one_x(p, E, V, xi, psi, 0);
 }
 
 static int check_problem(const ora_problem* p) {
@@ -363,6 +409,8 @@ static int check_problem(const ora_problem* p) {
         if (!(p->hi[a] > p->lo[a])) return -1;
     }
     if (p->batch < 1 || !(p->h > 0.0)) return -1;
+    if (p->integrator != 0 && p->integrator != 1) return -1;
+    if (p->noise_substeps > 1 && (p->noise_substeps & (p->noise_substeps - 1)) != 0) return -1;
     return 0;
 }
 
@@ -400,7 +448,10 @@ int ora_step_dense(const ora_problem* p, cplx* psi, int64_t step_index) {
     for (int64_t b = 0; b < p->batch; b++) {
         potential(p, b, V);
         if (xi) noise_field(p, b, step_index, xi);
-        step_one_x(p, E, V, xi, psi + b * M, 1);
+        if (p->integrator == 1)
+            si_step_one_x(p, E, V, xi, psi + b * M, 1);
+        else
+            step_one_x(p, E, V, xi, psi + b * M, 1);
     }
     free(E);
     free(V);
@@ -600,7 +651,7 @@ static void tangent_one(const ora_problem* p, const cplx* E, const double* V, co
 
 /* Tangent-linear run: advances psi and dpsi by nsteps; dV is [batch][M] or NULL. */
 int ora_tangent(const ora_problem* p, cplx* psi, cplx* dpsi, const double* dV, int64_t step0, int64_t nsteps) {
-    if (check_problem(p)) return -1;
+    if (check_problem(p) || p->integrator != 0) return -1; /* the RK4IP step's tangent only */
     int64_t M = npts(p);
     cplx* E = make_E(p, 1.0);
     double* V = malloc(sizeof(double) * (size_t)M);
@@ -686,7 +737,8 @@ static void adjoint_one(const ora_problem* p, const cplx* E, const cplx* Ec, con
  *   grad_psi0: [batch][M] (out);  grad_V: [batch][M] (out) or NULL. */
 int ora_adjoint(const ora_problem* p, const cplx* psi0, int64_t step0, int64_t nsteps, int64_t ckpt_every,
                 const cplx* lamT, cplx* grad_psi0, double* grad_V) {
-    if (check_problem(p) || nsteps < 0 || ckpt_every < 1) return -1;
+    /* the discrete adjoint of the RK4IP step only */
+    if (check_problem(p) || p->integrator != 0 || nsteps < 0 || ckpt_every < 1) return -1;
     int64_t M = npts(p);
     size_t bytes = sizeof(cplx) * (size_t)M;
     cplx* E = make_E(p, 1.0);
