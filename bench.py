@@ -27,7 +27,9 @@ HBM_PEAK_GBS = 8000.0
 # reads psi and writes two fields; D2, LF and XF read and write two; LAST2 reads two and
 # writes psi. A steady-state 3D step is D2, LF, D2, XF = 128 B per point (a run adds one
 # FIRST and swaps its last XF for LAST2); a 1D line step reads and writes psi once.
-PASS_BYTES = {"FIRST": 24, "D2": 32, "LF": 32, "XF": 32, "LAST2": 24, "line_step": 16}
+PASS_BYTES = {"FIRST": 24, "D2": 32, "LF": 32, "XF": 32, "LAST2": 24, "line_step": 16,
+              # the semi-implicit step works on psi in place: every pass reads and writes it once
+              "D1": 16, "D1x2": 16, "SI": 16, "line_si": 16}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_gpe3d_256.json")
 
 
@@ -277,6 +279,81 @@ def form_fp64_transforms(torch, rk4ip, workloads, steps: int = 100):
     return out
 
 
+def form_semi_implicit(torch, rk4ip, workloads, steps: int = 100):
+    """The semi-implicit integrator (RK4IP_FLAG_SEMI_IMPLICIT) next to RK4IP: throughput on
+    the 3D 256^3 and the batched 1D workloads, the semi-implicit 3D passes' rates (event
+    timed, eager), and its strong convergence measured on the GPU: 2048 paths of a damped
+    stochastic GPE (64 points on [-8, 8)) to T = 0.64 at h = 2^l h_f with 2^l noise
+    substeps, error of each level against the h_f run (one Wiener path per path)."""
+    import numpy as np
+
+    SI = rk4ip.RK4IP_FLAG_SEMI_IMPLICIT
+    out = {}
+    for name, w, base in (("gpe3d_256^3", workloads.gpe3d(nsteps=steps), rk4ip.RK4IP_FLAG_AUTOTUNE),
+                          ("sgpe1d_2048x1024", workloads.sgpe1d(nsteps=steps),
+                           rk4ip.RK4IP_FLAG_FUSE_1D | rk4ip.RK4IP_FLAG_AUTOTUNE)):
+        probs, _k = rk4ip.problems_from_workload(w)
+        pts = sum(g.batch * g.M for g in w.groups)
+        psi0 = rk4ip.field_to_device(w)
+        rates = {}
+        for form, extra in (("rk4ip", 0), ("semi_implicit", SI)):
+            plan = rk4ip.Plan(probs, flags=rk4ip.RK4IP_FLAG_GRAPH | base | extra)
+            psi = psi0.clone()
+            plan.run(psi, 40)  # records the replay graph
+            t = _timed(torch, lambda: (psi.copy_(psi0), plan.run(psi, steps)))
+            rates[form] = pts * steps / t
+            plan.destroy()
+        rec = {"rk4ip_pt_steps_per_s": rates["rk4ip"], "semi_implicit_pt_steps_per_s": rates["semi_implicit"],
+               "semi_implicit_ms_per_step": pts / rates["semi_implicit"] * 1e3,
+               "speed_ratio": rates["semi_implicit"] / rates["rk4ip"]}
+        if w.groups[0].ndim == 3:
+            plan = rk4ip.Plan(probs, flags=base | SI)
+            work = psi0.clone()
+            plan.run(work, 3)
+            plan.profile(True)
+            plan.run(work, 20, step0=3)
+            rec["passes"] = []
+            for i in range(plan.num_passes(0)):
+                n, mean = plan.profile_read(0, i)
+                nm = plan.schedule(0, i)
+                gbs = PASS_BYTES[nm.split(":")[0]] * pts / (mean / 1e3) / 1e9 if n else None
+                rec["passes"].append({"pass": nm, "launches": n, "mean_ms": mean, "achieved_GBps": gbs,
+                                      "hbm_frac": gbs / HBM_PEAK_GBS if gbs else None})
+            plan.destroy()
+        out[name] = rec
+
+    g = workloads.Group(n=(64,), lo=(-8.0,), hi=(8.0,), batch=2048, gnl=10.0, gamma=0.05, sigma=0.1,
+                        trap=(1.0, 0.0, 0.0), seed=21)
+    x = g.axis(0)
+    psi0 = np.broadcast_to(np.pi ** -0.25 * np.exp(-x ** 2 / 2), g.shape)
+    hf, T = 2.5e-4, 0.64
+    nf = int(round(T / hf))
+
+    def run(S):
+        w = workloads.Workload("sc", [g], hf * S, nf // S, [psi0])
+        probs, _k = rk4ip.problems_from_workload(w, noise_substeps=S)
+        plan = rk4ip.Plan(probs, flags=SI | rk4ip.RK4IP_FLAG_GRAPH | rk4ip.RK4IP_FLAG_FUSE_1D
+                          | rk4ip.RK4IP_FLAG_FP64_TRANSFORMS)
+        d = rk4ip.field_to_device(w)
+        plan.run(d, nf // S)
+        torch.cuda.synchronize()
+        plan.destroy()
+        return d.cpu().numpy().astype(np.complex128).reshape(g.shape)
+
+    fine = run(1)
+    levels = []
+    for S in (32, 16, 8, 4, 2):
+        e = np.linalg.norm(run(S) - fine, axis=1) / np.linalg.norm(fine, axis=1)
+        levels.append({"h": hf * S, "noise_substeps": S, "mean_strong_error": float(np.mean(e)),
+                       "stderr": float(np.std(e, ddof=1) / np.sqrt(len(e)))})
+    orders = [float(np.log2(levels[i]["mean_strong_error"] / levels[i + 1]["mean_strong_error"]))
+              for i in range(len(levels) - 1)]
+    out["strong_convergence"] = {"workload": "2048 paths x 64 points, g = 10, gamma = 0.05, sigma = 0.1, T = 0.64, "
+                                             "reference h_f = 2.5e-4 (FP64 transforms)",
+                                 "levels": levels, "orders": orders}
+    return out
+
+
 def other_workloads(torch, rk4ip, workloads):
     """Throughput of the 1D NLSE (256 points, 1000 steps) and the 2D GPE (512^2, 2000 steps)
     at their full run lengths, graph-replayed with tuned schedules."""
@@ -300,7 +377,8 @@ def measure_forms(torch, rk4ip, workloads):
             "batched_paths": form_batched_paths(torch, rk4ip, workloads),
             "uneven_batch": form_uneven_batch(torch, rk4ip, workloads),
             "adjoint": form_adjoint(torch, rk4ip, workloads),
-            "fp64_transforms": form_fp64_transforms(torch, rk4ip, workloads)}
+            "fp64_transforms": form_fp64_transforms(torch, rk4ip, workloads),
+            "semi_implicit": form_semi_implicit(torch, rk4ip, workloads)}
 
 
 def main() -> int:

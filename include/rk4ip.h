@@ -55,7 +55,8 @@ extern "C" {
 
 enum {
     RK4IP_OK = 0,
-    RK4IP_ERR_INVALID_ARG = -1,         /* null pointer, bad count, dt <= 0, unknown flag */
+    RK4IP_ERR_INVALID_ARG = -1,         /* null pointer, bad count, dt <= 0, unknown flag,
+                                           noise_substeps not a power of two <= 1024 */
     RK4IP_ERR_UNSUPPORTED_SHAPE = -2,   /* n[a] not a power of two in [8, 4096] (1D) or
                                            [8, 1024] (2D/3D), ndim not 1..3 */
     RK4IP_ERR_WORKSPACE_TOO_SMALL = -3,
@@ -76,6 +77,18 @@ enum {
  * high-k content (noise). Radix-8 schedules only; 1D lines up to 2048 points. The adjoint
  * passes keep FP32 transforms (their recomputed forward steps use this form). */
 #define RK4IP_FLAG_FP64_TRANSFORMS 0x8u
+/* The semi-implicit integrator (Sec. 3.5, the semi-implicit method, in the same
+ * interaction picture with its origin at the step midpoint) in place of RK4:
+ *
+ *     a = D psi_n,   m = a + (dt/2) G(m) by three fixed-point iterations from m = a,
+ *     psi_{n+1} = D (2 m - a).
+ *
+ * Second order in dt for deterministic problems, strong order one with additive noise,
+ * and one G evaluation per iteration instead of four stages: the integrator the paper
+ * uses for strong convergence of stochastic problems. The noise xi of a step is the same
+ * Stratonovich draw as for RK4 (see noise_substeps). rk4ip_adjoint does not support it
+ * (RK4IP_ERR_INVALID_ARG). */
+#define RK4IP_FLAG_SEMI_IMPLICIT 0x10u
 
 typedef struct rk4ip_plan_s* rk4ip_plan_t;
 
@@ -95,7 +108,11 @@ typedef struct {
     double sigma;            /* additive noise amplitude (0 = deterministic) */
     uint64_t seed;           /* Philox key */
     uint32_t id_base;        /* Philox instance id of the first instance of this group */
-    uint32_t reserved1;      /* must be 0 */
+    uint32_t noise_substeps; /* S: the noise of step s is the normalised sum of the draws of
+                                steps s S ... s S + S - 1 of a run with step dt/S, so that runs
+                                with dt and dt/S sample one Wiener path (strong convergence
+                                tests, Sec. 3.5). A power of two up to 1024; 0 and 1 mean one
+                                draw per step. */
 } rk4ip_problem;
 
 /* Bytes of device workspace rk4ip_plan needs for these groups: the spectral tables
@@ -114,7 +131,8 @@ int rk4ip_plan(const rk4ip_problem* probs, int nprob, void* workspace, size_t ws
 /* Rebind the plan to another stream (a hipStream_t). */
 int rk4ip_set_stream(rk4ip_plan_t plan, void* stream);
 
-/* One RK4IP step of every instance, in place on `psi` (device complex64). step_index
+/* One step of every instance (RK4IP, or the semi-implicit step for plans made with
+ * RK4IP_FLAG_SEMI_IMPLICIT), in place on `psi` (device complex64). step_index
  * selects the noise counters. */
 int rk4ip_step(rk4ip_plan_t plan, void* psi, int64_t step_index);
 
@@ -156,7 +174,8 @@ size_t rk4ip_adjoint_workspace_bytes(rk4ip_plan_t plan, int64_t ckpt_every);
  * grad_psi0 (device complex64, same convention) and, if grad_V != NULL, adds nothing
  * but overwrites grad_V (device float [ninst][M]) with dLoss/dV_grid. Each segment of
  * ckpt_every steps is recomputed from its checkpoint into adj_ws and walked
- * backwards; V gradients accumulate in FP64. */
+ * backwards; V gradients accumulate in FP64. Plans made with RK4IP_FLAG_SEMI_IMPLICIT
+ * return RK4IP_ERR_INVALID_ARG (the adjoint is that of the RK4IP step). */
 int rk4ip_adjoint(rk4ip_plan_t plan, const void* ckpt, int64_t step0, int64_t nsteps, int64_t ckpt_every,
                   const void* lambda_T, void* grad_psi0, float* grad_V, void* adj_ws, size_t adj_ws_bytes);
 

@@ -37,6 +37,8 @@ struct GroupDev {
     const float2* tw[3];     // per axis: e^{-2 pi i t / n_a}
     const double2* E64[3];   // the same tables in FP64 (FP64-transform plans, else null)
     const double2* tw64[3];
+    int noise_sub;           // noise of a step = normalised sum of this many finer draws
+    float inv_sqrt_sub;      // 1/sqrt(noise_sub)
 };
 
 // ---------------------------------------------------------------- Philox4x32-10
@@ -77,21 +79,34 @@ __device__ __forceinline__ U4 noise_counter(int64_t j, uint32_t inst, int64_t st
     return c;
 }
 
-// Box-Muller on two 24-bit uniforms: u1 in (0,1], u2 in [0,1). Returns a complex normal
-// with E|z|^2 = 2.
-__device__ __forceinline__ float2 box_muller(uint32_t ra, uint32_t rb) {
+// Box-Muller on two 24-bit uniforms: u1 in (0,1], u2 in [0,1). The complex normal
+// z = rad (cos, sin)(2 pi u2), E|z|^2 = 2, as its radius and unit phasor.
+__device__ __forceinline__ void box_muller(uint32_t ra, uint32_t rb, float& rad, float& c, float& s) {
     const float u1 = (float)((ra >> 8) + 1u) * 5.9604644775390625e-08f;  // 2^-24, exact
     const float u2 = (float)(rb >> 8) * 5.9604644775390625e-08f;
-    const float rad = sqrtf(-2.0f * logf(u1));
-    float s, c;
+    rad = sqrtf(-2.0f * logf(u1));
     sincospif(2.0f * u2, &s, &c);
-    return make_float2(rad * c, rad * s);
 }
 
-// Unit complex normal (E|z|^2 = 2) for point j of instance `inst` at `step`.
+// Unit complex normal (E|z|^2 = 2) for point j of instance `inst` at `step`. With S noise
+// substeps it is the sum of the normals of steps step*S ... step*S + S - 1 of a run with
+// step h/S, divided by sqrt(S): one Wiener path sampled at several step sizes. The sum is
+// written as explicit FMAs so that every kernel rounds it the same way (S = 1: the
+// rounded product rad * cos, as a single draw).
 __device__ __forceinline__ float2 noise_z(const GroupDev& g, int64_t j, uint32_t inst, int64_t step) {
-    const U4 r = philox4x32_10(noise_counter(j, inst, step), g.seed_lo, g.seed_hi);
-    return (j & 1) ? box_muller(r.z, r.w) : box_muller(r.x, r.y);
+    const int S = g.noise_sub;
+    float2 acc = make_float2(0.f, 0.f);
+    for (int s = 0; s < S; s++) {
+        const U4 r = philox4x32_10(noise_counter(j, inst, step * S + s), g.seed_lo, g.seed_hi);
+        float rad, c, sn;
+        if (j & 1)
+            box_muller(r.z, r.w, rad, c, sn);
+        else
+            box_muller(r.x, r.y, rad, c, sn);
+        acc.x = fmaf(rad, c, acc.x);
+        acc.y = fmaf(rad, sn, acc.y);
+    }
+    return make_float2(acc.x * g.inv_sqrt_sub, acc.y * g.inv_sqrt_sub);
 }
 
 // Trap potential at lattice indices (x, y, z).
@@ -110,17 +125,14 @@ __device__ __forceinline__ float trap_V(const GroupDev& g, int ix, int iy, int i
     return v;
 }
 
-// h G(phi) without the noise term: -i h (V + g |phi|^2) phi
-__device__ __forceinline__ c32 hG_det(const GroupDev& g, c32 phi, float V) {
+// h G(phi) = -i h (V + g |phi|^2) phi + hnz, with hnz = noise_c * z (already scaled). The last products
+// and the noise add are one explicit FMA, so every kernel that evaluates G (the fused
+// passes and the ones that open and close a run) rounds it identically and split runs
+// stay bitwise equal to whole ones.
+__device__ __forceinline__ c32 hG(const GroupDev& g, c32 phi, float V, c32 hnz) {
     const float m2 = fmaf(phi.x, phi.x, phi.y * phi.y);
     const float w = g.h * fmaf(g.gnl, m2, V);
-    return make_float2(w * phi.y, -w * phi.x);
-}
-
-// h G(phi) with the noise term; hnz = noise_c * z (already scaled)
-__device__ __forceinline__ c32 hG(const GroupDev& g, c32 phi, float V, c32 hnz) {
-    c32 r = hG_det(g, phi, V);
-    return make_float2(r.x + hnz.x, r.y + hnz.y);
+    return make_float2(fmaf(w, phi.y, hnz.x), fmaf(-w, phi.x, hnz.y));
 }
 
 // Transposes for the discrete adjoint (not in the paper). G is R-linear in (phi, conj phi):

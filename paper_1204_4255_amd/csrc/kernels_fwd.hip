@@ -9,8 +9,9 @@ namespace rk4ip {
 // One workgroup runs LPB whole lines (instances). Every value of the step stays in
 // registers; LDS only carries the FFT exchanges. RR values per thread (16 or 8: fewer
 // registers and more threads per line). P64: transforms in FP64 (RR = 8), everything
-// else as in the complex64 form.
-template <int N, int LPB, bool NOISE, bool P64, int RR>
+// else as in the complex64 form. SI: the semi-implicit step (one field: a = D psi, the
+// midpoint iteration, D(2m - a)) instead of RK4IP.
+template <int N, int LPB, bool NOISE, bool P64, int RR, bool SI>
 __global__ void __launch_bounds__((FFTShape<N, RR>::T * LPB))
     k_line_step(GroupDev g, float2* __restrict__ psi, int nsteps, int64_t step_off,
                 const int64_t* __restrict__ step_base) {
@@ -54,6 +55,23 @@ __global__ void __launch_bounds__((FFTShape<N, RR>::T * LPB))
             } else {
                 nz[m] = make_float2(0.f, 0.f);
             }
+        }
+        if constexpr (SI) {
+            c32(&f0)[1][R] = *reinterpret_cast<c32(*)[1][R]>(&f[0]);
+            propagate<F, L, 1>(f0, t, l, lds, tw, E, false);  // a = D psi
+#pragma unroll
+            for (int m = 0; m < R; m++) {
+                const c32 a = f[0][m];
+                c32 mid = a;
+#pragma unroll
+                for (int it = 0; it < 3; it++) {
+                    const c32 k = hG(g, mid, V[m], nz[m]);
+                    mid = make_float2(fmaf(0.5f, k.x, a.x), fmaf(0.5f, k.y, a.y));
+                }
+                f[0][m] = make_float2(fmaf(2.0f, mid.x, -a.x), fmaf(2.0f, mid.y, -a.y));
+            }
+            propagate<F, L, 1>(f0, t, l, lds, tw, E, false);  // psi' = D(2m - a)
+            continue;
         }
         // first pair: D psi and D[h G(psi)]
 #pragma unroll
@@ -111,6 +129,7 @@ hipError_t launch_axis(const GroupDev& g, int axis, int mode, const PassArgs& a,
         case PASS_FIRST:
         case PASS_LAST2: return launch_axis_first(g, axis, mode, a, s);
         case PASS_LF: return launch_axis_last(g, axis, mode, a, s);
+        case PASS_SI: return launch_axis_si(g, axis, a, s);
         case PASS_XF: return launch_axis_xf(g, axis, a, s);
         case PASS_U:
         case PASS_AW:
@@ -120,46 +139,53 @@ hipError_t launch_axis(const GroupDev& g, int axis, int mode, const PassArgs& a,
     }
 }
 
-template <int N, bool P64, int RR>
+template <int N, bool P64, int RR, bool SI>
 static hipError_t go_line(const GroupDev& g, float2* psi, int nsteps, int64_t step_off, const int64_t* step_base,
                           hipStream_t s) {
     constexpr int T = FFTShape<N, RR>::T;
     constexpr int LPB = T >= 64 ? 1 : 64 / T;
     const int64_t blocks = (g.batch + LPB - 1) / LPB;
     if (g.has_noise)
-        hipLaunchKernelGGL((k_line_step<N, LPB, true, P64, RR>), dim3((unsigned)blocks), dim3(T * LPB), 0, s, g, psi,
-                           nsteps, step_off, step_base);
+        hipLaunchKernelGGL((k_line_step<N, LPB, true, P64, RR, SI>), dim3((unsigned)blocks), dim3(T * LPB), 0, s, g,
+                           psi, nsteps, step_off, step_base);
     else
-        hipLaunchKernelGGL((k_line_step<N, LPB, false, P64, RR>), dim3((unsigned)blocks), dim3(T * LPB), 0, s, g, psi,
-                           nsteps, step_off, step_base);
+        hipLaunchKernelGGL((k_line_step<N, LPB, false, P64, RR, SI>), dim3((unsigned)blocks), dim3(T * LPB), 0, s, g,
+                           psi, nsteps, step_off, step_base);
     return hipGetLastError();
 }
 
-template <int N>
+template <int N, bool SI>
 static hipError_t go_line_p(const GroupDev& g, float2* psi, int nsteps, int64_t step_off, const int64_t* step_base,
                             bool f64, int radix, hipStream_t s) {
     if (f64) {
-        if constexpr (N <= 2048) return go_line<N, true, 8>(g, psi, nsteps, step_off, step_base, s);
+        if constexpr (N <= 2048) return go_line<N, true, 8, SI>(g, psi, nsteps, step_off, step_base, s);
         return hipErrorInvalidValue;  // FP64 tables and exchange buffers exceed the LDS
     }
-    if (radix == 8) return go_line<N, false, 8>(g, psi, nsteps, step_off, step_base, s);
-    if (radix == 0 || radix == 16) return go_line<N, false, 16>(g, psi, nsteps, step_off, step_base, s);
+    if (radix == 8) return go_line<N, false, 8, SI>(g, psi, nsteps, step_off, step_base, s);
+    if (radix == 0 || radix == 16) return go_line<N, false, 16, SI>(g, psi, nsteps, step_off, step_base, s);
     return hipErrorInvalidValue;
 }
 
+template <int N>
+static hipError_t go_line_n(const GroupDev& g, float2* psi, int nsteps, int64_t step_off, const int64_t* step_base,
+                            bool f64, int radix, bool si, hipStream_t s) {
+    if (si) return go_line_p<N, true>(g, psi, nsteps, step_off, step_base, f64, radix, s);
+    return go_line_p<N, false>(g, psi, nsteps, step_off, step_base, f64, radix, s);
+}
+
 hipError_t launch_line_step(const GroupDev& g, float2* psi, int nsteps, int64_t step_off, const int64_t* step_base,
-                            bool f64, int radix, hipStream_t s) {
+                            bool f64, int radix, bool semi_implicit, hipStream_t s) {
     switch (g.n[0]) {
-        case 8: return go_line_p<8>(g, psi, nsteps, step_off, step_base, f64, radix, s);
-        case 16: return go_line_p<16>(g, psi, nsteps, step_off, step_base, f64, radix, s);
-        case 32: return go_line_p<32>(g, psi, nsteps, step_off, step_base, f64, radix, s);
-        case 64: return go_line_p<64>(g, psi, nsteps, step_off, step_base, f64, radix, s);
-        case 128: return go_line_p<128>(g, psi, nsteps, step_off, step_base, f64, radix, s);
-        case 256: return go_line_p<256>(g, psi, nsteps, step_off, step_base, f64, radix, s);
-        case 512: return go_line_p<512>(g, psi, nsteps, step_off, step_base, f64, radix, s);
-        case 1024: return go_line_p<1024>(g, psi, nsteps, step_off, step_base, f64, radix, s);
-        case 2048: return go_line_p<2048>(g, psi, nsteps, step_off, step_base, f64, radix, s);
-        case 4096: return go_line_p<4096>(g, psi, nsteps, step_off, step_base, f64, radix, s);
+        case 8: return go_line_n<8>(g, psi, nsteps, step_off, step_base, f64, radix, semi_implicit, s);
+        case 16: return go_line_n<16>(g, psi, nsteps, step_off, step_base, f64, radix, semi_implicit, s);
+        case 32: return go_line_n<32>(g, psi, nsteps, step_off, step_base, f64, radix, semi_implicit, s);
+        case 64: return go_line_n<64>(g, psi, nsteps, step_off, step_base, f64, radix, semi_implicit, s);
+        case 128: return go_line_n<128>(g, psi, nsteps, step_off, step_base, f64, radix, semi_implicit, s);
+        case 256: return go_line_n<256>(g, psi, nsteps, step_off, step_base, f64, radix, semi_implicit, s);
+        case 512: return go_line_n<512>(g, psi, nsteps, step_off, step_base, f64, radix, semi_implicit, s);
+        case 1024: return go_line_n<1024>(g, psi, nsteps, step_off, step_base, f64, radix, semi_implicit, s);
+        case 2048: return go_line_n<2048>(g, psi, nsteps, step_off, step_base, f64, radix, semi_implicit, s);
+        case 4096: return go_line_n<4096>(g, psi, nsteps, step_off, step_base, f64, radix, semi_implicit, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -19,7 +19,8 @@ enum PassMode {
     PASS_AS = 7,
     PASS_AF = 8,
     PASS_LF = 9,   // last axis: D, the RK4 stage epilogue, D again
-    PASS_XF = 10   // axis 0: D, the end of one step, the start of the next, D again
+    PASS_XF = 10,  // axis 0: D, the end of one step, the start of the next, D again
+    PASS_SI = 11   // last axis, semi-implicit step: D, the midpoint iteration, D again
 };
 
 // Pointers of one pass; every field pointer addresses the concatenated field of all
@@ -39,6 +40,7 @@ struct PassArgs {
     int radix;                // values per thread in the transform: 16 (0 = default) or 8
     int f64;                  // transforms, propagator multiply and delta add in FP64 (radix 8)
     int occ;                  // minimum waves per SIMD the kernel is compiled for (0/1 = none, 4)
+    int twice;                // D1: apply the half-step propagator twice (a whole step)
     int64_t step_off;
     const int64_t* step_base; // step = step_off (+ *step_base when not null)
 };
@@ -59,12 +61,13 @@ hipError_t launch_axis_adjoint(const GroupDev& g, int axis, int mode, const Pass
 hipError_t launch_axis_d(const GroupDev& g, int axis, int mode, const PassArgs& a, hipStream_t s);
 hipError_t launch_axis_first(const GroupDev& g, int axis, int mode, const PassArgs& a, hipStream_t s);
 hipError_t launch_axis_xf(const GroupDev& g, int axis, const PassArgs& a, hipStream_t s);
+hipError_t launch_axis_si(const GroupDev& g, int axis, const PassArgs& a, hipStream_t s);
 hipError_t launch_axis_last(const GroupDev& g, int axis, int mode, const PassArgs& a, hipStream_t s);
 hipError_t launch_line_adjoint(const GroupDev& g, const float2* psi_n, float2* lam, double* vbar, int64_t step,
                                hipStream_t s);
 hipError_t launch_vbar_to_float(const double* vbar, float* out, int64_t n, hipStream_t s);
 hipError_t launch_line_step(const GroupDev& g, float2* psi, int nsteps, int64_t step_off, const int64_t* step_base, bool f64,
-                            int radix, hipStream_t s);
+                            int radix, bool semi_implicit, hipStream_t s);
 hipError_t launch_diag_axis(const GroupDev& g, int axis, const float2* psi, double kscale, double* part,
                             hipStream_t s);
 hipError_t launch_diag_final(const GroupDev& g, const DiagConst& c, const double* p0, const double* p1,

@@ -20,6 +20,13 @@
 //   LAST2 (axis 0):  (A, B) -> D_0 -> psi' -> psi                      closes the run
 // The noise of a step is drawn wherever that step evaluates G (XF draws step n-1's for k4
 // and step n's for the next start).
+//
+// The semi-implicit step (Sec. 3.5, in the same midpoint picture: a = D psi, m = a +
+// (h/2) G(m) by three fixed-point iterations, psi' = D(2m - a)) works on psi in place:
+//   D1 (axis 0, half step, opens a run); D1 (middle axes);
+//   SI (last axis): psi -> D_a -> a; m; 2m - a -> D_a -> psi;  D1 (middle axes);
+//   D1 (axis 0) twice in registers where two steps meet (the same arithmetic as closing
+//   one run and opening the next, so split runs stay bitwise equal), or once to close.
 // A 1D line fits one workgroup, so the whole step (eight transforms) runs in registers
 // and LDS with one read and one write of psi (k_line_step), optionally for several
 // steps per launch.
@@ -170,12 +177,12 @@ __device__ __forceinline__ void unflatten(const GroupDev& g, int64_t j, int& x, 
     z = (int)(j >> (g.log2n[0] + g.log2n[1]));
 }
 
-constexpr int fields_of(int mode) { return (mode == PASS_D1 || mode == PASS_U) ? 1 : 2; }
+constexpr int fields_of(int mode) { return (mode == PASS_D1 || mode == PASS_U || mode == PASS_SI) ? 1 : 2; }
 
 // passes whose pointwise work evaluates G (and so may draw noise)
 constexpr bool uses_rhs(int mode) {
     return mode == PASS_FIRST || mode == PASS_LAST2 || mode == PASS_U || mode == PASS_AS ||
-           mode == PASS_LF || mode == PASS_XF;
+           mode == PASS_LF || mode == PASS_XF || mode == PASS_SI;
 }
 
 // SEQ = 0: both fields go through the transform together (one exchange buffer each).
@@ -261,7 +268,7 @@ k_axis(GroupDev g, int axis, PassArgs args) {
     };
 
     c32 f[NF][R];
-    if constexpr (MODE == PASS_D1 || MODE == PASS_FIRST) {
+    if constexpr (MODE == PASS_D1 || MODE == PASS_FIRST || MODE == PASS_SI) {
 #pragma unroll
         for (int m = 0; m < R; m++) f[0][m] = tile.active ? ld2(ps, tile.b8(m)) : zero;
         if constexpr (MODE == PASS_FIRST) {
@@ -318,14 +325,28 @@ k_axis(GroupDev g, int axis, PassArgs args) {
 
     __syncthreads();  // tables staged (the loads above overlap the copy)
     transform(true);
+    if constexpr (MODE == PASS_D1) {
+        if (args.twice) transform(false);  // uniform over the grid
+    }
 
-    if constexpr (MODE == PASS_LF || MODE == PASS_XF) {
+    if constexpr (MODE == PASS_LF || MODE == PASS_XF || MODE == PASS_SI) {
         // the work between the two transforms of a fused pass (every thread takes part in
         // the second transform's barriers, active or not)
 #pragma unroll
         for (int m = 0; m < R; m++) {
             const float V = potential_at(m);
-            if constexpr (MODE == PASS_LF) {
+            if constexpr (MODE == PASS_SI) {
+                // semi-implicit step at the midpoint picture: m = a + (h/2) G(m) by three
+                // fixed-point iterations from m = a, then the end of the step 2m - a
+                const c32 a = f[0][m], nz = noise_at(m, step);
+                c32 mid = a;
+#pragma unroll
+                for (int it = 0; it < 3; it++) {
+                    const c32 k = hG(g, mid, V, nz);
+                    mid = make_float2(fmaf(0.5f, k.x, a.x), fmaf(0.5f, k.y, a.y));
+                }
+                f[0][m] = make_float2(fmaf(2.0f, mid.x, -a.x), fmaf(2.0f, mid.y, -a.y));
+            } else if constexpr (MODE == PASS_LF) {
                 stages(f[0][m], f[1][m], V, noise_at(m, step));
             } else {
                 // end of step n-1: psi_n = D acc + hG(D u)/6, then the start of step n:
@@ -340,7 +361,7 @@ k_axis(GroupDev g, int axis, PassArgs args) {
     }
 
     if (!tile.active) return;  // after the last barrier
-    if constexpr (MODE == PASS_D1 || MODE == PASS_U) {
+    if constexpr (MODE == PASS_D1 || MODE == PASS_U || MODE == PASS_SI) {
 #pragma unroll
         for (int m = 0; m < R; m++) st2(ps, tile.b8(m), f[0][m]);
     } else if constexpr (MODE == PASS_LAST2) {
@@ -428,12 +449,14 @@ constexpr bool contig_only(int mode) {
     return mode == PASS_FIRST || mode == PASS_U || mode == PASS_AW || mode == PASS_XF || mode == PASS_LAST2;
 }
 constexpr bool strided_only(int mode) {
-    return mode == PASS_AS || mode == PASS_AF || mode == PASS_LF;
+    return mode == PASS_AS || mode == PASS_AF || mode == PASS_LF || mode == PASS_SI;
 }
 // lengths with more than the default schedule compiled (the ones the workloads use)
 constexpr bool tuned_length(int N) { return N >= 128 && N <= 512; }
 // forward-step passes get the schedule variants; the adjoint passes use the default
-constexpr bool tuned_mode(int mode) { return mode <= PASS_LAST2 || mode == PASS_LF || mode == PASS_XF; }
+constexpr bool tuned_mode(int mode) {
+    return mode <= PASS_LAST2 || mode == PASS_LF || mode == PASS_XF || mode == PASS_SI;
+}
 // passes compiled with FP64 transforms (the forward step and the plain propagator)
 constexpr bool f64_mode(int mode) { return tuned_mode(mode); }
 // passes that read both fields of the pair from memory
@@ -579,6 +602,7 @@ static bool schedule_ok_n(int mode, bool contig, int lines, int seq, int rr, boo
         case PASS_LAST2: return contig && schedule_compiled<N, PASS_LAST2>(contig, lines, seq, rr, p64, occ);
         case PASS_LF: return !contig && schedule_compiled<N, PASS_LF>(contig, lines, seq, rr, p64, occ);
         case PASS_XF: return contig && schedule_compiled<N, PASS_XF>(contig, lines, seq, rr, p64, occ);
+        case PASS_SI: return !contig && schedule_compiled<N, PASS_SI>(contig, lines, seq, rr, p64, occ);
         default: return false;
     }
 }

@@ -23,7 +23,8 @@ namespace {
 constexpr double kPi = 3.14159265358979323846;
 constexpr size_t kAlign = 256;
 constexpr uint32_t kKnownFlags =
-    RK4IP_FLAG_GRAPH | RK4IP_FLAG_AUTOTUNE | RK4IP_FLAG_FUSE_1D | RK4IP_FLAG_FP64_TRANSFORMS;
+    RK4IP_FLAG_GRAPH | RK4IP_FLAG_AUTOTUNE | RK4IP_FLAG_FUSE_1D | RK4IP_FLAG_FP64_TRANSFORMS | RK4IP_FLAG_SEMI_IMPLICIT;
+constexpr uint32_t kMaxNoiseSubsteps = 1024;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -72,7 +73,9 @@ int validate(const rk4ip_problem* probs, int nprob, uint32_t flags) {
     int64_t ninst = 0;
     for (int i = 0; i < nprob; i++) {
         const rk4ip_problem& p = probs[i];
-        if (p.reserved0 != 0 || p.reserved1 != 0) return RK4IP_ERR_INVALID_ARG;
+        if (p.reserved0 != 0) return RK4IP_ERR_INVALID_ARG;
+        if (p.noise_substeps > kMaxNoiseSubsteps || (p.noise_substeps > 1 && !is_pow2(p.noise_substeps)))
+            return RK4IP_ERR_INVALID_ARG;
         if (!(p.dt > 0.0) || !std::isfinite(p.dt) || p.dt != dt0) return RK4IP_ERR_INVALID_ARG;
         if (!std::isfinite(p.alpha) || !std::isfinite(p.gamma) || p.gamma < 0.0) return RK4IP_ERR_INVALID_ARG;
         if (!std::isfinite(p.g_nl) || !std::isfinite(p.sigma) || p.sigma < 0.0) return RK4IP_ERR_INVALID_ARG;
@@ -160,6 +163,7 @@ struct rk4ip_plan_s {
     int64_t* counter = nullptr;
     int* flag = nullptr;
     bool f64 = false;  // FP64 transforms in the forward step
+    bool si = false;   // the semi-implicit integrator in place of RK4
     std::string err;
     std::vector<std::vector<std::string>> sched_names;  // [group][pass]
     std::vector<std::vector<Sched>> sched;  // [group][pass]; zeros = default schedule
@@ -247,9 +251,24 @@ void build_tables(const rk4ip_problem& p, int a, std::vector<float2>& E, std::ve
 enum Role { ROLE_OPEN, ROLE_MID, ROLE_NEXT, ROLE_CLOSE };
 struct PassDef {
     int axis, mode, role;
+    int twice = 0;  // D1 on axis 0 applied twice: the end of one step and the start of the next
 };
 
-int pass_list(int ndim, PassDef* out) {
+int pass_list(int ndim, bool si, PassDef* out) {
+    if (si) {
+        // in place on psi: D_0, the middle axes, the midpoint iteration between the two
+        // half steps of the last axis, the middle axes again, then D_0 twice where two
+        // steps meet (in one pass) or once at the end of the run
+        const int last = ndim - 1;
+        int k = 0;
+        out[k++] = {0, rk4ip::PASS_D1, ROLE_OPEN};
+        for (int a = 1; a < last; a++) out[k++] = {a, rk4ip::PASS_D1, ROLE_MID};
+        out[k++] = {last, rk4ip::PASS_SI, ROLE_MID};
+        for (int a = last - 1; a >= 1; a--) out[k++] = {a, rk4ip::PASS_D1, ROLE_MID};
+        out[k++] = {0, rk4ip::PASS_D1, ROLE_NEXT, 1};
+        out[k++] = {0, rk4ip::PASS_D1, ROLE_CLOSE};
+        return k;
+    }
     if (ndim == 2) {
         const PassDef seq[4] = {{0, rk4ip::PASS_FIRST, ROLE_OPEN},
                                 {1, rk4ip::PASS_LF, ROLE_MID},
@@ -274,6 +293,7 @@ const char* mode_name(int mode) {
         case rk4ip::PASS_LAST2: return "LAST2";
         case rk4ip::PASS_LF: return "LF";
         case rk4ip::PASS_XF: return "XF";
+        case rk4ip::PASS_SI: return "SI";
         default: return "?";
     }
 }
@@ -321,11 +341,13 @@ int collect_profile(rk4ip_plan_t plan) {
 }
 
 // Mean time (ms) of `reps` launches of one pass with a given schedule, on the work fields.
-int time_pass(rk4ip_plan_t plan, const GroupHost& g, int axis, int mode, const Sched& sc, int reps, float* ms) {
+int time_pass(rk4ip_plan_t plan, const GroupHost& g, const PassDef& def, const Sched& sc, int reps, float* ms) {
+    const int axis = def.axis, mode = def.mode;
     rk4ip::PassArgs pa{};
     pa.A = plan->A;
     pa.B = plan->B;
     pa.psi = (mode == rk4ip::PASS_FIRST) ? plan->B : plan->A;  // same tiles are read before written
+    pa.twice = def.twice;
     pa.step_off = 1;
     pa.f64 = plan->f64 ? 1 : 0;
     pa.lines = sc.lines;
@@ -351,11 +373,13 @@ int time_pass(rk4ip_plan_t plan, const GroupHost& g, int axis, int mode, const S
 // work field A (its contents are irrelevant).
 int time_line(rk4ip_plan_t plan, const GroupHost& g, int rr, int reps, float* ms) {
     hipStream_t st = plan->stream;
-    for (int i = 0; i < 2; i++) HIPCHK(plan, rk4ip::launch_line_step(g.d, plan->A, 4, 1, nullptr, false, rr, st));
+    for (int i = 0; i < 2; i++)
+        HIPCHK(plan, rk4ip::launch_line_step(g.d, plan->A, 4, 1, nullptr, false, rr, plan->si, st));
     hipEvent_t a = take_event(plan), b = take_event(plan);
     if (!a || !b) return fail(plan, RK4IP_ERR_HIP, "hipEventCreate failed");
     HIPCHK(plan, hipEventRecord(a, st));
-    for (int i = 0; i < reps; i++) HIPCHK(plan, rk4ip::launch_line_step(g.d, plan->A, 4, 1, nullptr, false, rr, st));
+    for (int i = 0; i < reps; i++)
+        HIPCHK(plan, rk4ip::launch_line_step(g.d, plan->A, 4, 1, nullptr, false, rr, plan->si, st));
     HIPCHK(plan, hipEventRecord(b, st));
     HIPCHK(plan, hipEventSynchronize(b));
     HIPCHK(plan, hipEventElapsedTime(ms, a, b));
@@ -367,10 +391,11 @@ int time_line(rk4ip_plan_t plan, const GroupHost& g, int rr, int reps, float* ms
 
 // Tuning cache: a flat JSON object {"key": [lines, seq], ...} in the file named by
 // RK4IP_TUNE_CACHE (optional).
-std::string tune_key(const GroupHost& g, int pass) {
+std::string tune_key(const GroupHost& g, int pass, bool si) {
     char k[160];
-    std::snprintf(k, sizeof(k), "gfx950|n=%lld,%lld,%lld|b=%lld|pass=%d%s", (long long)g.p.n[0], (long long)g.p.n[1],
-                  (long long)g.p.n[2], (long long)g.p.batch, pass, g.d.E64[0] ? "|f64" : "");
+    std::snprintf(k, sizeof(k), "gfx950|n=%lld,%lld,%lld|b=%lld|pass=%d%s%s", (long long)g.p.n[0],
+                  (long long)g.p.n[1], (long long)g.p.n[2], (long long)g.p.batch, pass, g.d.E64[0] ? "|f64" : "",
+                  si ? "|si" : "");
     return k;
 }
 
@@ -429,7 +454,7 @@ int autotune(rk4ip_plan_t plan) {
             // the whole-line step: 16 or 8 values per thread (FP64 transforms use 8)
             if (plan->f64) continue;
             Sched c;
-            if (cache_lookup(text, tune_key(g, 0), &c) && (c.radix == 8 || c.radix == 16)) {
+            if (cache_lookup(text, tune_key(g, 0, plan->si), &c) && (c.radix == 8 || c.radix == 16)) {
                 plan->sched[gi][0] = c;
                 continue;
             }
@@ -446,16 +471,16 @@ int autotune(rk4ip_plan_t plan) {
                 }
             }
             plan->sched[gi][0] = pick;
-            fresh.push_back({tune_key(g, 0), pick});
+            fresh.push_back({tune_key(g, 0, plan->si), pick});
             continue;
         }
         PassDef defs[kMaxPasses];
-        const int np = pass_list(g.p.ndim, defs);
+        const int np = pass_list(g.p.ndim, plan->si, defs);
         for (int i = 0; i < np; i++) {
             const int axis = defs[i].axis, mode = defs[i].mode;
             const int N = (int)g.p.n[axis], n0 = (int)g.p.n[0];
             Sched c;
-            if (cache_lookup(text, tune_key(g, i), &c) &&
+            if (cache_lookup(text, tune_key(g, i, plan->si), &c) &&
                 rk4ip::axis_schedule_ok(N, mode, axis, n0, c.lines, c.seq, c.radix, plan->f64, c.occ ? c.occ : 1)) {
                 plan->sched[gi][i] = c;
                 continue;
@@ -475,7 +500,7 @@ int autotune(rk4ip_plan_t plan) {
                         cand.radix = rr;
                         cand.occ = occ;
                         float ms = 0.f;
-                        int rc = time_pass(plan, g, axis, mode, cand, 5, &ms);
+                        int rc = time_pass(plan, g, defs[i], cand, 5, &ms);
                         if (rc) return rc;
                         if (ms < best) {
                             best = ms;
@@ -483,7 +508,7 @@ int autotune(rk4ip_plan_t plan) {
                         }
                     }
             plan->sched[gi][i] = pick;
-            fresh.push_back({tune_key(g, i), pick});
+            fresh.push_back({tune_key(g, i, plan->si), pick});
         }
     }
     if (path && !fresh.empty()) {
@@ -520,14 +545,14 @@ int enqueue_lines(rk4ip_plan_t plan, hipStream_t stream, float2* psi, int64_t st
         if (allow_fuse && (plan->flags & RK4IP_FLAG_FUSE_1D)) {
             rc = timed_launch(plan, stream, (int)gi, 0, capturing, [&] {
                 return rk4ip::launch_line_step(g.d, psi, (int)nsteps, step_off, step_base, plan->f64,
-                                                plan->sched[gi][0].radix, stream);
+                                                plan->sched[gi][0].radix, plan->si, stream);
             });
             if (rc) return rc;
         } else {
             for (int64_t s = 0; s < nsteps; s++) {
                 rc = timed_launch(plan, stream, (int)gi, 0, capturing, [&] {
                     return rk4ip::launch_line_step(g.d, psi, 1, step_off + s, step_base, plan->f64,
-                                                    plan->sched[gi][0].radix, stream);
+                                                    plan->sched[gi][0].radix, plan->si, stream);
                 });
                 if (rc) return rc;
             }
@@ -548,11 +573,12 @@ int enqueue_lattice(rk4ip_plan_t plan, hipStream_t stream, float2* psi, int64_t 
             auto& g = plan->groups[gi];
             if (g.p.ndim == 1) continue;
             PassDef defs[kMaxPasses];
-            const int np = pass_list(g.p.ndim, defs);
+            const int np = pass_list(g.p.ndim, plan->si, defs);
             for (int i = 0; i < np; i++) {
                 if (defs[i].role != role) continue;
                 rk4ip::PassArgs pa{};
                 pa.psi = psi;
+                pa.twice = defs[i].twice;
                 pa.A = plan->A;
                 pa.B = plan->B;
                 pa.step_off = step;
@@ -748,6 +774,7 @@ int rk4ip_plan(const rk4ip_problem* probs, int nprob, void* workspace, size_t ws
     plan->stream = static_cast<hipStream_t>(stream);
     plan->flags = flags;
     plan->f64 = (flags & RK4IP_FLAG_FP64_TRANSFORMS) != 0;
+    plan->si = (flags & RK4IP_FLAG_SEMI_IMPLICIT) != 0;
     plan->points = L.points;
     plan->counter = reinterpret_cast<int64_t*>(plan->ws + L.header);
     plan->flag = reinterpret_cast<int*>(plan->ws + L.header + 64);
@@ -789,6 +816,8 @@ int rk4ip_plan(const rk4ip_problem* probs, int nprob, void* workspace, size_t ws
         d.seed_hi = (uint32_t)(p.seed >> 32);
         d.id_base = p.id_base;
         d.has_noise = p.sigma != 0.0 ? 1 : 0;
+        d.noise_sub = p.noise_substeps > 1 ? (int)p.noise_substeps : 1;
+        d.inv_sqrt_sub = (float)(1.0 / std::sqrt((double)d.noise_sub));  // a power of two or its root
         d.Vgrid = p.V_grid;
         for (int a = 0; a < p.ndim; a++) {
             std::vector<float2> E, tw;
@@ -819,7 +848,7 @@ int rk4ip_plan(const rk4ip_problem* probs, int nprob, void* workspace, size_t ws
         inst += p.batch;
         {
             PassDef defs[kMaxPasses];
-            plan->sched.push_back(std::vector<Sched>(p.ndim == 1 ? 1 : pass_list(p.ndim, defs)));
+            plan->sched.push_back(std::vector<Sched>(p.ndim == 1 ? 1 : pass_list(p.ndim, plan->si, defs)));
         }
     }
     plan->ninst = inst;
@@ -830,7 +859,7 @@ int rk4ip_plan(const rk4ip_problem* probs, int nprob, void* workspace, size_t ws
             const GroupHost& g = plan->groups[gi];
             if (g.p.ndim == 1) continue;
             PassDef defs[kMaxPasses];
-            const int np = pass_list(g.p.ndim, defs);
+            const int np = pass_list(g.p.ndim, plan->si, defs);
             for (int k = 0; k < np; k++) {
                 if (!default_f64_sched(g, defs[k].axis, defs[k].mode, &plan->sched[gi][k])) {
                     delete plan;
@@ -853,17 +882,18 @@ int rk4ip_plan(const rk4ip_problem* probs, int nprob, void* workspace, size_t ws
         std::vector<std::string> names;
         if (p.ndim == 1) {
             const int rr = plan->f64 ? 8 : (plan->sched[gi][0].radix ? plan->sched[gi][0].radix : 16);
-            std::snprintf(name, sizeof(name), "line_step:n%lld:r%d%s", (long long)p.n[0], rr, plan->f64 ? ":f64" : "");
+            std::snprintf(name, sizeof(name), "%s:n%lld:r%d%s", plan->si ? "line_si" : "line_step", (long long)p.n[0], rr,
+                          plan->f64 ? ":f64" : "");
             names.push_back(name);
         } else {
             PassDef defs[kMaxPasses];
-            const int np = pass_list(p.ndim, defs);
+            const int np = pass_list(p.ndim, plan->si, defs);
             for (int k = 0; k < np; k++) {
                 const int a = defs[k].axis;
                 const Sched sc = plan->sched[gi][k];
                 const int lines = sc.lines ? sc.lines : rk4ip::axis_lines((int)p.n[a], a, (int)p.n[0]);
-                std::snprintf(name, sizeof(name), "%s:axis%d:n%lld:%s:lines%d:%s:r%d%s%s", mode_name(defs[k].mode), a,
-                              (long long)p.n[a], a == 0 ? "contig" : "strided", lines,
+                std::snprintf(name, sizeof(name), "%s%s:axis%d:n%lld:%s:lines%d:%s:r%d%s%s", mode_name(defs[k].mode),
+                              defs[k].twice ? "x2" : "", a, (long long)p.n[a], a == 0 ? "contig" : "strided", lines,
                               sc.seq == 2 ? "seq-deferred" : (sc.seq ? "seq" : "joint"), sc.radix ? sc.radix : 16,
                               sc.occ == 4 ? ":o4" : "", plan->f64 ? ":f64" : "");
                 names.push_back(name);
@@ -958,6 +988,7 @@ int rk4ip_adjoint(rk4ip_plan_t plan, const void* ckpt_v, int64_t step0, int64_t 
     if (!plan || !ckpt_v || !lambda_T || !grad_psi0 || !adj_ws || step0 < 0 || nsteps < 0 || ckpt_every < 1)
         return RK4IP_ERR_INVALID_ARG;
     if ((reinterpret_cast<uintptr_t>(adj_ws) % kAlign) != 0) return RK4IP_ERR_INVALID_ARG;
+    if (plan->si) return fail(plan, RK4IP_ERR_INVALID_ARG, "the adjoint covers the RK4 step only");
     if (adj_ws_bytes < rk4ip_adjoint_workspace_bytes(plan, ckpt_every)) return RK4IP_ERR_WORKSPACE_TOO_SMALL;
     hipStream_t st = plan->stream;
     const size_t field = align_up(sizeof(float2) * (size_t)plan->points);

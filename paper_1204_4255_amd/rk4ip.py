@@ -32,6 +32,7 @@ RK4IP_FLAG_GRAPH = 0x1
 RK4IP_FLAG_AUTOTUNE = 0x2
 RK4IP_FLAG_FUSE_1D = 0x4
 RK4IP_FLAG_FP64_TRANSFORMS = 0x8
+RK4IP_FLAG_SEMI_IMPLICIT = 0x10
 
 # every symbol include/rk4ip.h declares
 EXPORTS = [
@@ -56,7 +57,7 @@ class rk4ip_problem(ctypes.Structure):
         ("batch", ctypes.c_int64), ("dt", ctypes.c_double), ("alpha", ctypes.c_double),
         ("gamma", ctypes.c_double), ("g_nl", ctypes.c_double), ("trap", ctypes.c_double * 3),
         ("V_grid", ctypes.c_void_p), ("sigma", ctypes.c_double), ("seed", ctypes.c_uint64),
-        ("id_base", ctypes.c_uint32), ("reserved1", ctypes.c_uint32),
+        ("id_base", ctypes.c_uint32), ("noise_substeps", ctypes.c_uint32),
     ]
 
 
@@ -130,7 +131,8 @@ def _check(status: int, plan_handle=None, what: str = "rk4ip call"):
 
 def make_problem(n: Sequence[int], lo: Sequence[float], hi: Sequence[float], dt: float, batch: int = 1,
                  alpha: float = 0.5, gamma: float = 0.0, g_nl: float = 0.0, trap: Sequence[float] = (0, 0, 0),
-                 V_grid=None, sigma: float = 0.0, seed: int = 0, id_base: int = 0) -> rk4ip_problem:
+                 V_grid=None, sigma: float = 0.0, seed: int = 0, id_base: int = 0,
+                 noise_substeps: int = 1) -> rk4ip_problem:
     """Fill an rk4ip_problem; V_grid is a device float32 tensor [batch][M] or None."""
     p = rk4ip_problem()
     nd = len(n)
@@ -146,6 +148,7 @@ def make_problem(n: Sequence[int], lo: Sequence[float], hi: Sequence[float], dt:
     p.sigma = float(sigma)
     p.seed = int(seed) & 0xFFFFFFFFFFFFFFFF
     p.id_base = int(id_base) & 0xFFFFFFFF
+    p.noise_substeps = int(noise_substeps)
     return p
 
 
@@ -325,7 +328,7 @@ class Plan:
                "rk4ip_debug_apply_D")
 
 
-def problems_from_workload(w, device: str = "cuda"):
+def problems_from_workload(w, device: str = "cuda", noise_substeps: int = 1):
     """rk4ip_problem list (and the device V grids it points to) for a workloads.Workload."""
     import torch
 
@@ -336,7 +339,8 @@ def problems_from_workload(w, device: str = "cuda"):
             V = torch.tensor(np.asarray(g.Vgrid, dtype=np.float32), device=device).contiguous()
             keep.append(V)
         probs.append(make_problem(g.n, g.lo, g.hi, w.h, batch=g.batch, alpha=g.alpha, gamma=g.gamma, g_nl=g.gnl,
-                                  trap=g.trap, V_grid=V, sigma=g.sigma, seed=g.seed, id_base=g.id_base))
+                                  trap=g.trap, V_grid=V, sigma=g.sigma, seed=g.seed, id_base=g.id_base,
+                                  noise_substeps=noise_substeps))
     return probs, keep
 
 

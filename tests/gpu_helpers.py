@@ -13,10 +13,11 @@ def log(msg):
     sys.stdout.flush()
 
 
-def oprob(g: W.Group, h: float) -> oracle.Problem:
+def oprob(g: W.Group, h: float, integrator: int = 0, noise_substeps: int = 1) -> oracle.Problem:
     return oracle.Problem(n=g.n, lo=g.lo, hi=g.hi, h=h, batch=g.batch, alpha=g.alpha, gamma=g.gamma, gnl=g.gnl,
                           trap=g.trap, sigma=g.sigma, seed=g.seed, id_base=g.id_base,
-                          Vgrid=None if g.Vgrid is None else np.asarray(g.Vgrid, np.float32).astype(np.float64))
+                          Vgrid=None if g.Vgrid is None else np.asarray(g.Vgrid, np.float32).astype(np.float64),
+                          integrator=integrator, noise_substeps=noise_substeps)
 
 
 def rel(a, b):
@@ -31,8 +32,8 @@ def rel_per_instance(a, b, batch):
     return np.linalg.norm(a - b, axis=1) / np.linalg.norm(b, axis=1)
 
 
-def plan_for(w: W.Workload, flags: int = 0):
-    probs, keep = rk4ip.problems_from_workload(w)
+def plan_for(w: W.Workload, flags: int = 0, noise_substeps: int = 1):
+    probs, keep = rk4ip.problems_from_workload(w, noise_substeps=noise_substeps)
     plan = rk4ip.Plan(probs, flags=flags)
     plan._keep_V = keep
     return plan

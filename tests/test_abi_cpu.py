@@ -130,3 +130,19 @@ def test_fp64_transform_flag_sizes_and_limits(lib):
         assert (rk4ip.rk4ip_workspace_bytes([q], f64) > 0) == ok
         assert rk4ip.rk4ip_workspace_bytes([q]) > 0
     assert rk4ip.rk4ip_workspace_bytes([p], 0x100) == 0  # unknown flag bits
+
+
+def test_semi_implicit_flag_and_noise_substeps(lib):
+    """The semi-implicit form uses the RK4 form's tables (the half-step propagator, twice
+    where two steps meet) and workspace; noise_substeps is 0, 1 or a power of two up to
+    1024."""
+    si = rk4ip.RK4IP_FLAG_SEMI_IMPLICIT
+    p = _p()
+    assert rk4ip.rk4ip_workspace_bytes([p], si) == rk4ip.rk4ip_workspace_bytes([p]) > 0
+    line = rk4ip.make_problem(n=(256,), lo=(0,), hi=(1,), dt=0.1)
+    assert rk4ip.rk4ip_workspace_bytes([line], si) == rk4ip.rk4ip_workspace_bytes([line]) > 0
+    for S, ok in ((0, True), (1, True), (2, True), (64, True), (1024, True), (3, False), (12, False),
+                  (2048, False)):
+        assert (rk4ip.rk4ip_workspace_bytes([_p(noise_substeps=S)], si) > 0) == ok, S
+        assert (rk4ip.rk4ip_workspace_bytes([_p(noise_substeps=S)]) > 0) == ok, S
+    assert rk4ip.rk4ip_workspace_bytes([p], si | rk4ip.RK4IP_FLAG_FP64_TRANSFORMS) > rk4ip.rk4ip_workspace_bytes([p], si)
