@@ -372,13 +372,20 @@ def other_workloads(torch, rk4ip, workloads):
     return out
 
 
+def progress(msg: str) -> None:
+    """One line on stderr as each stage ends (the JSON result alone goes to stdout)."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
 def measure_forms(torch, rk4ip, workloads):
-    return {"other_workloads": other_workloads(torch, rk4ip, workloads),
-            "batched_paths": form_batched_paths(torch, rk4ip, workloads),
-            "uneven_batch": form_uneven_batch(torch, rk4ip, workloads),
-            "adjoint": form_adjoint(torch, rk4ip, workloads),
-            "fp64_transforms": form_fp64_transforms(torch, rk4ip, workloads),
-            "semi_implicit": form_semi_implicit(torch, rk4ip, workloads)}
+    out = {}
+    for name, fn in (("other_workloads", other_workloads), ("batched_paths", form_batched_paths),
+                     ("uneven_batch", form_uneven_batch), ("adjoint", form_adjoint),
+                     ("fp64_transforms", form_fp64_transforms), ("semi_implicit", form_semi_implicit)):
+        t0 = time.perf_counter()
+        out[name] = fn(torch, rk4ip, workloads)
+        progress(f"form {name} done ({time.perf_counter() - t0:.1f} s)")
+    return out
 
 
 def main() -> int:
@@ -446,6 +453,7 @@ def main() -> int:
     ms = ev0.elapsed_time(ev1)
     ms_per_step = ms / args.steps
     value = pts * args.steps / (ms / 1e3)
+    progress(f"timed {args.steps} steps: {ms_per_step:.4f} ms per step")
 
     # per-pass launch times with HIP events on the plan's stream (eager launches)
     prof_plan = rk4ip.Plan(probs, flags=tune)
@@ -533,6 +541,7 @@ def main() -> int:
                                   "sample": f"the first {cpu_steps} steps of the 256^3 workload (FP64, radix-2 FFT)",
                                   "seconds": cpu_s}
         result[f"parity_{cpu_steps}step_rel_l2"] = err
+        progress(f"cpu baseline done ({cpu_s:.1f} s)")
     if not args.no_forms:
         result["forms"] = measure_forms(torch, rk4ip, workloads)
     print(json.dumps(result))
