@@ -85,6 +85,11 @@ def _load():
         lib.ora_fft_nd.argtypes = [P, vp, ctypes.c_int]
         lib.ora_fft_nd.restype = ctypes.c_int
         lib.ora_threads.restype = ctypes.c_int
+        lib.ora_ck_tableau.argtypes = [vp]
+        lib.ora_ck_step.argtypes = [P, vp, ctypes.c_double, vp, vp]
+        lib.ora_ck_step.restype = ctypes.c_int
+        lib.ora_ark45.argtypes = [P, vp, ctypes.c_double, ctypes.c_double, i64, vp, vp, vp, i64]
+        lib.ora_ark45.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -245,6 +250,43 @@ def run(p: Problem, psi, nsteps: int, step0: int = 0, sample_every: int = 0, ckp
     if rc:
         raise ValueError("invalid problem")
     return f, diag, ckpt
+
+
+def ck_tableau():
+    """The Cash-Karp pair the adaptive integrator uses: (c[6], a[6][5], b[6], b*[6])."""
+    out = np.empty(48, dtype=np.float64)
+    _load().ora_ck_tableau(out.ctypes.data)
+    return out[:6], out[6:36].reshape(6, 5), out[36:42], out[42:48]
+
+
+def ck_step(p: Problem, psi, h: float):
+    """One Cash-Karp step of size h of every instance (Sec. 3.5's adaptive RK45 in the
+    interaction picture, readings R8). Returns (fifth-order result, error estimate[batch])."""
+    f = _cfield(p, psi)
+    out = np.empty_like(f)
+    err = np.empty(p.batch, dtype=np.float64)
+    pc = p._c()
+    if _load().ora_ck_step(ctypes.byref(pc), f.ctypes.data, float(h), out.ctypes.data, err.ctypes.data):
+        raise ValueError("invalid problem")
+    return out, err
+
+
+def ark45(p: Problem, psi, t_span: float, tol: float, h0, max_attempts: int = 1 << 20, log_cap: int = 0):
+    """Adaptive Cash-Karp integration of every instance over [0, t_span] (readings R8, R9),
+    each instance with its own step. h0: first trial step (scalar or [batch]).
+    Returns (psi, h_next[batch], stats[batch][2] = (accepted, rejected), h_log or None,
+    done) with h_log[b][i] the i-th accepted step of instance b (log_cap entries)."""
+    f = _cfield(p, psi)
+    h = np.ascontiguousarray(np.broadcast_to(np.asarray(h0, dtype=np.float64), (p.batch,))).copy()
+    stats = np.zeros((p.batch, 2), dtype=np.int64)
+    log = np.full((p.batch, log_cap), np.nan) if log_cap > 0 else None
+    pc = p._c()
+    rc = _load().ora_ark45(ctypes.byref(pc), f.ctypes.data, float(t_span), float(tol), int(max_attempts),
+                           h.ctypes.data, stats.ctypes.data, None if log is None else log.ctypes.data,
+                           int(log_cap))
+    if rc < 0:
+        raise ValueError("invalid problem")
+    return f, h, stats, log, rc == 0
 
 
 def diag(p: Problem, psi) -> np.ndarray:

@@ -47,6 +47,18 @@
  *       Sec. 3.5): with S = 2^L substeps the noise of step n is the mean of the S draws of
  *       a run with step h/S at steps nS ... nS + S - 1, i.e. xi = (sum_s z_s / sqrt(S)) /
  *       sqrt(2 h dV) with z_s the complex normals of those finer steps.
+ *   R8  The adaptive fourth-fifth order Runge-Kutta method (Sec. 3.5, deterministic only)
+ *       is the embedded pair of Cash and Karp (ACM TOMS 16, 201, 1990) applied to eq. (6)
+ *       with the picture origin at the start of each step, so stage i at t_n + c_i h is
+ *         Y_i = psi_n + sum_j a_ij k_j,   k_i = e^{-L c_i h} h G(e^{L c_i h} Y_i),
+ *       the step keeps the fifth-order result, psi_{n+1} = e^{L h}(psi_n + sum_i b_i k_i)
+ *       (local extrapolation), and the error estimate of the step is the relative L2
+ *       norm over the instance, in the picture frame, of the difference between the
+ *       fifth- and fourth-order results: ||sum_i (b_i - b*_i) k_i|| / ||psi_n + sum_i b_i k_i||.
+ *   R9  Step control (the paper gives none): a step is accepted when its error estimate is
+ *       at most tol; either way the next trial step is h min(5, max(1/5, 0.9 (tol/err)^{1/5}))
+ *       (5 when err = 0; 1/5 when err is not finite). A trial step that would pass the end
+ *       of the interval is cut to end on it. Each instance adapts its own step.
  *
  * Memory layout: one instance is n[0]*n[1]*n[2] complex values with axis 0 (x)
  * contiguous; instances are concatenated. Unused axes have n = 1.
@@ -793,6 +805,167 @@ int ora_adjoint(const ora_problem* p, const cplx* psi0, int64_t step0, int64_t n
  * Brute-force variant for tiny lattices: the same step with D applied through dense
  * DFT matrices (O(M^2)) instead of the FFT. Used only to pin the FFT-based step.
  * ---------------------------------------------------------------------------------- */
+/* ------------------------------------------------------------------------------------
+ * Adaptive Cash-Karp RK4(5) in the interaction picture (readings R8, R9).
+ * ---------------------------------------------------------------------------------- */
+
+/* The Cash-Karp embedded pair: nodes c, stage matrix a (lower triangle), fifth-order
+ * weights b and fourth-order weights b*. */
+static const double CK_C[6] = {0.0, 1.0 / 5.0, 3.0 / 10.0, 3.0 / 5.0, 1.0, 7.0 / 8.0};
+static const double CK_A[6][5] = {
+    {0.0, 0.0, 0.0, 0.0, 0.0},
+    {1.0 / 5.0, 0.0, 0.0, 0.0, 0.0},
+    {3.0 / 40.0, 9.0 / 40.0, 0.0, 0.0, 0.0},
+    {3.0 / 10.0, -9.0 / 10.0, 6.0 / 5.0, 0.0, 0.0},
+    {-11.0 / 54.0, 5.0 / 2.0, -70.0 / 27.0, 35.0 / 27.0, 0.0},
+    {1631.0 / 55296.0, 175.0 / 512.0, 575.0 / 13824.0, 44275.0 / 110592.0, 253.0 / 4096.0},
+};
+static const double CK_B5[6] = {37.0 / 378.0, 0.0, 250.0 / 621.0, 125.0 / 594.0, 0.0, 512.0 / 1771.0};
+static const double CK_B4[6] = {2825.0 / 27648.0, 0.0, 18575.0 / 48384.0, 13525.0 / 55296.0, 277.0 / 14336.0,
+                                1.0 / 4.0};
+
+/* c (6), a (6 x 5, row-major), b (6), b* (6): 48 doubles. */
+void ora_ck_tableau(double* out) {
+    for (int i = 0; i < 6; i++) out[i] = CK_C[i];
+    for (int i = 0; i < 6; i++)
+        for (int j = 0; j < 5; j++) out[6 + 5 * i + j] = CK_A[i][j];
+    for (int i = 0; i < 6; i++) out[36 + i] = CK_B5[i];
+    for (int i = 0; i < 6; i++) out[42 + i] = CK_B4[i];
+}
+
+/* f <- e^{L tau} f for one instance (tau of either sign): transform, multiply every mode
+ * by exp(L(k) tau) / M, transform back (Sec. 3.6). */
+static void apply_exp_L(const ora_problem* p, double tau, cplx* f) {
+    int64_t M = npts(p);
+    fft_nd(p, f, -1);
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < M; j++) {
+        int64_t idx[3];
+        unflatten(p, j, idx);
+        double k2 = 0.0;
+        for (int a = 0; a < p->ndim; a++) {
+            double k = k_of(p, a, idx[a]);
+            k2 += k * k;
+        }
+        f[j] *= cexp((-I * p->alpha * k2 - p->gamma) * tau) / (double)M;
+    }
+    fft_nd(p, f, +1);
+}
+
+/* One Cash-Karp step of size h of one instance from psi (x space at t_n, which is also the
+ * picture frame since the origin is t_n). Writes the fifth-order result at t_n + h (x
+ * space) to out and returns the error estimate (reading R8). */
+static double ck_step_one(const ora_problem* p, const double* V, const cplx* psi, double h, cplx* out) {
+    int64_t M = npts(p);
+    cplx* k[6];
+    for (int i = 0; i < 6; i++) k[i] = (cplx*)malloc(sizeof(cplx) * (size_t)M);
+    cplx* y = (cplx*)malloc(sizeof(cplx) * (size_t)M);
+    for (int i = 0; i < 6; i++) {
+        /* stage input in the picture frame, then moved to the stage time */
+        for (int64_t j = 0; j < M; j++) {
+            cplx v = psi[j];
+            for (int q = 0; q < i; q++) v += CK_A[i][q] * k[q][j];
+            y[j] = v;
+        }
+        if (CK_C[i] != 0.0) apply_exp_L(p, CK_C[i] * h, y);
+        /* h G at the stage time (G without noise: the method is deterministic only) */
+        for (int64_t j = 0; j < M; j++) {
+            double m2 = creal(y[j]) * creal(y[j]) + cimag(y[j]) * cimag(y[j]);
+            k[i][j] = h * (-I * (V[j] + p->gnl * m2) * y[j]);
+        }
+        /* back to the picture frame */
+        if (CK_C[i] != 0.0) apply_exp_L(p, -CK_C[i] * h, k[i]);
+    }
+    double num = 0.0, den = 0.0;
+    for (int64_t j = 0; j < M; j++) {
+        cplx y5 = psi[j], dlt = 0.0;
+        for (int i = 0; i < 6; i++) {
+            y5 += CK_B5[i] * k[i][j];
+            dlt += (CK_B5[i] - CK_B4[i]) * k[i][j];
+        }
+        out[j] = y5;
+        num += creal(dlt) * creal(dlt) + cimag(dlt) * cimag(dlt);
+        den += creal(y5) * creal(y5) + cimag(y5) * cimag(y5);
+    }
+    apply_exp_L(p, h, out);
+    for (int i = 0; i < 6; i++) free(k[i]);
+    free(y);
+    return sqrt(num / den);
+}
+
+static int check_ark45(const ora_problem* p) {
+    if (check_problem(p)) return -1;
+    if (p->sigma != 0.0) return -1; /* deterministic only */
+    return 0;
+}
+
+/* One Cash-Karp step of size h of every instance: out[batch][M] (fifth order, x space),
+ * err[batch]. */
+int ora_ck_step(const ora_problem* p, const cplx* psi, double h, cplx* out, double* err) {
+    if (check_ark45(p) || !(h > 0.0)) return -1;
+    int64_t M = npts(p);
+    double* V = (double*)malloc(sizeof(double) * (size_t)M);
+    for (int64_t b = 0; b < p->batch; b++) {
+        potential(p, b, V);
+        err[b] = ck_step_one(p, V, psi + b * M, h, out + b * M);
+    }
+    free(V);
+    return 0;
+}
+
+/* The step factor of reading R9. */
+static double ck_factor(double err, double tol) {
+    if (!isfinite(err)) return 0.2;
+    if (err == 0.0) return 5.0;
+    double f = 0.9 * pow(tol / err, 0.2);
+    return f < 0.2 ? 0.2 : (f > 5.0 ? 5.0 : f);
+}
+
+/* Integrate every instance over [0, t_span] with its own adaptive step (readings R8, R9).
+ * h[batch]: in, the first trial step; out, the next trial step. stats[batch][2]: accepted
+ * and rejected steps. h_log[batch][log_cap] (optional): the accepted step sizes in order.
+ * At most max_attempts trial steps per instance. Returns 0 when every instance reached
+ * t_span, 1 when one ran out of attempts, -1 on a bad argument. */
+int ora_ark45(const ora_problem* p, cplx* psi, double t_span, double tol, int64_t max_attempts, double* h,
+              int64_t* stats, double* h_log, int64_t log_cap) {
+    if (check_ark45(p) || !(t_span >= 0.0) || !(tol > 0.0) || max_attempts < 1) return -1;
+    int64_t M = npts(p);
+    double* V = (double*)malloc(sizeof(double) * (size_t)M);
+    cplx* out = (cplx*)malloc(sizeof(cplx) * (size_t)M);
+    int rc = 0;
+    for (int64_t b = 0; b < p->batch; b++) {
+        if (!(h[b] > 0.0)) {
+            rc = -1;
+            break;
+        }
+        potential(p, b, V);
+        cplx* f = psi + b * M;
+        double t = 0.0, hb = h[b];
+        int64_t acc = 0, rej = 0;
+        while (t < t_span && acc + rej < max_attempts) {
+            int last = t + hb >= t_span;
+            double htry = last ? t_span - t : hb;
+            double err = ck_step_one(p, V, f, htry, out);
+            if (err <= tol) {
+                memcpy(f, out, sizeof(cplx) * (size_t)M);
+                if (h_log && acc < log_cap) h_log[b * log_cap + acc] = htry;
+                t = last ? t_span : t + htry;
+                acc++;
+            } else {
+                rej++;
+            }
+            hb = htry * ck_factor(err, tol);
+        }
+        if (t < t_span) rc = 1;
+        h[b] = hb;
+        stats[2 * b] = acc;
+        stats[2 * b + 1] = rej;
+    }
+    free(V);
+    free(out);
+    return rc;
+}
+
 static void apply_D_dense(const ora_problem* p, const cplx* E, cplx* f) {
     int64_t M = npts(p);
     cplx* F = malloc(sizeof(cplx) * (size_t)M);

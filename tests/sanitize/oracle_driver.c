@@ -36,6 +36,10 @@ int ora_adjoint(const ora_problem* p, const cplx* psi0, int64_t step0, int64_t n
                 const cplx* lamT, cplx* grad_psi0, double* grad_V);
 int ora_apply_D(const ora_problem* p, cplx* f, int dense, int adjoint);
 int ora_fft_nd(const ora_problem* p, cplx* f, int sign);
+void ora_ck_tableau(double* out);
+int ora_ck_step(const ora_problem* p, const cplx* psi, double h, cplx* out, double* err);
+int ora_ark45(const ora_problem* p, cplx* psi, double t_span, double tol, int64_t max_attempts, double* h,
+              int64_t* stats, double* h_log, int64_t log_cap);
 
 static int fails = 0;
 #define CHECK(x)                                             \
@@ -106,6 +110,18 @@ static void exercise(int ndim, const int64_t* n, int64_t batch, int si) {
     } else if (ora_adjoint(&p, psi, 1, 5, 2, lam, g, gV) == 0) {
         fails++; /* the adjoint is of the RK4IP step only */
     }
+    /* the adaptive integrator is deterministic: it refuses noise, then runs without */
+    double* hs = malloc(sizeof(double) * batch);
+    int64_t* stats = malloc(sizeof(int64_t) * batch * 2);
+    double* hlog = malloc(sizeof(double) * batch * 8);
+    double* err = malloc(sizeof(double) * batch);
+    for (int64_t b = 0; b < batch; b++) hs[b] = 1e-3;
+    if (ora_ark45(&p, psi, 0.01, 1e-6, 100, hs, stats, hlog, 8) != -1) fails++;
+    p.sigma = 0.0;
+    CHECK(ora_ck_step(&p, psi, 2e-3, g, err));
+    CHECK(ora_ark45(&p, psi, 0.01, 1e-6, 100, hs, stats, hlog, 8));
+    CHECK(ora_ark45(&p, psi, 0.01, 1e-6, 100, hs, stats, NULL, 0));
+    free(hs), free(stats), free(hlog), free(err);
     free(V), free(psi), free(dpsi), free(lam), free(g), free(gV), free(dV), free(xi);
     free(diag), free(ckpt), free(ov), free(mean), free(var);
 }
@@ -117,6 +133,8 @@ int main(void) {
     ora_fft(a, 16, +1);
     uint32_t ctr[8] = {1, 2, 3, 4, 5, 6, 7, 8}, out[8];
     ora_philox_batch(ctr, 2, 0x1234567890ull, out);
+    double tab[48];
+    ora_ck_tableau(tab);
     const int64_t n1[1] = {16}, n2[2] = {8, 16}, n3[3] = {8, 8, 16};
     for (int si = 0; si < 2; si++) {
         exercise(1, n1, 3, si);
