@@ -168,6 +168,28 @@ int rk4ip_moments(rk4ip_plan_t plan, int group, const void* psi, double* mean, d
 /* Device workspace bytes rk4ip_adjoint needs for checkpoint spacing ckpt_every. */
 size_t rk4ip_adjoint_workspace_bytes(rk4ip_plan_t plan, int64_t ckpt_every);
 
+/* Adaptive fourth-fifth order Runge-Kutta in the interaction picture (Sec. 3.5: the
+ * adaptive Cash-Karp pair, deterministic only; Sec. 3.6: eq. (6)) over [0, t_span], in
+ * place on psi, for plans whose groups are all 1D and noise-free. Each instance adapts
+ * its own step. With the picture origin at the start of each step, stage i at
+ * t_n + c_i h is Y_i = psi_n + sum_j a_ij k_j, k_i = e^{-L c_i h} h G(e^{L c_i h} Y_i);
+ * the step keeps psi_{n+1} = e^{L h}(psi_n + sum_i b_i k_i) (fifth order) and estimates
+ * its error as ||sum_i (b_i - b*_i) k_i|| / ||psi_n + sum_i b_i k_i|| (relative L2 over
+ * the instance). A step is accepted when the estimate is at most tol; the next trial
+ * step is h min(5, max(1/5, 0.9 (tol/err)^{1/5})); the last step is cut to end on t_span.
+ *   h      device double [ninst]: in, the first trial step of each instance (> 0); out,
+ *          the next trial step (pass it back to continue the run over another interval).
+ *   stats  device int64 [ninst][3]: accepted steps, rejected steps, 1 if t_span was
+ *          reached (0 when the instance used max_attempts trial steps first).
+ *   h_log  device double [ninst][log_cap]: the accepted step sizes in order (entries past
+ *          the accepted count are left as they were), or NULL with log_cap = 0.
+ * Transforms are complex64 in every precision form; the propagator of each trial step is
+ * formed per mode from an FP64 phase. Asynchronous; allocates nothing. Returns
+ * RK4IP_ERR_UNSUPPORTED_SHAPE for a plan with a 2D or 3D group and RK4IP_ERR_INVALID_ARG
+ * for a noisy group, tol <= 0, t_span < 0 or max_attempts < 1. */
+int rk4ip_ark45(rk4ip_plan_t plan, void* psi, double t_span, double tol, int64_t max_attempts, double* h,
+                int64_t* stats, double* h_log, int64_t log_cap);
+
 /* Discrete adjoint of rk4ip_run over nsteps steps from step0 (not in the paper).
  * Given the checkpoints written by rk4ip_run (same step0, nsteps, ckpt_every) and
  * lambda_T = dLoss/dRe psi_T + i dLoss/dIm psi_T (device complex64), writes

@@ -45,6 +45,20 @@ struct PassArgs {
     const int64_t* step_base; // step = step_off (+ *step_base when not null)
 };
 
+// Arguments of the adaptive 1D integrator (k_line_ark45).
+struct ArkArgs {
+    double t_span;            // integrate every instance over [0, t_span]
+    double tol;               // accept a step when its error estimate is at most tol
+    double alpha, gamma;      // L(k) = -i alpha k^2 - gamma
+    double kscale;            // 2 pi / (hi - lo): k_m = kscale * (m < n/2 ? m : m - n)
+    int64_t max_attempts;     // trial steps per instance at most
+    int64_t inst_base;        // plan-wide index of the group's first instance
+    int64_t log_cap;          // entries per instance in h_log
+    double* h;                // [ninst] in: first trial step; out: next trial step
+    int64_t* stats;           // [ninst][3] accepted, rejected, reached t_span
+    double* h_log;            // [ninst][log_cap] accepted step sizes, or null
+};
+
 // Constants of the final diagnostic sum (FP64).
 struct DiagConst {
     double dV;
@@ -68,6 +82,7 @@ hipError_t launch_line_adjoint(const GroupDev& g, const float2* psi_n, float2* l
 hipError_t launch_vbar_to_float(const double* vbar, float* out, int64_t n, hipStream_t s);
 hipError_t launch_line_step(const GroupDev& g, float2* psi, int nsteps, int64_t step_off, const int64_t* step_base, bool f64,
                             int radix, bool semi_implicit, hipStream_t s);
+hipError_t launch_line_ark45(const GroupDev& g, float2* psi, const ArkArgs& x, hipStream_t s);
 hipError_t launch_diag_axis(const GroupDev& g, int axis, const float2* psi, double kscale, double* part,
                             hipStream_t s);
 hipError_t launch_diag_final(const GroupDev& g, const DiagConst& c, const double* p0, const double* p1,

@@ -975,6 +975,34 @@ int rk4ip_moments(rk4ip_plan_t plan, int group, const void* psi, double* mean, d
     return RK4IP_OK;
 }
 
+int rk4ip_ark45(rk4ip_plan_t plan, void* psi_v, double t_span, double tol, int64_t max_attempts, double* h,
+                int64_t* stats, double* h_log, int64_t log_cap) {
+    if (!plan || !psi_v || !h || !stats || !(t_span >= 0.0) || !std::isfinite(t_span) || !(tol > 0.0) ||
+        !std::isfinite(tol) || max_attempts < 1 || log_cap < 0 || (log_cap > 0) != (h_log != nullptr))
+        return RK4IP_ERR_INVALID_ARG;
+    for (auto& g : plan->groups) {
+        if (g.p.ndim != 1) return fail(plan, RK4IP_ERR_UNSUPPORTED_SHAPE, "the adaptive integrator takes 1D groups");
+        if (g.p.sigma != 0.0) return fail(plan, RK4IP_ERR_INVALID_ARG, "the adaptive integrator is deterministic");
+    }
+    float2* psi = static_cast<float2*>(psi_v);
+    for (auto& g : plan->groups) {
+        rk4ip::ArkArgs x{};
+        x.t_span = t_span;
+        x.tol = tol;
+        x.alpha = g.p.alpha;
+        x.gamma = g.p.gamma;
+        x.kscale = 2.0 * kPi / (g.p.hi[0] - g.p.lo[0]);
+        x.max_attempts = max_attempts;
+        x.inst_base = g.first_inst;
+        x.log_cap = log_cap;
+        x.h = h;
+        x.stats = stats;
+        x.h_log = h_log;
+        HIPCHK(plan, rk4ip::launch_line_ark45(g.d, psi, x, plan->stream));
+    }
+    return RK4IP_OK;
+}
+
 size_t rk4ip_adjoint_workspace_bytes(rk4ip_plan_t plan, int64_t ckpt_every) {
     if (!plan || ckpt_every < 1) return 0;
     // segment states, the recompute buffer, three work fields (w, and the adjoint pair)

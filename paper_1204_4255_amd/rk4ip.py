@@ -38,7 +38,7 @@ RK4IP_FLAG_SEMI_IMPLICIT = 0x10
 EXPORTS = [
     "rk4ip_workspace_bytes", "rk4ip_plan", "rk4ip_set_stream", "rk4ip_step", "rk4ip_run",
     "rk4ip_diagnostics", "rk4ip_overlap", "rk4ip_moments", "rk4ip_adjoint_workspace_bytes",
-    "rk4ip_adjoint", "rk4ip_status", "rk4ip_destroy", "rk4ip_strerror", "rk4ip_last_error",
+    "rk4ip_adjoint", "rk4ip_ark45", "rk4ip_status", "rk4ip_destroy", "rk4ip_strerror", "rk4ip_last_error",
     "rk4ip_schedule", "rk4ip_num_passes", "rk4ip_profile", "rk4ip_profile_read", "rk4ip_debug_philox", "rk4ip_debug_noise", "rk4ip_debug_fft",
     "rk4ip_debug_apply_D",
 ]
@@ -85,6 +85,7 @@ def load(path: str = LIB_PATH):
         "rk4ip_moments": (i32, [vp, i32, vp, vp, vp]),
         "rk4ip_adjoint_workspace_bytes": (ctypes.c_size_t, [vp, i64]),
         "rk4ip_adjoint": (i32, [vp, vp, i64, i64, i64, vp, vp, vp, vp, ctypes.c_size_t]),
+        "rk4ip_ark45": (i32, [vp, vp, ctypes.c_double, ctypes.c_double, i64, vp, vp, vp, i64]),
         "rk4ip_status": (i32, [vp]),
         "rk4ip_destroy": (i32, [vp]),
         "rk4ip_strerror": (ctypes.c_char_p, [i32]),
@@ -280,6 +281,22 @@ class Plan:
                self.handle, "rk4ip_adjoint")
         self._keep_adj_ws = ws
         return g, gV
+
+    def ark45(self, psi, t_span: float, tol: float, h, max_attempts: int = 1 << 20, log_cap: int = 0):
+        """Adaptive Cash-Karp integration over [0, t_span] (1D noise-free groups), in place on
+        psi. h: device float64 [ninst], the first trial steps, updated to the next ones.
+        Returns (stats [ninst][3] = accepted, rejected, reached; h_log [ninst][log_cap] or
+        None) as device tensors."""
+        import torch
+
+        self._sync_stream()
+        stats = torch.zeros((self.ninst, 3), dtype=torch.int64, device=psi.device)
+        log = None
+        if log_cap > 0:
+            log = torch.full((self.ninst, log_cap), float("nan"), dtype=torch.float64, device=psi.device)
+        _check(load().rk4ip_ark45(self.handle, _ptr(psi), float(t_span), float(tol), int(max_attempts), _ptr(h),
+                                  _ptr(stats), _ptr(log), int(log_cap)), self.handle, "rk4ip_ark45")
+        return stats, log
 
     def status(self) -> int:
         return int(load().rk4ip_status(self.handle))
