@@ -354,6 +354,71 @@ def form_semi_implicit(torch, rk4ip, workloads, steps: int = 100):
     return out
 
 
+def form_ark45(torch, rk4ip, workloads):
+    """The adaptive Cash-Karp RK4(5) in the interaction picture (rk4ip_ark45, 1D): 2048
+    lines of a trapped 1D GPE (1024 points) over t = 0.5 at tol 1e-6, each line adapting
+    its own step; the cost of an accepted step
+    next to a fixed RK4IP step on the same lattice; and the accepted steps of one soliton
+    (tol 1e-7, t = 2) at resolutions 256 ... 4096, which the interaction picture keeps
+    constant (the paper's step-count figure)."""
+    import numpy as np
+
+    out = {}
+    # 2048 trapped lines on [-8, 8) (h max V stays inside the explicit pair's stability
+    # interval), each displaced differently so that every line takes its own steps
+    g = workloads.Group(n=(1024,), lo=(-8.0,), hi=(8.0,), gnl=1.0, trap=(1.0, 0.0, 0.0), batch=2048)
+    x = g.axis(0)
+    shift = np.linspace(0.0, 2.0, g.batch)[:, None]
+    f0 = np.pi ** -0.25 * np.exp(-(x[None] - shift) ** 2 / 2)
+    w = workloads.Workload("ark45_2048x1024", [g], 1e-3, 100, [f0])
+    probs = [rk4ip.make_problem(g.n, g.lo, g.hi, w.h, batch=g.batch, alpha=g.alpha, gamma=g.gamma, g_nl=g.gnl,
+                                trap=g.trap)]
+    plan = rk4ip.Plan(probs)
+    psi0 = rk4ip.field_to_device(w)
+    psi = psi0.clone()
+    h = torch.full((g.batch,), 1e-3, dtype=torch.float64, device="cuda")
+    T, tol = 0.5, 1e-6
+    plan.ark45(psi, T, tol, h)  # warm-up
+    psi.copy_(psi0)
+    h.fill_(1e-3)
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    stats, _ = plan.ark45(psi, T, tol, h)
+    b.record()
+    torch.cuda.synchronize()
+    t = a.elapsed_time(b) / 1e3
+    st = stats.cpu().numpy()
+    accepted = int(st[:, 0].sum())
+    plan.destroy()
+    fixed = rk4ip.Plan(probs, flags=rk4ip.RK4IP_FLAG_FUSE_1D | rk4ip.RK4IP_FLAG_AUTOTUNE | rk4ip.RK4IP_FLAG_GRAPH)
+    psi.copy_(psi0)
+    tf = _timed(torch, lambda: fixed.run(psi, 100))
+    fixed.destroy()
+    out["batched"] = {"workload": "2048 x 1024 trapped 1D GPE on [-8, 8) (g = 1, no noise, displaced "
+                                  "Gaussians), t = 0.5, tol = 1e-6",
+                      "seconds": t, "accepted_steps_mean": accepted / g.batch,
+                      "rejected_steps_total": int(st[:, 1].sum()), "all_reached_end": bool(np.all(st[:, 2] == 1)),
+                      "accepted_pt_steps_per_s": accepted * g.M / t,
+                      "us_per_accepted_step": t / (accepted / g.batch) * 1e6,
+                      "rk4ip_fixed_us_per_step": tf / 100 * 1e6,
+                      "accepted_step_cost_in_rk4ip_steps": (t / (accepted / g.batch)) / (tf / 100)}
+    counts = {}
+    for n in (256, 512, 1024, 2048, 4096):
+        gs = workloads.Group(n=(n,), lo=(-20.0,), hi=(20.0,), gnl=-1.0)
+        x = gs.axis(0)
+        f0 = torch.tensor((1 / np.cosh(x) * np.exp(0.5j * x)).astype(np.complex64), device="cuda")
+        pl = rk4ip.Plan([rk4ip.make_problem(gs.n, gs.lo, gs.hi, 1e-3, g_nl=-1.0)])
+        hh = torch.full((1,), 1e-3, dtype=torch.float64, device="cuda")
+        s1, _ = pl.ark45(f0, 2.0, 1e-7, hh)
+        counts[str(n)] = int(s1[0, 0])
+        pl.destroy()
+    out["steps_vs_resolution"] = {"workload": "NLSE soliton on [-20, 20), t = 2, tol = 1e-7",
+                                  "accepted_steps": counts}
+    return out
+
+
 def other_workloads(torch, rk4ip, workloads):
     """Throughput of the 1D NLSE (256 points, 1000 steps) and the 2D GPE (512^2, 2000 steps)
     at their full run lengths, graph-replayed with tuned schedules."""
@@ -381,7 +446,8 @@ def measure_forms(torch, rk4ip, workloads):
     out = {}
     for name, fn in (("other_workloads", other_workloads), ("batched_paths", form_batched_paths),
                      ("uneven_batch", form_uneven_batch), ("adjoint", form_adjoint),
-                     ("fp64_transforms", form_fp64_transforms), ("semi_implicit", form_semi_implicit)):
+                     ("fp64_transforms", form_fp64_transforms), ("semi_implicit", form_semi_implicit),
+                     ("ark45", form_ark45)):
         t0 = time.perf_counter()
         out[name] = fn(torch, rk4ip, workloads)
         progress(f"form {name} done ({time.perf_counter() - t0:.1f} s)")
