@@ -47,6 +47,7 @@ class _Problem(ctypes.Structure):
         ("gamma", ctypes.c_double), ("gnl", ctypes.c_double), ("trap", ctypes.c_double * 3),
         ("sigma", ctypes.c_double), ("seed", ctypes.c_uint64), ("id_base", ctypes.c_uint32),
         ("noise_substeps", ctypes.c_uint32), ("Vgrid", ctypes.c_void_p),
+        ("sigma_V", ctypes.c_double), ("convK", ctypes.c_void_p),
     ]
 
 
@@ -85,6 +86,9 @@ def _load():
         lib.ora_fft_nd.argtypes = [P, vp, ctypes.c_int]
         lib.ora_fft_nd.restype = ctypes.c_int
         lib.ora_threads.restype = ctypes.c_int
+        lib.ora_vnoise.argtypes = [P, i64, vp]
+        lib.ora_conv_potential.argtypes = [P, vp, vp]
+        lib.ora_conv_potential.restype = ctypes.c_int
         lib.ora_ck_tableau.argtypes = [vp]
         lib.ora_ck_step.argtypes = [P, vp, ctypes.c_double, vp, vp]
         lib.ora_ck_step.restype = ctypes.c_int
@@ -118,6 +122,8 @@ class Problem:
     Vgrid: Optional[np.ndarray] = None  # [batch][M] float64
     integrator: int = 0        # 0: RK4IP; 1: semi-implicit in the interaction picture
     noise_substeps: int = 1    # noise of a step = normalised sum of this many finer draws
+    sigma_V: float = 0.0       # real Wiener noise in the potential (reading R10)
+    convK: Optional[np.ndarray] = None  # [n] kernel of the non-local potential (R11), 1D
     _keep: list = field(default_factory=list, repr=False)
 
     @property
@@ -148,12 +154,22 @@ class Problem:
         p.id_base = int(self.id_base) & 0xFFFFFFFF
         p.integrator = int(self.integrator)
         p.noise_substeps = int(self.noise_substeps)
+        self._keep = []
         if self.Vgrid is not None:
             vg = np.ascontiguousarray(self.Vgrid, dtype=np.float64).reshape(self.batch, self.M)
-            self._keep = [vg]
+            self._keep.append(vg)
             p.Vgrid = vg.ctypes.data
         else:
             p.Vgrid = None
+        p.sigma_V = float(self.sigma_V)
+        if self.convK is not None:
+            ck = np.ascontiguousarray(self.convK, dtype=np.float64).reshape(-1)
+            if ck.size != int(self.n[0]):
+                raise ValueError("convK needs one value per lattice offset")
+            self._keep.append(ck)
+            p.convK = ck.ctypes.data
+        else:
+            p.convK = None
         return p
 
 
@@ -215,6 +231,24 @@ def noise(p: Problem, step: int) -> np.ndarray:
     out = np.empty(p.shape, dtype=np.complex128)
     pc = p._c()
     _load().ora_noise(ctypes.byref(pc), int(step), out.ctypes.data)
+    return out
+
+
+def vnoise(p: Problem, step: int) -> np.ndarray:
+    """The real noise eta of the potential at a step, [batch][M] (E eta^2 = 1/(h dV))."""
+    out = np.empty((p.batch, p.M), dtype=np.float64)
+    pc = p._c()
+    _load().ora_vnoise(ctypes.byref(pc), int(step), out.ctypes.data)
+    return out
+
+
+def conv_potential(p: Problem, psi) -> np.ndarray:
+    """The non-local potential V_c of every instance (reading R11), [batch][n]."""
+    f = _cfield(p, psi)
+    out = np.empty((p.batch, p.M), dtype=np.float64)
+    pc = p._c()
+    if _load().ora_conv_potential(ctypes.byref(pc), f.ctypes.data, out.ctypes.data):
+        raise ValueError("invalid problem")
     return out
 
 

@@ -55,6 +55,15 @@
  *       (local extrapolation), and the error estimate of the step is the relative L2
  *       norm over the instance, in the picture frame, of the difference between the
  *       fifth- and fourth-order results: ||sum_i (b_i - b*_i) k_i|| / ||psi_n + sum_i b_i k_i||.
+ *   R10 Noise in the potential (the stochastics example, Sec. 4): G gains
+ *       -i sigma_V eta psi with eta a real Wiener noise per lattice point, held over the
+ *       step like xi, E eta^2 = 1/(h dV); it is the real part of the complex normal drawn
+ *       with counter tag 3 (unit variance), summed over noise substeps as in R7, divided by
+ *       sqrt(h dV).
+ *   R11 A non-local potential (the non-local example, Sec. 4: a convolution with the
+ *       density): G gains -i V_c psi with V_c(x_i) = dV sum_j K(x_i - x_j) |psi_j|^2 on the
+ *       periodic lattice, the kernel given at lattice offsets, K[d] = K(d dx) for
+ *       d < n/2 and K((d - n) dx) above (1D lattices).
  *   R9  Step control (the paper gives none): a step is accepted when its error estimate is
  *       at most tol; either way the next trial step is h min(5, max(1/5, 0.9 (tol/err)^{1/5}))
  *       (5 when err = 0; 1/5 when err is not finite). A trial step that would pass the end
@@ -89,6 +98,8 @@ typedef struct {
     uint32_t id_base;
     uint32_t noise_substeps; /* 0 or 1: one draw per step; 2^L: the sum of 2^L finer draws (R7) */
     const double* Vgrid; /* [batch][M] or NULL */
+    double sigma_V;      /* real noise in the potential (R10) */
+    const double* convK; /* [n] kernel of the non-local potential (R11), 1D, or NULL */
 } ora_problem;
 
 #define ORA_PI 3.14159265358979323846
@@ -274,24 +285,49 @@ static cplx noise_z(uint64_t seed, uint32_t inst, int64_t step, uint32_t tag, in
     return rad * (cos(2.0 * ORA_PI * u2) + I * sin(2.0 * ORA_PI * u2));
 }
 
-/* xi for the whole lattice of one instance at step `step` (test entry and used by G). */
+/* The noise of one instance at step `step`: xi[0..M) and, when the potential is noisy
+ * (R10), eta in the real parts of xi[M..2M) (test entries and used by G). */
 static void noise_field(const ora_problem* p, int64_t b, int64_t step, cplx* xi) {
     int64_t M = npts(p);
     double scale = 1.0 / sqrt(2.0 * p->h * dV_of(p));
+    double vscale = 1.0 / sqrt(p->h * dV_of(p));
     uint32_t inst = p->id_base + (uint32_t)b;
     int64_t S = p->noise_substeps > 1 ? (int64_t)p->noise_substeps : 1;
     double inv_sqrt_S = 1.0 / sqrt((double)S);
 #pragma omp parallel for schedule(static)
     for (int64_t j = 0; j < M; j++) {
-        cplx z = 0.0;
-        for (int64_t q = 0; q < S; q++) z += noise_z(p->seed, inst, step * S + q, 0u, j);
+        cplx z = 0.0, zv = 0.0;
+        for (int64_t q = 0; q < S; q++) {
+            z += noise_z(p->seed, inst, step * S + q, 0u, j);
+            if (p->sigma_V != 0.0) zv += noise_z(p->seed, inst, step * S + q, 3u, j);
+        }
         xi[j] = scale * inv_sqrt_S * z;
+        if (p->sigma_V != 0.0) xi[M + j] = vscale * inv_sqrt_S * creal(zv);
     }
 }
 
+/* eta [batch][M] of a step (R10). */
+void ora_vnoise(const ora_problem* p, int64_t step, double* eta) {
+    int64_t M = npts(p);
+    cplx* buf = (cplx*)malloc(sizeof(cplx) * 2 * (size_t)M);
+    for (int64_t b = 0; b < p->batch; b++) {
+        noise_field(p, b, step, buf);
+        for (int64_t j = 0; j < M; j++) eta[b * M + j] = p->sigma_V != 0.0 ? creal(buf[M + j]) : 0.0;
+    }
+    free(buf);
+}
+
+/* Does a step draw noise (additive or in the potential)? */
+static int noisy(const ora_problem* p) { return p->sigma != 0.0 || p->sigma_V != 0.0; }
+
 void ora_noise(const ora_problem* p, int64_t step, cplx* xi /* [batch][M] */) {
     int64_t M = npts(p);
-    for (int64_t b = 0; b < p->batch; b++) noise_field(p, b, step, xi + b * M);
+    cplx* buf = (cplx*)malloc(sizeof(cplx) * 2 * (size_t)M);
+    for (int64_t b = 0; b < p->batch; b++) {
+        noise_field(p, b, step, buf);
+        memcpy(xi + b * M, buf, sizeof(cplx) * (size_t)M);
+    }
+    free(buf);
 }
 
 /* ------------------------------------------------------------------------------------
@@ -315,16 +351,50 @@ static void potential(const ora_problem* p, int64_t b, double* V) {
     }
 }
 
-/* out = h * G(phi) */
+/* The non-local potential of one instance (R11): the periodic convolution written out. */
+static void conv_potential(const ora_problem* p, const cplx* phi, double* out) {
+    int64_t n = p->n[0];
+    double dv = dV_of(p);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; i++) {
+        double s = 0.0;
+        for (int64_t j = 0; j < n; j++) {
+            double rho = creal(phi[j]) * creal(phi[j]) + cimag(phi[j]) * cimag(phi[j]);
+            s += p->convK[(i - j + n) % n] * rho;
+        }
+        out[i] = dv * s;
+    }
+}
+
+static int check_problem(const ora_problem* p);
+
+/* V_c of every instance of psi [batch][n] (test entry; 1D with a kernel). */
+int ora_conv_potential(const ora_problem* p, const cplx* psi, double* out) {
+    if (check_problem(p) || !p->convK) return -1;
+    int64_t M = npts(p);
+    for (int64_t b = 0; b < p->batch; b++) conv_potential(p, psi + b * M, out + b * M);
+    return 0;
+}
+
+/* out = h * G(phi); xi is the step's noise buffer (noise_field) or NULL */
 static void hG(const ora_problem* p, const double* V, const cplx* xi, const cplx* phi, cplx* out) {
     int64_t M = npts(p);
+    double* vc = NULL;
+    if (p->convK) {
+        vc = (double*)malloc(sizeof(double) * (size_t)M);
+        conv_potential(p, phi, vc);
+    }
 #pragma omp parallel for schedule(static)
     for (int64_t j = 0; j < M; j++) {
         double m2 = creal(phi[j]) * creal(phi[j]) + cimag(phi[j]) * cimag(phi[j]);
-        cplx g = -I * (V[j] + p->gnl * m2) * phi[j];
+        double veff = V[j];
+        if (vc) veff += vc[j];
+        if (xi && p->sigma_V != 0.0) veff += p->sigma_V * creal(xi[M + j]);
+        cplx g = -I * (veff + p->gnl * m2) * phi[j];
         if (xi) g += p->sigma * xi[j];
         out[j] = p->h * g;
     }
+    free(vc);
 }
 
 static void apply_D_dense(const ora_problem* p, const cplx* E, cplx* f);
@@ -423,15 +493,21 @@ static int check_problem(const ora_problem* p) {
     if (p->batch < 1 || !(p->h > 0.0)) return -1;
     if (p->integrator != 0 && p->integrator != 1) return -1;
     if (p->noise_substeps > 1 && (p->noise_substeps & (p->noise_substeps - 1)) != 0) return -1;
+    if (!isfinite(p->sigma_V)) return -1;
+    if (p->convK && p->ndim != 1) return -1;
     return 0;
 }
+
+/* The tangent, the adjoint and the adaptive integrator cover G without the noisy or
+ * non-local potential. */
+static int plain_potential(const ora_problem* p) { return p->sigma_V == 0.0 && p->convK == NULL; }
 
 /* Advance every instance by nsteps steps, the first one having index step0. */
 static int run_steps(const ora_problem* p, cplx* psi, int64_t step0, int64_t nsteps) {
     int64_t M = npts(p);
     cplx* E = make_E(p, 1.0);
     double* V = (double*)malloc(sizeof(double) * (size_t)M);
-    cplx* xi = p->sigma != 0.0 ? (cplx*)malloc(sizeof(cplx) * (size_t)M) : NULL;
+    cplx* xi = noisy(p) ? (cplx*)malloc(sizeof(cplx) * 2 * (size_t)M) : NULL;
     for (int64_t b = 0; b < p->batch; b++) {
         potential(p, b, V);
         for (int64_t s = 0; s < nsteps; s++) {
@@ -456,7 +532,7 @@ int ora_step_dense(const ora_problem* p, cplx* psi, int64_t step_index) {
     int64_t M = npts(p);
     cplx* E = make_E(p, 1.0);
     double* V = (double*)malloc(sizeof(double) * (size_t)M);
-    cplx* xi = p->sigma != 0.0 ? (cplx*)malloc(sizeof(cplx) * (size_t)M) : NULL;
+    cplx* xi = noisy(p) ? (cplx*)malloc(sizeof(cplx) * 2 * (size_t)M) : NULL;
     for (int64_t b = 0; b < p->batch; b++) {
         potential(p, b, V);
         if (xi) noise_field(p, b, step_index, xi);
@@ -663,7 +739,8 @@ static void tangent_one(const ora_problem* p, const cplx* E, const double* V, co
 
 /* Tangent-linear run: advances psi and dpsi by nsteps; dV is [batch][M] or NULL. */
 int ora_tangent(const ora_problem* p, cplx* psi, cplx* dpsi, const double* dV, int64_t step0, int64_t nsteps) {
-    if (check_problem(p) || p->integrator != 0) return -1; /* the RK4IP step's tangent only */
+    /* the RK4IP step's tangent only, with the plain potential */
+    if (check_problem(p) || p->integrator != 0 || !plain_potential(p)) return -1;
     int64_t M = npts(p);
     cplx* E = make_E(p, 1.0);
     double* V = malloc(sizeof(double) * (size_t)M);
@@ -749,8 +826,8 @@ static void adjoint_one(const ora_problem* p, const cplx* E, const cplx* Ec, con
  *   grad_psi0: [batch][M] (out);  grad_V: [batch][M] (out) or NULL. */
 int ora_adjoint(const ora_problem* p, const cplx* psi0, int64_t step0, int64_t nsteps, int64_t ckpt_every,
                 const cplx* lamT, cplx* grad_psi0, double* grad_V) {
-    /* the discrete adjoint of the RK4IP step only */
-    if (check_problem(p) || p->integrator != 0 || nsteps < 0 || ckpt_every < 1) return -1;
+    /* the discrete adjoint of the RK4IP step only, with the plain potential */
+    if (check_problem(p) || p->integrator != 0 || !plain_potential(p) || nsteps < 0 || ckpt_every < 1) return -1;
     int64_t M = npts(p);
     size_t bytes = sizeof(cplx) * (size_t)M;
     cplx* E = make_E(p, 1.0);
@@ -894,7 +971,7 @@ static double ck_step_one(const ora_problem* p, const double* V, const cplx* psi
 }
 
 static int check_ark45(const ora_problem* p) {
-    if (check_problem(p)) return -1;
+    if (check_problem(p) || !plain_potential(p)) return -1;
     if (p->sigma != 0.0) return -1; /* deterministic only */
     return 0;
 }

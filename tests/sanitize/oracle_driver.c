@@ -18,6 +18,8 @@ typedef struct {
     uint64_t seed;
     uint32_t id_base, noise_substeps;
     const double* Vgrid;
+    double sigma_V;
+    const double* convK;
 } ora_problem;
 
 void ora_dft(const cplx* in, cplx* out, int64_t n, int sign);
@@ -37,6 +39,7 @@ int ora_adjoint(const ora_problem* p, const cplx* psi0, int64_t step0, int64_t n
 int ora_apply_D(const ora_problem* p, cplx* f, int dense, int adjoint);
 int ora_fft_nd(const ora_problem* p, cplx* f, int sign);
 void ora_ck_tableau(double* out);
+void ora_vnoise(const ora_problem* p, int64_t step, double* eta);
 int ora_ck_step(const ora_problem* p, const cplx* psi, double h, cplx* out, double* err);
 int ora_ark45(const ora_problem* p, cplx* psi, double t_span, double tol, int64_t max_attempts, double* h,
               int64_t* stats, double* h_log, int64_t log_cap);
@@ -110,6 +113,20 @@ static void exercise(int ndim, const int64_t* n, int64_t batch, int si) {
     } else if (ora_adjoint(&p, psi, 1, 5, 2, lam, g, gV) == 0) {
         fails++; /* the adjoint is of the RK4IP step only */
     }
+    /* noise in the potential (every lattice) and the non-local potential (1D) */
+    double* K = malloc(sizeof(double) * p.n[0]);
+    for (int64_t d = 0; d < p.n[0]; d++) K[d] = 1.0 / (1.0 + (double)(d < p.n[0] / 2 ? d : p.n[0] - d));
+    double* eta = malloc(sizeof(double) * tot);
+    p.sigma_V = 0.2;
+    if (ndim == 1) p.convK = K;
+    ora_vnoise(&p, 4, eta);
+    CHECK(ora_step(&p, psi, 5));
+    CHECK(ora_step_dense(&p, psi, 6));
+    CHECK(ora_run(&p, psi, 10, 4, 2, diag, ckpt, 3));
+    if (ora_tangent(&p, psi, dpsi, dV, 2, 3) == 0 || ora_adjoint(&p, psi, 1, 5, 2, lam, g, gV) == 0) fails++;
+    p.sigma_V = 0.0;
+    p.convK = NULL;
+    free(K), free(eta);
     /* the adaptive integrator is deterministic: it refuses noise, then runs without */
     double* hs = malloc(sizeof(double) * batch);
     int64_t* stats = malloc(sizeof(int64_t) * batch * 2);

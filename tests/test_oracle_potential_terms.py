@@ -1,0 +1,121 @@
+"""Pins of the oracle's noisy potential (the stochastics example of Sec. 4: a real Wiener
+noise in the trap) and non-local potential (the non-local example of Sec. 4: a
+convolution of the density with a kernel).
+
+Each rests on something other than the oracle's code: the moments of the noise, the
+definition of the noise substeps, the closed form of a step when the noisy potential is
+the only term (RK4 and the semi-implicit step on a constant linear equation per point),
+the orientation of the convolution shown by a shifted delta kernel, the equivalence of a
+delta kernel with the local nonlinearity, and a uniform kernel giving a uniform
+potential proportional to the norm."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1204_4255_amd import workloads as W
+
+
+def rel(a, b):
+    return np.linalg.norm(np.ravel(a - b)) / np.linalg.norm(np.ravel(b))
+
+
+def _prob(g, h, **kw):
+    return oracle.Problem(n=g.n, lo=g.lo, hi=g.hi, h=h, batch=g.batch, alpha=g.alpha, gamma=g.gamma, gnl=g.gnl,
+                          trap=g.trap, sigma=g.sigma, seed=g.seed, id_base=g.id_base, **kw)
+
+
+def test_potential_noise_moments_and_independence():
+    g = W.Group(n=(128, 64), lo=(-4, -4), hi=(4, 4), batch=4, seed=17, id_base=2, sigma=1.0)
+    h = 1e-3
+    p = _prob(g, h, sigma_V=1.0)
+    eta = oracle.vnoise(p, 9)
+    xi = oracle.noise(p, 9).reshape(g.batch, -1)
+    s = eta * np.sqrt(h * g.dV)  # unit normal
+    n = s.size
+    assert abs(s.mean()) < 4 / np.sqrt(n)
+    assert abs(s.var() - 1) < 4 * np.sqrt(2 / n)
+    # fourth moment of a normal: 3
+    assert abs(np.mean(s ** 4) - 3) < 8 * np.sqrt(96 / n)
+    c = np.mean(s * xi.real * np.sqrt(2 * h * g.dV))
+    assert abs(c) < 4 / np.sqrt(n)
+    assert not np.allclose(oracle.vnoise(p, 10), eta)
+
+
+@pytest.mark.parametrize("S", [2, 4])
+def test_potential_noise_substeps_are_the_mean_of_finer_draws(S):
+    g = W.Group(n=(32,), lo=(-2,), hi=(2,), batch=3, seed=5)
+    h = 0.01
+    coarse = oracle.vnoise(_prob(g, h, sigma_V=1.0, noise_substeps=S), 3)
+    fine = [oracle.vnoise(_prob(g, h / S, sigma_V=1.0), 3 * S + q) for q in range(S)]
+    assert np.max(np.abs(coarse - np.mean(fine, axis=0))) < 1e-12 * np.max(np.abs(coarse))
+
+
+@pytest.mark.parametrize("integrator", [0, 1])
+def test_noisy_potential_alone_has_the_closed_form_step(integrator):
+    # alpha = 0, g = 0, V = 0, no additive noise: every point obeys psi' = -i s eta psi with
+    # eta held over the step, so RK4 gives the degree-4 Taylor factor of e^z and the
+    # semi-implicit step 1 + 2w + 2w^2 + 2w^3 with w = z/2, z = -i h s eta
+    g = W.Group(n=(64,), lo=(-3,), hi=(3,), batch=2, alpha=0.0, seed=8)
+    h, sv = 0.02, 0.3
+    p = _prob(g, h, sigma_V=sv, integrator=integrator)
+    rng = np.random.Generator(np.random.PCG64(1))
+    psi = rng.standard_normal(g.shape) + 1j * rng.standard_normal(g.shape)
+    out = oracle.step(p, psi, 12)
+    z = -1j * h * sv * oracle.vnoise(p, 12)
+    if integrator == 0:
+        fac = 1 + z + z ** 2 / 2 + z ** 3 / 6 + z ** 4 / 24
+    else:
+        w = z / 2
+        fac = 1 + 2 * w + 2 * w ** 2 + 2 * w ** 3
+    assert rel(out, fac * psi) < 1e-13
+
+
+def test_convolution_orientation_by_a_shifted_delta():
+    # K(d) = 1/dx at d = +dx only: V_c(x_i) = density at x_i - dx
+    n = 32
+    g = W.Group(n=(n,), lo=(-4,), hi=(4,), batch=2)
+    K = np.zeros(n)
+    K[1] = 1 / g.dV
+    rng = np.random.Generator(np.random.PCG64(3))
+    psi = rng.standard_normal(g.shape) + 1j * rng.standard_normal(g.shape)
+    vc = oracle.conv_potential(_prob(g, 0.01, convK=K), psi)
+    assert np.allclose(vc, np.roll(np.abs(psi) ** 2, 1, axis=1), rtol=1e-14, atol=0)
+    # and a negative offset (the upper half of the kernel array)
+    K = np.zeros(n)
+    K[n - 2] = 1 / g.dV
+    vc = oracle.conv_potential(_prob(g, 0.01, convK=K), psi)
+    assert np.allclose(vc, np.roll(np.abs(psi) ** 2, -2, axis=1), rtol=1e-14, atol=0)
+
+
+def test_uniform_kernel_gives_the_norm():
+    n = 64
+    g = W.Group(n=(n,), lo=(-4,), hi=(4,), batch=3)
+    rng = np.random.Generator(np.random.PCG64(4))
+    psi = rng.standard_normal(g.shape) + 1j * rng.standard_normal(g.shape)
+    vc = oracle.conv_potential(_prob(g, 0.01, convK=np.full(n, 0.7)), psi)
+    N = np.sum(np.abs(psi) ** 2, axis=1) * g.dV
+    assert np.allclose(vc, 0.7 * N[:, None], rtol=1e-13)
+
+
+@pytest.mark.parametrize("integrator", [0, 1])
+def test_delta_kernel_is_the_local_nonlinearity(integrator):
+    # K = delta/dx makes V_c = |psi|^2: a run equals the run with g + 1 and no kernel
+    n = 128
+    g = W.Group(n=(n,), lo=(-8,), hi=(8,), batch=2, gnl=0.5, trap=(1.0, 0, 0), gamma=0.1, sigma=0.01, seed=6)
+    x = g.axis(0)
+    psi = np.pi ** -0.25 * np.exp(-(x[None] - np.array([[0.0], [1.0]])) ** 2 / 2) + 0j
+    K = np.zeros(n)
+    K[0] = 1 / g.dV
+    a, _, _ = oracle.run(_prob(g, 2e-3, convK=K, integrator=integrator), psi, 30)
+    g2 = W.Group(n=(n,), lo=(-8,), hi=(8,), batch=2, gnl=1.5, trap=(1.0, 0, 0), gamma=0.1, sigma=0.01, seed=6)
+    b, _, _ = oracle.run(_prob(g2, 2e-3, integrator=integrator), psi, 30)
+    assert rel(a, b) < 1e-13
+
+
+def test_unsupported_combinations_are_rejected():
+    g2 = W.Group(n=(8, 8), lo=(0, 0), hi=(1, 1))
+    with pytest.raises(ValueError):
+        oracle.step(_prob(g2, 0.01, convK=np.ones(8)), np.ones(g2.shape, complex))
+    g1 = W.Group(n=(16,), lo=(0,), hi=(1,))
+    with pytest.raises(ValueError):
+        oracle.ark45(_prob(g1, 0.01, sigma_V=0.1), np.ones((1, 16), complex), 1.0, 1e-6, 0.1)
