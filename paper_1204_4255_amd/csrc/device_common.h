@@ -39,6 +39,9 @@ struct GroupDev {
     const double2* tw64[3];
     int noise_sub;           // noise of a step = normalised sum of this many finer draws
     float inv_sqrt_sub;      // 1/sqrt(noise_sub)
+    int has_vnoise;          // real Wiener noise in the potential (1D groups)
+    float vnoise_c;          // sigma_V / sqrt(h dV): multiplies a unit real normal
+    const float2* convK;     // [n] (FFT of the non-local kernel) dV / n (1D groups), or null
 };
 
 // ---------------------------------------------------------------- Philox4x32-10
@@ -68,14 +71,16 @@ __device__ __forceinline__ U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1) {
 }
 
 // Counter of the pair of points (2q, 2q+1) of an instance at a step, tag 0 (dynamics).
-__device__ __forceinline__ U4 noise_counter(int64_t j, uint32_t inst, int64_t step) {
+// Counter of point j of instance `inst` at `step`; the tag (top byte of the last word)
+// separates streams: 0 the additive noise, 3 the noise in the potential.
+__device__ __forceinline__ U4 noise_counter(int64_t j, uint32_t inst, int64_t step, uint32_t tag = 0) {
     U4 c;
     const uint64_t q = (uint64_t)j >> 1;
     const uint64_t st = (uint64_t)step;
     c.x = (uint32_t)q;
     c.y = inst;
     c.z = (uint32_t)st;
-    c.w = (uint32_t)((st >> 32) & 0xFFFFFFu);
+    c.w = (tag << 24) | (uint32_t)((st >> 32) & 0xFFFFFFu);
     return c;
 }
 
@@ -107,6 +112,24 @@ __device__ __forceinline__ float2 noise_z(const GroupDev& g, int64_t j, uint32_t
         acc.y = fmaf(rad, sn, acc.y);
     }
     return make_float2(acc.x * g.inv_sqrt_sub, acc.y * g.inv_sqrt_sub);
+}
+
+// The noise of the potential at point j (in units of the potential): sigma_V eta with
+// eta = Re(z)/sqrt(h dV), z the complex normal of counter tag 3, summed over the noise
+// substeps like noise_z (explicit FMAs for the same reason).
+__device__ __forceinline__ float vnoise(const GroupDev& g, int64_t j, uint32_t inst, int64_t step) {
+    const int S = g.noise_sub;
+    float acc = 0.f;
+    for (int s = 0; s < S; s++) {
+        const U4 r = philox4x32_10(noise_counter(j, inst, step * S + s, 3u), g.seed_lo, g.seed_hi);
+        float rad, c, sn;
+        if (j & 1)
+            box_muller(r.z, r.w, rad, c, sn);
+        else
+            box_muller(r.x, r.y, rad, c, sn);
+        acc = fmaf(rad, c, acc);
+    }
+    return acc * g.inv_sqrt_sub * g.vnoise_c;
 }
 
 // Trap potential at lattice indices (x, y, z).

@@ -11,7 +11,29 @@ namespace rk4ip {
 // registers and more threads per line). P64: transforms in FP64 (RR = 8), everything
 // else as in the complex64 form. SI: the semi-implicit step (one field: a = D psi, the
 // midpoint iteration, D(2m - a)) instead of RK4IP.
-template <int N, int LPB, bool NOISE, bool P64, int RR, bool SI>
+// The non-local potential of a line (1D groups): V_c = F^{-1}[kh F|f|^2] with kh the
+// kernel's transform times dV/n, so V_c(x_i) = dV sum_j K(x_i - x_j) |f_j|^2 on the
+// periodic line. W: the transform's working type.
+template <class F, class L, class W>
+__device__ __forceinline__ void conv_V(const c32 (&f)[F::R], float (&vc)[F::R], int t, int l, W* lds, const W* tw,
+                                       const float2* __restrict__ kh) {
+    constexpr int R = F::R, T = F::T;
+    W d[1][R];
+#pragma unroll
+    for (int m = 0; m < R; m++) d[0][m] = widen(make_float2(fmaf(f[m].x, f[m].x, f[m].y * f[m].y), 0.f), W{});
+    fft_line<F, -1, L, 1>(d, t, l, lds, tw);
+#pragma unroll
+    for (int m = 0; m < R; m++) d[0][m] = cmul(d[0][m], widen(kh[t + m * T], W{}));
+    fft_line<F, +1, L, 1>(d, t, l, lds, tw);
+#pragma unroll
+    for (int m = 0; m < R; m++) vc[m] = (float)d[0][m].x;
+}
+
+// EXTRA: the variant with the potential's extra terms (1D groups): the real Wiener
+// noise in the potential and the non-local potential. Every G evaluation then needs the
+// non-local potential of its whole stage field, so the stages run in phases (one line
+// transform pair per G evaluation) instead of point by point.
+template <int N, int LPB, bool NOISE, bool P64, int RR, bool SI, bool EXTRA>
 __global__ void __launch_bounds__((FFTShape<N, RR>::T * LPB))
     k_line_step(GroupDev g, float2* __restrict__ psi, int nsteps, int64_t step_off,
                 const int64_t* __restrict__ step_base) {
@@ -55,6 +77,81 @@ __global__ void __launch_bounds__((FFTShape<N, RR>::T * LPB))
             } else {
                 nz[m] = make_float2(0.f, 0.f);
             }
+        }
+        if constexpr (EXTRA) {
+            // potential of this step: V + sigma_V eta, and V_c of each stage field
+            float Vs[R], vc[R];
+#pragma unroll
+            for (int m = 0; m < R; m++) Vs[m] = V[m];
+            if constexpr (NOISE) {
+                if (g.has_vnoise) {
+#pragma unroll
+                    for (int m = 0; m < R; m++) Vs[m] += vnoise(g, t + m * T, iid, step);
+                }
+            }
+            const bool conv = g.convK != nullptr;  // uniform
+            auto potential = [&](const c32(&x)[R]) {
+                if (conv) {
+                    conv_V<F, L>(x, vc, t, l, lds, tw, g.convK);
+#pragma unroll
+                    for (int m = 0; m < R; m++) vc[m] += Vs[m];
+                } else {
+#pragma unroll
+                    for (int m = 0; m < R; m++) vc[m] = Vs[m];
+                }
+            };
+            c32(&f0)[1][R] = *reinterpret_cast<c32(*)[1][R]>(&f[0]);
+            if constexpr (SI) {
+                propagate<F, L, 1>(f0, t, l, lds, tw, E, false);  // a = D psi
+                c32 mid[R];
+#pragma unroll
+                for (int m = 0; m < R; m++) mid[m] = f[0][m];
+                for (int it = 0; it < 3; it++) {
+                    potential(mid);
+#pragma unroll
+                    for (int m = 0; m < R; m++) {
+                        const c32 k = hG(g, mid[m], vc[m], nz[m]);
+                        mid[m] = make_float2(fmaf(0.5f, k.x, f[0][m].x), fmaf(0.5f, k.y, f[0][m].y));
+                    }
+                }
+#pragma unroll
+                for (int m = 0; m < R; m++)
+                    f[0][m] = make_float2(fmaf(2.0f, mid[m].x, -f[0][m].x), fmaf(2.0f, mid[m].y, -f[0][m].y));
+                propagate<F, L, 1>(f0, t, l, lds, tw, E, false);  // psi' = D(2m - a)
+            } else {
+                potential(f[0]);
+#pragma unroll
+                for (int m = 0; m < R; m++) f[1][m] = hG(g, f[0][m], vc[m], nz[m]);
+                propagate<F, L, 2>(f, t, l, lds, tw, E, false);  // (a, k1)
+                c32 q[R];
+#pragma unroll
+                for (int m = 0; m < R; m++)
+                    q[m] = make_float2(fmaf(0.5f, f[1][m].x, f[0][m].x), fmaf(0.5f, f[1][m].y, f[0][m].y));
+                potential(q);
+#pragma unroll
+                for (int m = 0; m < R; m++) {
+                    const c32 k2 = hG(g, q[m], vc[m], nz[m]);
+                    // acc so far: a + k1/6 + k2/3 (k1 is not needed after this)
+                    f[1][m] = make_float2(f[0][m].x + (f[1][m].x * (1.0f / 6.0f) + k2.x * (1.0f / 3.0f)),
+                                          f[0][m].y + (f[1][m].y * (1.0f / 6.0f) + k2.y * (1.0f / 3.0f)));
+                    q[m] = make_float2(fmaf(0.5f, k2.x, f[0][m].x), fmaf(0.5f, k2.y, f[0][m].y));
+                }
+                potential(q);
+#pragma unroll
+                for (int m = 0; m < R; m++) {
+                    const c32 k3 = hG(g, q[m], vc[m], nz[m]);
+                    f[0][m] = cadd(f[0][m], k3);  // u = a + k3
+                    f[1][m] = make_float2(fmaf(k3.x, 1.0f / 3.0f, f[1][m].x), fmaf(k3.y, 1.0f / 3.0f, f[1][m].y));
+                }
+                propagate<F, L, 2>(f, t, l, lds, tw, E, false);  // (D u, D acc)
+                potential(f[0]);
+#pragma unroll
+                for (int m = 0; m < R; m++) {
+                    const c32 k4 = hG(g, f[0][m], vc[m], nz[m]);
+                    f[0][m] = make_float2(fmaf(k4.x, 1.0f / 6.0f, f[1][m].x), fmaf(k4.y, 1.0f / 6.0f, f[1][m].y));
+                }
+            }
+            continue;
         }
         if constexpr (SI) {
             c32(&f0)[1][R] = *reinterpret_cast<c32(*)[1][R]>(&f[0]);
@@ -139,24 +236,32 @@ hipError_t launch_axis(const GroupDev& g, int axis, int mode, const PassArgs& a,
     }
 }
 
-template <int N, bool P64, int RR, bool SI>
+template <int N, bool P64, int RR, bool SI, bool EXTRA = false>
 static hipError_t go_line(const GroupDev& g, float2* psi, int nsteps, int64_t step_off, const int64_t* step_base,
                           hipStream_t s) {
     constexpr int T = FFTShape<N, RR>::T;
     constexpr int LPB = T >= 64 ? 1 : 64 / T;
     const int64_t blocks = (g.batch + LPB - 1) / LPB;
     if (g.has_noise)
-        hipLaunchKernelGGL((k_line_step<N, LPB, true, P64, RR, SI>), dim3((unsigned)blocks), dim3(T * LPB), 0, s, g,
-                           psi, nsteps, step_off, step_base);
+        hipLaunchKernelGGL((k_line_step<N, LPB, true, P64, RR, SI, EXTRA>), dim3((unsigned)blocks), dim3(T * LPB), 0, s,
+                           g, psi, nsteps, step_off, step_base);
     else
-        hipLaunchKernelGGL((k_line_step<N, LPB, false, P64, RR, SI>), dim3((unsigned)blocks), dim3(T * LPB), 0, s, g,
-                           psi, nsteps, step_off, step_base);
+        hipLaunchKernelGGL((k_line_step<N, LPB, false, P64, RR, SI, EXTRA>), dim3((unsigned)blocks), dim3(T * LPB), 0,
+                           s, g, psi, nsteps, step_off, step_base);
     return hipGetLastError();
 }
 
 template <int N, bool SI>
 static hipError_t go_line_p(const GroupDev& g, float2* psi, int nsteps, int64_t step_off, const int64_t* step_base,
                             bool f64, int radix, hipStream_t s) {
+    if (g.has_vnoise || g.convK) {
+        // the potential's extra terms: 8 values per thread
+        if (f64) {
+            if constexpr (N <= 2048) return go_line<N, true, 8, SI, true>(g, psi, nsteps, step_off, step_base, s);
+            return hipErrorInvalidValue;
+        }
+        return go_line<N, false, 8, SI, true>(g, psi, nsteps, step_off, step_base, s);
+    }
     if (f64) {
         if constexpr (N <= 2048) return go_line<N, true, 8, SI>(g, psi, nsteps, step_off, step_base, s);
         return hipErrorInvalidValue;  // FP64 tables and exchange buffers exceed the LDS

@@ -55,6 +55,7 @@ struct GroupHost {
     size_t tab64_off[3] = {0, 0, 0}; // FP64 copies (FP64-transform plans)
     size_t tw64_off[3] = {0, 0, 0};
     size_t part_off[3] = {0, 0, 0};  // diagnostic partials (batch * M/n_a * 4 doubles)
+    size_t conv_off = 0;             // transform of the non-local kernel (1D groups with one)
     double dV = 1.0;
 };
 
@@ -79,6 +80,13 @@ int validate(const rk4ip_problem* probs, int nprob, uint32_t flags) {
         if (!(p.dt > 0.0) || !std::isfinite(p.dt) || p.dt != dt0) return RK4IP_ERR_INVALID_ARG;
         if (!std::isfinite(p.alpha) || !std::isfinite(p.gamma) || p.gamma < 0.0) return RK4IP_ERR_INVALID_ARG;
         if (!std::isfinite(p.g_nl) || !std::isfinite(p.sigma) || p.sigma < 0.0) return RK4IP_ERR_INVALID_ARG;
+        if (!std::isfinite(p.sigma_V) || p.sigma_V < 0.0) return RK4IP_ERR_INVALID_ARG;
+        // the potential's extra terms are built for 1D groups
+        if ((p.sigma_V != 0.0 || p.conv_K) && p.ndim != 1) return RK4IP_ERR_UNSUPPORTED_SHAPE;
+        if (p.conv_K && p.ndim == 1 && p.n[0] >= 1 && p.n[0] <= 4096) {
+            for (int64_t d = 0; d < p.n[0]; d++)
+                if (!std::isfinite(p.conv_K[d])) return RK4IP_ERR_INVALID_ARG;
+        }
         if (p.batch < 1 || p.batch > (int64_t(1) << 31)) return RK4IP_ERR_INVALID_ARG;
         if ((uint64_t)p.id_base + (uint64_t)p.batch - 1 > 0xFFFFFFFFull) return RK4IP_ERR_INVALID_ARG;
         if (p.ndim < 1 || p.ndim > 3) return RK4IP_ERR_UNSUPPORTED_SHAPE;
@@ -130,6 +138,13 @@ Layout layout(const rk4ip_problem* probs, int nprob, uint32_t flags, std::vector
                 (*gh)[i].tab64_off[a] = e64;
                 (*gh)[i].tw64_off[a] = t64;
             }
+        }
+    }
+    for (int i = 0; i < nprob; i++) {
+        const rk4ip_problem& p = probs[i];
+        if (p.conv_K) {
+            if (gh) (*gh)[i].conv_off = off;
+            off = align_up(off + sizeof(float2) * (size_t)p.n[0]);
         }
     }
     for (int i = 0; i < nprob; i++) {
@@ -242,6 +257,27 @@ void build_tables(const rk4ip_problem& p, int a, std::vector<float2>& E, std::ve
         tw[m] = make_float2((float)std::cos(ang), (float)-std::sin(ang));
         if (E64) (*E64)[m] = make_double2(c * inv_n, s * inv_n);
         if (tw64) (*tw64)[m] = make_double2(std::cos(ang), -std::sin(ang));
+    }
+}
+
+// Transform of the non-local kernel times dV/n (FP64 sums over a twiddle table, stored
+// FP32): kh_m = (dV/n) sum_d K[d] e^{-2 pi i m d / n}.
+void build_conv_table(const rk4ip_problem& p, double dV, std::vector<float2>& kh) {
+    const int64_t n = p.n[0];
+    std::vector<double> c(n), sn(n);
+    for (int64_t q = 0; q < n; q++) {
+        c[q] = std::cos(2.0 * kPi * (double)q / (double)n);
+        sn[q] = std::sin(2.0 * kPi * (double)q / (double)n);
+    }
+    kh.resize(n);
+    for (int64_t m = 0; m < n; m++) {
+        double re = 0.0, im = 0.0;
+        for (int64_t d = 0; d < n; d++) {
+            const int64_t q = (m * d) & (n - 1);
+            re += p.conv_K[d] * c[q];
+            im -= p.conv_K[d] * sn[q];
+        }
+        kh[m] = make_float2((float)(re * dV / (double)n), (float)(im * dV / (double)n));
     }
 }
 
@@ -815,7 +851,9 @@ int rk4ip_plan(const rk4ip_problem* probs, int nprob, void* workspace, size_t ws
         d.seed_lo = (uint32_t)(p.seed & 0xFFFFFFFFu);
         d.seed_hi = (uint32_t)(p.seed >> 32);
         d.id_base = p.id_base;
-        d.has_noise = p.sigma != 0.0 ? 1 : 0;
+        d.has_noise = (p.sigma != 0.0 || p.sigma_V != 0.0) ? 1 : 0;
+        d.has_vnoise = p.sigma_V != 0.0 ? 1 : 0;
+        d.vnoise_c = (float)(p.sigma_V / std::sqrt(p.dt * g.dV));
         d.noise_sub = p.noise_substeps > 1 ? (int)p.noise_substeps : 1;
         d.inv_sqrt_sub = (float)(1.0 / std::sqrt((double)d.noise_sub));  // a power of two or its root
         d.Vgrid = p.V_grid;
@@ -842,6 +880,18 @@ int rk4ip_plan(const rk4ip_problem* probs, int nprob, void* workspace, size_t ws
                 d.E64[a] = reinterpret_cast<const double2*>(plan->ws + g.tab64_off[a]);
                 d.tw64[a] = reinterpret_cast<const double2*>(plan->ws + g.tw64_off[a]);
             }
+        }
+        if (p.conv_K) {
+            std::vector<float2> kh;
+            build_conv_table(p, g.dV, kh);
+            hipError_t e1 = hipMemcpy(plan->ws + g.conv_off, kh.data(), sizeof(float2) * kh.size(),
+                                      hipMemcpyHostToDevice);
+            if (e1 != hipSuccess) {
+                rc = fail_hip(plan, e1, "table upload");
+                delete plan;
+                return rc;
+            }
+            d.convK = reinterpret_cast<const float2*>(plan->ws + g.conv_off);
         }
         g.first_inst = inst;
         offset += p.batch * g.M;
@@ -982,7 +1032,9 @@ int rk4ip_ark45(rk4ip_plan_t plan, void* psi_v, double t_span, double tol, int64
         return RK4IP_ERR_INVALID_ARG;
     for (auto& g : plan->groups) {
         if (g.p.ndim != 1) return fail(plan, RK4IP_ERR_UNSUPPORTED_SHAPE, "the adaptive integrator takes 1D groups");
-        if (g.p.sigma != 0.0) return fail(plan, RK4IP_ERR_INVALID_ARG, "the adaptive integrator is deterministic");
+        if (g.p.sigma != 0.0 || g.p.sigma_V != 0.0)
+            return fail(plan, RK4IP_ERR_INVALID_ARG, "the adaptive integrator is deterministic");
+        if (g.p.conv_K) return fail(plan, RK4IP_ERR_INVALID_ARG, "the adaptive integrator takes the local potential");
     }
     float2* psi = static_cast<float2*>(psi_v);
     for (auto& g : plan->groups) {
@@ -1017,6 +1069,9 @@ int rk4ip_adjoint(rk4ip_plan_t plan, const void* ckpt_v, int64_t step0, int64_t 
         return RK4IP_ERR_INVALID_ARG;
     if ((reinterpret_cast<uintptr_t>(adj_ws) % kAlign) != 0) return RK4IP_ERR_INVALID_ARG;
     if (plan->si) return fail(plan, RK4IP_ERR_INVALID_ARG, "the adjoint covers the RK4 step only");
+    for (auto& g : plan->groups)
+        if (g.p.sigma_V != 0.0 || g.p.conv_K)
+            return fail(plan, RK4IP_ERR_INVALID_ARG, "the adjoint covers the local, noise-free potential only");
     if (adj_ws_bytes < rk4ip_adjoint_workspace_bytes(plan, ckpt_every)) return RK4IP_ERR_WORKSPACE_TOO_SMALL;
     hipStream_t st = plan->stream;
     const size_t field = align_up(sizeof(float2) * (size_t)plan->points);

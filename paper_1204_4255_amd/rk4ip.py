@@ -58,6 +58,7 @@ class rk4ip_problem(ctypes.Structure):
         ("gamma", ctypes.c_double), ("g_nl", ctypes.c_double), ("trap", ctypes.c_double * 3),
         ("V_grid", ctypes.c_void_p), ("sigma", ctypes.c_double), ("seed", ctypes.c_uint64),
         ("id_base", ctypes.c_uint32), ("noise_substeps", ctypes.c_uint32),
+        ("sigma_V", ctypes.c_double), ("conv_K", ctypes.c_void_p),
     ]
 
 
@@ -133,8 +134,9 @@ def _check(status: int, plan_handle=None, what: str = "rk4ip call"):
 def make_problem(n: Sequence[int], lo: Sequence[float], hi: Sequence[float], dt: float, batch: int = 1,
                  alpha: float = 0.5, gamma: float = 0.0, g_nl: float = 0.0, trap: Sequence[float] = (0, 0, 0),
                  V_grid=None, sigma: float = 0.0, seed: int = 0, id_base: int = 0,
-                 noise_substeps: int = 1) -> rk4ip_problem:
-    """Fill an rk4ip_problem; V_grid is a device float32 tensor [batch][M] or None."""
+                 noise_substeps: int = 1, sigma_V: float = 0.0, conv_K=None) -> rk4ip_problem:
+    """Fill an rk4ip_problem; V_grid is a device float32 tensor [batch][M] or None; conv_K
+    a host float64 array [n] (kept alive on the returned struct until the plan is made)."""
     p = rk4ip_problem()
     nd = len(n)
     p.ndim = nd
@@ -150,6 +152,13 @@ def make_problem(n: Sequence[int], lo: Sequence[float], hi: Sequence[float], dt:
     p.seed = int(seed) & 0xFFFFFFFFFFFFFFFF
     p.id_base = int(id_base) & 0xFFFFFFFF
     p.noise_substeps = int(noise_substeps)
+    p.sigma_V = float(sigma_V)
+    if conv_K is not None:
+        ck = np.ascontiguousarray(conv_K, dtype=np.float64).reshape(-1)
+        p._conv_K = ck
+        p.conv_K = ck.ctypes.data
+    else:
+        p.conv_K = None
     return p
 
 

@@ -5,6 +5,8 @@ import ctypes
 import os
 import re
 
+import numpy as np
+
 import pytest
 
 from paper_1204_4255_amd import rk4ip
@@ -148,3 +150,19 @@ def test_semi_implicit_flag_and_noise_substeps(lib):
         assert (rk4ip.rk4ip_workspace_bytes([_p(noise_substeps=S)], si) > 0) == ok, S
         assert (rk4ip.rk4ip_workspace_bytes([_p(noise_substeps=S)]) > 0) == ok, S
     assert rk4ip.rk4ip_workspace_bytes([p], si | rk4ip.RK4IP_FLAG_FP64_TRANSFORMS) > rk4ip.rk4ip_workspace_bytes([p], si)
+
+
+def test_potential_terms_sizes_and_limits(lib):
+    """The non-local kernel's transform adds n complex64 entries to the workspace; both
+    extra potential terms are taken on 1D groups only, with a finite kernel and sigma_V >= 0."""
+    line = dict(n=(256,), lo=(0,), hi=(1,), dt=0.1)
+    base = rk4ip.rk4ip_workspace_bytes([rk4ip.make_problem(**line)])
+    K = np.ones(256)
+    assert rk4ip.rk4ip_workspace_bytes([rk4ip.make_problem(**line, conv_K=K)]) >= base + 256 * 8
+    assert rk4ip.rk4ip_workspace_bytes([rk4ip.make_problem(**line, sigma_V=0.3)]) == base
+    assert rk4ip.rk4ip_workspace_bytes([rk4ip.make_problem(**line, sigma_V=-0.3)]) == 0
+    bad = K.copy()
+    bad[3] = np.nan
+    assert rk4ip.rk4ip_workspace_bytes([rk4ip.make_problem(**line, conv_K=bad)]) == 0
+    assert rk4ip.rk4ip_workspace_bytes([_p(sigma_V=0.1)]) == 0
+    assert rk4ip.rk4ip_workspace_bytes([_p(conv_K=np.ones(64))]) == 0
