@@ -419,6 +419,37 @@ def form_ark45(torch, rk4ip, workloads):
     return out
 
 
+def form_potential_terms(torch, rk4ip, workloads, steps: int = 100):
+    """The batched 1D workload (2048 x 1024, RK4IP, graph-replayed fused launches) with the
+    potential's extra terms: the real Wiener noise in the potential (sigma_V = 0.01), the
+    non-local potential (a softened Coulomb kernel, strength 0.1), and both, next to the
+    plain step."""
+    import numpy as np
+
+    w = workloads.sgpe1d(nsteps=steps)
+    g = w.groups[0]
+    n, L = g.n[0], g.hi[0] - g.lo[0]
+    d = np.arange(n)
+    d = np.where(d < n // 2, d, d - n) * (L / n)
+    K = 0.1 / np.sqrt(d ** 2 + 1.0)
+    psi0 = rk4ip.field_to_device(w)
+    pts = g.batch * g.M
+    out = {"workload": "2048 x 1024 damped stochastic 1D GPE, RK4IP, 100 steps per timed run"}
+    for name, sv, ck in (("plain", 0.0, None), ("noisy_potential", 0.01, None), ("non_local", 0.0, K),
+                         ("both", 0.01, K)):
+        p = rk4ip.make_problem(g.n, g.lo, g.hi, w.h, batch=g.batch, alpha=g.alpha, gamma=g.gamma, g_nl=g.gnl,
+                               trap=g.trap, sigma=g.sigma, seed=g.seed, id_base=g.id_base, sigma_V=sv, conv_K=ck)
+        plan = rk4ip.Plan([p], flags=rk4ip.RK4IP_FLAG_GRAPH | rk4ip.RK4IP_FLAG_FUSE_1D | rk4ip.RK4IP_FLAG_AUTOTUNE)
+        psi = psi0.clone()
+        plan.run(psi, 40)
+        t = _timed(torch, lambda: (psi.copy_(psi0), plan.run(psi, steps)))
+        out[name] = {"pt_steps_per_s": pts * steps / t, "us_per_step": t / steps * 1e6}
+        plan.destroy()
+    for k in ("noisy_potential", "non_local", "both"):
+        out[k]["cost_vs_plain"] = out["plain"]["pt_steps_per_s"] / out[k]["pt_steps_per_s"]
+    return out
+
+
 def other_workloads(torch, rk4ip, workloads):
     """Throughput of the 1D NLSE (256 points, 1000 steps) and the 2D GPE (512^2, 2000 steps)
     at their full run lengths, graph-replayed with tuned schedules."""
@@ -447,7 +478,7 @@ def measure_forms(torch, rk4ip, workloads):
     for name, fn in (("other_workloads", other_workloads), ("batched_paths", form_batched_paths),
                      ("uneven_batch", form_uneven_batch), ("adjoint", form_adjoint),
                      ("fp64_transforms", form_fp64_transforms), ("semi_implicit", form_semi_implicit),
-                     ("ark45", form_ark45)):
+                     ("ark45", form_ark45), ("potential_terms", form_potential_terms)):
         t0 = time.perf_counter()
         out[name] = fn(torch, rk4ip, workloads)
         progress(f"form {name} done ({time.perf_counter() - t0:.1f} s)")

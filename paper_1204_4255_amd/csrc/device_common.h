@@ -100,6 +100,16 @@ __device__ __forceinline__ void box_muller(uint32_t ra, uint32_t rb, float& rad,
 // rounded product rad * cos, as a single draw).
 __device__ __forceinline__ float2 noise_z(const GroupDev& g, int64_t j, uint32_t inst, int64_t step) {
     const int S = g.noise_sub;
+    if (S == 1) {
+        // one draw per step (the common case; the same value as the loop below)
+        const U4 r = philox4x32_10(noise_counter(j, inst, step), g.seed_lo, g.seed_hi);
+        float rad, c, sn;
+        if (j & 1)
+            box_muller(r.z, r.w, rad, c, sn);
+        else
+            box_muller(r.x, r.y, rad, c, sn);
+        return make_float2(rad * c, rad * sn);
+    }
     float2 acc = make_float2(0.f, 0.f);
     for (int s = 0; s < S; s++) {
         const U4 r = philox4x32_10(noise_counter(j, inst, step * S + s), g.seed_lo, g.seed_hi);
