@@ -113,14 +113,14 @@ typedef struct {
                                 with dt and dt/S sample one Wiener path (strong convergence
                                 tests, Sec. 3.5). A power of two up to 1024; 0 and 1 mean one
                                 draw per step. */
-    /* The potential's extra terms (1D groups; RK4IP_ERR_UNSUPPORTED_SHAPE otherwise):
-     * G gains -i (sigma_V eta + V_c) psi. */
+    /* The potential's extra terms: G gains -i (sigma_V eta + V_c) psi. */
     double sigma_V;          /* real Wiener noise in the potential (the stochastics example,
                                 Sec. 4): eta is a real per-point noise held over the step,
                                 E eta^2 = 1/(dt dV), Philox with counter tag 3 in the top byte
                                 of the last counter word (the real part of the complex normal),
                                 noise substeps as for xi. >= 0; 0 = none. */
-    const double* conv_K;    /* host [n[0]] or NULL: the non-local potential (the non-local
+    const double* conv_K;    /* host [n[0]] or NULL (1D groups only, else
+                                RK4IP_ERR_UNSUPPORTED_SHAPE): the non-local potential (the non-local
                                 example, Sec. 4) V_c(x_i) = dV sum_j K(x_i - x_j) |psi_j|^2 on
                                 the periodic line, with K[d] = K(d dx) for d < n/2 and
                                 K((d - n) dx) above. Read only by rk4ip_plan (and

@@ -254,6 +254,14 @@ k_axis(GroupDev g, int axis, PassArgs args) {
             return make_float2(g.noise_c * zz.x, g.noise_c * zz.y);
         }
     };
+    // the potential G sees at step st: V plus the real Wiener noise in the potential
+    auto pot_at = [&](int m, int64_t st) {
+        float V = potential_at(m);
+        if constexpr (NOISE) {
+            if (g.has_vnoise) V += vnoise(g, tile.j(m), iid, st);  // uniform
+        }
+        return V;
+    };
     const c32 zero = make_float2(0.f, 0.f);
 
     // RK4 stages at the midpoint picture: (a, k1) -> (u, acc) in place
@@ -273,7 +281,7 @@ k_axis(GroupDev g, int axis, PassArgs args) {
         for (int m = 0; m < R; m++) f[0][m] = tile.active ? ld2(ps, tile.b8(m)) : zero;
         if constexpr (MODE == PASS_FIRST) {
 #pragma unroll
-            for (int m = 0; m < R; m++) f[1][m] = hG(g, f[0][m], potential_at(m), noise_at(m, step));
+            for (int m = 0; m < R; m++) f[1][m] = hG(g, f[0][m], pot_at(m, step), noise_at(m, step));
         }
     } else if constexpr (MODE == PASS_U) {
         // u = a + k3 from (a, k1)
@@ -334,7 +342,7 @@ k_axis(GroupDev g, int axis, PassArgs args) {
         // the second transform's barriers, active or not)
 #pragma unroll
         for (int m = 0; m < R; m++) {
-            const float V = potential_at(m);
+            const float V = pot_at(m, step);
             if constexpr (MODE == PASS_SI) {
                 // semi-implicit step at the midpoint picture: m = a + (h/2) G(m) by three
                 // fixed-point iterations from m = a, then the end of the step 2m - a
@@ -351,7 +359,7 @@ k_axis(GroupDev g, int axis, PassArgs args) {
             } else {
                 // end of step n-1: psi_n = D acc + hG(D u)/6, then the start of step n:
                 // (psi_n, h G(psi_n))
-                const c32 k4 = hG(g, f[0][m], V, noise_at(m, step - 1));
+                const c32 k4 = hG(g, f[0][m], pot_at(m, step - 1), noise_at(m, step - 1));
                 const c32 psi_n = make_float2(fmaf(k4.x, 1.0f / 6.0f, f[1][m].x), fmaf(k4.y, 1.0f / 6.0f, f[1][m].y));
                 f[0][m] = psi_n;
                 f[1][m] = hG(g, psi_n, V, noise_at(m, step));
@@ -367,7 +375,7 @@ k_axis(GroupDev g, int axis, PassArgs args) {
     } else if constexpr (MODE == PASS_LAST2) {
 #pragma unroll
         for (int m = 0; m < R; m++) {
-            const c32 k4 = hG(g, f[0][m], potential_at(m), noise_at(m, step));
+            const c32 k4 = hG(g, f[0][m], pot_at(m, step), noise_at(m, step));
             st2(ps, tile.b8(m), make_float2(fmaf(k4.x, 1.0f / 6.0f, f[1][m].x), fmaf(k4.y, 1.0f / 6.0f, f[1][m].y)));
         }
     } else if constexpr (MODE == PASS_AS) {

@@ -81,8 +81,8 @@ int validate(const rk4ip_problem* probs, int nprob, uint32_t flags) {
         if (!std::isfinite(p.alpha) || !std::isfinite(p.gamma) || p.gamma < 0.0) return RK4IP_ERR_INVALID_ARG;
         if (!std::isfinite(p.g_nl) || !std::isfinite(p.sigma) || p.sigma < 0.0) return RK4IP_ERR_INVALID_ARG;
         if (!std::isfinite(p.sigma_V) || p.sigma_V < 0.0) return RK4IP_ERR_INVALID_ARG;
-        // the potential's extra terms are built for 1D groups
-        if ((p.sigma_V != 0.0 || p.conv_K) && p.ndim != 1) return RK4IP_ERR_UNSUPPORTED_SHAPE;
+        // the non-local potential is built for 1D groups
+        if (p.conv_K && p.ndim != 1) return RK4IP_ERR_UNSUPPORTED_SHAPE;
         if (p.conv_K && p.ndim == 1 && p.n[0] >= 1 && p.n[0] <= 4096) {
             for (int64_t d = 0; d < p.n[0]; d++)
                 if (!std::isfinite(p.conv_K[d])) return RK4IP_ERR_INVALID_ARG;

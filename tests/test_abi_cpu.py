@@ -153,8 +153,8 @@ def test_semi_implicit_flag_and_noise_substeps(lib):
 
 
 def test_potential_terms_sizes_and_limits(lib):
-    """The non-local kernel's transform adds n complex64 entries to the workspace; both
-    extra potential terms are taken on 1D groups only, with a finite kernel and sigma_V >= 0."""
+    """The non-local kernel's transform adds n complex64 entries to the workspace and is
+    taken on 1D groups only, with finite values; the noise in the potential needs sigma_V >= 0."""
     line = dict(n=(256,), lo=(0,), hi=(1,), dt=0.1)
     base = rk4ip.rk4ip_workspace_bytes([rk4ip.make_problem(**line)])
     K = np.ones(256)
@@ -164,5 +164,5 @@ def test_potential_terms_sizes_and_limits(lib):
     bad = K.copy()
     bad[3] = np.nan
     assert rk4ip.rk4ip_workspace_bytes([rk4ip.make_problem(**line, conv_K=bad)]) == 0
-    assert rk4ip.rk4ip_workspace_bytes([_p(sigma_V=0.1)]) == 0
+    assert rk4ip.rk4ip_workspace_bytes([_p(sigma_V=0.1)]) == rk4ip.rk4ip_workspace_bytes([_p()])
     assert rk4ip.rk4ip_workspace_bytes([_p(conv_K=np.ones(64))]) == 0
