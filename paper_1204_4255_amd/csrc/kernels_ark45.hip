@@ -55,8 +55,12 @@ __device__ __forceinline__ void propagate_tau(c32 (&f)[F::R], int t, int l, c32*
 #pragma unroll
     for (int m = 0; m < R; m++) d[0][m] = f[m];
     fft_line<F, -1, L, 1>(d, t, l, lds, tw);
-    const float damp = (float)exp(-x.gamma * tau);
-    const float em1 = (float)expm1(-x.gamma * tau);
+    // the damping factor and its distance from 1 (uniform; skipped without damping)
+    float damp = 1.0f, em1 = 0.0f;
+    if (x.gamma != 0.0) {
+        damp = (float)exp(-x.gamma * tau);
+        em1 = (float)expm1(-x.gamma * tau);
+    }
     constexpr float inv_n = 1.0f / (float)N;  // exact power of two
     const double ph0 = 0.5 * x.alpha * x.kscale * x.kscale * tau;
 #pragma unroll
