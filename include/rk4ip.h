@@ -182,7 +182,8 @@ size_t rk4ip_adjoint_workspace_bytes(rk4ip_plan_t plan, int64_t ckpt_every);
 
 /* Adaptive fourth-fifth order Runge-Kutta in the interaction picture (Sec. 3.5: the
  * adaptive Cash-Karp pair, deterministic only; Sec. 3.6: eq. (6)) over [0, t_span], in
- * place on psi, for plans whose groups are all 1D and noise-free. Each instance adapts
+ * place on psi, for plans whose groups are all 1D and noise-free (sigma = sigma_V = 0;
+ * G may include the non-local potential conv_K). Each instance adapts
  * its own step. With the picture origin at the start of each step, stage i at
  * t_n + c_i h is Y_i = psi_n + sum_j a_ij k_j, k_i = e^{-L c_i h} h G(e^{L c_i h} Y_i);
  * the step keeps psi_{n+1} = e^{L h}(psi_n + sum_i b_i k_i) (fifth order) and estimates

@@ -498,8 +498,8 @@ static int check_problem(const ora_problem* p) {
     return 0;
 }
 
-/* The tangent, the adjoint and the adaptive integrator cover G without the noisy or
- * non-local potential. */
+/* The tangent and the adjoint cover G without the noisy or non-local potential (the
+ * adaptive integrator takes the non-local one; it is deterministic, so not the noise). */
 static int plain_potential(const ora_problem* p) { return p->sigma_V == 0.0 && p->convK == NULL; }
 
 /* Advance every instance by nsteps steps, the first one having index step0. */
@@ -937,6 +937,7 @@ static double ck_step_one(const ora_problem* p, const double* V, const cplx* psi
     cplx* k[6];
     for (int i = 0; i < 6; i++) k[i] = (cplx*)malloc(sizeof(cplx) * (size_t)M);
     cplx* y = (cplx*)malloc(sizeof(cplx) * (size_t)M);
+    double* vc = p->convK ? (double*)malloc(sizeof(double) * (size_t)M) : NULL;
     for (int i = 0; i < 6; i++) {
         /* stage input in the picture frame, then moved to the stage time */
         for (int64_t j = 0; j < M; j++) {
@@ -945,10 +946,13 @@ static double ck_step_one(const ora_problem* p, const double* V, const cplx* psi
             y[j] = v;
         }
         if (CK_C[i] != 0.0) apply_exp_L(p, CK_C[i] * h, y);
-        /* h G at the stage time (G without noise: the method is deterministic only) */
+        /* h G at the stage time (G without noise: the method is deterministic only; with
+         * the non-local potential of the stage field when there is a kernel, R11) */
+        if (vc) conv_potential(p, y, vc);
         for (int64_t j = 0; j < M; j++) {
             double m2 = creal(y[j]) * creal(y[j]) + cimag(y[j]) * cimag(y[j]);
-            k[i][j] = h * (-I * (V[j] + p->gnl * m2) * y[j]);
+            double veff = vc ? V[j] + vc[j] : V[j];
+            k[i][j] = h * (-I * (veff + p->gnl * m2) * y[j]);
         }
         /* back to the picture frame */
         if (CK_C[i] != 0.0) apply_exp_L(p, -CK_C[i] * h, k[i]);
@@ -967,11 +971,12 @@ static double ck_step_one(const ora_problem* p, const double* V, const cplx* psi
     apply_exp_L(p, h, out);
     for (int i = 0; i < 6; i++) free(k[i]);
     free(y);
+    free(vc);
     return sqrt(num / den);
 }
 
 static int check_ark45(const ora_problem* p) {
-    if (check_problem(p) || !plain_potential(p)) return -1;
+    if (check_problem(p) || p->sigma_V != 0.0) return -1;
     if (p->sigma != 0.0) return -1; /* deterministic only */
     return 0;
 }

@@ -89,7 +89,7 @@ __device__ __forceinline__ c32 hG_ark(const GroupDev& g, c32 phi, float V, float
 // Stage I (1..5) of a trial step of size h: k_I = e^{-L c_I h} h G(e^{L c_I h} Y_I) with
 // Y_I = y + sum_{j<I} a_Ij k_j. A template per stage keeps every index of k a constant,
 // so the stages stay in registers.
-template <int I, class F, class L>
+template <int I, bool CONV, class F, class L>
 __device__ __forceinline__ void ck_stage(c32 (&k)[6][F::R], const c32 (&y)[F::R], const float (&V)[F::R],
                                          const GroupDev& g, int t, int l, c32* lds, const c32* tw,
                                          const ArkArgs& x, double h, float hf) {
@@ -101,12 +101,21 @@ __device__ __forceinline__ void ck_stage(c32 (&k)[6][F::R], const c32 (&y)[F::R]
         k[I][m] = v;
     }
     propagate_tau<F, L>(k[I], t, l, lds, tw, x, kC[I] * h);  // to the stage time
+    if constexpr (CONV) {
+        // with the non-local potential of the stage field
+        float vc[F::R];
+        conv_V<F, L>(k[I], vc, t, l, lds, tw, g.convK);
 #pragma unroll
-    for (int m = 0; m < F::R; m++) k[I][m] = hG_ark(g, k[I][m], V[m], hf);
+        for (int m = 0; m < F::R; m++) k[I][m] = hG_ark(g, k[I][m], V[m] + vc[m], hf);
+    } else {
+#pragma unroll
+        for (int m = 0; m < F::R; m++) k[I][m] = hG_ark(g, k[I][m], V[m], hf);
+    }
     propagate_tau<F, L>(k[I], t, l, lds, tw, x, -kC[I] * h);  // back to the picture frame
 }
 
-template <int N, int LPB>
+// CONV: G includes the non-local potential (the variant compiled for groups with a kernel).
+template <int N, int LPB, bool CONV>
 __global__ void __launch_bounds__((FFTShape<N, 8>::T * LPB))
     k_line_ark45(GroupDev g, float2* __restrict__ psi, ArkArgs x) {
     using F = FFTShape<N, 8>;
@@ -147,13 +156,20 @@ __global__ void __launch_bounds__((FFTShape<N, 8>::T * LPB))
         const float hf = (float)htry;
         c32 k[6][R];
         // stage 1 (c = 0): h G(psi_n)
+        if constexpr (CONV) {
+            float vc[R];
+            conv_V<F, L>(y, vc, t, l, lds, tw, g.convK);
 #pragma unroll
-        for (int m = 0; m < R; m++) k[0][m] = hG_ark(g, y[m], V[m], hf);
-        ck_stage<1, F, L>(k, y, V, g, t, l, lds, tw, x, htry, hf);
-        ck_stage<2, F, L>(k, y, V, g, t, l, lds, tw, x, htry, hf);
-        ck_stage<3, F, L>(k, y, V, g, t, l, lds, tw, x, htry, hf);
-        ck_stage<4, F, L>(k, y, V, g, t, l, lds, tw, x, htry, hf);
-        ck_stage<5, F, L>(k, y, V, g, t, l, lds, tw, x, htry, hf);
+            for (int m = 0; m < R; m++) k[0][m] = hG_ark(g, y[m], V[m] + vc[m], hf);
+        } else {
+#pragma unroll
+            for (int m = 0; m < R; m++) k[0][m] = hG_ark(g, y[m], V[m], hf);
+        }
+        ck_stage<1, CONV, F, L>(k, y, V, g, t, l, lds, tw, x, htry, hf);
+        ck_stage<2, CONV, F, L>(k, y, V, g, t, l, lds, tw, x, htry, hf);
+        ck_stage<3, CONV, F, L>(k, y, V, g, t, l, lds, tw, x, htry, hf);
+        ck_stage<4, CONV, F, L>(k, y, V, g, t, l, lds, tw, x, htry, hf);
+        ck_stage<5, CONV, F, L>(k, y, V, g, t, l, lds, tw, x, htry, hf);
         // fifth-order result and the embedded difference (weights that vanish are skipped)
         c32 y5[R], dl[R];
 #pragma unroll
@@ -237,7 +253,10 @@ static hipError_t go_ark45(const GroupDev& g, float2* psi, const ArkArgs& x, hip
     constexpr int T = FFTShape<N, 8>::T;
     constexpr int LPB = T >= 64 ? 1 : 64 / T;
     const int64_t blocks = (g.batch + LPB - 1) / LPB;
-    hipLaunchKernelGGL((k_line_ark45<N, LPB>), dim3((unsigned)blocks), dim3(T * LPB), 0, s, g, psi, x);
+    if (g.convK)
+        hipLaunchKernelGGL((k_line_ark45<N, LPB, true>), dim3((unsigned)blocks), dim3(T * LPB), 0, s, g, psi, x);
+    else
+        hipLaunchKernelGGL((k_line_ark45<N, LPB, false>), dim3((unsigned)blocks), dim3(T * LPB), 0, s, g, psi, x);
     return hipGetLastError();
 }
 

@@ -11,24 +11,6 @@ namespace rk4ip {
 // registers and more threads per line). P64: transforms in FP64 (RR = 8), everything
 // else as in the complex64 form. SI: the semi-implicit step (one field: a = D psi, the
 // midpoint iteration, D(2m - a)) instead of RK4IP.
-// The non-local potential of a line (1D groups): V_c = F^{-1}[kh F|f|^2] with kh the
-// kernel's transform times dV/n, so V_c(x_i) = dV sum_j K(x_i - x_j) |f_j|^2 on the
-// periodic line. W: the transform's working type.
-template <class F, class L, class W>
-__device__ __forceinline__ void conv_V(const c32 (&f)[F::R], float (&vc)[F::R], int t, int l, W* lds, const W* tw,
-                                       const float2* __restrict__ kh) {
-    constexpr int R = F::R, T = F::T;
-    W d[1][R];
-#pragma unroll
-    for (int m = 0; m < R; m++) d[0][m] = widen(make_float2(fmaf(f[m].x, f[m].x, f[m].y * f[m].y), 0.f), W{});
-    fft_line<F, -1, L, 1>(d, t, l, lds, tw);
-#pragma unroll
-    for (int m = 0; m < R; m++) d[0][m] = cmul(d[0][m], widen(kh[t + m * T], W{}));
-    fft_line<F, +1, L, 1>(d, t, l, lds, tw);
-#pragma unroll
-    for (int m = 0; m < R; m++) vc[m] = (float)d[0][m].x;
-}
-
 // EXTRA: the variant with the potential's extra terms (1D groups): the real Wiener
 // noise in the potential and the non-local potential. Every G evaluation then needs the
 // non-local potential of its whole stage field, so the stages run in phases (one line

@@ -88,6 +88,24 @@ __device__ __forceinline__ void propagate(c32 (&f)[NF][F::R], int t, int l, V* l
         for (int m = 0; m < F::R; m++) f[q][m] = narrow(cadd(widen(f[q][m], V{}), d[q][m]));
 }
 
+// The non-local potential of a line (1D groups): V_c = F^{-1}[kh F|f|^2] with kh the
+// kernel's transform times dV/n, so V_c(x_i) = dV sum_j K(x_i - x_j) |f_j|^2 on the
+// periodic line. W: the transform's working type.
+template <class F, class L, class W>
+__device__ __forceinline__ void conv_V(const c32 (&f)[F::R], float (&vc)[F::R], int t, int l, W* lds, const W* tw,
+                                       const float2* __restrict__ kh) {
+    constexpr int R = F::R, T = F::T;
+    W d[1][R];
+#pragma unroll
+    for (int m = 0; m < R; m++) d[0][m] = widen(make_float2(fmaf(f[m].x, f[m].x, f[m].y * f[m].y), 0.f), W{});
+    fft_line<F, -1, L, 1>(d, t, l, lds, tw);
+#pragma unroll
+    for (int m = 0; m < R; m++) d[0][m] = cmul(d[0][m], widen(kh[t + m * T], W{}));
+    fft_line<F, +1, L, 1>(d, t, l, lds, tw);
+#pragma unroll
+    for (int m = 0; m < R; m++) vc[m] = (float)d[0][m].x;
+}
+
 // Which lines a workgroup owns and where element e of its line l lives.
 // CONTIG: LINES consecutive lines along axis 0 (threads of a line are adjacent lanes).
 // strided: LINES adjacent x columns of one (instance, outer index) along axis 1 or 2

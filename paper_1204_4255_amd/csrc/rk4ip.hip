@@ -1034,7 +1034,6 @@ int rk4ip_ark45(rk4ip_plan_t plan, void* psi_v, double t_span, double tol, int64
         if (g.p.ndim != 1) return fail(plan, RK4IP_ERR_UNSUPPORTED_SHAPE, "the adaptive integrator takes 1D groups");
         if (g.p.sigma != 0.0 || g.p.sigma_V != 0.0)
             return fail(plan, RK4IP_ERR_INVALID_ARG, "the adaptive integrator is deterministic");
-        if (g.p.conv_K) return fail(plan, RK4IP_ERR_INVALID_ARG, "the adaptive integrator takes the local potential");
     }
     float2* psi = static_cast<float2*>(psi_v);
     for (auto& g : plan->groups) {

@@ -29,9 +29,9 @@ def torch():
     return t
 
 
-def _oprob(g):
+def _oprob(g, convK=None):
     return oracle.Problem(n=g.n, lo=g.lo, hi=g.hi, h=1e-3, batch=1, alpha=g.alpha, gamma=g.gamma, gnl=g.gnl,
-                          trap=g.trap)
+                          trap=g.trap, convK=convK)
 
 
 def _plan(gs, torch):
@@ -52,11 +52,11 @@ def _factor(err, tol):
     return min(5.0, max(0.2, 0.9 * (tol / err) ** 0.2))
 
 
-def _replay_check(g, f0, steps, tol, h_first, span, rejected, slack=0.1):
+def _replay_check(g, f0, steps, tol, h_first, span, rejected, slack=0.1, convK=None):
     """Replay the accepted steps of one instance on the oracle; check each one meets tol
     by the oracle's estimate and that the step changes follow the controller. Returns the
     replayed field."""
-    p = _oprob(g)
+    p = _oprob(g, convK)
     f = np.asarray(f0, complex)[None]
     errs = []
     for h in steps:
@@ -182,6 +182,36 @@ def test_ark45_trap_period_in_samples(torch):
             total += int(stats[b, 0])
     log(f"  50 intervals: {total} accepted steps over 3 instances, worst interval replay rel {worst:.2e}")
     assert worst < 2e-6
+
+
+def test_ark45_with_the_non_local_potential(torch):
+    """Solitons with a softened Coulomb non-local potential (the non-local example of Sec. 4
+    integrated adaptively, as the paper's 1D examples are): replayed on the oracle."""
+    tol, T, h0 = 1e-6, 1.0, 1e-3
+    n, L = 256, 40.0
+    g, f0 = _solitons(n, [0.8, 1.0, 1.3])
+    d_ = np.arange(n)
+    d_ = np.where(d_ < n // 2, d_, d_ - n) * (L / n)
+    K = 0.2 / np.sqrt(d_ ** 2 + 1.0)
+    p = rk4ip.make_problem(g.n, g.lo, g.hi, 1e-3, batch=g.batch, alpha=g.alpha, g_nl=g.gnl, conv_K=K)
+    plan = rk4ip.Plan([p])
+    d = _dev(torch, f0)
+    h = torch.full((g.batch,), h0, dtype=torch.float64, device="cuda")
+    stats, hl = plan.ark45(d, T, tol, h, log_cap=400)
+    stats = stats.cpu().numpy()
+    hl = hl.cpu().numpy()
+    out = d.cpu().numpy().astype(np.complex128).reshape(g.shape)
+    assert np.all(stats[:, 2] == 1)
+    for b in range(g.batch):
+        acc, rej = int(stats[b, 0]), int(stats[b, 1])
+        ref = _replay_check(g, f0[b], hl[b, :acc], tol, h0, T, rej, convK=K)
+        gb = W.Group(n=(n,), lo=g.lo, hi=g.hi, gnl=g.gnl)
+        _, _, ost, _, _ = oracle.ark45(_oprob(gb, K), f0[b:b + 1], T, tol, h0)
+        err = rel(out[b], ref)
+        log(f"  non-local, instance {b}: {acc} accepted, {rej} rejected (oracle {ost[0, 0]}, {ost[0, 1]}); "
+            f"replay rel {err:.2e}")
+        assert err < 1e-5
+        assert abs(acc - ost[0, 0]) <= 2
 
 
 def test_ark45_stops_after_max_attempts(torch):

@@ -112,6 +112,21 @@ def test_delta_kernel_is_the_local_nonlinearity(integrator):
     assert rel(a, b) < 1e-13
 
 
+def test_delta_kernel_is_the_local_nonlinearity_for_the_adaptive_integrator():
+    # the same equivalence through the adaptive Cash-Karp integrator: same steps, same field
+    n = 128
+    g = W.Group(n=(n,), lo=(-8,), hi=(8,), batch=2, gnl=0.5, trap=(1.0, 0, 0))
+    x = g.axis(0)
+    psi = np.pi ** -0.25 * np.exp(-(x[None] - np.array([[0.0], [1.0]])) ** 2 / 2) + 0j
+    K = np.zeros(n)
+    K[0] = 1 / g.dV
+    a, ha, sa, la, _ = oracle.ark45(_prob(g, 1e-3, convK=K), psi, 1.0, 1e-7, 1e-3, log_cap=64)
+    g2 = W.Group(n=(n,), lo=(-8,), hi=(8,), batch=2, gnl=1.5, trap=(1.0, 0, 0))
+    b, hb, sb, lb, _ = oracle.ark45(_prob(g2, 1e-3), psi, 1.0, 1e-7, 1e-3, log_cap=64)
+    assert np.array_equal(sa, sb) and np.allclose(la, lb, rtol=1e-9, equal_nan=True)
+    assert rel(a, b) < 1e-12
+
+
 def test_unsupported_combinations_are_rejected():
     g2 = W.Group(n=(8, 8), lo=(0, 0), hi=(1, 1))
     with pytest.raises(ValueError):
