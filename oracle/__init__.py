@@ -48,6 +48,7 @@ class _Problem(ctypes.Structure):
         ("sigma", ctypes.c_double), ("seed", ctypes.c_uint64), ("id_base", ctypes.c_uint32),
         ("noise_substeps", ctypes.c_uint32), ("Vgrid", ctypes.c_void_p),
         ("sigma_V", ctypes.c_double), ("convK", ctypes.c_void_p),
+        ("basis", ctypes.c_int32), ("pad0", ctypes.c_int32),
     ]
 
 
@@ -124,6 +125,7 @@ class Problem:
     noise_substeps: int = 1    # noise of a step = normalised sum of this many finer draws
     sigma_V: float = 0.0       # real Wiener noise in the potential (reading R10)
     convK: Optional[np.ndarray] = None  # [n] kernel of the non-local potential (R11), 1D
+    basis: int = 0             # 0 Fourier; 1 cosine, 2 sine on a half domain (R12), 1D
     _keep: list = field(default_factory=list, repr=False)
 
     @property
@@ -162,6 +164,7 @@ class Problem:
         else:
             p.Vgrid = None
         p.sigma_V = float(self.sigma_V)
+        p.basis = int(self.basis)
         if self.convK is not None:
             ck = np.ascontiguousarray(self.convK, dtype=np.float64).reshape(-1)
             if ck.size != int(self.n[0]):

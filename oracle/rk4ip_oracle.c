@@ -64,6 +64,11 @@
  *       density): G gains -i V_c psi with V_c(x_i) = dV sum_j K(x_i - x_j) |psi_j|^2 on the
  *       periodic lattice, the kernel given at lattice offsets, K[d] = K(d dx) for
  *       d < n/2 and K((d - n) dx) above (1D lattices).
+ *   R12 Cosine and sine bases (Sec. 3.1: even and odd boundary conditions at both ends of
+ *       a 1D domain): the lattice is cell-centred, x_j = lo + (j + 1/2) dx; the modes are
+ *       cos(k_m (x - lo)) with k_m = pi m / L (m = 0..n-1) and sin(k_m (x - lo)) with
+ *       k_m = pi (m + 1) / L; the transforms are the DCT-II / DST-II sums and their
+ *       inverses (DCT-III / DST-III), so e^{L h/2} multiplies mode m by exp(L(k_m) h/2).
  *   R9  Step control (the paper gives none): a step is accepted when its error estimate is
  *       at most tol; either way the next trial step is h min(5, max(1/5, 0.9 (tol/err)^{1/5}))
  *       (5 when err = 0; 1/5 when err is not finite). A trial step that would pass the end
@@ -100,6 +105,8 @@ typedef struct {
     const double* Vgrid; /* [batch][M] or NULL */
     double sigma_V;      /* real noise in the potential (R10) */
     const double* convK; /* [n] kernel of the non-local potential (R11), 1D, or NULL */
+    int32_t basis;       /* 0 Fourier; 1 cosine, 2 sine (R12), 1D */
+    int32_t pad0;
 } ora_problem;
 
 #define ORA_PI 3.14159265358979323846
@@ -217,9 +224,55 @@ static cplx* make_E(const ora_problem* p, double sign_of_phase) {
     return E;
 }
 
+/* e^{L h/2} in the cosine or sine basis of a 1D half domain (reading R12): the DCT-II or
+ * DST-II sums, the multiply by exp(L(k_m) h/2), and the matching inverse sums (weights
+ * 1, 2, ..., 2 for the cosines and 2, ..., 2, 1 for the sines, over n). The angles
+ * pi q / (2n) come from one table indexed by q = m'(2j + 1) mod 4n. */
+static void apply_D_basis(const ora_problem* p, cplx* f) {
+    int64_t n = p->n[0];
+    double L = p->hi[0] - p->lo[0];
+    int sine = p->basis == 2;
+    double* ct = (double*)malloc(sizeof(double) * 4 * (size_t)n);
+    double* st = (double*)malloc(sizeof(double) * 4 * (size_t)n);
+    for (int64_t q = 0; q < 4 * n; q++) {
+        ct[q] = cos(ORA_PI * (double)q / (2.0 * (double)n));
+        st[q] = sin(ORA_PI * (double)q / (2.0 * (double)n));
+    }
+    cplx* c = (cplx*)malloc(sizeof(cplx) * (size_t)n);
+#pragma omp parallel for schedule(static)
+    for (int64_t m = 0; m < n; m++) {
+        int64_t mm = m + sine;
+        cplx acc = 0.0;
+        for (int64_t j = 0; j < n; j++) {
+            int64_t q = (mm * (2 * j + 1)) % (4 * n);
+            acc += f[j] * (sine ? st[q] : ct[q]);
+        }
+        double k = ORA_PI * (double)mm / L;
+        c[m] = acc * cexp((-I * p->alpha * k * k - p->gamma) * p->h / 2.0);
+    }
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < n; j++) {
+        cplx acc = 0.0;
+        for (int64_t m = 0; m < n; m++) {
+            int64_t mm = m + sine;
+            int64_t q = (mm * (2 * j + 1)) % (4 * n);
+            double w = sine ? (m == n - 1 ? 1.0 : 2.0) : (m == 0 ? 1.0 : 2.0);
+            acc += w * c[m] * (sine ? st[q] : ct[q]);
+        }
+        f[j] = acc / (double)n;
+    }
+    free(ct);
+    free(st);
+    free(c);
+}
+
 /* D f = F^{-1}[E F[f]]: the interaction-picture propagator e^{L h/2} applied by a
  * local multiplication in the spectral basis (Sec. 3.6, last paragraph). */
 static void apply_D(const ora_problem* p, const cplx* E, cplx* f) {
+    if (p->basis) {
+        apply_D_basis(p, f);
+        return;
+    }
     int64_t M = npts(p);
     fft_nd(p, f, -1);
 #pragma omp parallel for schedule(static)
@@ -343,7 +396,7 @@ static void potential(const ora_problem* p, int64_t b, double* V) {
         unflatten(p, j, idx);
         double v = 0.0;
         for (int a = 0; a < p->ndim; a++) {
-            double x = p->lo[a] + (double)idx[a] * dx_of(p, a);
+            double x = p->lo[a] + ((double)idx[a] + (p->basis ? 0.5 : 0.0)) * dx_of(p, a);
             v += 0.5 * p->trap[a] * x * x;
         }
         if (p->Vgrid) v += p->Vgrid[b * M + j];
@@ -495,12 +548,13 @@ static int check_problem(const ora_problem* p) {
     if (p->noise_substeps > 1 && (p->noise_substeps & (p->noise_substeps - 1)) != 0) return -1;
     if (!isfinite(p->sigma_V)) return -1;
     if (p->convK && p->ndim != 1) return -1;
+    if (p->basis < 0 || p->basis > 2 || (p->basis && (p->ndim != 1 || p->convK))) return -1;
     return 0;
 }
 
 /* The tangent and the adjoint cover G without the noisy or non-local potential (the
  * adaptive integrator takes the non-local one; it is deterministic, so not the noise). */
-static int plain_potential(const ora_problem* p) { return p->sigma_V == 0.0 && p->convK == NULL; }
+static int plain_potential(const ora_problem* p) { return p->sigma_V == 0.0 && p->convK == NULL && !p->basis; }
 
 /* Advance every instance by nsteps steps, the first one having index step0. */
 static int run_steps(const ora_problem* p, cplx* psi, int64_t step0, int64_t nsteps) {
@@ -976,7 +1030,7 @@ static double ck_step_one(const ora_problem* p, const double* V, const cplx* psi
 }
 
 static int check_ark45(const ora_problem* p) {
-    if (check_problem(p) || p->sigma_V != 0.0) return -1;
+    if (check_problem(p) || p->sigma_V != 0.0 || p->basis) return -1;
     if (p->sigma != 0.0) return -1; /* deterministic only */
     return 0;
 }
@@ -1049,6 +1103,10 @@ int ora_ark45(const ora_problem* p, cplx* psi, double t_span, double tol, int64_
 }
 
 static void apply_D_dense(const ora_problem* p, const cplx* E, cplx* f) {
+    if (p->basis) {
+        apply_D_basis(p, f);  /* already a dense sum */
+        return;
+    }
     int64_t M = npts(p);
     cplx* F = malloc(sizeof(cplx) * (size_t)M);
     /* forward multi-D DFT by direct summation over all lattice points */

@@ -20,6 +20,7 @@ typedef struct {
     const double* Vgrid;
     double sigma_V;
     const double* convK;
+    int32_t basis, pad0;
 } ora_problem;
 
 void ora_dft(const cplx* in, cplx* out, int64_t n, int sign);
@@ -126,6 +127,15 @@ static void exercise(int ndim, const int64_t* n, int64_t batch, int si) {
     if (ora_tangent(&p, psi, dpsi, dV, 2, 3) == 0 || ora_adjoint(&p, psi, 1, 5, 2, lam, g, gV) == 0) fails++;
     p.sigma_V = 0.0;
     p.convK = NULL;
+    if (ndim == 1) {
+        /* the cosine and sine bases of a half domain */
+        for (int basis = 1; basis <= 2; basis++) {
+            p.basis = basis;
+            CHECK(ora_step(&p, psi, 7));
+            CHECK(ora_run(&p, psi, 10, 3, 0, NULL, NULL, 0));
+        }
+        p.basis = 0;
+    }
     free(K), free(eta);
     /* the adaptive integrator is deterministic: it refuses noise, then runs without */
     double* hs = malloc(sizeof(double) * batch);
