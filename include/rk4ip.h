@@ -95,7 +95,16 @@ typedef struct rk4ip_plan_s* rk4ip_plan_t;
 /* One group of same-shape instances (paths or problem instances). */
 typedef struct {
     int32_t ndim;            /* 1, 2 or 3 */
-    int32_t reserved0;       /* must be 0 */
+    int32_t basis;           /* 0: Fourier (periodic). 1D only: 1 cosine, 2 sine basis of a half
+                                domain (Sec. 3.1: even / odd boundary conditions at both ends),
+                                on the cell centres x_j = lo + (j + 1/2)(hi - lo)/n with modes
+                                cos / sin(k_m (x - lo)), k_m = pi m / (hi - lo) (cosine,
+                                m = 0..n-1) or pi (m + 1) / (hi - lo) (sine). The step runs on
+                                the even / odd extension of the line (2n <= 4096, 2048 with
+                                FP64 transforms), one step per launch (RK4IP_FLAG_FUSE_1D does
+                                not fuse it); not with conv_K. Plans holding such a group
+                                take rk4ip_step and rk4ip_run without samples; the other
+                                entry points return RK4IP_ERR_INVALID_ARG. */
     int64_t n[3];            /* points per axis, axis 0 = x (contiguous); unused axes = 1 */
     double lo[3], hi[3];     /* periodic domain [lo, hi) per axis */
     int64_t batch;           /* instances in this group, >= 1 */

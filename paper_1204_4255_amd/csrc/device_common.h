@@ -42,6 +42,8 @@ struct GroupDev {
     int has_vnoise;          // real Wiener noise in the potential (1D groups)
     float vnoise_c;          // sigma_V / sqrt(h dV): multiplies a unit real normal
     const float2* convK;     // [n] (FFT of the non-local kernel) dV / n (1D groups), or null
+    int basis;               // 1D: 0 Fourier; 1 cosine, 2 sine (n[0] is then the length of the
+                             // even / odd extension, twice the stored points)
 };
 
 // ---------------------------------------------------------------- Philox4x32-10

@@ -34,16 +34,35 @@ __global__ void __launch_bounds__((FFTShape<N, RR>::T * LPB))
     const int l = threadIdx.x / T;
     const int64_t inst = (int64_t)blockIdx.x * LPB + l;
     const bool active = inst < g.batch;
-    float2* p = psi + g.offset + inst * N;
+    // A cosine or sine group stores the n = N/2 cell centres of a half domain; the line
+    // here is its even or odd extension: element e < n is the mirror image of point
+    // n - 1 - e (negated for the sine basis), element e >= n is point e - n.
+    const int NM = g.basis ? N / 2 : N;
+    auto fold = [&](int e, int& j, float& sg) {
+        j = e;
+        sg = 1.0f;
+        if (g.basis) {
+            if (e < NM) {
+                j = NM - 1 - e;
+                if (g.basis == 2) sg = -1.0f;
+            } else {
+                j = e - NM;
+            }
+        }
+    };
+    float2* p = psi + g.offset + inst * NM;
 
     c32 f[2][R];
     float V[R];
 #pragma unroll
     for (int m = 0; m < R; m++) {
-        const int e = t + m * T;
-        f[0][m] = active ? p[e] : make_float2(0.f, 0.f);
-        float v = trap_V(g, e, 0, 0);
-        if (g.Vgrid && active) v += g.Vgrid[inst * N + e];
+        int j;
+        float sg;
+        fold(t + m * T, j, sg);
+        const float2 v0 = active ? p[j] : make_float2(0.f, 0.f);
+        f[0][m] = make_float2(sg * v0.x, sg * v0.y);
+        float v = trap_V(g, j, 0, 0);
+        if (g.Vgrid && active) v += g.Vgrid[inst * NM + j];
         V[m] = v;
     }
     const uint32_t iid = g.id_base + (uint32_t)inst;
@@ -54,8 +73,11 @@ __global__ void __launch_bounds__((FFTShape<N, RR>::T * LPB))
 #pragma unroll
         for (int m = 0; m < R; m++) {
             if constexpr (NOISE) {
-                const float2 z = noise_z(g, t + m * T, iid, step);
-                nz[m] = make_float2(g.noise_c * z.x, g.noise_c * z.y);
+                int j;
+                float sg;
+                fold(t + m * T, j, sg);
+                const float2 z = noise_z(g, j, iid, step);  // odd in the sine basis
+                nz[m] = make_float2(sg * (g.noise_c * z.x), sg * (g.noise_c * z.y));
             } else {
                 nz[m] = make_float2(0.f, 0.f);
             }
@@ -68,7 +90,12 @@ __global__ void __launch_bounds__((FFTShape<N, RR>::T * LPB))
             if constexpr (NOISE) {
                 if (g.has_vnoise) {
 #pragma unroll
-                    for (int m = 0; m < R; m++) Vs[m] += vnoise(g, t + m * T, iid, step);
+                    for (int m = 0; m < R; m++) {
+                        int j;
+                        float sg;
+                        fold(t + m * T, j, sg);
+                        Vs[m] += vnoise(g, j, iid, step);  // a potential: even in both bases
+                    }
                 }
             }
             const bool conv = g.convK != nullptr;  // uniform
@@ -177,7 +204,10 @@ __global__ void __launch_bounds__((FFTShape<N, RR>::T * LPB))
     }
     if (active) {
 #pragma unroll
-        for (int m = 0; m < R; m++) p[t + m * T] = f[0][m];
+        for (int m = 0; m < R; m++) {
+            const int e = t + m * T;
+            if (g.basis == 0 || e >= NM) p[g.basis ? e - NM : e] = f[0][m];  // the half domain
+        }
     }
 }
 

@@ -30,6 +30,21 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
 
+// Length of the transform along axis a: a cosine / sine group runs the even / odd
+// extension of its half domain, twice the stored points.
+int64_t transform_len(const rk4ip_problem& p, int a) { return (p.basis && a == 0) ? 2 * p.n[0] : p.n[a]; }
+
+// The problem seen by the transforms: for a cosine / sine group, the extension's length
+// and a domain twice as long (so k_m = pi m / L).
+rk4ip_problem transform_problem(const rk4ip_problem& p) {
+    rk4ip_problem q = p;
+    if (p.basis) {
+        q.n[0] = 2 * p.n[0];
+        q.hi[0] = p.hi[0] + (p.hi[0] - p.lo[0]);
+    }
+    return q;
+}
+
 int ilog2i(int64_t v) {
     int r = 0;
     while ((int64_t(1) << r) < v) r++;
@@ -74,7 +89,9 @@ int validate(const rk4ip_problem* probs, int nprob, uint32_t flags) {
     int64_t ninst = 0;
     for (int i = 0; i < nprob; i++) {
         const rk4ip_problem& p = probs[i];
-        if (p.reserved0 != 0) return RK4IP_ERR_INVALID_ARG;
+        if (p.basis < 0 || p.basis > 2) return RK4IP_ERR_INVALID_ARG;
+        // the cosine and sine bases: 1D half domains, local potential
+        if (p.basis && (p.ndim != 1 || p.conv_K)) return RK4IP_ERR_UNSUPPORTED_SHAPE;
         if (p.noise_substeps > kMaxNoiseSubsteps || (p.noise_substeps > 1 && !is_pow2(p.noise_substeps)))
             return RK4IP_ERR_INVALID_ARG;
         if (!(p.dt > 0.0) || !std::isfinite(p.dt) || p.dt != dt0) return RK4IP_ERR_INVALID_ARG;
@@ -95,7 +112,7 @@ int validate(const rk4ip_problem* probs, int nprob, uint32_t flags) {
         int64_t M = 1;
         for (int a = 0; a < 3; a++) {
             if (a < p.ndim) {
-                if (!is_pow2(p.n[a]) || p.n[a] < 8 || p.n[a] > nmax) return RK4IP_ERR_UNSUPPORTED_SHAPE;
+                if (!is_pow2(p.n[a]) || p.n[a] < 8 || transform_len(p, a) > nmax) return RK4IP_ERR_UNSUPPORTED_SHAPE;
                 if (!(p.hi[a] > p.lo[a]) || !std::isfinite(p.hi[a]) || !std::isfinite(p.lo[a]))
                     return RK4IP_ERR_INVALID_ARG;
                 if (!std::isfinite(p.trap[a])) return RK4IP_ERR_INVALID_ARG;
@@ -122,15 +139,15 @@ Layout layout(const rk4ip_problem* probs, int nprob, uint32_t flags, std::vector
         const rk4ip_problem& p = probs[i];
         for (int a = 0; a < p.ndim; a++) {
             size_t e = off;
-            off = align_up(off + sizeof(float2) * (size_t)p.n[a]);
+            off = align_up(off + sizeof(float2) * (size_t)transform_len(p, a));
             size_t t = off;
-            off = align_up(off + sizeof(float2) * (size_t)p.n[a]);
+            off = align_up(off + sizeof(float2) * (size_t)transform_len(p, a));
             size_t e64 = 0, t64 = 0;
             if (f64) {
                 e64 = off;
-                off = align_up(off + sizeof(double2) * (size_t)p.n[a]);
+                off = align_up(off + sizeof(double2) * (size_t)transform_len(p, a));
                 t64 = off;
-                off = align_up(off + sizeof(double2) * (size_t)p.n[a]);
+                off = align_up(off + sizeof(double2) * (size_t)transform_len(p, a));
             }
             if (gh) {
                 (*gh)[i].tab_off[a] = e;
@@ -578,7 +595,9 @@ int enqueue_lines(rk4ip_plan_t plan, hipStream_t stream, float2* psi, int64_t st
     for (size_t gi = 0; gi < plan->groups.size(); gi++) {
         auto& g = plan->groups[gi];
         if (g.p.ndim != 1 || nsteps <= 0) continue;
-        if (allow_fuse && (plan->flags & RK4IP_FLAG_FUSE_1D)) {
+        // a cosine / sine group takes one step per launch: each step rebuilds the even / odd
+        // extension from the stored half domain, so it stays exactly symmetric
+        if (allow_fuse && (plan->flags & RK4IP_FLAG_FUSE_1D) && !g.p.basis) {
             rc = timed_launch(plan, stream, (int)gi, 0, capturing, [&] {
                 return rk4ip::launch_line_step(g.d, psi, (int)nsteps, step_off, step_base, plan->f64,
                                                 plan->sched[gi][0].radix, plan->si, stream);
@@ -678,7 +697,17 @@ int device_ok(rk4ip_plan_t plan) {
     return RK4IP_OK;
 }
 
+// Does the plan hold a cosine / sine group? Only the step (rk4ip_step, rk4ip_run without
+// samples) takes those: the other kernels index the lattice as a Fourier line.
+bool has_basis_group(rk4ip_plan_t plan) {
+    for (auto& g : plan->groups)
+        if (g.p.basis) return true;
+    return false;
+}
+
 int do_diagnostics(rk4ip_plan_t plan, const float2* psi, double* out) {
+    if (has_basis_group(plan))
+        return fail(plan, RK4IP_ERR_INVALID_ARG, "diagnostics take Fourier groups only");
     for (auto& g : plan->groups) {
         const double* parts[3] = {nullptr, nullptr, nullptr};
         for (int a = 0; a < g.p.ndim; a++) {
@@ -829,18 +858,21 @@ int rk4ip_plan(const rk4ip_problem* probs, int nprob, void* workspace, size_t ws
         g.M = 1;
         g.dV = 1.0;
         for (int a = 0; a < 3; a++) {
-            d.n[a] = (int)p.n[a];
-            d.log2n[a] = ilog2i(p.n[a]);
+            const int64_t nt = transform_len(p, a);
+            d.n[a] = (int)nt;
+            d.log2n[a] = ilog2i(nt);
             g.M *= p.n[a];
             if (a < p.ndim) {
                 const double dx = (p.hi[a] - p.lo[a]) / (double)p.n[a];
                 g.dV *= dx;
-                d.lo[a] = (float)p.lo[a];
+                // a cosine / sine group's points are the cell centres lo + (j + 1/2) dx
+                d.lo[a] = (float)(p.basis ? p.lo[a] + 0.5 * dx : p.lo[a]);
                 d.dx[a] = (float)dx;
                 d.half_trap[a] = (float)(0.5 * p.trap[a]);
-                d.inv_n[a] = (float)(1.0 / (double)p.n[a]);
+                d.inv_n[a] = (float)(1.0 / (double)nt);
             }
         }
+        d.basis = p.basis;
         d.M = g.M;
         d.batch = p.batch;
         d.offset = offset;
@@ -860,7 +892,7 @@ int rk4ip_plan(const rk4ip_problem* probs, int nprob, void* workspace, size_t ws
         for (int a = 0; a < p.ndim; a++) {
             std::vector<float2> E, tw;
             std::vector<double2> E64, tw64;
-            build_tables(p, a, E, tw, plan->f64 ? &E64 : nullptr, plan->f64 ? &tw64 : nullptr);
+            build_tables(transform_problem(p), a, E, tw, plan->f64 ? &E64 : nullptr, plan->f64 ? &tw64 : nullptr);
             hipError_t e1 = hipMemcpy(plan->ws + g.tab_off[a], E.data(), sizeof(float2) * E.size(), hipMemcpyHostToDevice);
             hipError_t e2 = hipMemcpy(plan->ws + g.tw_off[a], tw.data(), sizeof(float2) * tw.size(), hipMemcpyHostToDevice);
             if (e1 == hipSuccess && e2 == hipSuccess && plan->f64) {
@@ -1012,6 +1044,7 @@ int rk4ip_run(rk4ip_plan_t plan, void* psi_v, int64_t step0, int64_t nsteps, int
 
 int rk4ip_overlap(rk4ip_plan_t plan, int group, const void* phi, const void* psi, double* out) {
     if (!plan || !phi || !psi || !out || group < 0 || group >= (int)plan->groups.size()) return RK4IP_ERR_INVALID_ARG;
+    if (plan->groups[group].p.basis) return fail(plan, RK4IP_ERR_INVALID_ARG, "overlaps take Fourier groups only");
     const GroupHost& g = plan->groups[group];
     HIPCHK(plan, rk4ip::launch_overlap(g.d, g.dV, static_cast<const float2*>(phi), static_cast<const float2*>(psi), out,
                                        plan->stream));
@@ -1020,6 +1053,7 @@ int rk4ip_overlap(rk4ip_plan_t plan, int group, const void* phi, const void* psi
 
 int rk4ip_moments(rk4ip_plan_t plan, int group, const void* psi, double* mean, double* var) {
     if (!plan || !psi || !mean || !var || group < 0 || group >= (int)plan->groups.size()) return RK4IP_ERR_INVALID_ARG;
+    if (plan->groups[group].p.basis) return fail(plan, RK4IP_ERR_INVALID_ARG, "moments take Fourier groups only");
     const GroupHost& g = plan->groups[group];
     HIPCHK(plan, rk4ip::launch_moments(g.d, static_cast<const float2*>(psi), mean, var, plan->stream));
     return RK4IP_OK;
@@ -1034,6 +1068,7 @@ int rk4ip_ark45(rk4ip_plan_t plan, void* psi_v, double t_span, double tol, int64
         if (g.p.ndim != 1) return fail(plan, RK4IP_ERR_UNSUPPORTED_SHAPE, "the adaptive integrator takes 1D groups");
         if (g.p.sigma != 0.0 || g.p.sigma_V != 0.0)
             return fail(plan, RK4IP_ERR_INVALID_ARG, "the adaptive integrator is deterministic");
+        if (g.p.basis) return fail(plan, RK4IP_ERR_INVALID_ARG, "the adaptive integrator takes Fourier groups");
     }
     float2* psi = static_cast<float2*>(psi_v);
     for (auto& g : plan->groups) {
@@ -1068,6 +1103,7 @@ int rk4ip_adjoint(rk4ip_plan_t plan, const void* ckpt_v, int64_t step0, int64_t 
         return RK4IP_ERR_INVALID_ARG;
     if ((reinterpret_cast<uintptr_t>(adj_ws) % kAlign) != 0) return RK4IP_ERR_INVALID_ARG;
     if (plan->si) return fail(plan, RK4IP_ERR_INVALID_ARG, "the adjoint covers the RK4 step only");
+    if (has_basis_group(plan)) return fail(plan, RK4IP_ERR_INVALID_ARG, "the adjoint takes Fourier groups only");
     for (auto& g : plan->groups)
         if (g.p.sigma_V != 0.0 || g.p.conv_K)
             return fail(plan, RK4IP_ERR_INVALID_ARG, "the adjoint covers the local, noise-free potential only");
@@ -1245,14 +1281,14 @@ int rk4ip_debug_fft(rk4ip_plan_t plan, int group, int axis, const void* in, void
     if (!plan || !in || !out || nlines < 0 || (sign != -1 && sign != 1)) return RK4IP_ERR_INVALID_ARG;
     if (group < 0 || group >= (int)plan->groups.size()) return RK4IP_ERR_INVALID_ARG;
     const GroupHost& g = plan->groups[group];
-    if (axis < 0 || axis >= g.p.ndim) return RK4IP_ERR_INVALID_ARG;
+    if (axis < 0 || axis >= g.p.ndim || g.p.basis) return RK4IP_ERR_INVALID_ARG;
     HIPCHK(plan, rk4ip::launch_fft_lines(static_cast<const float2*>(in), static_cast<float2*>(out), g.p.n[axis], nlines,
                                          sign, g.d.tw[axis], plan->stream));
     return RK4IP_OK;
 }
 
 int rk4ip_debug_apply_D(rk4ip_plan_t plan, void* psi, int adjoint) {
-    if (!plan || !psi) return RK4IP_ERR_INVALID_ARG;
+    if (!plan || !psi || has_basis_group(plan)) return RK4IP_ERR_INVALID_ARG;
     rk4ip::PassArgs pa{};
     pa.psi = static_cast<float2*>(psi);
     pa.adj = adjoint ? 1 : 0;

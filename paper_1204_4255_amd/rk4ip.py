@@ -33,6 +33,7 @@ RK4IP_FLAG_AUTOTUNE = 0x2
 RK4IP_FLAG_FUSE_1D = 0x4
 RK4IP_FLAG_FP64_TRANSFORMS = 0x8
 RK4IP_FLAG_SEMI_IMPLICIT = 0x10
+BASIS_FOURIER, BASIS_COSINE, BASIS_SINE = 0, 1, 2
 
 # every symbol include/rk4ip.h declares
 EXPORTS = [
@@ -52,7 +53,7 @@ class Rk4ipError(RuntimeError):
 
 class rk4ip_problem(ctypes.Structure):
     _fields_ = [
-        ("ndim", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+        ("ndim", ctypes.c_int32), ("basis", ctypes.c_int32),
         ("n", ctypes.c_int64 * 3), ("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3),
         ("batch", ctypes.c_int64), ("dt", ctypes.c_double), ("alpha", ctypes.c_double),
         ("gamma", ctypes.c_double), ("g_nl", ctypes.c_double), ("trap", ctypes.c_double * 3),
@@ -134,7 +135,7 @@ def _check(status: int, plan_handle=None, what: str = "rk4ip call"):
 def make_problem(n: Sequence[int], lo: Sequence[float], hi: Sequence[float], dt: float, batch: int = 1,
                  alpha: float = 0.5, gamma: float = 0.0, g_nl: float = 0.0, trap: Sequence[float] = (0, 0, 0),
                  V_grid=None, sigma: float = 0.0, seed: int = 0, id_base: int = 0,
-                 noise_substeps: int = 1, sigma_V: float = 0.0, conv_K=None) -> rk4ip_problem:
+                 noise_substeps: int = 1, sigma_V: float = 0.0, conv_K=None, basis: int = 0) -> rk4ip_problem:
     """Fill an rk4ip_problem; V_grid is a device float32 tensor [batch][M] or None; conv_K
     a host float64 array [n] (kept alive on the returned struct until the plan is made)."""
     p = rk4ip_problem()
@@ -153,6 +154,7 @@ def make_problem(n: Sequence[int], lo: Sequence[float], hi: Sequence[float], dt:
     p.id_base = int(id_base) & 0xFFFFFFFF
     p.noise_substeps = int(noise_substeps)
     p.sigma_V = float(sigma_V)
+    p.basis = int(basis)
     if conv_K is not None:
         ck = np.ascontiguousarray(conv_K, dtype=np.float64).reshape(-1)
         p._conv_K = ck

@@ -91,7 +91,7 @@ def test_plan_argument_checks_without_device(lib):
     mixed = rk4ip.problems_array([_p(), _p(dt=2e-3)])
     assert lib.rk4ip_plan(mixed, 2, ctypes.c_void_p(256), 1 << 30, None, 0, ctypes.byref(h)) == rk4ip.RK4IP_ERR_INVALID_ARG
     bad = _p()
-    bad.reserved0 = 1
+    bad.basis = 3
     assert rk4ip.rk4ip_workspace_bytes([bad]) == 0
     ids = _p(batch=10)
     ids.id_base = 0xFFFFFFFF - 3
@@ -166,3 +166,20 @@ def test_potential_terms_sizes_and_limits(lib):
     assert rk4ip.rk4ip_workspace_bytes([rk4ip.make_problem(**line, conv_K=bad)]) == 0
     assert rk4ip.rk4ip_workspace_bytes([_p(sigma_V=0.1)]) == rk4ip.rk4ip_workspace_bytes([_p()])
     assert rk4ip.rk4ip_workspace_bytes([_p(conv_K=np.ones(64))]) == 0
+
+
+def test_cosine_and_sine_bases_sizes_and_limits(lib):
+    """A cosine / sine group keeps transform tables of its extension (twice the stored
+    points) and is taken on 1D lattices whose extension fits the line kernel."""
+    line = dict(lo=(0,), hi=(7,), dt=0.1)
+    f = rk4ip.rk4ip_workspace_bytes([rk4ip.make_problem(n=(256,), **line)])
+    for basis in (1, 2):
+        c = rk4ip.rk4ip_workspace_bytes([rk4ip.make_problem(n=(256,), basis=basis, **line)])
+        assert c >= f + 2 * 256 * 8  # the two tables doubled
+        assert rk4ip.rk4ip_workspace_bytes([rk4ip.make_problem(n=(2048,), basis=basis, **line)]) > 0
+        assert rk4ip.rk4ip_workspace_bytes([rk4ip.make_problem(n=(4096,), basis=basis, **line)]) == 0
+        assert rk4ip.rk4ip_workspace_bytes([rk4ip.make_problem(n=(2048,), basis=basis, **line)],
+                                           rk4ip.RK4IP_FLAG_FP64_TRANSFORMS) == 0
+        assert rk4ip.rk4ip_workspace_bytes([_p(basis=basis)]) == 0
+        assert rk4ip.rk4ip_workspace_bytes([rk4ip.make_problem(n=(64,), basis=basis, conv_K=np.ones(64),
+                                                               **line)]) == 0
