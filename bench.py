@@ -450,6 +450,35 @@ def form_potential_terms(torch, rk4ip, workloads, steps: int = 100):
     return out
 
 
+def form_bases(torch, rk4ip, workloads, steps: int = 100):
+    """The cosine basis on a half domain next to the Fourier basis on the full one (the
+    half-interval example of Sec. 4, batched): 2048 lines of the trapped 1D GPE, 512
+    cosine points on (0, 8) against 1024 Fourier points on (-8, 8), graph-replayed."""
+    import numpy as np
+
+    out = {"workload": "2048 lines, trapped 1D GPE (g = 1), 512 cosine points on (0, 8) vs 1024 Fourier points "
+                       "on (-8, 8), 100 steps"}
+    B, n, L, h = 2048, 512, 8.0, 1e-3
+    dx = L / n
+    x = (np.arange(n) + 0.5) * dx
+    f_half = np.broadcast_to(np.pi ** -0.25 * np.exp(-x ** 2 / 2), (B, n)).astype(np.complex64)
+    f_full = np.concatenate([f_half[:, ::-1], f_half], axis=1)
+    for name, prob, f in (
+            ("cosine_half", rk4ip.make_problem((n,), (0.0,), (L,), h, batch=B, g_nl=1.0, trap=(1.0, 0, 0), basis=1),
+             f_half),
+            ("fourier_full", rk4ip.make_problem((2 * n,), (-L + dx / 2,), (L + dx / 2,), h, batch=B, g_nl=1.0,
+                                                trap=(1.0, 0, 0)), f_full)):
+        plan = rk4ip.Plan([prob], flags=rk4ip.RK4IP_FLAG_GRAPH | rk4ip.RK4IP_FLAG_AUTOTUNE)
+        psi0 = torch.tensor(f.reshape(-1), device="cuda")
+        psi = psi0.clone()
+        plan.run(psi, 40)
+        t = _timed(torch, lambda: (psi.copy_(psi0), plan.run(psi, steps)))
+        out[name] = {"us_per_step": t / steps * 1e6, "stored_points": int(psi0.numel())}
+        plan.destroy()
+    out["time_ratio_half_to_full"] = out["cosine_half"]["us_per_step"] / out["fourier_full"]["us_per_step"]
+    return out
+
+
 def other_workloads(torch, rk4ip, workloads):
     """Throughput of the 1D NLSE (256 points, 1000 steps) and the 2D GPE (512^2, 2000 steps)
     at their full run lengths, graph-replayed with tuned schedules."""
@@ -478,7 +507,7 @@ def measure_forms(torch, rk4ip, workloads):
     for name, fn in (("other_workloads", other_workloads), ("batched_paths", form_batched_paths),
                      ("uneven_batch", form_uneven_batch), ("adjoint", form_adjoint),
                      ("fp64_transforms", form_fp64_transforms), ("semi_implicit", form_semi_implicit),
-                     ("ark45", form_ark45), ("potential_terms", form_potential_terms)):
+                     ("ark45", form_ark45), ("potential_terms", form_potential_terms), ("bases", form_bases)):
         t0 = time.perf_counter()
         out[name] = fn(torch, rk4ip, workloads)
         progress(f"form {name} done ({time.perf_counter() - t0:.1f} s)")
