@@ -141,13 +141,14 @@ def markdown(out: dict) -> str:
 
 
 COMMANDS = """    cd /tmp && export TMPDIR=/tmp
-    export RK4IP_TUNE_CACHE=/root/repo/gpurun_out/tune_gpe3d_256.json
-    python3 /root/repo/bench.py --no-cpu-baseline --no-forms --steps 20 --warmup 5
-    rocprofv3 --kernel-trace --stats --output-format csv -d /root/repo/gpurun_out/prof -o kt -- python3 /root/repo/bench.py --no-cpu-baseline --no-forms --steps 50 --warmup 5 --calibrate-copy
-    rocprofv3 --pmc FETCH_SIZE --output-format csv -d /root/repo/gpurun_out/prof -o fetch -- python3 /root/repo/bench.py --no-cpu-baseline --no-forms --steps 3 --warmup 1 --profile-steps 2 --calibrate-copy
-    rocprofv3 --pmc WRITE_SIZE --output-format csv -d /root/repo/gpurun_out/prof -o write -- python3 /root/repo/bench.py --no-cpu-baseline --no-forms --steps 3 --warmup 1 --profile-steps 2 --calibrate-copy
-    rocprofv3 --pmc SQ_INSTS_VALU SQ_INSTS_LDS SQ_LDS_BANK_CONFLICT SQ_WAVES --output-format csv -d /root/repo/gpurun_out/prof -o valu -- python3 /root/repo/bench.py --no-cpu-baseline --no-forms --steps 3 --warmup 1 --profile-steps 2
-    python3 -m paper_1204_4255_amd.rocprof_summary /root/repo/gpurun_out/prof profiles"""
+    R=<repository root>; OUT=<a writable output directory>
+    export RK4IP_TUNE_CACHE=$OUT/tune_gpe3d_256.json
+    python3 $R/bench.py --no-cpu-baseline --no-forms --steps 20 --warmup 5
+    rocprofv3 --kernel-trace --stats --output-format csv -d $OUT/prof -o kt -- python3 $R/bench.py --no-cpu-baseline --no-forms --steps 50 --warmup 5 --calibrate-copy
+    rocprofv3 --pmc FETCH_SIZE --output-format csv -d $OUT/prof -o fetch -- python3 $R/bench.py --no-cpu-baseline --no-forms --steps 3 --warmup 1 --profile-steps 2 --calibrate-copy
+    rocprofv3 --pmc WRITE_SIZE --output-format csv -d $OUT/prof -o write -- python3 $R/bench.py --no-cpu-baseline --no-forms --steps 3 --warmup 1 --profile-steps 2 --calibrate-copy
+    rocprofv3 --pmc SQ_INSTS_VALU SQ_INSTS_LDS SQ_LDS_BANK_CONFLICT SQ_WAVES --output-format csv -d $OUT/prof -o valu -- python3 $R/bench.py --no-cpu-baseline --no-forms --steps 3 --warmup 1 --profile-steps 2
+    cd $R && python3 -m paper_1204_4255_amd.rocprof_summary $OUT/prof profiles"""
 
 COPY_GBPS = 5900.0  # a plain elementwise copy of 256 MiB in and out on this GPU
 
