@@ -31,6 +31,7 @@ PASS_BYTES = {"FIRST": 24, "D2": 32, "LF": 32, "XF": 32, "LAST2": 24, "line_step
               # the semi-implicit step works on psi in place: every pass reads and writes it once
               "D1": 16, "D1x2": 16, "SI": 16, "line_si": 16}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_gpe3d_256.json")
+TRAFFIC_FILE_SI = os.path.join(ROOT, "profiles", "traffic_gpe3d_256_semi_implicit.json")
 
 
 def kernel_source_hash() -> str:
@@ -39,11 +40,11 @@ def kernel_source_hash() -> str:
     return source_hash()
 
 
-def measured_counters(kernel: str):
+def measured_counters(kernel: str, path: str = TRAFFIC_FILE):
     """Counter record of `kernel` from the committed rocprofv3 summary, or None when it is
     missing or the kernels changed since the counters were taken."""
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(path) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
         return None
@@ -52,9 +53,9 @@ def measured_counters(kernel: str):
     return t.get("kernels", {}).get(kernel)
 
 
-def measured_traffic(kernel: str):
+def measured_traffic(kernel: str, path: str = TRAFFIC_FILE):
     """HBM bytes per launch of `kernel` (scaled FETCH_SIZE + WRITE_SIZE), or None."""
-    rec = measured_counters(kernel)
+    rec = measured_counters(kernel, path)
     return rec.get("bytes_per_launch") if rec else None
 
 def _timed(torch, fn, reps: int = 1) -> float:
@@ -522,6 +523,8 @@ def main() -> int:
     ap.add_argument("--profile-steps", type=int, default=20)
     ap.add_argument("--no-graph", action="store_true", help="launch passes eagerly instead of replaying a hipGraph")
     ap.add_argument("--no-autotune", action="store_true", help="use the default tile schedules")
+    ap.add_argument("--semi-implicit", action="store_true",
+                    help="time the semi-implicit step instead of RK4IP (not the headline line; for profiling)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the batched and adjoint forms (each timed against the plain path)")
@@ -555,7 +558,9 @@ def main() -> int:
     pts = g.M * g.batch
     probs, _keep = rk4ip.problems_from_workload(w)
     tune = 0 if args.no_autotune else rk4ip.RK4IP_FLAG_AUTOTUNE
+    tune |= rk4ip.RK4IP_FLAG_SEMI_IMPLICIT if args.semi_implicit else 0
     flags = (0 if args.no_graph else rk4ip.RK4IP_FLAG_GRAPH) | tune
+    traffic_file = TRAFFIC_FILE_SI if args.semi_implicit else TRAFFIC_FILE
     plan = rk4ip.Plan(probs, flags=flags)
     psi0 = rk4ip.field_to_device(w)
     psi = psi0.clone()
@@ -604,13 +609,13 @@ def main() -> int:
     dom_mean_ms = dom["total_ms"] / dom["launches"]
     bytes_per_launch = PASS_BYTES[dom["kind"]] * pts
     achieved = bytes_per_launch / (dom_mean_ms / 1e3) / 1e9
-    traffic = measured_traffic(dom_name)
-    counters = measured_counters(dom_name) or {}
+    traffic = measured_traffic(dom_name, traffic_file)
+    counters = measured_counters(dom_name, traffic_file) or {}
     per_kernel = []
     for name, k in sorted(kernels.items(), key=lambda kv: -kv[1]["total_ms"]):
         mean = k["total_ms"] / k["launches"]
         gbs = PASS_BYTES[k["kind"]] * pts / (mean / 1e3) / 1e9
-        c = measured_counters(name) or {}
+        c = measured_counters(name, traffic_file) or {}
         per_kernel.append({"kernel": name, "mean_ms": mean, "launches": k["launches"], "achieved_GBps": gbs,
                            "hbm_frac": gbs / HBM_PEAK_GBS, "valu_issue_frac_profiled": c.get("valu_issue_frac"),
                            "traffic_ratio_profiled": c.get("ratio")})
@@ -633,7 +638,8 @@ def main() -> int:
         "config": {"workload": "gpe3d_256^3", "lattice": [256, 256, 256], "domain": [-10, 10], "dt": w.h,
                    "g": 2000.0, "trap": [1.0, 1.5, 2.0], "instances": 1,
                    "launch": "hipGraph of 32 steps" if not args.no_graph else "eager passes",
-                   "autotune": not args.no_autotune},
+                   "autotune": not args.no_autotune,
+                   "integrator": "semi-implicit" if args.semi_implicit else "rk4ip"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "kernel": dom_name, "kernel_mean_ms": dom_mean_ms,

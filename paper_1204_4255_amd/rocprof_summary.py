@@ -6,12 +6,13 @@ Reads the CSV output of three rocprofv3 runs from one directory:
   write_counter_collection.csv  --pmc WRITE_SIZE         (KiB written per dispatch)
 and optionally
   valu_counter_collection.csv   --pmc SQ_INSTS_VALU SQ_INSTS_LDS SQ_LDS_BANK_CONFLICT SQ_WAVES
-and writes ``traffic_gpe3d_256.json`` (read by bench.py) plus markdown tables.
+and writes ``traffic_gpe3d_256[_semi_implicit].json`` (read by bench.py) plus a markdown
+summary, for the RK4IP step or (with bench.py --semi-implicit) the semi-implicit step.
 
 The counters are scaled to bytes with the same counters read for one elementwise copy of
 known size (bench.py --calibrate-copy: 256 MiB in, 256 MiB out).
 
-    python -m paper_1204_4255_amd.rocprof_summary <csv dir> <out dir> "<command lines>"
+    python -m paper_1204_4255_amd.rocprof_summary <csv dir> <out dir> [rk4ip | semi_implicit]
 """
 from __future__ import annotations
 
@@ -25,9 +26,12 @@ from collections import defaultdict
 from .build import source_hash
 
 POINTS = 256 ** 3
-KINDS = {0: "D1", 1: "D2", 2: "FIRST", 4: "LAST2", 5: "U", 6: "AW", 7: "AS", 8: "AF", 9: "LF", 10: "XF"}
-# algorithmic HBM bytes per lattice point of each pass kind (complex64 = 8 B)
-PASS_BYTES = {"FIRST": 24, "D2": 32, "LF": 32, "XF": 32, "LAST2": 24}
+KINDS = {0: "D1", 1: "D2", 2: "FIRST", 4: "LAST2", 5: "U", 6: "AW", 7: "AS", 8: "AF", 9: "LF", 10: "XF", 11: "SI"}
+# algorithmic HBM bytes per lattice point of each pass kind (complex64 = 8 B); the
+# semi-implicit step's passes (D1, applied once or twice, and SI) read and write psi once
+PASS_BYTES = {"FIRST": 24, "D2": 32, "LF": 32, "XF": 32, "LAST2": 24, "D1": 16, "SI": 16}
+# the step forms profiled: file-name suffix and the extra benchmark switch
+FORMS = {"rk4ip": ("", ""), "semi_implicit": ("_semi_implicit", " --semi-implicit")}
 COPY_BYTES = 256 << 20
 AXIS_RE = re.compile(r"k_axis<(\d+), (\d+), (true|false), (\d+), (true|false), (\d), (\d+)(?:, (true|false), (\d+))?>")
 
@@ -68,7 +72,7 @@ def _copy_kernel(cnt, counter: str):
     return best
 
 
-def summarise(src: str, dst: str, commands: str) -> dict:
+def summarise(src: str, dst: str, commands: str, form: str = "rk4ip") -> dict:
     fetch = _counters(os.path.join(src, "fetch_counter_collection.csv"))
     write = _counters(os.path.join(src, "write_counter_collection.csv"))
     valu = _counters(os.path.join(src, "valu_counter_collection.csv"))
@@ -117,12 +121,12 @@ def summarise(src: str, dst: str, commands: str) -> dict:
         if key in kernels and kernels[key].get("calls", 0) >= rec.get("calls", 0):
             continue
         kernels[key] = rec
-    out = {"source_hash": source_hash(), "workload": "gpe3d_256^3",
+    out = {"source_hash": source_hash(), "workload": "gpe3d_256^3", "form": form,
            "calibration": {"kernel": "torch elementwise x*1.0, 256 MiB in + 256 MiB out", "FETCH_SIZE_KiB": cf,
                            "WRITE_SIZE_KiB": cw, "fetch_factor": fetch_factor, "write_factor": write_factor},
            "commands": commands, "kernels": kernels}
     os.makedirs(dst, exist_ok=True)
-    with open(os.path.join(dst, "traffic_gpe3d_256.json"), "w") as fh:
+    with open(os.path.join(dst, f"traffic_gpe3d_256{FORMS[form][0]}.json"), "w") as fh:
         json.dump(out, fh, indent=1)
     return out
 
@@ -142,28 +146,31 @@ def markdown(out: dict) -> str:
 
 COMMANDS = """    cd /tmp && export TMPDIR=/tmp
     R=<repository root>; OUT=<a writable output directory>
-    export RK4IP_TUNE_CACHE=$OUT/tune_gpe3d_256.json
-    python3 $R/bench.py --no-cpu-baseline --no-forms --steps 20 --warmup 5
-    rocprofv3 --kernel-trace --stats --output-format csv -d $OUT/prof -o kt -- python3 $R/bench.py --no-cpu-baseline --no-forms --steps 50 --warmup 5 --calibrate-copy
-    rocprofv3 --pmc FETCH_SIZE --output-format csv -d $OUT/prof -o fetch -- python3 $R/bench.py --no-cpu-baseline --no-forms --steps 3 --warmup 1 --profile-steps 2 --calibrate-copy
-    rocprofv3 --pmc WRITE_SIZE --output-format csv -d $OUT/prof -o write -- python3 $R/bench.py --no-cpu-baseline --no-forms --steps 3 --warmup 1 --profile-steps 2 --calibrate-copy
-    rocprofv3 --pmc SQ_INSTS_VALU SQ_INSTS_LDS SQ_LDS_BANK_CONFLICT SQ_WAVES --output-format csv -d $OUT/prof -o valu -- python3 $R/bench.py --no-cpu-baseline --no-forms --steps 3 --warmup 1 --profile-steps 2
-    cd $R && python3 -m paper_1204_4255_amd.rocprof_summary $OUT/prof profiles"""
+    export RK4IP_TUNE_CACHE=$OUT/tune_gpe3d_256{sfx}.json
+    python3 $R/bench.py --no-cpu-baseline --no-forms{sw} --steps 20 --warmup 5
+    rocprofv3 --kernel-trace --stats --output-format csv -d $OUT/prof{sfx} -o kt -- python3 $R/bench.py --no-cpu-baseline --no-forms{sw} --steps 50 --warmup 5 --calibrate-copy
+    rocprofv3 --pmc FETCH_SIZE --output-format csv -d $OUT/prof{sfx} -o fetch -- python3 $R/bench.py --no-cpu-baseline --no-forms{sw} --steps 3 --warmup 1 --profile-steps 2 --calibrate-copy
+    rocprofv3 --pmc WRITE_SIZE --output-format csv -d $OUT/prof{sfx} -o write -- python3 $R/bench.py --no-cpu-baseline --no-forms{sw} --steps 3 --warmup 1 --profile-steps 2 --calibrate-copy
+    rocprofv3 --pmc SQ_INSTS_VALU SQ_INSTS_LDS SQ_LDS_BANK_CONFLICT SQ_WAVES --output-format csv -d $OUT/prof{sfx} -o valu -- python3 $R/bench.py --no-cpu-baseline --no-forms{sw} --steps 3 --warmup 1 --profile-steps 2
+    cd $R && python3 -m paper_1204_4255_amd.rocprof_summary $OUT/prof{sfx} profiles {form}"""
 
 COPY_GBPS = 5900.0  # a plain elementwise copy of 256 MiB in and out on this GPU
 
 
 def report(out: dict, tune: str = "") -> str:
     cal = out["calibration"]
+    form = out.get("form", "rk4ip")
+    sfx, sw = FORMS[form]
+    title = "the RK4IP step" if form == "rk4ip" else "the semi-implicit step"
     lines = [
-        "# Step kernels of the 256^3 3D GPE workload: rocprofv3 kernel trace and counters",
+        f"# Step kernels of the 256^3 3D GPE workload, {title}: rocprofv3 kernel trace and counters",
         "",
         "Commands (one MI355X, repository root). `RK4IP_TUNE_CACHE` keeps the schedules the",
         "autotuner picks in the first run, so every later run launches the same kernels:",
         "",
-        COMMANDS,
+        COMMANDS.format(sfx=sfx, sw=sw, form=form),
         "",
-        "The last command writes this file and `traffic_gpe3d_256.json`, which `bench.py` reads",
+        f"The last command writes this file and `traffic_gpe3d_256{sfx}.json`, which `bench.py{sw}` reads",
         f"for `roofline.traffic` while the kernel sources still hash to `{out['source_hash']}`.",
         "",
     ]
@@ -179,7 +186,7 @@ def report(out: dict, tune: str = "") -> str:
         "Columns:",
         "* Calls, durations and % of GPU time come from `kt_kernel_stats.csv`. That run also holds the",
         "  profiling plan's eager steps and the autotuner's launches, so call counts are not whole steps.",
-        "* Algorithmic GB/s = the pass's algorithmic bytes (24 or 32 B per point x 256^3) / average",
+        "* Algorithmic GB/s = the pass's algorithmic bytes (16, 24 or 32 B per point x 256^3) / average",
         "  duration.",
         "* Measured / algorithmic = (scaled FETCH + WRITE) / algorithmic bytes.",
         "* VALU lane-instructions per point = SQ_INSTS_VALU x 64 / 256^3.",
@@ -191,7 +198,8 @@ def report(out: dict, tune: str = "") -> str:
         "Template arguments of `k_axis`: (length, pass kind, contiguous axis, lines or columns per",
         "workgroup, noise drawn, field order 0 joint / 1 one after the other / 2 the same with the",
         "second load deferred, values per thread, FP64 transforms, minimum waves per SIMD). Pass",
-        "kinds: 1 = D2, 2 = FIRST, 4 = LAST2, 9 = LF, 10 = XF.",
+        "kinds: 0 = D1 (once, or twice where two semi-implicit steps meet), 1 = D2, 2 = FIRST,",
+        "4 = LAST2, 9 = LF, 10 = XF, 11 = SI.",
         "",
         "Reading (thresholds: within 10% of the copy rate = HBM-bound; VALU issue above 0.6 and",
         "under half the copy rate = VALU-bound):",
@@ -210,12 +218,14 @@ def report(out: dict, tune: str = "") -> str:
 
 
 if __name__ == "__main__":
-    res = summarise(sys.argv[1], sys.argv[2], sys.argv[3] if len(sys.argv) > 3 else "see step_kernels_gpe3d_256.md")
+    # python -m paper_1204_4255_amd.rocprof_summary <csv dir> <out dir> [rk4ip | semi_implicit]
+    form = sys.argv[3] if len(sys.argv) > 3 else "rk4ip"
+    res = summarise(sys.argv[1], sys.argv[2], COMMANDS.format(sfx=FORMS[form][0], sw=FORMS[form][1], form=form), form)
     tune = ""
     path = os.environ.get("RK4IP_TUNE_CACHE")
     if path and os.path.exists(path):
         tune = open(path).read()
     text = report(res, tune)
-    with open(os.path.join(sys.argv[2], "step_kernels_gpe3d_256.md"), "w") as fh:
+    with open(os.path.join(sys.argv[2], f"step_kernels_gpe3d_256{FORMS[form][0]}.md"), "w") as fh:
         fh.write(text)
     print(text)
