@@ -91,9 +91,9 @@ def _load():
         lib.ora_conv_potential.argtypes = [P, vp, vp]
         lib.ora_conv_potential.restype = ctypes.c_int
         lib.ora_ck_tableau.argtypes = [vp]
-        lib.ora_ck_step.argtypes = [P, vp, ctypes.c_double, vp, vp]
+        lib.ora_ck_step.argtypes = [P, vp, ctypes.c_double, vp, vp, ctypes.c_int]
         lib.ora_ck_step.restype = ctypes.c_int
-        lib.ora_ark45.argtypes = [P, vp, ctypes.c_double, ctypes.c_double, i64, vp, vp, vp, i64]
+        lib.ora_ark45.argtypes = [P, vp, ctypes.c_double, ctypes.c_double, i64, vp, vp, vp, i64, ctypes.c_int]
         lib.ora_ark45.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -296,19 +296,21 @@ def ck_tableau():
     return out[:6], out[6:36].reshape(6, 5), out[36:42], out[42:48]
 
 
-def ck_step(p: Problem, psi, h: float):
+def ck_step(p: Problem, psi, h: float, ip: bool = True):
     """One Cash-Karp step of size h of every instance (Sec. 3.5's adaptive RK45 in the
-    interaction picture, readings R8). Returns (fifth-order result, error estimate[batch])."""
+    interaction picture, reading R8; ip=False: the explicit comparison method of Sec. 3.6).
+    Returns (fifth-order result, error estimate[batch])."""
     f = _cfield(p, psi)
     out = np.empty_like(f)
     err = np.empty(p.batch, dtype=np.float64)
     pc = p._c()
-    if _load().ora_ck_step(ctypes.byref(pc), f.ctypes.data, float(h), out.ctypes.data, err.ctypes.data):
+    if _load().ora_ck_step(ctypes.byref(pc), f.ctypes.data, float(h), out.ctypes.data, err.ctypes.data, int(bool(ip))):
         raise ValueError("invalid problem")
     return out, err
 
 
-def ark45(p: Problem, psi, t_span: float, tol: float, h0, max_attempts: int = 1 << 20, log_cap: int = 0):
+def ark45(p: Problem, psi, t_span: float, tol: float, h0, max_attempts: int = 1 << 20, log_cap: int = 0,
+          ip: bool = True):
     """Adaptive Cash-Karp integration of every instance over [0, t_span] (readings R8, R9),
     each instance with its own step. h0: first trial step (scalar or [batch]).
     Returns (psi, h_next[batch], stats[batch][2] = (accepted, rejected), h_log or None,
@@ -320,7 +322,7 @@ def ark45(p: Problem, psi, t_span: float, tol: float, h0, max_attempts: int = 1 
     pc = p._c()
     rc = _load().ora_ark45(ctypes.byref(pc), f.ctypes.data, float(t_span), float(tol), int(max_attempts),
                            h.ctypes.data, stats.ctypes.data, None if log is None else log.ctypes.data,
-                           int(log_cap))
+                           int(log_cap), int(bool(ip)))
     if rc < 0:
         raise ValueError("invalid problem")
     return f, h, stats, log, rc == 0

@@ -55,6 +55,9 @@
  *       (local extrapolation), and the error estimate of the step is the relative L2
  *       norm over the instance, in the picture frame, of the difference between the
  *       fifth- and fourth-order results: ||sum_i (b_i - b*_i) k_i|| / ||psi_n + sum_i b_i k_i||.
+ *       The comparison method of Sec. 3.6 ("explicit") takes the same pair on eq. (5) with the
+ *       linear part evaluated in the stages as a spectral derivative, k_i = h (L Y_i + G(Y_i)),
+ *       L Y = F^{-1}[L(k) F Y], and psi_{n+1} = psi_n + sum_i b_i k_i.
  *   R10 Noise in the potential (the stochastics example, Sec. 4): G gains
  *       -i sigma_V eta psi with eta a real Wiener noise per lattice point, held over the
  *       step like xi, E eta^2 = 1/(h dV); it is the real part of the complex normal drawn
@@ -986,7 +989,26 @@ static void apply_exp_L(const ora_problem* p, double tau, cplx* f) {
 /* One Cash-Karp step of size h of one instance from psi (x space at t_n, which is also the
  * picture frame since the origin is t_n). Writes the fifth-order result at t_n + h (x
  * space) to out and returns the error estimate (reading R8). */
-static double ck_step_one(const ora_problem* p, const double* V, const cplx* psi, double h, cplx* out) {
+/* out = L f for one instance: transform, multiply every mode by L(k) / M, transform back. */
+static void apply_L(const ora_problem* p, const cplx* f, cplx* out) {
+    int64_t M = npts(p);
+    memcpy(out, f, sizeof(cplx) * (size_t)M);
+    fft_nd(p, out, -1);
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < M; j++) {
+        int64_t idx[3];
+        unflatten(p, j, idx);
+        double k2 = 0.0;
+        for (int a = 0; a < p->ndim; a++) {
+            double k = k_of(p, a, idx[a]);
+            k2 += k * k;
+        }
+        out[j] *= (-I * p->alpha * k2 - p->gamma) / (double)M;
+    }
+    fft_nd(p, out, +1);
+}
+
+static double ck_step_one(const ora_problem* p, const double* V, const cplx* psi, double h, cplx* out, int ip) {
     int64_t M = npts(p);
     cplx* k[6];
     for (int i = 0; i < 6; i++) k[i] = (cplx*)malloc(sizeof(cplx) * (size_t)M);
@@ -999,7 +1021,7 @@ static double ck_step_one(const ora_problem* p, const double* V, const cplx* psi
             for (int q = 0; q < i; q++) v += CK_A[i][q] * k[q][j];
             y[j] = v;
         }
-        if (CK_C[i] != 0.0) apply_exp_L(p, CK_C[i] * h, y);
+        if (ip && CK_C[i] != 0.0) apply_exp_L(p, CK_C[i] * h, y);
         /* h G at the stage time (G without noise: the method is deterministic only; with
          * the non-local potential of the stage field when there is a kernel, R11) */
         if (vc) conv_potential(p, y, vc);
@@ -1008,8 +1030,14 @@ static double ck_step_one(const ora_problem* p, const double* V, const cplx* psi
             double veff = vc ? V[j] + vc[j] : V[j];
             k[i][j] = h * (-I * (veff + p->gnl * m2) * y[j]);
         }
-        /* back to the picture frame */
-        if (CK_C[i] != 0.0) apply_exp_L(p, -CK_C[i] * h, k[i]);
+        if (ip) {
+            /* back to the picture frame */
+            if (CK_C[i] != 0.0) apply_exp_L(p, -CK_C[i] * h, k[i]);
+        } else {
+            /* the explicit method: the linear part in the stage too */
+            apply_L(p, y, out);
+            for (int64_t j = 0; j < M; j++) k[i][j] += h * out[j];
+        }
     }
     double num = 0.0, den = 0.0;
     for (int64_t j = 0; j < M; j++) {
@@ -1022,7 +1050,7 @@ static double ck_step_one(const ora_problem* p, const double* V, const cplx* psi
         num += creal(dlt) * creal(dlt) + cimag(dlt) * cimag(dlt);
         den += creal(y5) * creal(y5) + cimag(y5) * cimag(y5);
     }
-    apply_exp_L(p, h, out);
+    if (ip) apply_exp_L(p, h, out);
     for (int i = 0; i < 6; i++) free(k[i]);
     free(y);
     free(vc);
@@ -1037,13 +1065,13 @@ static int check_ark45(const ora_problem* p) {
 
 /* One Cash-Karp step of size h of every instance: out[batch][M] (fifth order, x space),
  * err[batch]. */
-int ora_ck_step(const ora_problem* p, const cplx* psi, double h, cplx* out, double* err) {
+int ora_ck_step(const ora_problem* p, const cplx* psi, double h, cplx* out, double* err, int ip) {
     if (check_ark45(p) || !(h > 0.0)) return -1;
     int64_t M = npts(p);
     double* V = (double*)malloc(sizeof(double) * (size_t)M);
     for (int64_t b = 0; b < p->batch; b++) {
         potential(p, b, V);
-        err[b] = ck_step_one(p, V, psi + b * M, h, out + b * M);
+        err[b] = ck_step_one(p, V, psi + b * M, h, out + b * M, ip);
     }
     free(V);
     return 0;
@@ -1063,7 +1091,7 @@ static double ck_factor(double err, double tol) {
  * At most max_attempts trial steps per instance. Returns 0 when every instance reached
  * t_span, 1 when one ran out of attempts, -1 on a bad argument. */
 int ora_ark45(const ora_problem* p, cplx* psi, double t_span, double tol, int64_t max_attempts, double* h,
-              int64_t* stats, double* h_log, int64_t log_cap) {
+              int64_t* stats, double* h_log, int64_t log_cap, int ip) {
     if (check_ark45(p) || !(t_span >= 0.0) || !(tol > 0.0) || max_attempts < 1) return -1;
     int64_t M = npts(p);
     double* V = (double*)malloc(sizeof(double) * (size_t)M);
@@ -1081,7 +1109,7 @@ int ora_ark45(const ora_problem* p, cplx* psi, double t_span, double tol, int64_
         while (t < t_span && acc + rej < max_attempts) {
             int last = t + hb >= t_span;
             double htry = last ? t_span - t : hb;
-            double err = ck_step_one(p, V, f, htry, out);
+            double err = ck_step_one(p, V, f, htry, out, ip);
             if (err <= tol) {
                 memcpy(f, out, sizeof(cplx) * (size_t)M);
                 if (h_log && acc < log_cap) h_log[b * log_cap + acc] = htry;

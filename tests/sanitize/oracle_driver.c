@@ -41,9 +41,9 @@ int ora_apply_D(const ora_problem* p, cplx* f, int dense, int adjoint);
 int ora_fft_nd(const ora_problem* p, cplx* f, int sign);
 void ora_ck_tableau(double* out);
 void ora_vnoise(const ora_problem* p, int64_t step, double* eta);
-int ora_ck_step(const ora_problem* p, const cplx* psi, double h, cplx* out, double* err);
+int ora_ck_step(const ora_problem* p, const cplx* psi, double h, cplx* out, double* err, int ip);
 int ora_ark45(const ora_problem* p, cplx* psi, double t_span, double tol, int64_t max_attempts, double* h,
-              int64_t* stats, double* h_log, int64_t log_cap);
+              int64_t* stats, double* h_log, int64_t log_cap, int ip);
 
 static int fails = 0;
 #define CHECK(x)                                             \
@@ -143,11 +143,12 @@ static void exercise(int ndim, const int64_t* n, int64_t batch, int si) {
     double* hlog = malloc(sizeof(double) * batch * 8);
     double* err = malloc(sizeof(double) * batch);
     for (int64_t b = 0; b < batch; b++) hs[b] = 1e-3;
-    if (ora_ark45(&p, psi, 0.01, 1e-6, 100, hs, stats, hlog, 8) != -1) fails++;
+    if (ora_ark45(&p, psi, 0.01, 1e-6, 100, hs, stats, hlog, 8, 1) != -1) fails++;
     p.sigma = 0.0;
-    CHECK(ora_ck_step(&p, psi, 2e-3, g, err));
-    CHECK(ora_ark45(&p, psi, 0.01, 1e-6, 100, hs, stats, hlog, 8));
-    CHECK(ora_ark45(&p, psi, 0.01, 1e-6, 100, hs, stats, NULL, 0));
+    CHECK(ora_ck_step(&p, psi, 2e-3, g, err, 1));
+    CHECK(ora_ck_step(&p, psi, 2e-3, g, err, 0));
+    CHECK(ora_ark45(&p, psi, 0.01, 1e-6, 100, hs, stats, hlog, 8, 1));
+    CHECK(ora_ark45(&p, psi, 0.01, 1e-6, 100, hs, stats, NULL, 0, 0));
     free(hs), free(stats), free(hlog), free(err);
     free(V), free(psi), free(dpsi), free(lam), free(g), free(gV), free(dV), free(xi);
     free(diag), free(ckpt), free(ov), free(mean), free(var);

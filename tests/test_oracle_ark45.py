@@ -156,3 +156,36 @@ def test_noise_is_rejected():
     g = W.Group(n=(16,), lo=(0.0,), hi=(1.0,))
     with pytest.raises(ValueError):
         oracle.ark45(_prob(g, sigma=0.1), np.ones((1, 16), complex), 1.0, 1e-6, 0.1)
+
+
+def test_explicit_method_steps_grow_with_resolution():
+    # the comparison of Sec. 3.6 (the step-count figure): with the kinetic term in the
+    # stages the stable step falls as 1/k_max^2, so doubling the points costs about 4x the
+    # steps; the interaction picture keeps the count
+    ip_counts, ex_counts = [], []
+    for n in (128, 256, 512):
+        g = W.Group(n=(n,), lo=(-20.0,), hi=(20.0,), gnl=-1.0)
+        x = g.axis(0)
+        psi0 = (1 / np.cosh(x) * np.exp(0.5j * x))[None]
+        for ip, counts in ((True, ip_counts), (False, ex_counts)):
+            _, _, st, _, done = oracle.ark45(_prob(g), psi0, 1.0, 1e-7, 1e-3, ip=ip)
+            assert done
+            counts.append(int(st[0, 0]))
+    assert max(ip_counts) - min(ip_counts) <= 1, ip_counts
+    assert ex_counts[2] / ex_counts[1] > 3 and ex_counts[1] / ex_counts[0] > 3, ex_counts
+
+
+def test_explicit_method_on_the_free_gaussian():
+    # with G = 0 the explicit method integrates L psi alone: the closed form to the tolerance
+    n, L, s0, x0, k0 = 128, 40.0, 1.3, 0.5, 1.0
+    g = W.Group(n=(n,), lo=(-L / 2,), hi=(L / 2,))
+    x = g.axis(0)
+
+    def free(t):
+        cc = 1 + 1j * t / s0 ** 2
+        return ((np.pi * s0 ** 2) ** -0.25 * cc ** -0.5
+                * np.exp(-(x - x0 - k0 * t) ** 2 / (2 * s0 ** 2 * cc) + 1j * k0 * x - 0.5j * k0 ** 2 * t))
+
+    out, _, st, _, done = oracle.ark45(_prob(g), free(0.0)[None], 1.0, 1e-9, 1e-3, ip=False)
+    assert done and st[0, 0] > 10  # not exact in one step, unlike the interaction picture
+    assert rel(out[0], free(1.0)) < 1e-6
