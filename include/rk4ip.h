@@ -208,9 +208,13 @@ size_t rk4ip_adjoint_workspace_bytes(rk4ip_plan_t plan, int64_t ckpt_every);
  * Transforms are complex64 in every precision form; the propagator of each trial step is
  * formed per mode from an FP64 phase. Asynchronous; allocates nothing. Returns
  * RK4IP_ERR_UNSUPPORTED_SHAPE for a plan with a 2D or 3D group and RK4IP_ERR_INVALID_ARG
- * for a noisy group, tol <= 0, t_span < 0 or max_attempts < 1. */
+ * for a noisy group, tol <= 0, t_span < 0 or max_attempts < 1.
+ *   explicit_L  0: the interaction picture (above). 1: the comparison method of Sec. 3.6,
+ *          the same pair on eq. (5) with the linear part evaluated in every stage as a
+ *          spectral derivative, k_i = h (L Y_i + G(Y_i)), L Y = F^{-1}[L(k) F Y], and
+ *          psi_{n+1} = psi_n + sum_i b_i k_i (its stable step falls as 1/k_max^2). */
 int rk4ip_ark45(rk4ip_plan_t plan, void* psi, double t_span, double tol, int64_t max_attempts, double* h,
-                int64_t* stats, double* h_log, int64_t log_cap);
+                int64_t* stats, double* h_log, int64_t log_cap, int explicit_L);
 
 /* Discrete adjoint of rk4ip_run over nsteps steps from step0 (not in the paper).
  * Given the checkpoints written by rk4ip_run (same step0, nsteps, ckpt_every) and

@@ -79,6 +79,29 @@ __device__ __forceinline__ void propagate_tau(c32 (&f)[F::R], int t, int l, c32*
     for (int m = 0; m < R; m++) f[m] = cadd(f[m], d[0][m]);
 }
 
+// out = h L v on this thread's R values (the explicit comparison method): transform,
+// multiply mode m by h L(k_m) / n = h (-i alpha k_m^2 - gamma) / n, transform back.
+template <class F, class L>
+__device__ __forceinline__ void apply_hL(const c32 (&v)[F::R], c32 (&out)[F::R], int t, int l, c32* lds,
+                                         const c32* tw, const ArkArgs& x, double h) {
+    constexpr int R = F::R, T = F::T, N = F::NN;
+    c32 d[1][R];
+#pragma unroll
+    for (int m = 0; m < R; m++) d[0][m] = v[m];
+    fft_line<F, -1, L, 1>(d, t, l, lds, tw);
+    const double c0 = x.alpha * x.kscale * x.kscale * h / (double)N;
+    const float re = (float)(-x.gamma * h / (double)N);
+#pragma unroll
+    for (int m = 0; m < R; m++) {
+        const int e = t + m * T;
+        const double km = (double)(e < N / 2 ? e : e - N);
+        d[0][m] = cmul(d[0][m], make_float2(re, (float)(-c0 * km * km)));
+    }
+    fft_line<F, +1, L, 1>(d, t, l, lds, tw);
+#pragma unroll
+    for (int m = 0; m < R; m++) out[m] = d[0][m];
+}
+
 // h G(phi) without noise: -i h (V + g |phi|^2) phi
 __device__ __forceinline__ c32 hG_ark(const GroupDev& g, c32 phi, float V, float h) {
     const float m2 = fmaf(phi.x, phi.x, phi.y * phi.y);
@@ -89,7 +112,30 @@ __device__ __forceinline__ c32 hG_ark(const GroupDev& g, c32 phi, float V, float
 // Stage I (1..5) of a trial step of size h: k_I = e^{-L c_I h} h G(e^{L c_I h} Y_I) with
 // Y_I = y + sum_{j<I} a_Ij k_j. A template per stage keeps every index of k a constant,
 // so the stages stay in registers.
-template <int I, bool CONV, class F, class L>
+// EX: the explicit comparison method: the stage input stays in x space and the linear
+// part is added to G, k_I = h (L Y_I + G(Y_I)).
+template <class F, class L, bool CONV, bool EX>
+__device__ __forceinline__ void stage_rhs(c32 (&s)[F::R], const float (&V)[F::R], const GroupDev& g, int t, int l,
+                                          c32* lds, const c32* tw, const ArkArgs& x, double h, float hf) {
+    c32 lin[F::R];
+    if constexpr (EX) apply_hL<F, L>(s, lin, t, l, lds, tw, x, h);
+    if constexpr (CONV) {
+        // with the non-local potential of the stage field
+        float vc[F::R];
+        conv_V<F, L>(s, vc, t, l, lds, tw, g.convK);
+#pragma unroll
+        for (int m = 0; m < F::R; m++) s[m] = hG_ark(g, s[m], V[m] + vc[m], hf);
+    } else {
+#pragma unroll
+        for (int m = 0; m < F::R; m++) s[m] = hG_ark(g, s[m], V[m], hf);
+    }
+    if constexpr (EX) {
+#pragma unroll
+        for (int m = 0; m < F::R; m++) s[m] = cadd(s[m], lin[m]);
+    }
+}
+
+template <int I, bool CONV, bool EX, class F, class L>
 __device__ __forceinline__ void ck_stage(c32 (&k)[6][F::R], const c32 (&y)[F::R], const float (&V)[F::R],
                                          const GroupDev& g, int t, int l, c32* lds, const c32* tw,
                                          const ArkArgs& x, double h, float hf) {
@@ -100,22 +146,18 @@ __device__ __forceinline__ void ck_stage(c32 (&k)[6][F::R], const c32 (&y)[F::R]
         for (int j = 0; j < I; j++) v = make_float2(fmaf(kA[I][j], k[j][m].x, v.x), fmaf(kA[I][j], k[j][m].y, v.y));
         k[I][m] = v;
     }
-    propagate_tau<F, L>(k[I], t, l, lds, tw, x, kC[I] * h);  // to the stage time
-    if constexpr (CONV) {
-        // with the non-local potential of the stage field
-        float vc[F::R];
-        conv_V<F, L>(k[I], vc, t, l, lds, tw, g.convK);
-#pragma unroll
-        for (int m = 0; m < F::R; m++) k[I][m] = hG_ark(g, k[I][m], V[m] + vc[m], hf);
-    } else {
-#pragma unroll
-        for (int m = 0; m < F::R; m++) k[I][m] = hG_ark(g, k[I][m], V[m], hf);
+    if constexpr (EX) {
+        stage_rhs<F, L, CONV, true>(k[I], V, g, t, l, lds, tw, x, h, hf);
+        return;
     }
+    propagate_tau<F, L>(k[I], t, l, lds, tw, x, kC[I] * h);  // to the stage time
+    stage_rhs<F, L, CONV, false>(k[I], V, g, t, l, lds, tw, x, h, hf);
     propagate_tau<F, L>(k[I], t, l, lds, tw, x, -kC[I] * h);  // back to the picture frame
 }
 
 // CONV: G includes the non-local potential (the variant compiled for groups with a kernel).
-template <int N, int LPB, bool CONV>
+// EX: the explicit comparison method instead of the interaction picture.
+template <int N, int LPB, bool CONV, bool EX>
 __global__ void __launch_bounds__((FFTShape<N, 8>::T * LPB))
     k_line_ark45(GroupDev g, float2* __restrict__ psi, ArkArgs x) {
     using F = FFTShape<N, 8>;
@@ -156,20 +198,14 @@ __global__ void __launch_bounds__((FFTShape<N, 8>::T * LPB))
         const float hf = (float)htry;
         c32 k[6][R];
         // stage 1 (c = 0): h G(psi_n)
-        if constexpr (CONV) {
-            float vc[R];
-            conv_V<F, L>(y, vc, t, l, lds, tw, g.convK);
 #pragma unroll
-            for (int m = 0; m < R; m++) k[0][m] = hG_ark(g, y[m], V[m] + vc[m], hf);
-        } else {
-#pragma unroll
-            for (int m = 0; m < R; m++) k[0][m] = hG_ark(g, y[m], V[m], hf);
-        }
-        ck_stage<1, CONV, F, L>(k, y, V, g, t, l, lds, tw, x, htry, hf);
-        ck_stage<2, CONV, F, L>(k, y, V, g, t, l, lds, tw, x, htry, hf);
-        ck_stage<3, CONV, F, L>(k, y, V, g, t, l, lds, tw, x, htry, hf);
-        ck_stage<4, CONV, F, L>(k, y, V, g, t, l, lds, tw, x, htry, hf);
-        ck_stage<5, CONV, F, L>(k, y, V, g, t, l, lds, tw, x, htry, hf);
+        for (int m = 0; m < R; m++) k[0][m] = y[m];
+        stage_rhs<F, L, CONV, EX>(k[0], V, g, t, l, lds, tw, x, htry, hf);
+        ck_stage<1, CONV, EX, F, L>(k, y, V, g, t, l, lds, tw, x, htry, hf);
+        ck_stage<2, CONV, EX, F, L>(k, y, V, g, t, l, lds, tw, x, htry, hf);
+        ck_stage<3, CONV, EX, F, L>(k, y, V, g, t, l, lds, tw, x, htry, hf);
+        ck_stage<4, CONV, EX, F, L>(k, y, V, g, t, l, lds, tw, x, htry, hf);
+        ck_stage<5, CONV, EX, F, L>(k, y, V, g, t, l, lds, tw, x, htry, hf);
         // fifth-order result and the embedded difference (weights that vanish are skipped)
         c32 y5[R], dl[R];
 #pragma unroll
@@ -215,8 +251,8 @@ __global__ void __launch_bounds__((FFTShape<N, 8>::T * LPB))
         }
         const double err = sqrt(num / den);
         // the fifth-order result moved to t_n + h (computed by every line; kept only on
-        // acceptance)
-        propagate_tau<F, L>(y5, t, l, lds, tw, x, htry);
+        // acceptance); the explicit method's result is already at t_n + h
+        if constexpr (!EX) propagate_tau<F, L>(y5, t, l, lds, tw, x, htry);
         __syncthreads();  // every line has read its partials before the next step writes them
         if (live) {
             const bool ok = err <= x.tol;
@@ -253,10 +289,18 @@ static hipError_t go_ark45(const GroupDev& g, float2* psi, const ArkArgs& x, hip
     constexpr int T = FFTShape<N, 8>::T;
     constexpr int LPB = T >= 64 ? 1 : 64 / T;
     const int64_t blocks = (g.batch + LPB - 1) / LPB;
-    if (g.convK)
-        hipLaunchKernelGGL((k_line_ark45<N, LPB, true>), dim3((unsigned)blocks), dim3(T * LPB), 0, s, g, psi, x);
-    else
-        hipLaunchKernelGGL((k_line_ark45<N, LPB, false>), dim3((unsigned)blocks), dim3(T * LPB), 0, s, g, psi, x);
+    const dim3 grid((unsigned)blocks), block(T * LPB);
+    if (x.explicit_L) {
+        if (g.convK)
+            hipLaunchKernelGGL((k_line_ark45<N, LPB, true, true>), grid, block, 0, s, g, psi, x);
+        else
+            hipLaunchKernelGGL((k_line_ark45<N, LPB, false, true>), grid, block, 0, s, g, psi, x);
+    } else {
+        if (g.convK)
+            hipLaunchKernelGGL((k_line_ark45<N, LPB, true, false>), grid, block, 0, s, g, psi, x);
+        else
+            hipLaunchKernelGGL((k_line_ark45<N, LPB, false, false>), grid, block, 0, s, g, psi, x);
+    }
     return hipGetLastError();
 }
 

@@ -57,6 +57,7 @@ struct ArkArgs {
     double* h;                // [ninst] in: first trial step; out: next trial step
     int64_t* stats;           // [ninst][3] accepted, rejected, reached t_span
     double* h_log;            // [ninst][log_cap] accepted step sizes, or null
+    int explicit_L;           // 1: the explicit comparison method (no interaction picture)
 };
 
 // Constants of the final diagnostic sum (FP64).

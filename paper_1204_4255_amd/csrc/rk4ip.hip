@@ -1060,7 +1060,7 @@ int rk4ip_moments(rk4ip_plan_t plan, int group, const void* psi, double* mean, d
 }
 
 int rk4ip_ark45(rk4ip_plan_t plan, void* psi_v, double t_span, double tol, int64_t max_attempts, double* h,
-                int64_t* stats, double* h_log, int64_t log_cap) {
+                int64_t* stats, double* h_log, int64_t log_cap, int explicit_L) {
     if (!plan || !psi_v || !h || !stats || !(t_span >= 0.0) || !std::isfinite(t_span) || !(tol > 0.0) ||
         !std::isfinite(tol) || max_attempts < 1 || log_cap < 0 || (log_cap > 0) != (h_log != nullptr))
         return RK4IP_ERR_INVALID_ARG;
@@ -1084,6 +1084,7 @@ int rk4ip_ark45(rk4ip_plan_t plan, void* psi_v, double t_span, double tol, int64
         x.h = h;
         x.stats = stats;
         x.h_log = h_log;
+        x.explicit_L = explicit_L ? 1 : 0;
         HIPCHK(plan, rk4ip::launch_line_ark45(g.d, psi, x, plan->stream));
     }
     return RK4IP_OK;

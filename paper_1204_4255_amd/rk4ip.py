@@ -87,7 +87,7 @@ def load(path: str = LIB_PATH):
         "rk4ip_moments": (i32, [vp, i32, vp, vp, vp]),
         "rk4ip_adjoint_workspace_bytes": (ctypes.c_size_t, [vp, i64]),
         "rk4ip_adjoint": (i32, [vp, vp, i64, i64, i64, vp, vp, vp, vp, ctypes.c_size_t]),
-        "rk4ip_ark45": (i32, [vp, vp, ctypes.c_double, ctypes.c_double, i64, vp, vp, vp, i64]),
+        "rk4ip_ark45": (i32, [vp, vp, ctypes.c_double, ctypes.c_double, i64, vp, vp, vp, i64, i32]),
         "rk4ip_status": (i32, [vp]),
         "rk4ip_destroy": (i32, [vp]),
         "rk4ip_strerror": (ctypes.c_char_p, [i32]),
@@ -293,7 +293,8 @@ class Plan:
         self._keep_adj_ws = ws
         return g, gV
 
-    def ark45(self, psi, t_span: float, tol: float, h, max_attempts: int = 1 << 20, log_cap: int = 0):
+    def ark45(self, psi, t_span: float, tol: float, h, max_attempts: int = 1 << 20, log_cap: int = 0,
+              explicit: bool = False):
         """Adaptive Cash-Karp integration over [0, t_span] (1D noise-free groups), in place on
         psi. h: device float64 [ninst], the first trial steps, updated to the next ones.
         Returns (stats [ninst][3] = accepted, rejected, reached; h_log [ninst][log_cap] or
@@ -306,7 +307,8 @@ class Plan:
         if log_cap > 0:
             log = torch.full((self.ninst, log_cap), float("nan"), dtype=torch.float64, device=psi.device)
         _check(load().rk4ip_ark45(self.handle, _ptr(psi), float(t_span), float(tol), int(max_attempts), _ptr(h),
-                                  _ptr(stats), _ptr(log), int(log_cap)), self.handle, "rk4ip_ark45")
+                                  _ptr(stats), _ptr(log), int(log_cap), int(bool(explicit))), self.handle,
+               "rk4ip_ark45")
         return stats, log
 
     def status(self) -> int:

@@ -106,7 +106,7 @@ def test_null_plan_calls_are_rejected(lib):
     assert lib.rk4ip_last_error(None) == b""
     assert lib.rk4ip_debug_philox(0, None, 1, None, None) == rk4ip.RK4IP_ERR_INVALID_ARG
     assert lib.rk4ip_ark45(None, ctypes.c_void_p(256), 1.0, 1e-6, 10, ctypes.c_void_p(256), ctypes.c_void_p(256),
-                           None, 0) == rk4ip.RK4IP_ERR_INVALID_ARG
+                           None, 0, 0) == rk4ip.RK4IP_ERR_INVALID_ARG
 
 
 def test_valid_plan_without_gpu_reports_no_device(lib):

@@ -52,7 +52,7 @@ def _factor(err, tol):
     return min(5.0, max(0.2, 0.9 * (tol / err) ** 0.2))
 
 
-def _replay_check(g, f0, steps, tol, h_first, span, rejected, slack=0.1, convK=None):
+def _replay_check(g, f0, steps, tol, h_first, span, rejected, slack=0.1, convK=None, ip=True):
     """Replay the accepted steps of one instance on the oracle; check each one meets tol
     by the oracle's estimate and that the step changes follow the controller. Returns the
     replayed field."""
@@ -60,7 +60,7 @@ def _replay_check(g, f0, steps, tol, h_first, span, rejected, slack=0.1, convK=N
     f = np.asarray(f0, complex)[None]
     errs = []
     for h in steps:
-        f, e = oracle.ck_step(p, f, h)
+        f, e = oracle.ck_step(p, f, h, ip=ip)
         errs.append(e[0])
     errs = np.array(errs)
     assert np.all(errs <= tol * (1 + slack)), (errs.max(), tol)
@@ -212,6 +212,62 @@ def test_ark45_with_the_non_local_potential(torch):
             f"replay rel {err:.2e}")
         assert err < 1e-5
         assert abs(acc - ost[0, 0]) <= 2
+
+
+@pytest.mark.parametrize("n", [128, 256])
+def test_ark45_explicit_method_replay(torch, n):
+    """The explicit comparison method (the linear part in the stages): replayed on the
+    oracle's explicit steps, with the oracle's own step counts. The controller keeps this
+    method at its stability limit, where the pair amplifies the highest modes a little
+    each step; the soliton has no content there, but the complex64 run carries its
+    rounding floor in them, which the FP64 run does not. So the fields are compared on
+    the modes below half the Nyquist wavenumber (1e-5, the bar of every other replay), and
+    the rounding-driven remainder in the highest modes is reported."""
+    tol, T, h0 = 1e-6, 1.0, 1e-3
+    g, f0 = _solitons(n, [0.8, 1.0])
+    plan = _plan([g], torch)
+    d = _dev(torch, f0)
+    h = torch.full((g.batch,), h0, dtype=torch.float64, device="cuda")
+    stats, hl = plan.ark45(d, T, tol, h, log_cap=2048, explicit=True)
+    stats = stats.cpu().numpy()
+    hl = hl.cpu().numpy()
+    out = d.cpu().numpy().astype(np.complex128).reshape(g.shape)
+    assert np.all(stats[:, 2] == 1)
+    for b in range(g.batch):
+        acc, rej = int(stats[b, 0]), int(stats[b, 1])
+        ref = _replay_check(g, f0[b], hl[b, :acc], tol, h0, T, rej, ip=False)
+        gb = W.Group(n=(n,), lo=g.lo, hi=g.hi, gnl=g.gnl)
+        _, _, ost, _, _ = oracle.ark45(_oprob(gb), f0[b:b + 1], T, tol, h0, ip=False)
+        err = rel(out[b], ref)
+        k = np.fft.fftfreq(n) * n
+        low = np.abs(k) < n // 4
+
+        def lowpass(f):
+            return np.fft.ifft(np.where(low, np.fft.fft(f), 0))
+
+        err_low = rel(lowpass(out[b]), lowpass(ref))
+        log(f"  explicit n={n}, instance {b}: {acc} accepted, {rej} rejected (oracle {ost[0, 0]}, {ost[0, 1]}); "
+            f"replay rel {err:.2e}, below half the Nyquist wavenumber {err_low:.2e}")
+        assert err_low < 1e-5
+        assert abs(acc - ost[0, 0]) <= max(2, 0.02 * ost[0, 0])
+
+
+def test_ark45_explicit_steps_grow_with_resolution(torch):
+    """The paper's step-count comparison on the GPU: the explicit method's accepted steps
+    grow about fourfold per doubling of the points, the interaction picture's do not."""
+    ip, ex = [], []
+    for n in (128, 256, 512):
+        g, f0 = _solitons(n, [1.0])
+        plan = _plan([g], torch)
+        for explicit, counts in ((False, ip), (True, ex)):
+            d = _dev(torch, f0)
+            h = torch.full((1,), 1e-3, dtype=torch.float64, device="cuda")
+            stats, _ = plan.ark45(d, 1.0, 1e-7, h, explicit=explicit)
+            assert int(stats[0, 2]) == 1
+            counts.append(int(stats[0, 0]))
+    log(f"  accepted steps at n = 128, 256, 512: interaction picture {ip}, explicit {ex}")
+    assert max(ip) - min(ip) <= 1
+    assert ex[2] / ex[1] > 3 and ex[1] / ex[0] > 3
 
 
 def test_ark45_stops_after_max_attempts(torch):
