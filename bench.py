@@ -405,18 +405,22 @@ def form_ark45(torch, rk4ip, workloads):
                       "us_per_accepted_step": t / (accepted / g.batch) * 1e6,
                       "rk4ip_fixed_us_per_step": tf / 100 * 1e6,
                       "accepted_step_cost_in_rk4ip_steps": (t / (accepted / g.batch)) / (tf / 100)}
-    counts = {}
+    counts, ex_counts = {}, {}
     for n in (256, 512, 1024, 2048, 4096):
         gs = workloads.Group(n=(n,), lo=(-20.0,), hi=(20.0,), gnl=-1.0)
         x = gs.axis(0)
-        f0 = torch.tensor((1 / np.cosh(x) * np.exp(0.5j * x)).astype(np.complex64), device="cuda")
+        f0 = (1 / np.cosh(x) * np.exp(0.5j * x)).astype(np.complex64)
         pl = rk4ip.Plan([rk4ip.make_problem(gs.n, gs.lo, gs.hi, 1e-3, g_nl=-1.0)])
-        hh = torch.full((1,), 1e-3, dtype=torch.float64, device="cuda")
-        s1, _ = pl.ark45(f0, 2.0, 1e-7, hh)
-        counts[str(n)] = int(s1[0, 0])
+        for explicit, dst in ((False, counts), (True, ex_counts)):
+            if explicit and n > 1024:
+                continue  # the explicit method needs ~N^2 steps
+            d = torch.tensor(f0, device="cuda")
+            hh = torch.full((1,), 1e-3, dtype=torch.float64, device="cuda")
+            s1, _ = pl.ark45(d, 2.0, 1e-7, hh, explicit=explicit)
+            dst[str(n)] = int(s1[0, 0])
         pl.destroy()
     out["steps_vs_resolution"] = {"workload": "NLSE soliton on [-20, 20), t = 2, tol = 1e-7",
-                                  "accepted_steps": counts}
+                                  "accepted_steps": counts, "accepted_steps_explicit_method": ex_counts}
     return out
 
 
