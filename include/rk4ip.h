@@ -21,6 +21,15 @@
  * D is applied per lattice axis (the tensor-product factorisation of Sec. 3.2):
  * a 1D FFT along the axis, a multiply by e^{L_a dt/2}, the inverse FFT.
  *
+ * Also available (each described at its flag, field or entry point):
+ *   - the semi-implicit step (RK4IP_FLAG_SEMI_IMPLICIT) and noise substeps that sample one
+ *     Wiener path at several step sizes (rk4ip_problem.noise_substeps);
+ *   - the adaptive Cash-Karp RK4(5) in the interaction picture, or the explicit
+ *     comparison method, for 1D groups (rk4ip_ark45);
+ *   - a real Wiener noise in the potential (sigma_V) and, on 1D groups, a non-local
+ *     convolution potential (conv_K);
+ *   - cosine and sine bases on 1D half domains (basis).
+ *
  * Conventions shared by every entry point
  *   - Fields are complex64, interleaved (re, im) float pairs, in device memory owned
  *     by the caller. One instance is n[2] x n[1] x n[0] values with axis 0 (x)
