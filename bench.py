@@ -458,7 +458,8 @@ def form_potential_terms(torch, rk4ip, workloads, steps: int = 100):
 def form_bases(torch, rk4ip, workloads, steps: int = 100):
     """The cosine basis on a half domain next to the Fourier basis on the full one (the
     half-interval example of Sec. 4, batched): 2048 lines of the trapped 1D GPE, 512
-    cosine points on (0, 8) against 1024 Fourier points on (-8, 8), graph-replayed."""
+    cosine points on (0, 8) against 1024 Fourier points on (-8, 8), graph-replayed with
+    several steps per launch."""
     import numpy as np
 
     out = {"workload": "2048 lines, trapped 1D GPE (g = 1), 512 cosine points on (0, 8) vs 1024 Fourier points "
@@ -473,7 +474,7 @@ def form_bases(torch, rk4ip, workloads, steps: int = 100):
              f_half),
             ("fourier_full", rk4ip.make_problem((2 * n,), (-L + dx / 2,), (L + dx / 2,), h, batch=B, g_nl=1.0,
                                                 trap=(1.0, 0, 0)), f_full)):
-        plan = rk4ip.Plan([prob], flags=rk4ip.RK4IP_FLAG_GRAPH | rk4ip.RK4IP_FLAG_AUTOTUNE)
+        plan = rk4ip.Plan([prob], flags=rk4ip.RK4IP_FLAG_GRAPH | rk4ip.RK4IP_FLAG_AUTOTUNE | rk4ip.RK4IP_FLAG_FUSE_1D)
         psi0 = torch.tensor(f.reshape(-1), device="cuda")
         psi = psi0.clone()
         plan.run(psi, 40)

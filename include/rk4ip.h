@@ -110,8 +110,7 @@ typedef struct {
                                 cos / sin(k_m (x - lo)), k_m = pi m / (hi - lo) (cosine,
                                 m = 0..n-1) or pi (m + 1) / (hi - lo) (sine). The step runs on
                                 the even / odd extension of the line (2n <= 4096, 2048 with
-                                FP64 transforms), one step per launch (RK4IP_FLAG_FUSE_1D does
-                                not fuse it); not with conv_K. Plans holding such a group
+                                FP64 transforms); not with conv_K. Plans holding such a group
                                 take rk4ip_step and rk4ip_run without samples; the other
                                 entry points return RK4IP_ERR_INVALID_ARG. */
     int64_t n[3];            /* points per axis, axis 0 = x (contiguous); unused axes = 1 */

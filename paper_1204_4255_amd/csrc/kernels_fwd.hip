@@ -69,6 +69,29 @@ __global__ void __launch_bounds__((FFTShape<N, RR>::T * LPB))
     int64_t step = read_step(step_off, step_base);
     __syncthreads();  // tables staged
     for (int s = 0; s < nsteps; s++, step++) {
+        if (g.basis && s > 0) {
+            // rebuild the mirrored half from the stored half's values, exactly as a reload
+            // between launches would: element e < n takes element 2n - 1 - e (the same
+            // point), negated for the sine basis (uniform branch)
+            c32* xs = reinterpret_cast<c32*>(lds);  // room for LPB lines of N values
+            __syncthreads();  // the last step's exchanges are done
+#pragma unroll
+            for (int m = 0; m < R; m++) {
+                const int e = t + m * T;
+                if (e >= NM) xs[l * N + e] = f[0][m];
+            }
+            __syncthreads();
+            const float sg = g.basis == 2 ? -1.0f : 1.0f;
+#pragma unroll
+            for (int m = 0; m < R; m++) {
+                const int e = t + m * T;
+                if (e < NM) {
+                    const c32 v = xs[l * N + (N - 1 - e)];
+                    f[0][m] = make_float2(sg * v.x, sg * v.y);
+                }
+            }
+            __syncthreads();  // before this step's transforms reuse the buffer
+        }
         c32 nz[R];
 #pragma unroll
         for (int m = 0; m < R; m++) {

@@ -595,9 +595,7 @@ int enqueue_lines(rk4ip_plan_t plan, hipStream_t stream, float2* psi, int64_t st
     for (size_t gi = 0; gi < plan->groups.size(); gi++) {
         auto& g = plan->groups[gi];
         if (g.p.ndim != 1 || nsteps <= 0) continue;
-        // a cosine / sine group takes one step per launch: each step rebuilds the even / odd
-        // extension from the stored half domain, so it stays exactly symmetric
-        if (allow_fuse && (plan->flags & RK4IP_FLAG_FUSE_1D) && !g.p.basis) {
+        if (allow_fuse && (plan->flags & RK4IP_FLAG_FUSE_1D)) {
             rc = timed_launch(plan, stream, (int)gi, 0, capturing, [&] {
                 return rk4ip::launch_line_step(g.d, psi, (int)nsteps, step_off, step_base, plan->f64,
                                                 plan->sched[gi][0].radix, plan->si, stream);
