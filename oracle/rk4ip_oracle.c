@@ -231,7 +231,7 @@ static cplx* make_E(const ora_problem* p, double sign_of_phase) {
  * DST-II sums, the multiply by exp(L(k_m) h/2), and the matching inverse sums (weights
  * 1, 2, ..., 2 for the cosines and 2, ..., 2, 1 for the sines, over n). The angles
  * pi q / (2n) come from one table indexed by q = m'(2j + 1) mod 4n. */
-static void apply_D_basis(const ora_problem* p, cplx* f) {
+static void apply_D_basis(const ora_problem* p, cplx* f, double sign_of_phase) {
     int64_t n = p->n[0];
     double L = p->hi[0] - p->lo[0];
     int sine = p->basis == 2;
@@ -251,7 +251,7 @@ static void apply_D_basis(const ora_problem* p, cplx* f) {
             acc += f[j] * (sine ? st[q] : ct[q]);
         }
         double k = ORA_PI * (double)mm / L;
-        c[m] = acc * cexp((-I * p->alpha * k * k - p->gamma) * p->h / 2.0);
+        c[m] = acc * cexp((-I * sign_of_phase * p->alpha * k * k - p->gamma) * p->h / 2.0);
     }
 #pragma omp parallel for schedule(static)
     for (int64_t j = 0; j < n; j++) {
@@ -273,7 +273,7 @@ static void apply_D_basis(const ora_problem* p, cplx* f) {
  * local multiplication in the spectral basis (Sec. 3.6, last paragraph). */
 static void apply_D(const ora_problem* p, const cplx* E, cplx* f) {
     if (p->basis) {
-        apply_D_basis(p, f);
+        apply_D_basis(p, f, 1.0);
         return;
     }
     int64_t M = npts(p);
@@ -1132,7 +1132,7 @@ int ora_ark45(const ora_problem* p, cplx* psi, double t_span, double tol, int64_
 
 static void apply_D_dense(const ora_problem* p, const cplx* E, cplx* f) {
     if (p->basis) {
-        apply_D_basis(p, f);  /* already a dense sum */
+        apply_D_basis(p, f, 1.0);  /* already a dense sum */
         return;
     }
     int64_t M = npts(p);
@@ -1172,7 +1172,9 @@ int ora_apply_D(const ora_problem* p, cplx* f, int dense, int adjoint) {
     cplx* E = make_E(p, adjoint ? -1.0 : 1.0);
     int64_t M = npts(p);
     for (int64_t b = 0; b < p->batch; b++) {
-        if (dense)
+        if (p->basis)
+            apply_D_basis(p, f + b * M, adjoint ? -1.0 : 1.0);  /* the basis sums are dense */
+        else if (dense)
             apply_D_dense(p, E, f + b * M);
         else
             apply_D(p, E, f + b * M);
