@@ -75,3 +75,16 @@ def test_without_the_kinetic_term_only_the_damping_is_left(case, gamma):
     f = _field(np.random.Generator(np.random.PCG64(seed)), p.shape)
     d = oracle.apply_D(p, f)
     assert np.linalg.norm(d - np.exp(-gamma * kw["h"] / 2) * f) < 1e-12 * np.linalg.norm(f)
+
+
+@SETTINGS
+@given(lattices(bases=(0, 1, 2)), st.floats(-5.0, 5.0), st.floats(0.0, 2.0 * np.pi), st.sampled_from([0, 1]))
+def test_a_global_phase_commutes_with_the_step(case, gnl, phase, integrator):
+    # G depends on |psi|^2 only, so without noise step(e^{i c} psi) = e^{i c} step(psi)
+    kw, seed = case
+    kw = dict(kw, h=min(kw["h"], 0.05))
+    p = oracle.Problem(gnl=gnl, trap=(1.0, 0.5, 0.3), gamma=0.1, integrator=integrator, **kw)
+    f = 0.5 * _field(np.random.Generator(np.random.PCG64(seed)), p.shape)
+    a = oracle.step(p, np.exp(1j * phase) * f)
+    b = np.exp(1j * phase) * oracle.step(p, f)
+    assert np.linalg.norm(a - b) < 1e-11 * np.linalg.norm(b)
