@@ -1,7 +1,8 @@
 """Slow GPU parity run, skipped unless RK4IP_SLOW_TESTS=1: the 3D GPE on 256^3 for its
-full 500 steps, the whole field of both precision forms against the FP64 oracle every 50
-steps. The oracle needs about ten minutes of 16 host cores for this, so it prints its
-progress every 25 steps."""
+full 500 steps, RK4IP and the semi-implicit step, the whole field of both precision forms
+against the FP64 oracle every 50 steps. The oracle needs about ten (RK4IP) or seven
+(semi-implicit) minutes of 16 host cores for this, so it prints its progress every 25
+steps."""
 import os
 import time
 
@@ -17,15 +18,16 @@ pytestmark = [pytest.mark.gpu,
               pytest.mark.skipif(os.environ.get("RK4IP_SLOW_TESTS") != "1", reason="set RK4IP_SLOW_TESTS=1")]
 
 
-def test_gpe3d_256_full_run_vs_oracle():
+@pytest.mark.parametrize("integrator", [0, 1], ids=["rk4ip", "semi_implicit"])
+def test_gpe3d_256_full_run_vs_oracle(integrator):
     import torch
 
     w = W.gpe3d()
     g = w.groups[0]
-    p = oprob(g, w.h)
+    p = oprob(g, w.h, integrator=integrator)
     f = quantised(w.psi0[0])
     probs, _k = rk4ip.problems_from_workload(w)
-    base = rk4ip.RK4IP_FLAG_GRAPH | rk4ip.RK4IP_FLAG_AUTOTUNE
+    base = rk4ip.RK4IP_FLAG_GRAPH | rk4ip.RK4IP_FLAG_AUTOTUNE | (rk4ip.RK4IP_FLAG_SEMI_IMPLICIT if integrator else 0)
     forms = {"c64": base, "fp64": base | rk4ip.RK4IP_FLAG_FP64_TRANSFORMS}
     plans = {k: rk4ip.Plan(probs, flags=fl) for k, fl in forms.items()}
     fields = {k: torch.tensor(f.astype(np.complex64).reshape(-1), device="cuda") for k in forms}
