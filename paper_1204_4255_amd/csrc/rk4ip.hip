@@ -248,6 +248,20 @@ void drop_graph(rk4ip_plan_t plan) {
     plan->graph_steps = 0;
 }
 
+// Waits for the plan's stream, frees the HIP objects the plan created (graph, capture
+// stream, timing events) and the plan itself. The workspace is the caller's.
+void release_plan(rk4ip_plan_t plan) {
+    (void)hipStreamSynchronize(plan->stream);
+    drop_graph(plan);
+    if (plan->capture_stream) (void)hipStreamDestroy(plan->capture_stream);
+    for (auto& t : plan->timed) {
+        (void)hipEventDestroy(t.a);
+        (void)hipEventDestroy(t.b);
+    }
+    for (auto e : plan->spare) (void)hipEventDestroy(e);
+    delete plan;
+}
+
 // Tables of one axis (FP64 arithmetic; stored in FP32, and in FP64 for FP64-transform plans).
 void build_tables(const rk4ip_problem& p, int a, std::vector<float2>& E, std::vector<float2>& tw,
                   std::vector<double2>* E64 = nullptr, std::vector<double2>* tw64 = nullptr) {
@@ -901,7 +915,7 @@ int rk4ip_plan(const rk4ip_problem* probs, int nprob, void* workspace, size_t ws
             }
             if (e1 != hipSuccess || e2 != hipSuccess) {
                 rc = fail_hip(plan, e1 != hipSuccess ? e1 : e2, "table upload");
-                delete plan;
+                release_plan(plan);
                 return rc;
             }
             d.E[a] = reinterpret_cast<const float2*>(plan->ws + g.tab_off[a]);
@@ -918,7 +932,7 @@ int rk4ip_plan(const rk4ip_problem* probs, int nprob, void* workspace, size_t ws
                                       hipMemcpyHostToDevice);
             if (e1 != hipSuccess) {
                 rc = fail_hip(plan, e1, "table upload");
-                delete plan;
+                release_plan(plan);
                 return rc;
             }
             d.convK = reinterpret_cast<const float2*>(plan->ws + g.conv_off);
@@ -942,7 +956,7 @@ int rk4ip_plan(const rk4ip_problem* probs, int nprob, void* workspace, size_t ws
             const int np = pass_list(g.p.ndim, plan->si, defs);
             for (int k = 0; k < np; k++) {
                 if (!default_f64_sched(g, defs[k].axis, defs[k].mode, &plan->sched[gi][k])) {
-                    delete plan;
+                    release_plan(plan);
                     return RK4IP_ERR_UNSUPPORTED_SHAPE;
                 }
             }
@@ -951,7 +965,7 @@ int rk4ip_plan(const rk4ip_problem* probs, int nprob, void* workspace, size_t ws
     if (flags & RK4IP_FLAG_AUTOTUNE) {
         rc = autotune(plan);
         if (rc != RK4IP_OK) {
-            delete plan;
+            release_plan(plan);
             return rc;
         }
     }
@@ -984,7 +998,7 @@ int rk4ip_plan(const rk4ip_problem* probs, int nprob, void* workspace, size_t ws
     hipError_t e = hipMemset(plan->ws + L.header, 0, kAlign);
     if (e != hipSuccess) {
         rc = fail_hip(plan, e, "hipMemset");
-        delete plan;
+        release_plan(plan);
         return rc;
     }
     *out = plan;
@@ -1213,15 +1227,7 @@ int rk4ip_status(rk4ip_plan_t plan) {
 
 int rk4ip_destroy(rk4ip_plan_t plan) {
     if (!plan) return RK4IP_ERR_INVALID_ARG;
-    (void)hipStreamSynchronize(plan->stream);
-    drop_graph(plan);
-    if (plan->capture_stream) (void)hipStreamDestroy(plan->capture_stream);
-    for (auto& t : plan->timed) {
-        (void)hipEventDestroy(t.a);
-        (void)hipEventDestroy(t.b);
-    }
-    for (auto e : plan->spare) (void)hipEventDestroy(e);
-    delete plan;
+    release_plan(plan);
     return RK4IP_OK;
 }
 

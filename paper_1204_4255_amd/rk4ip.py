@@ -115,6 +115,21 @@ def _ptr(t) -> Optional[int]:
     return int(t.data_ptr())
 
 
+def _buf(t, numel: int, dtype, what: str, optional: bool = False) -> Optional[int]:
+    """Device pointer of a contiguous tensor of exactly `numel` elements of `dtype`. The C
+    ABI sees only the pointer, so a buffer of the wrong size or type is refused here
+    before any kernel could read or write past its end."""
+    if t is None:
+        if optional:
+            return None
+        raise Rk4ipError(RK4IP_ERR_INVALID_ARG, f"{what}: missing")
+    if not t.is_cuda or t.dtype != dtype or not t.is_contiguous() or t.numel() != numel:
+        raise Rk4ipError(RK4IP_ERR_INVALID_ARG,
+                         f"{what}: need a contiguous device {dtype} tensor of {numel} elements, got "
+                         f"{t.dtype} {tuple(t.shape)} on {t.device}{'' if t.is_contiguous() else ' (strided)'}")
+    return int(t.data_ptr())
+
+
 def _stream():
     import torch
 
@@ -148,7 +163,14 @@ def make_problem(n: Sequence[int], lo: Sequence[float], hi: Sequence[float], dt:
         p.trap[a] = float(trap[a]) if a < len(trap) else 0.0
     p.batch = int(batch)
     p.dt, p.alpha, p.gamma, p.g_nl = float(dt), float(alpha), float(gamma), float(g_nl)
-    p.V_grid = _ptr(V_grid)
+    if V_grid is not None:
+        import torch
+
+        M = int(np.prod([p.n[a] for a in range(3)]))
+        p.V_grid = _buf(V_grid, p.batch * M, torch.float32, "V_grid")
+        p._V_grid = V_grid  # the struct holds the tensor alive with its pointer
+    else:
+        p.V_grid = None
     p.sigma = float(sigma)
     p.seed = int(seed) & 0xFFFFFFFFFFFFFFFF
     p.id_base = int(id_base) & 0xFFFFFFFF
@@ -157,6 +179,8 @@ def make_problem(n: Sequence[int], lo: Sequence[float], hi: Sequence[float], dt:
     p.basis = int(basis)
     if conv_K is not None:
         ck = np.ascontiguousarray(conv_K, dtype=np.float64).reshape(-1)
+        if ck.size != p.n[0]:
+            raise Rk4ipError(RK4IP_ERR_INVALID_ARG, f"conv_K: need {p.n[0]} values, got {ck.size}")
         p._conv_K = ck
         p.conv_K = ck.ctypes.data
     else:
@@ -180,8 +204,14 @@ def rk4ip_strerror(status: int) -> str:
 
 def rk4ip_debug_philox(seed: int, ctr, out) -> None:
     """Philox4x32-10 of device uint32 counters [n][4] (torch int32 storage) into out."""
+    import torch
+
     n = ctr.numel() // 4
-    _check(load().rk4ip_debug_philox(int(seed) & 0xFFFFFFFFFFFFFFFF, _ptr(ctr), n, _ptr(out), _stream()),
+    if ctr.numel() != 4 * n:
+        raise Rk4ipError(RK4IP_ERR_INVALID_ARG, "ctr: need [n][4] words")
+    cp = _buf(ctr, 4 * n, torch.int32, "ctr")
+    op = _buf(out, 4 * n, torch.int32, "out")
+    _check(load().rk4ip_debug_philox(int(seed) & 0xFFFFFFFFFFFFFFFF, cp, n, op, _stream()),
            what="rk4ip_debug_philox")
 
 
@@ -222,13 +252,24 @@ class Plan:
         except Exception:
             pass
 
+    def _group_points(self, group: int) -> int:
+        if not 0 <= int(group) < len(self.probs):
+            raise Rk4ipError(RK4IP_ERR_INVALID_ARG, f"group {group} out of range")
+        p = self.probs[group]
+        return int(p.n[0] * p.n[1] * p.n[2])
+
+    def _psi(self, psi, what: str = "psi") -> int:
+        import torch
+
+        return _buf(psi, self.points, torch.complex64, what)
+
     def _sync_stream(self):
         load().rk4ip_set_stream(self.handle, _stream())
 
     # -- calls
     def step(self, psi, step_index: int = 0):
         self._sync_stream()
-        _check(load().rk4ip_step(self.handle, _ptr(psi), int(step_index)), self.handle, "rk4ip_step")
+        _check(load().rk4ip_step(self.handle, self._psi(psi), int(step_index)), self.handle, "rk4ip_step")
 
     def run(self, psi, nsteps: int, step0: int = 0, sample_every: int = 0, ckpt_every: int = 0):
         """Returns (diag or None, ckpt or None) as device tensors."""
@@ -242,7 +283,7 @@ class Plan:
         if ckpt_every > 0:
             nck = (nsteps + ckpt_every - 1) // ckpt_every
             ckpt = torch.empty((max(nck, 1), self.points), dtype=torch.complex64, device=psi.device)
-        _check(load().rk4ip_run(self.handle, _ptr(psi), int(step0), int(nsteps), int(sample_every), _ptr(diag),
+        _check(load().rk4ip_run(self.handle, self._psi(psi), int(step0), int(nsteps), int(sample_every), _ptr(diag),
                                 _ptr(ckpt), int(ckpt_every)), self.handle, "rk4ip_run")
         return diag, ckpt
 
@@ -251,7 +292,7 @@ class Plan:
 
         self._sync_stream()
         out = torch.zeros((self.ninst, 4), dtype=torch.float64, device=psi.device)
-        _check(load().rk4ip_diagnostics(self.handle, _ptr(psi), _ptr(out)), self.handle, "rk4ip_diagnostics")
+        _check(load().rk4ip_diagnostics(self.handle, self._psi(psi), _ptr(out)), self.handle, "rk4ip_diagnostics")
         return out
 
     def overlap(self, group: int, phi, psi):
@@ -259,7 +300,8 @@ class Plan:
 
         self._sync_stream()
         out = torch.zeros((int(self.probs[group].batch), 2), dtype=torch.float64, device=psi.device)
-        _check(load().rk4ip_overlap(self.handle, group, _ptr(phi), _ptr(psi), _ptr(out)), self.handle, "rk4ip_overlap")
+        _check(load().rk4ip_overlap(self.handle, group, _buf(phi, self._group_points(group), torch.complex64, "phi"),
+                                    self._psi(psi), _ptr(out)), self.handle, "rk4ip_overlap")
         return out
 
     def moments(self, group: int, psi):
@@ -270,7 +312,7 @@ class Plan:
         M = int(p.n[0] * p.n[1] * p.n[2])
         mean = torch.zeros(M, dtype=torch.float64, device=psi.device)
         var = torch.zeros(M, dtype=torch.float64, device=psi.device)
-        _check(load().rk4ip_moments(self.handle, group, _ptr(psi), _ptr(mean), _ptr(var)), self.handle,
+        _check(load().rk4ip_moments(self.handle, group, self._psi(psi), _ptr(mean), _ptr(var)), self.handle,
                "rk4ip_moments")
         return mean, var
 
@@ -287,8 +329,10 @@ class Plan:
         aligned = (ws.data_ptr() + 255) // 256 * 256
         g = torch.empty_like(lambda_T)
         gV = torch.zeros(self.points, dtype=torch.float32, device=lambda_T.device) if want_V else None
-        _check(load().rk4ip_adjoint(self.handle, _ptr(ckpt), int(step0), int(nsteps), int(ckpt_every),
-                                    _ptr(lambda_T), _ptr(g), _ptr(gV), ctypes.c_void_p(aligned), nb),
+        nck = max((int(nsteps) + int(ckpt_every) - 1) // max(int(ckpt_every), 1), 1)
+        _check(load().rk4ip_adjoint(self.handle, _buf(ckpt, nck * self.points, torch.complex64, "ckpt"), int(step0),
+                                    int(nsteps), int(ckpt_every), self._psi(lambda_T, "lambda_T"), _ptr(g), _ptr(gV),
+                                    ctypes.c_void_p(aligned), nb),
                self.handle, "rk4ip_adjoint")
         self._keep_adj_ws = ws
         return g, gV
@@ -306,7 +350,8 @@ class Plan:
         log = None
         if log_cap > 0:
             log = torch.full((self.ninst, log_cap), float("nan"), dtype=torch.float64, device=psi.device)
-        _check(load().rk4ip_ark45(self.handle, _ptr(psi), float(t_span), float(tol), int(max_attempts), _ptr(h),
+        _check(load().rk4ip_ark45(self.handle, self._psi(psi), float(t_span), float(tol), int(max_attempts),
+                                  _buf(h, self.ninst, torch.float64, "h"),
                                   _ptr(stats), _ptr(log), int(log_cap), int(bool(explicit))), self.handle,
                "rk4ip_ark45")
         return stats, log
@@ -346,15 +391,19 @@ class Plan:
         import torch
 
         self._sync_stream()
+        self._group_points(group)
+        n = int(self.probs[group].n[axis]) if 0 <= int(axis) < 3 else 0
+        if n <= 0 or x.numel() % n:
+            raise Rk4ipError(RK4IP_ERR_INVALID_ARG, f"fft: {x.numel()} elements are not whole lines of {n}")
+        xp = _buf(x, x.numel(), torch.complex64, "x")
         out = torch.empty_like(x)
-        n = int(self.probs[group].n[axis])
-        _check(load().rk4ip_debug_fft(self.handle, group, axis, _ptr(x), _ptr(out), x.numel() // n, sign),
+        _check(load().rk4ip_debug_fft(self.handle, group, axis, xp, _ptr(out), x.numel() // n, sign),
                self.handle, "rk4ip_debug_fft")
         return out
 
     def apply_D(self, psi, adjoint: bool = False):
         self._sync_stream()
-        _check(load().rk4ip_debug_apply_D(self.handle, _ptr(psi), int(bool(adjoint))), self.handle,
+        _check(load().rk4ip_debug_apply_D(self.handle, self._psi(psi), int(bool(adjoint))), self.handle,
                "rk4ip_debug_apply_D")
 
 

@@ -183,3 +183,19 @@ def test_cosine_and_sine_bases_sizes_and_limits(lib):
         assert rk4ip.rk4ip_workspace_bytes([_p(basis=basis)]) == 0
         assert rk4ip.rk4ip_workspace_bytes([rk4ip.make_problem(n=(64,), basis=basis, conv_K=np.ones(64),
                                                                **line)]) == 0
+
+
+def test_binding_refuses_buffers_that_do_not_fit(lib):
+    """The C ABI takes bare pointers, so the binding checks every tensor it hands over:
+    host tensors, wrong dtypes, strided views and wrong sizes are refused before a call."""
+    import torch
+
+    with pytest.raises(rk4ip.Rk4ipError):
+        rk4ip._buf(torch.zeros(8, dtype=torch.complex64), 8, torch.complex64, "psi")  # host memory
+    with pytest.raises(rk4ip.Rk4ipError):
+        rk4ip._buf(None, 8, torch.complex64, "psi")
+    assert rk4ip._buf(None, 8, torch.complex64, "psi", optional=True) is None
+    with pytest.raises(rk4ip.Rk4ipError):
+        rk4ip.make_problem((64,), (0,), (1,), 1e-3, conv_K=np.ones(63))
+    with pytest.raises(rk4ip.Rk4ipError):
+        rk4ip.make_problem((64,), (0,), (1,), 1e-3, batch=2, V_grid=torch.zeros(128))  # host memory
