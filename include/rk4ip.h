@@ -51,6 +51,10 @@
  *   - Every call returns RK4IP_OK (0) or a negative status; nothing aborts and no C++
  *     exception crosses the ABI. A plan is not thread-safe; distinct plans are
  *     independent.
+ *   - Device buffers are bare pointers, checked for NULL only: each must hold at least
+ *     the elements its call documents (a field holds every point of every instance of
+ *     every group, in group order), or kernels read and write past its end. Callers
+ *     that hold sized buffers (the Python binding does) check the sizes before the call.
  */
 #ifndef RK4IP_H
 #define RK4IP_H
