@@ -214,8 +214,8 @@ size_t rk4ip_adjoint_workspace_bytes(rk4ip_plan_t plan, int64_t ckpt_every);
  *   h      device double [ninst]: in, the first trial step of each instance (> 0); out,
  *          the next trial step (pass it back to continue the run over another interval).
  *          h lives on the device, so it is not checked here: an instance whose trial
- *          step is not positive and finite stops after max_attempts trial steps without
- *          reaching t_span (stats[2] = 0).
+ *          step is not positive and finite takes no step (its field and h are left as
+ *          they were, stats = {0, 0, t_span == 0}).
  *   stats  device int64 [ninst][3]: accepted steps, rejected steps, 1 if t_span was
  *          reached (0 when the instance used max_attempts trial steps first).
  *   h_log  device double [ninst][log_cap]: the accepted step sizes in order (entries past

@@ -1,0 +1,129 @@
+"""Degenerate cases of the entry points on a GPU: a run of zero steps leaves the field as
+it was in every form (and its one sample is the field's diagnostics), and the adaptive
+integrator over an empty interval, or with a trial step that is not positive and
+finite, takes no step while the other instances of the batch run as they would alone."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_helpers import log, quantised, rel
+from paper_1204_4255_amd import rk4ip
+from paper_1204_4255_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+G = rk4ip.RK4IP_FLAG_GRAPH
+A = rk4ip.RK4IP_FLAG_AUTOTUNE
+F1 = rk4ip.RK4IP_FLAG_FUSE_1D
+F64 = rk4ip.RK4IP_FLAG_FP64_TRANSFORMS
+SI = rk4ip.RK4IP_FLAG_SEMI_IMPLICIT
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+
+    assert t.cuda.is_available(), "GPU tests need a GPU"
+    rk4ip.load()
+    return t
+
+
+def _field(torch, shape, seed=3):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    f = quantised(rng.standard_normal(shape) + 1j * rng.standard_normal(shape))
+    return torch.tensor(f.astype(np.complex64).reshape(-1), device="cuda")
+
+
+@pytest.mark.parametrize("n,batch", [((256,), 3), ((64, 32), 2), ((32, 16, 8), 2)])
+@pytest.mark.parametrize("flags", [0, G | A, G | F1, SI, SI | G, F64])
+def test_zero_steps_leave_the_field(torch, n, batch, flags):
+    log(f"zero steps: n={n} batch={batch} flags={flags}")
+    nd = len(n)
+    p = rk4ip.make_problem(n, (-4.0,) * nd, (4.0,) * nd, 1e-3, batch=batch, g_nl=1.0, trap=(1.0,) * nd,
+                           gamma=0.05, sigma=0.01, seed=5)
+    plan = rk4ip.Plan([p], flags=flags)
+    d = _field(torch, (batch,) + tuple(reversed(n)))
+    before = d.clone()
+    plan.run(d, 0, step0=17)
+    diag, _ = plan.run(d, 0, sample_every=1)
+    ref = plan.diagnostics(d)
+    torch.cuda.synchronize()
+    assert torch.equal(d, before)
+    assert diag.shape == (1, batch, 4) and torch.equal(diag[0], ref)
+    # a zero-step run between two runs changes nothing either
+    a = before.clone()
+    plan.run(a, 6, step0=3)
+    b = before.clone()
+    plan.run(b, 2, step0=3)
+    plan.run(b, 0, step0=5)
+    plan.run(b, 4, step0=5)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("basis", [1, 2])
+def test_zero_steps_on_a_half_domain(torch, basis):
+    p = rk4ip.make_problem((128,), (0.0,), (7.0,), 1e-3, batch=2, g_nl=1.0, trap=(1.0, 0, 0), basis=basis)
+    for flags in (0, G | F1, SI):
+        plan = rk4ip.Plan([p], flags=flags)
+        d = _field(torch, (2, 128))
+        before = d.clone()
+        plan.run(d, 0)
+        torch.cuda.synchronize()
+        assert torch.equal(d, before)
+
+
+def _solitons(n, amps):
+    g = W.Group(n=(n,), lo=(-20.0,), hi=(20.0,), gnl=-1.0, batch=len(amps))
+    x = g.axis(0)
+    a = np.asarray(amps, float)[:, None]
+    return g, quantised(a / np.cosh(a * x[None]) * np.exp(0.5j * x[None]))
+
+
+def test_ark45_over_an_empty_interval(torch):
+    g, f0 = _solitons(256, [1.0, 1.5, 2.0])
+    plan = rk4ip.Plan([rk4ip.make_problem(g.n, g.lo, g.hi, 1e-3, batch=g.batch, g_nl=g.gnl)])
+    d = torch.tensor(f0.astype(np.complex64).reshape(-1), device="cuda")
+    before = d.clone()
+    h = torch.tensor([1e-3, 0.5, 2.0], dtype=torch.float64, device="cuda")
+    h0 = h.clone()
+    stats, _ = plan.ark45(d, 0.0, 1e-6, h)
+    torch.cuda.synchronize()
+    assert torch.equal(d, before) and torch.equal(h, h0)
+    assert stats.cpu().numpy().tolist() == [[0, 0, 1]] * 3
+
+
+def test_ark45_trial_steps_that_are_not_positive(torch):
+    """Instances given h = 0, -1e-3 or NaN take no step and keep field and h; the valid
+    instances of the same launch end exactly as in a batch of valid instances, and match
+    the oracle's Cash-Karp steps of the sizes they took."""
+    amps = [1.0, 1.5, 2.0, 1.2]
+    g, f0 = _solitons(256, amps)
+    plan = rk4ip.Plan([rk4ip.make_problem(g.n, g.lo, g.hi, 1e-3, batch=g.batch, g_nl=g.gnl)])
+    T, tol = 0.5, 1e-6
+    good = torch.full((4,), 1e-3, dtype=torch.float64, device="cuda")
+    a = torch.tensor(f0.astype(np.complex64).reshape(-1), device="cuda")
+    sa, _ = plan.ark45(a, T, tol, good)
+    bad = torch.tensor([1e-3, 0.0, -1e-3, float("nan")], dtype=torch.float64, device="cuda")
+    b = torch.tensor(f0.astype(np.complex64).reshape(-1), device="cuda")
+    before = b.clone()
+    sb, hl = plan.ark45(b, T, tol, bad, log_cap=64)
+    torch.cuda.synchronize()
+    sa, sb = sa.cpu().numpy(), sb.cpu().numpy()
+    a2, b2, before2 = (t.reshape(4, 256) for t in (a, b, before))
+    log(f"  stats valid batch {sa.tolist()}, mixed batch {sb.tolist()}")
+    assert torch.equal(b2[0], a2[0]) and sb[0].tolist() == sa[0].tolist() and bad[0].item() == good[0].item()
+    assert torch.equal(b2[1:], before2[1:])
+    assert sb[1:].tolist() == [[0, 0, 0]] * 3
+    hb = bad.cpu().numpy()
+    assert hb[1] == 0.0 and hb[2] == -1e-3 and np.isnan(hb[3])
+    # the valid instance against the oracle's Cash-Karp steps of the same sizes
+    acc = int(sb[0, 0])
+    assert 0 < acc <= 64
+    op = oracle.Problem(n=g.n, lo=g.lo, hi=g.hi, h=1e-3, gnl=g.gnl)
+    ref = f0[0:1].astype(np.complex128)
+    for hh in hl.cpu().numpy()[0, :acc]:
+        ref, _ = oracle.ck_step(op, ref, hh)
+    err = rel(b2[0].cpu().numpy().astype(np.complex128), ref[0])
+    log(f"  valid instance: {acc} accepted steps, vs the oracle's steps {err:.2e}")
+    assert err < 1e-5
