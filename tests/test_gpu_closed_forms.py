@@ -1,0 +1,95 @@
+"""The GPU step against closed forms, with no oracle in between.
+
+* Free spreading: with G = 0 the RK4IP step is D^2 = e^{L h} exactly, and so is the
+  semi-implicit step, so a Gaussian wave packet on a 3D lattice follows the analytic
+  free-particle solution (a product over axes), damped by e^{-gamma t}.
+* Plane wave in a constant potential c: every stage is a multiple of the same mode, so
+  one step multiplies it by e^{L(k) h} (1 + z + z^2/2 + z^3/6 + z^4/24) with z = -i c h,
+  the fourth-order Taylor factor of e^z. A wrong stage weight or a dropped stage changes
+  that factor at some order up to z^4; with |z| = 0.2 every order is far above the
+  rounding, and the factor is told apart from e^z itself."""
+import numpy as np
+import pytest
+
+from gpu_helpers import log, rel
+from paper_1204_4255_amd import rk4ip
+
+pytestmark = pytest.mark.gpu
+
+G = rk4ip.RK4IP_FLAG_GRAPH
+A = rk4ip.RK4IP_FLAG_AUTOTUNE
+SI = rk4ip.RK4IP_FLAG_SEMI_IMPLICIT
+F64 = rk4ip.RK4IP_FLAG_FP64_TRANSFORMS
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+
+    assert t.cuda.is_available(), "GPU tests need a GPU"
+    rk4ip.load()
+    return t
+
+
+def _free_1d(x, t, s0, x0, k0):
+    # i psi_t = -(1/2) psi_xx from a Gaussian of width s0 centred at x0 with momentum k0
+    c = 1 + 1j * t / s0 ** 2
+    return ((np.pi * s0 ** 2) ** -0.25 * c ** -0.5
+            * np.exp(-(x - x0 - k0 * t) ** 2 / (2 * s0 ** 2 * c) + 1j * k0 * x - 0.5j * k0 ** 2 * t))
+
+
+@pytest.mark.parametrize("flags", [G | A, SI | G, F64])
+def test_free_gaussian_in_3d(torch, flags):
+    n = (64, 32, 32)
+    lo, hi = (-10.0, -8.0, -8.0), (10.0, 8.0, 8.0)
+    pars = [(1.3, 0.5, 1.0), (1.2, -0.3, 0.0), (1.4, 0.0, -0.5)]  # (width, centre, momentum) per axis
+    h, S, gam = 0.01, 50, 0.05
+    ax = [lo[a] + np.arange(n[a]) * (hi[a] - lo[a]) / n[a] for a in range(3)]
+
+    def field(t):
+        f = [_free_1d(ax[a], t, *pars[a]) for a in range(3)]
+        return np.einsum("z,y,x->zyx", f[2], f[1], f[0]) * np.exp(-gam * t)
+
+    p = rk4ip.make_problem(n, lo, hi, h, gamma=gam)
+    plan = rk4ip.Plan([p], flags=flags)
+    d = torch.tensor(field(0.0).astype(np.complex64).reshape(-1), device="cuda")
+    plan.run(d, S)
+    torch.cuda.synchronize()
+    got = d.cpu().numpy().astype(np.complex128).reshape(n[::-1])
+    # the complex64 rounding of the initial field (about 6e-8 relative) is carried along
+    # by the exact evolution and counts towards the bound
+    exact = field(S * h)
+    err = rel(got, exact)
+    log(f"free 3D Gaussian, flags {flags}: rel L2 after {S} steps {err:.2e} "
+        f"(norm ratio {np.linalg.norm(got) / np.linalg.norm(exact):.9f})")
+    assert err < 3e-6
+
+
+@pytest.mark.parametrize("flags", [0, G | A, F64])
+def test_plane_waves_in_a_constant_potential(torch, flags):
+    n, L = (32, 16), (8.0, 4.0)
+    modes = [(3, -2), (-5, 1), (0, 7)]  # (m_x, m_y) of each instance
+    h, S, c, gam, alpha = 2e-3, 20, 100.0, 0.1, 0.5
+    x = [np.arange(n[a]) * L[a] / n[a] for a in range(2)]
+    psi0 = np.stack([np.exp(2j * np.pi * (mx * x[0][None, :] / L[0] + my * x[1][:, None] / L[1]))
+                     for mx, my in modes])
+    Vg = torch.full((len(modes), n[1] * n[0]), c, dtype=torch.float32, device="cuda")
+    p = rk4ip.make_problem(n, (0.0, 0.0), L, h, batch=len(modes), alpha=alpha, gamma=gam, V_grid=Vg)
+    plan = rk4ip.Plan([p], flags=flags)
+    d = torch.tensor(psi0.astype(np.complex64).reshape(-1), device="cuda")
+    plan.run(d, S)
+    torch.cuda.synchronize()
+    got = d.cpu().numpy().astype(np.complex128).reshape(psi0.shape)
+    z = -1j * c * h
+    taylor = 1 + z + z ** 2 / 2 + z ** 3 / 6 + z ** 4 / 24
+    for b, (mx, my) in enumerate(modes):
+        k2 = (2 * np.pi * mx / L[0]) ** 2 + (2 * np.pi * my / L[1]) ** 2
+        factor = (np.exp((-1j * alpha * k2 - gam) * h) * taylor) ** S
+        err = rel(got[b], factor * psi0[b])
+        # with |z| = 0.2 the exact e^z is far from the fourth-order factor, so the test
+        # tells the RK4 weights from an exact exponential
+        err_exp = rel(got[b], (np.exp((-1j * alpha * k2 - gam) * h + z)) ** S * psi0[b])
+        log(f"plane wave ({mx}, {my}), flags {flags}: rel L2 after {S} steps {err:.2e} "
+            f"(against e^(z S): {err_exp:.2e})")
+        assert err < 3e-6
+        assert err_exp > 1e-5
