@@ -7,7 +7,8 @@
   one step multiplies it by e^{L(k) h} (1 + z + z^2/2 + z^3/6 + z^4/24) with z = -i c h,
   the fourth-order Taylor factor of e^z. A wrong stage weight or a dropped stage changes
   that factor at some order up to z^4; with |z| = 0.2 every order is far above the
-  rounding, and the factor is told apart from e^z itself."""
+  rounding, and the factor is told apart from e^z itself. The semi-implicit step's
+  factor is 1 + z + z^2/2 + z^3/4 (three midpoint iterations)."""
 import numpy as np
 import pytest
 
@@ -65,29 +66,45 @@ def test_free_gaussian_in_3d(torch, flags):
     assert err < 3e-6
 
 
-@pytest.mark.parametrize("flags", [0, G | A, F64])
-def test_plane_waves_in_a_constant_potential(torch, flags):
-    n, L = (32, 16), (8.0, 4.0)
-    modes = [(3, -2), (-5, 1), (0, 7)]  # (m_x, m_y) of each instance
+@pytest.mark.parametrize("flags", [0, G | A, F64, SI, SI | G, G | rk4ip.RK4IP_FLAG_FUSE_1D,
+                                   SI | G | rk4ip.RK4IP_FLAG_FUSE_1D])
+@pytest.mark.parametrize("dims", [1, 2])
+def test_plane_waves_in_a_constant_potential(torch, flags, dims):
+    """The RK4 factor, and for the semi-implicit step (three iterations of
+    m = a + (h/2) G(m) from m = a, then D(2m - a)) the factor 1 + z + z^2/2 + z^3/4: on a
+    2D lattice (per-axis passes) and on 1D lines (the whole-line kernel)."""
+    if dims == 1:
+        n, L = (256,), (8.0,)
+        modes = [(3, 0), (-20, 0), (40, 0)]
+    else:
+        n, L = (32, 16), (8.0, 4.0)
+        modes = [(3, -2), (-5, 1), (0, 7)]  # (m_x, m_y) of each instance
     h, S, c, gam, alpha = 2e-3, 20, 100.0, 0.1, 0.5
-    x = [np.arange(n[a]) * L[a] / n[a] for a in range(2)]
-    psi0 = np.stack([np.exp(2j * np.pi * (mx * x[0][None, :] / L[0] + my * x[1][:, None] / L[1]))
-                     for mx, my in modes])
-    Vg = torch.full((len(modes), n[1] * n[0]), c, dtype=torch.float32, device="cuda")
-    p = rk4ip.make_problem(n, (0.0, 0.0), L, h, batch=len(modes), alpha=alpha, gamma=gam, V_grid=Vg)
+    x = [np.arange(n[a]) * L[a] / n[a] for a in range(dims)]
+    if dims == 1:
+        psi0 = np.stack([np.exp(2j * np.pi * mx * x[0] / L[0]) for mx, _ in modes])
+    else:
+        psi0 = np.stack([np.exp(2j * np.pi * (mx * x[0][None, :] / L[0] + my * x[1][:, None] / L[1]))
+                         for mx, my in modes])
+    M = int(np.prod(n))
+    Vg = torch.full((len(modes), M), c, dtype=torch.float32, device="cuda")
+    p = rk4ip.make_problem(n, (0.0,) * dims, L, h, batch=len(modes), alpha=alpha, gamma=gam, V_grid=Vg)
     plan = rk4ip.Plan([p], flags=flags)
     d = torch.tensor(psi0.astype(np.complex64).reshape(-1), device="cuda")
     plan.run(d, S)
     torch.cuda.synchronize()
     got = d.cpu().numpy().astype(np.complex128).reshape(psi0.shape)
     z = -1j * c * h
-    taylor = 1 + z + z ** 2 / 2 + z ** 3 / 6 + z ** 4 / 24
+    if flags & SI:
+        taylor = 1 + z + z ** 2 / 2 + z ** 3 / 4
+    else:
+        taylor = 1 + z + z ** 2 / 2 + z ** 3 / 6 + z ** 4 / 24
     for b, (mx, my) in enumerate(modes):
-        k2 = (2 * np.pi * mx / L[0]) ** 2 + (2 * np.pi * my / L[1]) ** 2
+        k2 = (2 * np.pi * mx / L[0]) ** 2 + (2 * np.pi * my / L[-1]) ** 2 * (dims == 2)
         factor = (np.exp((-1j * alpha * k2 - gam) * h) * taylor) ** S
         err = rel(got[b], factor * psi0[b])
-        # with |z| = 0.2 the exact e^z is far from the fourth-order factor, so the test
-        # tells the RK4 weights from an exact exponential
+        # with |z| = 0.2 the exact e^z is far from either factor, so the test tells the
+        # stage weights from an exact exponential
         err_exp = rel(got[b], (np.exp((-1j * alpha * k2 - gam) * h + z)) ** S * psi0[b])
         log(f"plane wave ({mx}, {my}), flags {flags}: rel L2 after {S} steps {err:.2e} "
             f"(against e^(z S): {err_exp:.2e})")
