@@ -110,3 +110,32 @@ def test_plane_waves_in_a_constant_potential(torch, flags, dims):
             f"(against e^(z S): {err_exp:.2e})")
         assert err < 3e-6
         assert err_exp > 1e-5
+
+
+@pytest.mark.parametrize("basis", [1, 2])
+@pytest.mark.parametrize("flags", [0, G | rk4ip.RK4IP_FLAG_FUSE_1D, SI, F64])
+def test_cosine_and_sine_modes_in_a_constant_potential(torch, basis, flags):
+    """On a half domain (0, L) with cell-centred points, cos(q pi x / L) (cosine basis,
+    q >= 0) and sin(q pi x / L) (sine basis, q >= 1) are single modes with k = q pi / L:
+    each step multiplies them by the same factor as a plane wave. This pins the bases'
+    wavenumbers and boundary conditions without the oracle."""
+    n, L = 256, 7.0
+    qs = [0, 3, 40] if basis == 1 else [1, 3, 40]
+    h, S, c, gam, alpha = 2e-3, 20, 100.0, 0.1, 0.5
+    x = (np.arange(n) + 0.5) * L / n
+    mode = np.cos if basis == 1 else np.sin
+    psi0 = np.stack([mode(q * np.pi * x / L) + 0j for q in qs])
+    Vg = torch.full((len(qs), n), c, dtype=torch.float32, device="cuda")
+    p = rk4ip.make_problem((n,), (0.0,), (L,), h, batch=len(qs), alpha=alpha, gamma=gam, V_grid=Vg, basis=basis)
+    plan = rk4ip.Plan([p], flags=flags)
+    d = torch.tensor(psi0.astype(np.complex64).reshape(-1), device="cuda")
+    plan.run(d, S)
+    torch.cuda.synchronize()
+    got = d.cpu().numpy().astype(np.complex128).reshape(psi0.shape)
+    z = -1j * c * h
+    taylor = 1 + z + z ** 2 / 2 + (z ** 3 / 4 if flags & SI else z ** 3 / 6 + z ** 4 / 24)
+    for b, q in enumerate(qs):
+        k2 = (q * np.pi / L) ** 2
+        err = rel(got[b], (np.exp((-1j * alpha * k2 - gam) * h) * taylor) ** S * psi0[b])
+        log(f"basis {basis} mode q={q}, flags {flags}: rel L2 after {S} steps {err:.2e}")
+        assert err < 3e-6
