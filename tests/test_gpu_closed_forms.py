@@ -139,3 +139,42 @@ def test_cosine_and_sine_modes_in_a_constant_potential(torch, basis, flags):
         err = rel(got[b], (np.exp((-1j * alpha * k2 - gam) * h) * taylor) ** S * psi0[b])
         log(f"basis {basis} mode q={q}, flags {flags}: rel L2 after {S} steps {err:.2e}")
         assert err < 3e-6
+
+
+def test_ark45_plane_waves_follow_the_cash_karp_factor(torch):
+    """The adaptive Cash-Karp integrator in the interaction picture on plane waves in a
+    constant potential: every accepted step of size h multiplies the mode by
+    e^{L(k) h} R(-i c h), where R(w) = 1 + w b^T (I - w A)^{-1} 1 is the stability
+    function of the published pair (its coefficients are pinned by the order-condition
+    test of the oracle's tableau). The product over the step sizes the GPU took must
+    give its result."""
+    import oracle
+
+    cc, A, b, _ = oracle.ck_tableau()
+    a = np.zeros((6, 6))
+    a[:, :5] = A
+
+    def R(w):
+        return 1 + w * (b @ np.linalg.solve(np.eye(6) - w * a, np.ones(6)))
+
+    n, L, c, gam, alpha, T = 256, 8.0, 20.0, 0.1, 0.5, 0.2
+    qs = [3, -10, 40]
+    x = np.arange(n) * L / n
+    psi0 = np.stack([np.exp(2j * np.pi * q * x / L) for q in qs])
+    Vg = torch.full((len(qs), n), c, dtype=torch.float32, device="cuda")
+    p = rk4ip.make_problem((n,), (0.0,), (L,), 1e-3, batch=len(qs), alpha=alpha, gamma=gam, V_grid=Vg)
+    plan = rk4ip.Plan([p])
+    d = torch.tensor(psi0.astype(np.complex64).reshape(-1), device="cuda")
+    h = torch.full((len(qs),), 1e-3, dtype=torch.float64, device="cuda")
+    stats, hl = plan.ark45(d, T, 1e-6, h, log_cap=256)
+    torch.cuda.synchronize()
+    stats, hl = stats.cpu().numpy(), hl.cpu().numpy()
+    got = d.cpu().numpy().astype(np.complex128).reshape(psi0.shape)
+    for i, q in enumerate(qs):
+        acc = int(stats[i, 0])
+        assert stats[i, 2] == 1 and 0 < acc <= 256
+        lam = -1j * alpha * (2 * np.pi * q / L) ** 2 - gam
+        fac = np.prod([np.exp(lam * s) * R(-1j * c * s) for s in hl[i, :acc]])
+        err = rel(got[i], fac * psi0[i])
+        log(f"ark45 plane wave q={q}: {acc} accepted, {int(stats[i, 1])} rejected steps; rel L2 {err:.2e}")
+        assert err < 3e-6
