@@ -12,6 +12,7 @@
 import numpy as np
 import pytest
 
+from closed_forms import non_local_case, plane_wave_amplitude
 from gpu_helpers import log, rel
 from paper_1204_4255_amd import rk4ip
 
@@ -224,3 +225,30 @@ def test_linear_sde_with_additive_noise(torch, dims, flags):
         f"(the noise moves the field by {noise_part:.1e})")
     assert noise_part > 1e-2
     assert err < 3e-6
+
+
+@pytest.mark.parametrize("flags", [0, G | rk4ip.RK4IP_FLAG_FUSE_1D, SI])
+def test_plane_waves_under_the_non_local_potential(torch, flags):
+    """A plane wave has a uniform density, so the non-local potential
+    V_c = dV sum_j K(x_i - x_j) |psi_j|^2 is the constant |A|^2 dV sum_d K(d) and the wave
+    stays a plane wave A(t) e^{ikx}. Its amplitude follows the same step applied to the
+    scalar equation dA/dt = L(k) A - i (g + dV sum_d K(d)) |A|^2 A, a recursion written
+    out in FP64. This pins the kernel's normalisation (dV, no 1/n left over) and sign."""
+    gam, alpha, h, S = 0.05, 0.5, 2e-3, 40
+    n, L, gnl, dx, K, qs, amps, psi0 = non_local_case()
+    psi0 = psi0.astype(np.complex64).astype(np.complex128)  # the field the GPU starts from
+    p = rk4ip.make_problem((n,), (-L / 2,), (L / 2,), h, batch=len(qs), alpha=alpha, gamma=gam, g_nl=gnl, conv_K=K)
+    plan = rk4ip.Plan([p], flags=flags)
+    d = torch.tensor(psi0.astype(np.complex64).reshape(-1), device="cuda")
+    plan.run(d, S)
+    torch.cuda.synchronize()
+    got = d.cpu().numpy().astype(np.complex128).reshape(psi0.shape)
+    for i, (q, a0) in enumerate(zip(qs, amps)):
+        E = np.exp((-1j * alpha * (2 * np.pi * q / L) ** 2 - gam) * h / 2)
+        A0 = psi0[i, 0]  # the stored amplitude at x = lo
+        want = plane_wave_amplitude(A0, S, h, E, gnl + dx * K.sum(), flags & SI) / A0 * psi0[i]
+        local = plane_wave_amplitude(A0, S, h, E, gnl, flags & SI) / A0 * psi0[i]
+        err, err_local = rel(got[i], want), rel(got[i], local)
+        log(f"non-local plane wave q={q} |A|={a0}, flags {flags}: rel L2 {err:.2e} "
+            f"(against the local term alone: {err_local:.1e})")
+        assert err < 3e-6 and err_local > 1e-2

@@ -8,6 +8,7 @@ import numpy as np
 import pytest
 
 import oracle
+from closed_forms import non_local_case, plane_wave_amplitude
 
 
 @pytest.mark.parametrize("dims", [1, 2])
@@ -39,3 +40,22 @@ def test_linear_sde_step_is_simpson_or_midpoint(dims, integrator):
     for s in range(S):
         g = E1 * g + w2 * np.fft.fftn(oracle.noise(op, 5 + s), axes=fax)
     assert np.linalg.norm(ref - np.fft.ifftn(g, axes=fax)) / np.linalg.norm(exact) > 1e-8
+
+
+@pytest.mark.parametrize("integrator", [0, 1])
+def test_non_local_potential_on_plane_waves(integrator):
+    """A plane wave's density is uniform, so the non-local potential is the constant
+    |A|^2 dV sum_d K(d): the oracle's run equals the same step applied to the scalar
+    amplitude equation, and differs from the run without the non-local term."""
+    gam, alpha, h, S = 0.05, 0.5, 2e-3, 40
+    n, L, gnl, dx, K, qs, amps, psi0 = non_local_case()
+    op = oracle.Problem(n=(n,), lo=(-L / 2,), hi=(L / 2,), h=h, batch=len(qs), alpha=alpha, gamma=gam, gnl=gnl,
+                        convK=K, integrator=integrator)
+    ref, _, _ = oracle.run(op, psi0, S)
+    for i, q in enumerate(qs):
+        E = np.exp((-1j * alpha * (2 * np.pi * q / L) ** 2 - gam) * h / 2)
+        A0 = psi0[i, 0]
+        want = plane_wave_amplitude(A0, S, h, E, gnl + dx * K.sum(), integrator) / A0 * psi0[i]
+        local = plane_wave_amplitude(A0, S, h, E, gnl, integrator) / A0 * psi0[i]
+        assert np.linalg.norm(ref[i] - want) / np.linalg.norm(want) < 1e-13
+        assert np.linalg.norm(ref[i] - local) / np.linalg.norm(want) > 1e-2
