@@ -181,23 +181,27 @@ def test_ark45_plane_waves_follow_the_cash_karp_factor(torch):
         assert err < 3e-6
 
 
-@pytest.mark.parametrize("dims,flags", [(1, 0), (1, G | rk4ip.RK4IP_FLAG_FUSE_1D), (1, SI), (1, SI | G),
-                                        (2, 0), (2, G | A), (2, SI), (2, SI | G)])
-def test_linear_sde_with_additive_noise(torch, dims, flags):
+@pytest.mark.parametrize("dims,flags,sub", [(1, 0, 1), (1, G | rk4ip.RK4IP_FLAG_FUSE_1D, 1), (1, SI, 1),
+                                            (1, SI | G, 1), (2, 0, 1), (2, G | A, 1), (2, SI, 1), (2, SI | G, 1),
+                                            (1, SI | G, 8), (2, SI, 4), (2, G, 4)])
+def test_linear_sde_with_additive_noise(torch, dims, flags, sub):
     """d psi/dt = L psi + sigma xi with the noise xi held constant over a step (V = 0,
     g = 0). Then every stage is linear in psi and xi, and one RK4IP step is
     psi <- e^{Lh} psi + h sigma (e^{Lh} + 4 e^{Lh/2} + 1) xi / 6 (Simpson's rule for the
     integral of e^{L(h-s)} xi over the step), the semi-implicit step
     psi <- e^{Lh} psi + h sigma e^{Lh/2} xi (the midpoint rule). The expected field uses
-    the oracle's noise (bit-identical Philox words, FP64 Box-Muller) and FP64 FFTs."""
+    the oracle's noise (bit-identical Philox words, FP64 Box-Muller) and FP64 FFTs; with
+    noise substeps it is the normalised sum of the sub draws."""
     import oracle
 
     n = (256,) if dims == 1 else (32, 16)
     lo, hi = (-8.0,) * dims, (8.0,) * dims
     batch, h, S, sig, gam, alpha = 3, 1e-3, 30, 0.2, 0.05, 0.5
-    p = rk4ip.make_problem(n, lo, hi, h, batch=batch, alpha=alpha, gamma=gam, sigma=sig, seed=77, id_base=2)
+    p = rk4ip.make_problem(n, lo, hi, h, batch=batch, alpha=alpha, gamma=gam, sigma=sig, seed=77, id_base=2,
+                           noise_substeps=sub)
     plan = rk4ip.Plan([p], flags=flags)
-    op = oracle.Problem(n=n, lo=lo, hi=hi, h=h, batch=batch, alpha=alpha, gamma=gam, sigma=sig, seed=77, id_base=2)
+    op = oracle.Problem(n=n, lo=lo, hi=hi, h=h, batch=batch, alpha=alpha, gamma=gam, sigma=sig, seed=77, id_base=2,
+                        noise_substeps=sub)
     ax = [lo[a] + np.arange(n[a]) * (hi[a] - lo[a]) / n[a] for a in range(dims)]
     env = np.exp(-ax[0] ** 2 / 2) if dims == 1 else np.exp(-ax[0][None, :] ** 2 / 2 - ax[1][:, None] ** 2 / 2)
     psi0 = np.broadcast_to(env, (batch,) + env.shape).astype(np.complex64).astype(np.complex128)
@@ -221,7 +225,7 @@ def test_linear_sde_with_additive_noise(torch, dims, flags):
     exact = np.fft.ifftn(f, axes=fax)
     err = rel(got, exact)
     noise_part = rel(exact, np.fft.ifftn(np.fft.fftn(psi0, axes=fax) * E1 ** S, axes=fax))
-    log(f"linear SDE dims={dims} flags={flags}: rel L2 after {S} steps {err:.2e} "
+    log(f"linear SDE dims={dims} flags={flags} substeps={sub}: rel L2 after {S} steps {err:.2e} "
         f"(the noise moves the field by {noise_part:.1e})")
     assert noise_part > 1e-2
     assert err < 3e-6
