@@ -145,22 +145,28 @@ def test_noisy_potential_on_lattices(torch, n, batch, si):
     assert err < 5e-6
 
 
-def test_potential_noise_is_the_oracles(torch):
+@pytest.mark.parametrize("n,si", [((256,), False), ((256,), True), ((32, 16), False), ((16, 8, 8), False),
+                                  ((16, 8, 8), True)])
+def test_potential_noise_is_the_oracles(torch, n, si):
     """A step with only the noisy potential (alpha = 0, g = 0, V = 0) multiplies every
-    point by the RK4 factor of e^{-i h sigma_V eta}: the GPU's step, divided by the input,
-    gives back eta to single precision, and eta is the oracle's."""
-    n, batch, h, sv = 256, 4, 0.01, 0.2
-    g = W.Group(n=(n,), lo=(-4.0,), hi=(4.0,), batch=batch, alpha=0.0, seed=12)
+    point by the RK4 factor of e^{-i h sigma_V eta} (the semi-implicit step: by
+    1 + z + z^2/2 + z^3/4), with eta the oracle's real noise at that step and point."""
+    batch, h, sv = 4, 0.01, 0.2
+    nd = len(n)
+    g = W.Group(n=n, lo=(-4.0,) * nd, hi=(4.0,) * nd, batch=batch, alpha=0.0, seed=12)
     p = rk4ip.make_problem(g.n, g.lo, g.hi, h, batch=batch, alpha=0.0, seed=12, sigma_V=sv)
-    plan = rk4ip.Plan([p])
+    plan = rk4ip.Plan([p], flags=SI if si else 0)
     f0 = np.ones(g.shape, complex)
     d = _dev(torch, f0)
     plan.step(d, 5)
-    got = _host(d, g.shape)
+    got = _host(d, g.shape).reshape(batch, -1)
     op = oracle.Problem(n=g.n, lo=g.lo, hi=g.hi, h=h, batch=batch, alpha=0.0, seed=12, sigma_V=sv)
     eta = oracle.vnoise(op, 5)
     z = -1j * h * sv * eta
-    assert np.max(np.abs(got - (1 + z + z ** 2 / 2 + z ** 3 / 6 + z ** 4 / 24))) < 1e-6
+    factor = 1 + z + z ** 2 / 2 + (z ** 3 / 4 if si else z ** 3 / 6 + z ** 4 / 24)
+    err = np.max(np.abs(got - factor))
+    log(f"noisy potential alone n={n} si={si}: max |step - closed form| {err:.2e}, max |z| {np.max(np.abs(z)):.2f}")
+    assert err < 1e-6
 
 
 def test_unsupported_combinations_are_rejected(torch):
