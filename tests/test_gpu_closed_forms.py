@@ -183,7 +183,7 @@ def test_ark45_plane_waves_follow_the_cash_karp_factor(torch):
 
 @pytest.mark.parametrize("dims,flags,sub", [(1, 0, 1), (1, G | rk4ip.RK4IP_FLAG_FUSE_1D, 1), (1, SI, 1),
                                             (1, SI | G, 1), (2, 0, 1), (2, G | A, 1), (2, SI, 1), (2, SI | G, 1),
-                                            (1, SI | G, 8), (2, SI, 4), (2, G, 4)])
+                                            (1, SI | G, 8), (2, SI, 4), (2, G, 4), (3, G | A, 1), (3, SI | G, 2)])
 def test_linear_sde_with_additive_noise(torch, dims, flags, sub):
     """d psi/dt = L psi + sigma xi with the noise xi held constant over a step (V = 0,
     g = 0). Then every stage is linear in psi and xi, and one RK4IP step is
@@ -194,7 +194,7 @@ def test_linear_sde_with_additive_noise(torch, dims, flags, sub):
     noise substeps it is the normalised sum of the sub draws."""
     import oracle
 
-    n = (256,) if dims == 1 else (32, 16)
+    n = {1: (256,), 2: (32, 16), 3: (32, 16, 8)}[dims]
     lo, hi = (-8.0,) * dims, (8.0,) * dims
     batch, h, S, sig, gam, alpha = 3, 1e-3, 30, 0.2, 0.05, 0.5
     p = rk4ip.make_problem(n, lo, hi, h, batch=batch, alpha=alpha, gamma=gam, sigma=sig, seed=77, id_base=2,
@@ -203,7 +203,8 @@ def test_linear_sde_with_additive_noise(torch, dims, flags, sub):
     op = oracle.Problem(n=n, lo=lo, hi=hi, h=h, batch=batch, alpha=alpha, gamma=gam, sigma=sig, seed=77, id_base=2,
                         noise_substeps=sub)
     ax = [lo[a] + np.arange(n[a]) * (hi[a] - lo[a]) / n[a] for a in range(dims)]
-    env = np.exp(-ax[0] ** 2 / 2) if dims == 1 else np.exp(-ax[0][None, :] ** 2 / 2 - ax[1][:, None] ** 2 / 2)
+    mesh = np.meshgrid(*ax[::-1], indexing="ij")  # memory order: the last index is x
+    env = np.exp(-sum(m ** 2 for m in mesh) / 2)
     psi0 = np.broadcast_to(env, (batch,) + env.shape).astype(np.complex64).astype(np.complex128)
     d = torch.tensor(psi0.astype(np.complex64).reshape(-1), device="cuda")
     step0 = 5
@@ -213,7 +214,7 @@ def test_linear_sde_with_additive_noise(torch, dims, flags, sub):
 
     # k^2 on the lattice, axes in memory order (last axis = x)
     ks = [2 * np.pi * np.fft.fftfreq(n[a], d=(hi[a] - lo[a]) / n[a]) for a in range(dims)]
-    k2 = ks[0] ** 2 if dims == 1 else ks[0][None, :] ** 2 + ks[1][:, None] ** 2
+    k2 = sum(K ** 2 for K in np.meshgrid(*ks[::-1], indexing="ij"))
     Lk = -1j * alpha * k2 - gam
     fax = tuple(range(1, dims + 1))
     E1, Eh = np.exp(Lk * h), np.exp(Lk * h / 2)
