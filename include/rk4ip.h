@@ -71,7 +71,8 @@ enum {
     RK4IP_ERR_INVALID_ARG = -1,         /* null pointer, bad count, dt <= 0, unknown flag,
                                            noise_substeps not a power of two <= 1024 */
     RK4IP_ERR_UNSUPPORTED_SHAPE = -2,   /* n[a] not a power of two in [8, 4096] (1D) or
-                                           [8, 1024] (2D/3D), ndim not 1..3 */
+                                           [8, 1024] (2D/3D), more than 2^29 points per
+                                           instance (e.g. 1024^3), ndim not 1..3 */
     RK4IP_ERR_WORKSPACE_TOO_SMALL = -3,
     RK4IP_ERR_HIP = -4,                 /* a HIP runtime call failed; see rk4ip_last_error */
     RK4IP_ERR_NONFINITE = -5,           /* a diagnostic found a NaN or Inf in a field */

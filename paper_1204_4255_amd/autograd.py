@@ -24,11 +24,18 @@ class _RK4IPFunction(torch.autograd.Function):
         _, ckpt = solver.plan.run(psi, solver.nsteps, step0=solver.step0, ckpt_every=solver.ckpt_every)
         ctx.solver = solver
         ctx.ckpt = ckpt
+        # the plan reads V from the solver's one buffer, which a later call overwrites:
+        # keep this call's potential for the backward recompute
+        ctx.V = solver.V.clone()
         return psi
 
     @staticmethod
     def backward(ctx, grad_out):
         s = ctx.solver
+        # the recompute and the adjoint must see the potential of the forward call this
+        # backward belongs to (copy and adjoint run in order on the current stream)
+        with torch.no_grad():
+            s.V.copy_(ctx.V)
         g, gV = s.plan.adjoint(ctx.ckpt, s.nsteps, s.ckpt_every, grad_out.contiguous().to(torch.complex64),
                                step0=s.step0, want_V=True)
         return g, gV, None

@@ -42,6 +42,10 @@ struct GroupDev {
     int has_vnoise;          // real Wiener noise in the potential (1D groups)
     float vnoise_c;          // sigma_V / sqrt(h dV): multiplies a unit real normal
     const float2* convK;     // [n] (FFT of the non-local kernel) dV / n (1D groups), or null
+    const float2* E2;        // [n] (e^{L h} - 1)/n of axis 0 (1D Fourier groups: the k-space line
+                             // step), else null
+    float2* K;               // [batch][n] the k-space state of a 1D group run by the k-space line
+                             // step (kept between the launches of a run), else null
     int basis;               // 1D: 0 Fourier; 1 cosine, 2 sine (n[0] is then the length of the
                              // even / odd extension, twice the stored points)
 };

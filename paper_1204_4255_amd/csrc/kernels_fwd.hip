@@ -234,6 +234,163 @@ __global__ void __launch_bounds__((FFTShape<N, RR>::T * LPB))
     }
 }
 
+// ------------------------------------------------------------- 1D step, k-space state
+
+// The same step on a whole 1D Fourier line with its state kept in k-space between the
+// steps of a launch: P = F psi (unnormalised). With the picture origin at the midpoint,
+// D a = D^2 psi_n, so the RK4 step reads
+//     psi_n = F^-1 P / n,  a = F^-1(E P) / n,  k1 = D[h G(psi_n)],
+//     k2 = h G(a + k1/2),  k3 = h G(a + k2/2),  k4 = h G(D(a + k3)),
+//     P' = E^2 P + E F(k1/6 + k2/3 + k3/3) + F(k4)/6,
+// and the semi-implicit step (a = D psi_n, m = a + (h/2) G(m) by three fixed-point
+// iterations, psi' = D(2m - a) = D(a + h G(m_2)) with m_2 the second iterate)
+//     a = F^-1(E P) / n,  P' = E^2 P + E F(h G(m_2)).
+// Both are the steps of the x-space kernel above, regrouped: the field itself is only
+// multiplied by E^2 per step and never passes through a transform pair, so the FP32
+// rounding of the transforms (their twiddles in particular, whose error is the same every
+// step and so adds up linearly) reaches the state only through the stage terms, which
+// are of size h G. The transform count is the same (8 per RK4 step, in 6 sequences) or
+// halved (2 per semi-implicit step). The state stays in k-space between the launches of
+// a run (in the group's buffer g.K: io bit 0 reads it from there, bit 1 leaves it there);
+// the first launch of a run transforms psi and the last transforms the state back. The
+// rounding of that transform pair is the same every time it is applied (it does not
+// shrink with |E - 1| like the propagator's), so it is applied once per run, not per
+// launch. Fourier groups without the potential's extra terms, FP32 transforms.
+// The two propagator tables are read from global memory where they are used (every
+// workgroup reads the same few KB, which stay cached); LDS holds the twiddles and the
+// exchange buffers only.
+template <int N, int LPB, bool NOISE, int RR, bool SI>
+__global__ void __launch_bounds__((FFTShape<N, RR>::T * LPB))
+    k_line_kstep(GroupDev g, float2* __restrict__ psi, int nsteps, int64_t step_off,
+                 const int64_t* __restrict__ step_base, int io) {
+    using F = FFTShape<N, RR>;
+    using L = LdsLayout<N, LPB, true, F::R>;
+    constexpr int R = F::R, T = F::T;
+    __shared__ c32 lds[(SI ? 1 : 2) * L::SIZE];
+    __shared__ c32 tw[N];
+    stage_twiddles<F>(tw, g.tw[0]);
+    const float2* __restrict__ E1 = g.E[0];  // (E - 1)/n
+    const float2* __restrict__ E2 = g.E2;    // (E^2 - 1)/n
+    const int t = threadIdx.x % T;
+    const int l = threadIdx.x / T;
+    const int64_t inst = (int64_t)blockIdx.x * LPB + l;
+    const bool active = inst < g.batch;
+    float2* p = psi + g.offset + inst * N;
+    float2* kp = g.K + inst * N;
+    const float fn = (float)N, inv_n = g.inv_n[0];  // exact powers of two
+    const c32 zero = make_float2(0.f, 0.f);
+
+    c32 P[1][R];
+    float V[R];
+#pragma unroll
+    for (int m = 0; m < R; m++) {
+        const int j = t + m * T;
+        P[0][m] = active ? ((io & 1) ? kp[j] : p[j]) : zero;
+        float v = trap_V(g, j, 0, 0);
+        if (g.Vgrid && active) v += g.Vgrid[inst * N + j];
+        V[m] = v;
+    }
+    const uint32_t iid = g.id_base + (uint32_t)inst;
+    int64_t step = read_step(step_off, step_base);
+    __syncthreads();  // tables staged
+    if (!(io & 1)) fft_line<F, -1, L, 1>(P, t, l, lds, tw);  // P = F psi (uniform branch)
+    // E^q z = z + n ((E^q - 1)/n) z for a k-space value z at element j
+    auto mulE = [&](c32 z, int j) { return cadd(z, cmul(z, cscale(E1[j], fn))); };
+    for (int s = 0; s < nsteps; s++, step++) {
+        c32 nz[R];
+#pragma unroll
+        for (int m = 0; m < R; m++) {
+            if constexpr (NOISE) {
+                const float2 z = noise_z(g, t + m * T, iid, step);
+                nz[m] = make_float2(g.noise_c * z.x, g.noise_c * z.y);
+            } else {
+                nz[m] = zero;
+            }
+        }
+        c32 inc[1][R];  // F of the step's increment, without E^2 P
+        if constexpr (SI) {
+            c32 x[1][R];
+#pragma unroll
+            for (int m = 0; m < R; m++) x[0][m] = mulE(P[0][m], t + m * T);
+            fft_line<F, +1, L, 1>(x, t, l, lds, tw);
+#pragma unroll
+            for (int m = 0; m < R; m++) {
+                const c32 a = cscale(x[0][m], inv_n);
+                c32 mid = a;
+#pragma unroll
+                for (int it = 0; it < 2; it++) {
+                    const c32 k = hG(g, mid, V[m], nz[m]);
+                    mid = make_float2(fmaf(0.5f, k.x, a.x), fmaf(0.5f, k.y, a.y));
+                }
+                inc[0][m] = hG(g, mid, V[m], nz[m]);  // 2 (m_3 - a)
+            }
+            fft_line<F, -1, L, 1>(inc, t, l, lds, tw);
+#pragma unroll
+            for (int m = 0; m < R; m++) inc[0][m] = mulE(inc[0][m], t + m * T);
+        } else {
+            // psi_n and a = D psi_n from the state
+            c32 x[2][R];
+#pragma unroll
+            for (int m = 0; m < R; m++) {
+                x[0][m] = P[0][m];
+                x[1][m] = mulE(P[0][m], t + m * T);
+            }
+            fft_line<F, +1, L, 2>(x, t, l, lds, tw);
+            // k1 = D[h G(psi_n)] (delta form)
+            c32 k1[1][R];
+#pragma unroll
+            for (int m = 0; m < R; m++) {
+                x[0][m] = cscale(x[0][m], inv_n);  // psi_n
+                x[1][m] = cscale(x[1][m], inv_n);  // a
+                k1[0][m] = hG(g, x[0][m], V[m], nz[m]);
+            }
+            propagate<F, L, 1>(k1, t, l, lds, tw, E1, false);
+            // stages: u = a + k3 in x[0], c = k1/6 + k2/3 + k3/3 in x[1]
+#pragma unroll
+            for (int m = 0; m < R; m++) {
+                const c32 a = x[1][m], q1 = k1[0][m];
+                const c32 k2 = hG(g, make_float2(fmaf(0.5f, q1.x, a.x), fmaf(0.5f, q1.y, a.y)), V[m], nz[m]);
+                const c32 k3 = hG(g, make_float2(fmaf(0.5f, k2.x, a.x), fmaf(0.5f, k2.y, a.y)), V[m], nz[m]);
+                x[0][m] = cadd(a, k3);
+                x[1][m] = make_float2(q1.x * (1.0f / 6.0f) + (k2.x + k3.x) * (1.0f / 3.0f),
+                                      q1.y * (1.0f / 6.0f) + (k2.y + k3.y) * (1.0f / 3.0f));
+            }
+            fft_line<F, -1, L, 2>(x, t, l, lds, tw);  // (F u, F c)
+            // w = D u = F^-1(E F u)/n, k4 = h G(w)
+            c32 w[1][R];
+#pragma unroll
+            for (int m = 0; m < R; m++) w[0][m] = mulE(x[0][m], t + m * T);
+            fft_line<F, +1, L, 1>(w, t, l, lds, tw);
+#pragma unroll
+            for (int m = 0; m < R; m++) inc[0][m] = hG(g, cscale(w[0][m], inv_n), V[m], nz[m]);
+            fft_line<F, -1, L, 1>(inc, t, l, lds, tw);  // F k4
+#pragma unroll
+            for (int m = 0; m < R; m++) {
+                const c32 Ec = mulE(x[1][m], t + m * T);
+                inc[0][m] = make_float2(fmaf(inc[0][m].x, 1.0f / 6.0f, Ec.x), fmaf(inc[0][m].y, 1.0f / 6.0f, Ec.y));
+            }
+        }
+        // P' = E^2 P + increment = P + (n (E^2 - 1)/n P + increment)
+#pragma unroll
+        for (int m = 0; m < R; m++) {
+            const c32 d = cmul(P[0][m], cscale(E2[t + m * T], fn));
+            P[0][m] = cadd(P[0][m], cadd(d, inc[0][m]));
+        }
+    }
+    if (io & 2) {
+        if (active) {
+#pragma unroll
+            for (int m = 0; m < R; m++) kp[t + m * T] = P[0][m];
+        }
+        return;
+    }
+    fft_line<F, +1, L, 1>(P, t, l, lds, tw);  // back to x-space
+    if (active) {
+#pragma unroll
+        for (int m = 0; m < R; m++) p[t + m * T] = cscale(P[0][m], inv_n);
+    }
+}
+
 // ---------------------------------------------------------------------------- launchers
 
 int axis_lines(int N, int axis, int n0) { return axis == 0 ? contig_lines(N) : strided_lines(N, n0); }
@@ -286,9 +443,32 @@ static hipError_t go_line(const GroupDev& g, float2* psi, int nsteps, int64_t st
     return hipGetLastError();
 }
 
+template <int N, int RR, bool SI>
+static hipError_t go_kline(const GroupDev& g, float2* psi, int nsteps, int64_t step_off, const int64_t* step_base,
+                           int io, hipStream_t s) {
+    constexpr int T = FFTShape<N, RR>::T;
+    constexpr int LPB = T >= 64 ? 1 : 64 / T;
+    const int64_t blocks = (g.batch + LPB - 1) / LPB;
+    if (g.has_noise)
+        hipLaunchKernelGGL((k_line_kstep<N, LPB, true, RR, SI>), dim3((unsigned)blocks), dim3(T * LPB), 0, s, g, psi,
+                           nsteps, step_off, step_base, io);
+    else
+        hipLaunchKernelGGL((k_line_kstep<N, LPB, false, RR, SI>), dim3((unsigned)blocks), dim3(T * LPB), 0, s, g, psi,
+                           nsteps, step_off, step_base, io);
+    return hipGetLastError();
+}
+
 template <int N, bool SI>
 static hipError_t go_line_p(const GroupDev& g, float2* psi, int nsteps, int64_t step_off, const int64_t* step_base,
-                            bool f64, int radix, hipStream_t s) {
+                            bool f64, int radix, int io, hipStream_t s) {
+    if (g.K) {
+        // Fourier lines with a k-space state buffer: the step with the state in k-space
+        if (f64 || g.basis || g.has_vnoise || g.convK || !g.E2) return hipErrorInvalidValue;
+        if (radix == 8) return go_kline<N, 8, SI>(g, psi, nsteps, step_off, step_base, io, s);
+        if (radix == 0 || radix == 16) return go_kline<N, 16, SI>(g, psi, nsteps, step_off, step_base, io, s);
+        return hipErrorInvalidValue;
+    }
+    if (io) return hipErrorInvalidValue;  // no k-space state to read or keep
     if (g.has_vnoise || g.convK) {
         // the potential's extra terms: 8 values per thread
         if (f64) {
@@ -308,24 +488,24 @@ static hipError_t go_line_p(const GroupDev& g, float2* psi, int nsteps, int64_t 
 
 template <int N>
 static hipError_t go_line_n(const GroupDev& g, float2* psi, int nsteps, int64_t step_off, const int64_t* step_base,
-                            bool f64, int radix, bool si, hipStream_t s) {
-    if (si) return go_line_p<N, true>(g, psi, nsteps, step_off, step_base, f64, radix, s);
-    return go_line_p<N, false>(g, psi, nsteps, step_off, step_base, f64, radix, s);
+                            bool f64, int radix, bool si, int io, hipStream_t s) {
+    if (si) return go_line_p<N, true>(g, psi, nsteps, step_off, step_base, f64, radix, io, s);
+    return go_line_p<N, false>(g, psi, nsteps, step_off, step_base, f64, radix, io, s);
 }
 
 hipError_t launch_line_step(const GroupDev& g, float2* psi, int nsteps, int64_t step_off, const int64_t* step_base,
-                            bool f64, int radix, bool semi_implicit, hipStream_t s) {
+                            bool f64, int radix, bool semi_implicit, hipStream_t s, int io) {
     switch (g.n[0]) {
-        case 8: return go_line_n<8>(g, psi, nsteps, step_off, step_base, f64, radix, semi_implicit, s);
-        case 16: return go_line_n<16>(g, psi, nsteps, step_off, step_base, f64, radix, semi_implicit, s);
-        case 32: return go_line_n<32>(g, psi, nsteps, step_off, step_base, f64, radix, semi_implicit, s);
-        case 64: return go_line_n<64>(g, psi, nsteps, step_off, step_base, f64, radix, semi_implicit, s);
-        case 128: return go_line_n<128>(g, psi, nsteps, step_off, step_base, f64, radix, semi_implicit, s);
-        case 256: return go_line_n<256>(g, psi, nsteps, step_off, step_base, f64, radix, semi_implicit, s);
-        case 512: return go_line_n<512>(g, psi, nsteps, step_off, step_base, f64, radix, semi_implicit, s);
-        case 1024: return go_line_n<1024>(g, psi, nsteps, step_off, step_base, f64, radix, semi_implicit, s);
-        case 2048: return go_line_n<2048>(g, psi, nsteps, step_off, step_base, f64, radix, semi_implicit, s);
-        case 4096: return go_line_n<4096>(g, psi, nsteps, step_off, step_base, f64, radix, semi_implicit, s);
+        case 8: return go_line_n<8>(g, psi, nsteps, step_off, step_base, f64, radix, semi_implicit, io, s);
+        case 16: return go_line_n<16>(g, psi, nsteps, step_off, step_base, f64, radix, semi_implicit, io, s);
+        case 32: return go_line_n<32>(g, psi, nsteps, step_off, step_base, f64, radix, semi_implicit, io, s);
+        case 64: return go_line_n<64>(g, psi, nsteps, step_off, step_base, f64, radix, semi_implicit, io, s);
+        case 128: return go_line_n<128>(g, psi, nsteps, step_off, step_base, f64, radix, semi_implicit, io, s);
+        case 256: return go_line_n<256>(g, psi, nsteps, step_off, step_base, f64, radix, semi_implicit, io, s);
+        case 512: return go_line_n<512>(g, psi, nsteps, step_off, step_base, f64, radix, semi_implicit, io, s);
+        case 1024: return go_line_n<1024>(g, psi, nsteps, step_off, step_base, f64, radix, semi_implicit, io, s);
+        case 2048: return go_line_n<2048>(g, psi, nsteps, step_off, step_base, f64, radix, semi_implicit, io, s);
+        case 4096: return go_line_n<4096>(g, psi, nsteps, step_off, step_base, f64, radix, semi_implicit, io, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -81,8 +81,10 @@ hipError_t launch_axis_last(const GroupDev& g, int axis, int mode, const PassArg
 hipError_t launch_line_adjoint(const GroupDev& g, const float2* psi_n, float2* lam, double* vbar, int64_t step,
                                hipStream_t s);
 hipError_t launch_vbar_to_float(const double* vbar, float* out, int64_t n, hipStream_t s);
+// io (groups with a k-space state buffer, GroupDev::K, only): bit 0 reads the state from K
+// instead of transforming psi, bit 1 leaves it in K instead of transforming it back into psi.
 hipError_t launch_line_step(const GroupDev& g, float2* psi, int nsteps, int64_t step_off, const int64_t* step_base, bool f64,
-                            int radix, bool semi_implicit, hipStream_t s);
+                            int radix, bool semi_implicit, hipStream_t s, int io = 0);
 hipError_t launch_line_ark45(const GroupDev& g, float2* psi, const ArkArgs& x, hipStream_t s);
 hipError_t launch_diag_axis(const GroupDev& g, int axis, const float2* psi, double kscale, double* part,
                             hipStream_t s);

@@ -45,6 +45,12 @@ rk4ip_problem transform_problem(const rk4ip_problem& p) {
     return q;
 }
 
+// 1D groups that the k-space line step runs: Fourier basis, no extra potential terms,
+// FP32 transforms. They keep their k-space state in the workspace between launches.
+bool is_kline(const rk4ip_problem& p, uint32_t flags) {
+    return p.ndim == 1 && !p.basis && !p.conv_K && p.sigma_V == 0.0 && !(flags & RK4IP_FLAG_FP64_TRANSFORMS);
+}
+
 int ilog2i(int64_t v) {
     int r = 0;
     while ((int64_t(1) << r) < v) r++;
@@ -71,6 +77,9 @@ struct GroupHost {
     size_t tw64_off[3] = {0, 0, 0};
     size_t part_off[3] = {0, 0, 0};  // diagnostic partials (batch * M/n_a * 4 doubles)
     size_t conv_off = 0;             // transform of the non-local kernel (1D groups with one)
+    size_t e2_off = 0;               // (e^{L h} - 1)/n of a 1D Fourier group (its k-space line step)
+    size_t k_off = 0;                // k-space state of a group run by the k-space line step
+    bool kline = false;              // run by the k-space line step (state in the workspace)
     double dV = 1.0;
 };
 
@@ -121,7 +130,9 @@ int validate(const rk4ip_problem* probs, int nprob, uint32_t flags) {
                 return RK4IP_ERR_UNSUPPORTED_SHAPE;
             }
         }
-        if (M > (int64_t(1) << 31) / 1 || p.batch * M > (int64_t(1) << 40)) return RK4IP_ERR_UNSUPPORTED_SHAPE;
+        // the pass kernels address a tile with 32-bit byte offsets from the instance origin,
+        // so one instance must span less than 4 GiB of complex64 (M <= 2^29)
+        if (M > (int64_t(1) << 29) || p.batch * M > (int64_t(1) << 40)) return RK4IP_ERR_UNSUPPORTED_SHAPE;
         ninst += p.batch;
     }
     if (ninst > (int64_t(1) << 31)) return RK4IP_ERR_INVALID_ARG;
@@ -162,6 +173,20 @@ Layout layout(const rk4ip_problem* probs, int nprob, uint32_t flags, std::vector
         if (p.conv_K) {
             if (gh) (*gh)[i].conv_off = off;
             off = align_up(off + sizeof(float2) * (size_t)p.n[0]);
+        }
+        if (is_kline(p, flags)) {
+            if (gh) (*gh)[i].e2_off = off;
+            off = align_up(off + sizeof(float2) * (size_t)p.n[0]);
+        }
+    }
+    for (int i = 0; i < nprob; i++) {
+        const rk4ip_problem& p = probs[i];
+        if (is_kline(p, flags)) {
+            if (gh) {
+                (*gh)[i].k_off = off;
+                (*gh)[i].kline = true;
+            }
+            off = align_up(off + sizeof(float2) * (size_t)(p.batch * p.n[0]));
         }
     }
     for (int i = 0; i < nprob; i++) {
@@ -264,7 +289,8 @@ void release_plan(rk4ip_plan_t plan) {
 
 // Tables of one axis (FP64 arithmetic; stored in FP32, and in FP64 for FP64-transform plans).
 void build_tables(const rk4ip_problem& p, int a, std::vector<float2>& E, std::vector<float2>& tw,
-                  std::vector<double2>* E64 = nullptr, std::vector<double2>* tw64 = nullptr) {
+                  std::vector<double2>* E64 = nullptr, std::vector<double2>* tw64 = nullptr,
+                  std::vector<float2>* E2 = nullptr) {
     const int64_t n = p.n[a];
     const double Lx = p.hi[a] - p.lo[a];
     const double h = p.dt;
@@ -274,6 +300,7 @@ void build_tables(const rk4ip_problem& p, int a, std::vector<float2>& E, std::ve
     tw.resize(n);
     if (E64) E64->resize(n);
     if (tw64) tw64->resize(n);
+    if (E2) E2->resize(n);
     const double inv_n = 1.0 / (double)n;  // exact power of two
     for (int64_t m = 0; m < n; m++) {
         const double k = 2.0 * kPi / Lx * (double)(m < n / 2 ? m : m - n);
@@ -287,6 +314,14 @@ void build_tables(const rk4ip_problem& p, int a, std::vector<float2>& E, std::ve
         const double ang = 2.0 * kPi * (double)m / (double)n;
         tw[m] = make_float2((float)std::cos(ang), (float)-std::sin(ang));
         if (E64) (*E64)[m] = make_double2(c * inv_n, s * inv_n);
+        if (E2) {
+            // e^{L h} - 1 = damp^2 e^{-2 i theta} - 1, written without cancellation:
+            // damp^2 cos(2 theta) - 1 = (damp^2 - 1) - 2 damp^2 sin^2(theta)
+            const double d2 = damp * damp, em2 = std::expm1(-p.gamma * h), st = std::sin(theta);
+            const double c2 = (a == 0 ? em2 : 0.0) - 2.0 * d2 * st * st;
+            const double s2 = -d2 * std::sin(2.0 * theta);
+            (*E2)[m] = make_float2((float)(c2 * inv_n), (float)(s2 * inv_n));
+        }
         if (tw64) (*tw64)[m] = make_double2(std::cos(ang), -std::sin(ang));
     }
 }
@@ -436,17 +471,20 @@ int time_pass(rk4ip_plan_t plan, const GroupHost& g, const PassDef& def, const S
     return RK4IP_OK;
 }
 
-// Mean time (ms) of `reps` launches of four 1D steps with `rr` values per thread, on the
-// work field A (its contents are irrelevant).
+// Mean time (ms) of `reps` launches of eight 1D steps with `rr` values per thread, on the
+// work field A (its contents are irrelevant; a k-space line keeps its state in the
+// workspace, as in the steady state of a run).
 int time_line(rk4ip_plan_t plan, const GroupHost& g, int rr, int reps, float* ms) {
     hipStream_t st = plan->stream;
+    const int io = g.kline ? 3 : 0;
+    if (g.kline) HIPCHK(plan, rk4ip::launch_line_step(g.d, plan->A, 0, 1, nullptr, false, rr, plan->si, st, 2));
     for (int i = 0; i < 2; i++)
-        HIPCHK(plan, rk4ip::launch_line_step(g.d, plan->A, 4, 1, nullptr, false, rr, plan->si, st));
+        HIPCHK(plan, rk4ip::launch_line_step(g.d, plan->A, 8, 1, nullptr, false, rr, plan->si, st, io));
     hipEvent_t a = take_event(plan), b = take_event(plan);
     if (!a || !b) return fail(plan, RK4IP_ERR_HIP, "hipEventCreate failed");
     HIPCHK(plan, hipEventRecord(a, st));
     for (int i = 0; i < reps; i++)
-        HIPCHK(plan, rk4ip::launch_line_step(g.d, plan->A, 4, 1, nullptr, false, rr, plan->si, st));
+        HIPCHK(plan, rk4ip::launch_line_step(g.d, plan->A, 8, 1, nullptr, false, rr, plan->si, st, io));
     HIPCHK(plan, hipEventRecord(b, st));
     HIPCHK(plan, hipEventSynchronize(b));
     HIPCHK(plan, hipEventElapsedTime(ms, a, b));
@@ -602,27 +640,35 @@ int autotune(rk4ip_plan_t plan) {
 }
 
 // Enqueue `nsteps` steps of every 1D group. step_base != null: step = *step_base + step_off.
+// Groups run by the k-space line step keep their state in k-space between launches:
+// from_k says it is there at entry (else it is psi), to_k that it stays there at exit (else
+// it is transformed back into psi). A zero-step launch only converts. Other 1D groups
+// always hold their state in psi.
 int enqueue_lines(rk4ip_plan_t plan, hipStream_t stream, float2* psi, int64_t step_off, int64_t nsteps,
-                  const int64_t* step_base, bool allow_fuse) {
+                  const int64_t* step_base, bool allow_fuse, bool from_k = false, bool to_k = false) {
     const bool capturing = step_base != nullptr;
+    const bool fuse = allow_fuse && (plan->flags & RK4IP_FLAG_FUSE_1D);
     int rc;
     for (size_t gi = 0; gi < plan->groups.size(); gi++) {
         auto& g = plan->groups[gi];
-        if (g.p.ndim != 1 || nsteps <= 0) continue;
-        if (allow_fuse && (plan->flags & RK4IP_FLAG_FUSE_1D)) {
-            rc = timed_launch(plan, stream, (int)gi, 0, capturing, [&] {
-                return rk4ip::launch_line_step(g.d, psi, (int)nsteps, step_off, step_base, plan->f64,
-                                                plan->sched[gi][0].radix, plan->si, stream);
+        if (g.p.ndim != 1) continue;
+        const int radix = plan->sched[gi][0].radix;
+        auto launch = [&](int64_t n, int64_t s0, bool fk, bool tk) {
+            const int io = g.kline ? ((fk ? 1 : 0) | (tk ? 2 : 0)) : 0;
+            return timed_launch(plan, stream, (int)gi, 0, capturing, [&] {
+                return rk4ip::launch_line_step(g.d, psi, (int)n, s0, step_base, plan->f64, radix, plan->si, stream,
+                                                io);
             });
-            if (rc) return rc;
+        };
+        if (nsteps <= 0) {
+            if (g.kline && from_k != to_k && (rc = launch(0, step_off, from_k, to_k))) return rc;
+            continue;
+        }
+        if (fuse) {
+            if ((rc = launch(nsteps, step_off, from_k, to_k))) return rc;
         } else {
-            for (int64_t s = 0; s < nsteps; s++) {
-                rc = timed_launch(plan, stream, (int)gi, 0, capturing, [&] {
-                    return rk4ip::launch_line_step(g.d, psi, 1, step_off + s, step_base, plan->f64,
-                                                    plan->sched[gi][0].radix, plan->si, stream);
-                });
-                if (rc) return rc;
-            }
+            for (int64_t s = 0; s < nsteps; s++)
+                if ((rc = launch(1, step_off + s, s == 0 ? from_k : true, s == nsteps - 1 ? to_k : true))) return rc;
         }
     }
     return RK4IP_OK;
@@ -751,7 +797,7 @@ int ensure_graph(rk4ip_plan_t plan, float2* psi, int gsteps) {
     hipStream_t s = plan->capture_stream;
     hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return fail_hip(plan, e, "hipStreamBeginCapture");
-    int rc = enqueue_lines(plan, s, psi, 0, gsteps, plan->counter, true);
+    int rc = enqueue_lines(plan, s, psi, 0, gsteps, plan->counter, true, true, true);
     if (rc == RK4IP_OK) rc = enqueue_lattice(plan, s, psi, 0, gsteps, false, false, plan->counter);
     hipError_t e2 = rk4ip::launch_counter(plan->counter, gsteps, 1, s);
     hipGraph_t gr = nullptr;
@@ -789,6 +835,8 @@ int advance(rk4ip_plan_t plan, float2* psi, int64_t step, int64_t nsteps) {
         const int gsteps = (int)(units < kGraphSteps ? units : kGraphSteps);
         if ((rc = ensure_graph(plan, psi, gsteps))) return rc;
         HIPCHK(plan, rk4ip::launch_counter(plan->counter, step, 0, plan->stream));
+        // the replays step the k-space lines' states in the workspace
+        if ((rc = enqueue_lines(plan, plan->stream, psi, step, 0, nullptr, true, false, true))) return rc;
         while (units - done >= gsteps) {
             hipError_t e = hipGraphLaunch(plan->graph, plan->stream);
             if (e != hipSuccess) {
@@ -798,7 +846,8 @@ int advance(rk4ip_plan_t plan, float2* psi, int64_t step, int64_t nsteps) {
             done += gsteps;
         }
     }
-    if ((rc = enqueue_lines(plan, plan->stream, psi, step + done, nsteps - done, nullptr, true))) return rc;
+    if ((rc = enqueue_lines(plan, plan->stream, psi, step + done, nsteps - done, nullptr, true, done > 0, false)))
+        return rc;
     if (lattice) return enqueue_lattice(plan, plan->stream, psi, step + done, units - done, false, true, nullptr);
     return RK4IP_OK;
 }
@@ -902,11 +951,17 @@ int rk4ip_plan(const rk4ip_problem* probs, int nprob, void* workspace, size_t ws
         d.inv_sqrt_sub = (float)(1.0 / std::sqrt((double)d.noise_sub));  // a power of two or its root
         d.Vgrid = p.V_grid;
         for (int a = 0; a < p.ndim; a++) {
-            std::vector<float2> E, tw;
+            std::vector<float2> E, tw, E2;
             std::vector<double2> E64, tw64;
-            build_tables(transform_problem(p), a, E, tw, plan->f64 ? &E64 : nullptr, plan->f64 ? &tw64 : nullptr);
+            const bool kline = g.kline;
+            build_tables(transform_problem(p), a, E, tw, plan->f64 ? &E64 : nullptr, plan->f64 ? &tw64 : nullptr,
+                         kline ? &E2 : nullptr);
             hipError_t e1 = hipMemcpy(plan->ws + g.tab_off[a], E.data(), sizeof(float2) * E.size(), hipMemcpyHostToDevice);
             hipError_t e2 = hipMemcpy(plan->ws + g.tw_off[a], tw.data(), sizeof(float2) * tw.size(), hipMemcpyHostToDevice);
+            if (e1 == hipSuccess && e2 == hipSuccess && kline) {
+                e1 = hipMemcpy(plan->ws + g.e2_off, E2.data(), sizeof(float2) * E2.size(), hipMemcpyHostToDevice);
+                d.E2 = reinterpret_cast<const float2*>(plan->ws + g.e2_off);
+            }
             if (e1 == hipSuccess && e2 == hipSuccess && plan->f64) {
                 e1 = hipMemcpy(plan->ws + g.tab64_off[a], E64.data(), sizeof(double2) * E64.size(),
                                hipMemcpyHostToDevice);
@@ -925,6 +980,7 @@ int rk4ip_plan(const rk4ip_problem* probs, int nprob, void* workspace, size_t ws
                 d.tw64[a] = reinterpret_cast<const double2*>(plan->ws + g.tw64_off[a]);
             }
         }
+        if (g.kline) d.K = reinterpret_cast<float2*>(plan->ws + g.k_off);
         if (p.conv_K) {
             std::vector<float2> kh;
             build_conv_table(p, g.dV, kh);

@@ -52,3 +52,23 @@ def random_field(g: W.Group, seed: int, envelope: bool = True):
 def quantised(f):
     """The complex64 value both sides start from."""
     return np.asarray(f, dtype=np.complex64).astype(np.complex128)
+
+
+def assert_same_runs(torch, groups, whole, other, split, kspace_lines=True):
+    """Runs of one workload: `whole` and `other` are one run call each (through different
+    launch structures: eager, graph-replayed, several 1D steps per launch) and are bitwise
+    equal; `split` is the same run as two calls. A 1D Fourier line run in FP32 keeps its
+    state in k-space for the whole of a run call and transforms it back at the end, so
+    where a run is split its lines agree to rounding (relative 1e-6) instead; every other
+    group is bitwise equal there too."""
+    off = 0
+    for g in groups:
+        n = g.batch * g.M
+        ref = whole[off:off + n]
+        assert torch.equal(other[off:off + n], ref), g.n
+        x = split[off:off + n]
+        if kspace_lines and len(g.n) == 1:
+            assert float(torch.linalg.vector_norm(x - ref) / torch.linalg.vector_norm(ref)) < 1e-6, g.n
+        else:
+            assert torch.equal(x, ref), g.n
+        off += n

@@ -154,12 +154,18 @@ def test_semi_implicit_flag_and_noise_substeps(lib):
 
 def test_potential_terms_sizes_and_limits(lib):
     """The non-local kernel's transform adds n complex64 entries to the workspace and is
-    taken on 1D groups only, with finite values; the noise in the potential needs sigma_V >= 0."""
+    taken on 1D groups only, with finite values; the noise in the potential needs sigma_V >= 0.
+    A plain Fourier line also keeps the table (e^{L h} - 1)/n (n entries) and its k-space
+    state (batch x n complex64), which the lines with the potential's extra terms (run in
+    x-space) do not."""
     line = dict(n=(256,), lo=(0,), hi=(1,), dt=0.1)
-    base = rk4ip.rk4ip_workspace_bytes([rk4ip.make_problem(**line)])
+    plain = rk4ip.rk4ip_workspace_bytes([rk4ip.make_problem(**line)])
+    base = rk4ip.rk4ip_workspace_bytes([rk4ip.make_problem(**line, sigma_V=0.3)])
+    assert plain == base + 2 * 256 * 8
     K = np.ones(256)
-    assert rk4ip.rk4ip_workspace_bytes([rk4ip.make_problem(**line, conv_K=K)]) >= base + 256 * 8
-    assert rk4ip.rk4ip_workspace_bytes([rk4ip.make_problem(**line, sigma_V=0.3)]) == base
+    assert rk4ip.rk4ip_workspace_bytes([rk4ip.make_problem(**line, conv_K=K)]) == base + 256 * 8
+    assert rk4ip.rk4ip_workspace_bytes([rk4ip.make_problem(**line, batch=4)]) == (
+        rk4ip.rk4ip_workspace_bytes([rk4ip.make_problem(**line, batch=4, sigma_V=0.3)]) + 5 * 256 * 8)
     assert rk4ip.rk4ip_workspace_bytes([rk4ip.make_problem(**line, sigma_V=-0.3)]) == 0
     bad = K.copy()
     bad[3] = np.nan
@@ -170,9 +176,10 @@ def test_potential_terms_sizes_and_limits(lib):
 
 def test_cosine_and_sine_bases_sizes_and_limits(lib):
     """A cosine / sine group keeps transform tables of its extension (twice the stored
-    points) and is taken on 1D lattices whose extension fits the line kernel."""
+    points) and is taken on 1D lattices whose extension fits the line kernel (compared
+    here with a Fourier line that also runs in x-space: one with noise in its potential)."""
     line = dict(lo=(0,), hi=(7,), dt=0.1)
-    f = rk4ip.rk4ip_workspace_bytes([rk4ip.make_problem(n=(256,), **line)])
+    f = rk4ip.rk4ip_workspace_bytes([rk4ip.make_problem(n=(256,), sigma_V=0.1, **line)])
     for basis in (1, 2):
         c = rk4ip.rk4ip_workspace_bytes([rk4ip.make_problem(n=(256,), basis=basis, **line)])
         assert c >= f + 2 * 256 * 8  # the two tables doubled
@@ -199,3 +206,17 @@ def test_binding_refuses_buffers_that_do_not_fit(lib):
         rk4ip.make_problem((64,), (0,), (1,), 1e-3, conv_K=np.ones(63))
     with pytest.raises(rk4ip.Rk4ipError):
         rk4ip.make_problem((64,), (0,), (1,), 1e-3, batch=2, V_grid=torch.zeros(128))  # host memory
+
+
+def test_instances_beyond_32bit_tile_offsets_are_refused(lib):
+    """The pass kernels address a tile with 32-bit byte offsets from the instance origin, so
+    one instance holds at most 2^29 complex64 points: 1024^3 is refused, 1024 x 1024 x 512
+    (exactly 4 GiB) is taken, and so is 512^3 with a large batch."""
+    big = dict(lo=(0, 0, 0), hi=(1, 1, 1), dt=1e-3)
+    assert rk4ip.rk4ip_workspace_bytes([rk4ip.make_problem(n=(1024, 1024, 1024), **big)]) == 0
+    assert rk4ip.rk4ip_workspace_bytes([rk4ip.make_problem(n=(1024, 1024, 512), **big)]) > 0
+    assert rk4ip.rk4ip_workspace_bytes([rk4ip.make_problem(n=(512, 512, 512), batch=8, **big)]) > 0
+    h = ctypes.c_void_p()
+    arr = (rk4ip.rk4ip_problem * 1)(rk4ip.make_problem(n=(1024, 1024, 1024), **big))
+    rc = lib.rk4ip_plan(arr, 1, ctypes.c_void_p(256), 1 << 40, None, 0, ctypes.byref(h))
+    assert rc == rk4ip.RK4IP_ERR_UNSUPPORTED_SHAPE and not h.value

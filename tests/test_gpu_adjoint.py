@@ -62,7 +62,7 @@ def _run_case(torch, shapes, nsteps, M, step0=5):
         e1 = rel(g_psi[off:off + n], ref_g)
         e2 = rel(g_V[off:off + n], ref_V)
         log(f"  group n={gr.n} x{gr.batch}: grad_psi0 rel {e1:.2e}, grad_V rel {e2:.2e}")
-        assert e1 < 1e-5 and e2 < 1e-4, (e1, e2)
+        assert e1 < 1e-5 and e2 < 1e-5, (e1, e2)
         off += n
     return solver
 
@@ -118,7 +118,7 @@ def test_adjoint2d_workload_shapes(torch):
         e1 = rel(g_psi[off:off + n], ref_g)
         e2 = rel(g_V[off:off + n], ref_V)
         log(f"  n={g.n} x{g.batch}: psi_T rel {e0:.2e}, grad_psi0 rel {e1:.2e}, grad_V rel {e2:.2e}")
-        assert e0 < 1e-5 and e1 < 1e-5 and e2 < 1e-4
+        assert e0 < 1e-5 and e1 < 1e-5 and e2 < 1e-5
         off += n
 
 
@@ -166,3 +166,40 @@ def test_gpu_gradient_central_difference(torch):
     log(f"  FD psi0: {fd:.6e} vs adjoint {an:.6e}; FD V: {fdv:.6e} vs adjoint {anv:.6e}")
     assert abs(fd - an) <= 2e-3 * abs(an) + 1e-6
     assert abs(fdv - anv) <= 2e-3 * abs(anv) + 1e-6
+
+
+def test_solver_called_twice_before_backward(torch):
+    """The plan reads V from the solver's one buffer. Two calls with different V before one
+    backward: the gradient through the first call must equal that of the first call alone
+    (each call keeps its own potential for the backward recompute)."""
+    from paper_1204_4255_amd.autograd import RK4IPSolver
+
+    gs = _groups([((32, 16), 2)], sigma=0.01, gamma=0.02)
+    nsteps, M, h = 8, 3, 2e-3
+    fields = [quantised(random_field(g, 5)) for g in gs]
+    w = W.Workload("reent", gs, h, nsteps, fields)
+    probs, _ = rk4ip.problems_from_workload(w)
+    solver = RK4IPSolver(probs, nsteps, M)
+    base = rk4ip.field_to_device(w)
+    V1 = torch.tensor(gs[0].Vgrid.reshape(-1), device="cuda")
+    V2 = V1 * 3.0 + 0.5
+    rng = np.random.Generator(np.random.PCG64(2))
+    lam = torch.tensor((rng.standard_normal(base.numel()) + 1j * rng.standard_normal(base.numel()))
+                       .astype(np.complex64), device="cuda")
+
+    def grads(second):
+        p = base.clone().requires_grad_(True)
+        V = V1.clone().requires_grad_(True)
+        out1 = solver(p, V)
+        if second:
+            p2 = base.clone().requires_grad_(True)
+            out2 = solver(p2, V2.clone().requires_grad_(True))
+            del out2
+        torch.sum((torch.conj(lam) * out1).real).backward()
+        return p.grad.clone(), V.grad.clone()
+
+    g_alone, gv_alone = grads(False)
+    g_both, gv_both = grads(True)
+    log(f"  grad_psi0 diff {float((g_both - g_alone).abs().max()):.3e}, grad_V diff "
+        f"{float((gv_both - gv_alone).abs().max()):.3e}")
+    assert torch.equal(g_both, g_alone) and torch.equal(gv_both, gv_alone)

@@ -58,7 +58,12 @@ def test_zero_steps_leave_the_field(torch, n, batch, flags):
     plan.run(b, 0, step0=5)
     plan.run(b, 4, step0=5)
     torch.cuda.synchronize()
-    assert torch.equal(a, b)
+    if len(n) == 1 and not flags & F64:
+        # a 1D line keeps its state in k-space for a whole run call: the split run
+        # transforms it back and forth once more, so the runs agree to rounding only
+        assert rel(b.cpu().numpy(), a.cpu().numpy()) < 1e-6
+    else:
+        assert torch.equal(a, b)
 
 
 @pytest.mark.parametrize("basis", [1, 2])

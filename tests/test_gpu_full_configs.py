@@ -70,7 +70,7 @@ def test_gpe2d_512_full_run(torch, flags, bound):
     assert np.all(np.abs(gdiag / rdiag - 1) < np.array([1e-5, 1e-4, 1e-5, 1e-5]))
 
 
-@pytest.mark.parametrize("flags,bound", [(0, 2.5e-5), (F64, 1e-5)], ids=["c64", "fp64"])
+@pytest.mark.parametrize("flags,bound", [(0, 1e-5), (F64, 1e-5)], ids=["c64", "fp64"])
 def test_sgpe1d_full_length(torch, flags, bound):
     """2048 paths x 1024, 5000 steps, several steps per launch from a graph: 16 sampled
     paths against the oracle one by one over the run, and the ensemble norm of all paths
@@ -154,10 +154,32 @@ def test_gpe3d_256_full_run_conserves(torch):
     assert dN < 1e-5 and dE < 1e-5
 
 
+def test_gpe3d_256_hundred_steps_vs_oracle(torch):
+    """256^3 with the benchmark's flags over 100 steps: the whole field against the oracle
+    every 25 steps (the graph replays 32-step blocks, so the samples fall inside and
+    across replays)."""
+    w = W.gpe3d(nsteps=100)
+    g = w.groups[0]
+    log("gpe3d 256^3, 100 steps, graph + autotune, whole field vs oracle every 25 steps")
+    f = quantised(w.psi0[0])
+    plan = _plan(w, BENCH_FLAGS)
+    d = torch.tensor(f.astype(np.complex64).reshape(-1), device="cuda")
+    ref = f.copy()
+    p = oprob(g, w.h)
+    errs = []
+    for s in range(0, 100, 25):
+        plan.run(d, 25, step0=s)
+        ref, _, _ = oracle.run(p, ref, 25, step0=s)
+        errs.append(rel(_host(d, g.shape), ref))
+        log(f"  step {s + 25}: rel L2 {errs[-1]:.3e}")
+    assert max(errs) < 1e-5
+
+
 def test_adjoint2d_full_length(torch):
     """The 64-instance uneven batch, 1000 steps, checkpoint every 50, loss
-    sum_b 1 - |<phi|psi_b(T)>|^2: psi(T) and both gradients of the first instance of
-    each size against the oracle's forward run and discrete adjoint."""
+    sum_b 1 - |<phi|psi_b(T)>|^2: psi(T) and both gradients of four instances of each
+    size (spread over the group, each with its own id and potential grid) against the
+    oracle's forward run and discrete adjoint."""
     from paper_1204_4255_amd.autograd import RK4IPSolver
 
     w = W.adjoint2d()
@@ -182,21 +204,23 @@ def test_adjoint2d_full_length(torch):
     g_V = V.grad.cpu().numpy().astype(np.float64)
     off = 0
     for g, phi, f in zip(w.groups, w.target, w.psi0):
-        # the first instance of the group alone (its own id and potential grid)
-        g1 = W.Group(n=g.n, lo=g.lo, hi=g.hi, batch=1, gnl=g.gnl, trap=g.trap, seed=g.seed, id_base=g.id_base)
-        g1.Vgrid = np.asarray(g.Vgrid[:1], np.float32).astype(np.float64)
-        p = oprob(g1, w.h)
-        f1 = quantised(f[:1])
-        ref_T, _, _ = oracle.run(p, f1, w.nsteps)
-        c = oracle.overlap(p, phi, ref_T)
-        lamT = -2 * g.dV * c[:, None, None] * phi[None]
-        ref_g, ref_V = oracle.adjoint(p, f1, lamT, nsteps=w.nsteps, ckpt_every=M)
-        sl = slice(off, off + g.M)
-        e0 = rel(outs[sl], ref_T)
-        e1 = rel(g_psi[sl], ref_g)
-        e2 = rel(g_V[sl], ref_V)
-        log(f"  n={g.n} instance 0: psi_T rel {e0:.2e}, grad_psi0 rel {e1:.2e}, grad_V rel {e2:.2e}")
-        assert e0 < 1e-5 and e1 < 1e-5 and e2 < 1e-4
+        for b in (0, 10, 21, g.batch - 1):
+            # instance b of the group alone (its own id and potential grid)
+            g1 = W.Group(n=g.n, lo=g.lo, hi=g.hi, batch=1, gnl=g.gnl, trap=g.trap, seed=g.seed,
+                         id_base=g.id_base + b)
+            g1.Vgrid = np.asarray(g.Vgrid[b:b + 1], np.float32).astype(np.float64)
+            p = oprob(g1, w.h)
+            f1 = quantised(f[b:b + 1])
+            ref_T, _, _ = oracle.run(p, f1, w.nsteps)
+            c = oracle.overlap(p, phi, ref_T)
+            lamT = -2 * g.dV * c[:, None, None] * phi[None]
+            ref_g, ref_V = oracle.adjoint(p, f1, lamT, nsteps=w.nsteps, ckpt_every=M)
+            sl = slice(off + b * g.M, off + (b + 1) * g.M)
+            e0 = rel(outs[sl], ref_T)
+            e1 = rel(g_psi[sl], ref_g)
+            e2 = rel(g_V[sl], ref_V)
+            log(f"  n={g.n} instance {b}: psi_T rel {e0:.2e}, grad_psi0 rel {e1:.2e}, grad_V rel {e2:.2e}")
+            assert e0 < 1e-5 and e1 < 1e-5 and e2 < 1e-5
         off += g.batch * g.M
 
 
@@ -221,10 +245,7 @@ def test_gpe3d_256_semi_implicit_eight_steps_full_size(torch):
     assert err < 1e-6
 
 
-# The complex64 form of the semi-implicit run carries the same coherent FP32 transform
-# rounding as RK4IP on this workload: measured 2.57e-5 (RK4IP 1.8e-5); its bound keeps
-# that floor with margin, and the FP64-transform form is held to 1e-5.
-@pytest.mark.parametrize("flags,bound", [(0, 3.5e-5), (F64, 1e-5)], ids=["c64", "fp64"])
+@pytest.mark.parametrize("flags,bound", [(0, 1e-5), (F64, 1e-5)], ids=["c64", "fp64"])
 def test_sgpe1d_semi_implicit_full_length(torch, flags, bound):
     """2048 paths x 1024, 5000 semi-implicit steps, several steps per launch from a graph:
     16 sampled paths against the oracle's semi-implicit run one by one over the run."""

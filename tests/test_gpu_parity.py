@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 import oracle
-from gpu_helpers import log, oprob, plan_for, quantised, random_field, rel, rel_per_instance
+from gpu_helpers import assert_same_runs, log, oprob, plan_for, quantised, random_field, rel, rel_per_instance
 from paper_1204_4255_amd import rk4ip
 from paper_1204_4255_amd import workloads as W
 
@@ -248,8 +248,7 @@ def test_determinism_resume_and_graph(torch, flags):
     plan.run(c, 11, step0=100)
     plan.run(c, 12, step0=111)
     torch.cuda.synchronize()
-    assert torch.equal(a, b)
-    assert torch.equal(a, c)
+    assert_same_runs(torch, gs, a, b, c)
 
 
 def test_graph_replays_match_eager_with_work_between(torch):
