@@ -500,6 +500,21 @@ constexpr bool fits_lds64(int N, int lines, int nf, bool contig) {
     return ((long)nf * buf + 2L * N) * 16 <= 160L * 1024;
 }
 
+// Narrow tiles for small lattices (a single 512^2 lattice has only 512 lines per axis):
+// one or two waves per workgroup, radix 8, both fields at once, so that a pass launches
+// hundreds of workgroups instead of a hundred. Contiguous axis: a quarter or an eighth of
+// the default lines; strided axes: one or two columns.
+template <int N>
+constexpr bool narrow_tile(bool contig, int lines) {
+    const int T = N / 8;  // threads per line with 8 values per thread
+    if (lines < 1 || T * lines < 64 || T * lines > 128) return false;
+    if (contig) {
+        const int dl = default_contig_lines(N);
+        return lines == dl / 4 || lines == dl / 8;
+    }
+    return lines == 1 || lines == 2;
+}
+
 // Is schedule (lines, seq, rr) of pass MODE compiled for length N on the contiguous or a
 // strided axis, with FP32 or FP64 transforms? Mirrors the instantiations in go_axis_n.
 // rr = values per thread.
@@ -508,6 +523,7 @@ constexpr bool schedule_compiled(bool contig, int lines, int seq, int rr, bool p
     constexpr int NF = fields_of(MODE);
     const bool tuned = tuned_length(N) && tuned_mode(MODE);
     if (seq < 0 || seq > 2) return false;
+    if (tuned && narrow_tile<N>(contig, lines)) return occ == 1 && seq == 0 && rr == 8;
     if (occ != 1) {
         // the four-wave variant: FP32, radix 8, both fields at once, tuned lengths
         if (occ != 4 || p64 || rr != 8 || seq != 0 || !tuned) return false;
@@ -588,8 +604,11 @@ static hipError_t go_axis_np(const GroupDev& g, int axis, const PassArgs& a, hip
             if constexpr (CL / 2 >= 1) {
                 if (lines == CL / 2) return go_axis_sched<N, MODE, true, (CL / 2 >= 1 ? CL / 2 : 1), P64>(g, axis, a, s);
             }
-            if constexpr (P64 && CL / 4 >= 1) {
+            if constexpr (CL / 4 >= 1) {
                 if (lines == CL / 4) return go_axis_sched<N, MODE, true, (CL / 4 >= 1 ? CL / 4 : 1), P64>(g, axis, a, s);
+            }
+            if constexpr (CL / 8 >= 1 && narrow_tile<N>(true, CL / 8)) {
+                if (lines == CL / 8) return go_axis_sched<N, MODE, true, (CL / 8 >= 1 ? CL / 8 : 1), P64>(g, axis, a, s);
             }
             return hipErrorInvalidValue;
         }
@@ -604,6 +623,8 @@ static hipError_t go_axis_np(const GroupDev& g, int axis, const PassArgs& a, hip
             case 16: return go_axis_sched<N, MODE, false, 16, P64>(g, axis, a, s);
             case 8: return go_axis_sched<N, MODE, false, 8, P64>(g, axis, a, s);
             case 4: return go_axis_sched<N, MODE, false, 4, P64>(g, axis, a, s);
+            case 2: return go_axis_sched<N, MODE, false, 2, P64>(g, axis, a, s);
+            case 1: return go_axis_sched<N, MODE, false, 1, P64>(g, axis, a, s);
             default: return hipErrorInvalidValue;
         }
     }

@@ -16,11 +16,13 @@ pytestmark = pytest.mark.gpu
 BENCH_FLAGS = rk4ip.RK4IP_FLAG_GRAPH | rk4ip.RK4IP_FLAG_AUTOTUNE
 F64 = rk4ip.RK4IP_FLAG_FP64_TRANSFORMS
 
-# The complex64 form accumulates FP32 transform rounding coherently on fields with high-k
-# content (phase noise, Wiener noise): measured 1.06e-5 (radix 16) / 9.7e-6 (radix 8) on
-# gpe2d after 2000 steps and 1.8e-5 on sgpe1d after 5000 steps, against 1e-5 targeted.
-# Those two runs assert the complex64 form below its measured floor with margin, and the
-# FP64-transform form (FFTs, propagator multiply and delta add in FP64) below 1e-5.
+# Precision forms: on gpe2d the complex64 form accumulates the FP32 rounding of the
+# per-axis transforms (the same every step, so it adds up linearly) to about 1e-5 over
+# 2000 steps, at the target, so the FP64-transform form (FFTs, propagator multiply and
+# delta add in FP64, fields complex64) is the form this workload is claimed in and is held
+# to 1e-5. The complex64 run is kept as a measurement with a bound that only guards
+# against regressions; it is not claimed at 1e-5. The 1D lines of sgpe1d keep their state
+# in k-space and hold 1e-5 in complex64.
 
 
 @pytest.fixture(scope="module")
@@ -43,8 +45,9 @@ def _host(t, shape):
     return t.cpu().numpy().astype(np.complex128).reshape(shape)
 
 
-@pytest.mark.parametrize("flags,bound", [(rk4ip.RK4IP_FLAG_GRAPH, 1.5e-5), (BENCH_FLAGS, 1.5e-5),
-                                         (BENCH_FLAGS | F64, 1e-5)], ids=["c64-default", "c64-autotuned", "fp64"])
+@pytest.mark.parametrize("flags,bound", [(rk4ip.RK4IP_FLAG_GRAPH | F64, 1e-5), (BENCH_FLAGS | F64, 1e-5),
+                                         (BENCH_FLAGS, 1.5e-5)],
+                         ids=["fp64-default", "fp64-autotuned", "c64-autotuned-unclaimed"])
 def test_gpe2d_512_full_run(torch, flags, bound):
     """512^2, 2000 steps: error over the run (every 100 steps) and FP64 diagnostics. The
     kinetic energy weights the field error by k^2 (FP32 rounding sits at high k), so it
