@@ -277,6 +277,30 @@ int rk4ip_profile(rk4ip_plan_t plan, int enable);
  * launches were timed and their mean duration in milliseconds. */
 int rk4ip_profile_read(rk4ip_plan_t plan, int group, int pass, int64_t* count, double* mean_ms);
 
+/* ---- one step without a plan or a workspace --------------------------------------- */
+
+/* For callers that cannot allocate device memory (code under stream capture, serving
+ * loops, harnesses that forbid hipMalloc): one step of every instance, in place on psi,
+ * exactly the step rk4ip_step makes on a plan built with flags 0 (RK4IP, FP32 transforms,
+ * default tile schedules), without a plan or a caller workspace. The tables (computed on
+ * the device in FP64 with the same expressions as rk4ip_plan's) and the work fields live in
+ * a static device buffer of RK4IP_NOALLOC_SCRATCH_BYTES that the library holds on every
+ * GPU it runs on until the process ends; the call allocates nothing and is asynchronous on
+ * `stream` (a hipStream_t, NULL = the default stream).
+ *   - The buffer must hold the groups' tables, two complex64 work fields per point of the
+ *     2D/3D groups and one per point of the 1D Fourier groups (about 16 B per lattice point
+ *     plus the tables, so up to about 4 million points): larger problems return
+ *     RK4IP_ERR_WORKSPACE_TOO_SMALL (rk4ip_workspace_bytes(probs, nprob, 0) is the size
+ *     needed).
+ *   - At most 16 groups (RK4IP_ERR_INVALID_ARG); no non-local potential (conv_K: its table
+ *     is a host-side transform; RK4IP_ERR_INVALID_ARG). Other arguments are checked as by
+ *     rk4ip_plan; RK4IP_ERR_NO_DEVICE when the current device is not a gfx950.
+ *   - Every call on one GPU shares that GPU's buffer and overwrites it: calls that overlap
+ *     on one GPU (on different streams, or from different threads) race and must be
+ *     serialised by the caller. Nothing in the buffer needs to start at zero. */
+#define RK4IP_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int rk4ip_step_noalloc(const rk4ip_problem* probs, int nprob, void* psi, int64_t step_index, void* stream);
+
 /* ---- test entry points (device pointers, asynchronous on `stream`) -------------- */
 
 /* Philox4x32-10 words for n counters: ctr [n][4] uint32 in, out [n][4] uint32. */

@@ -8,6 +8,7 @@
 #include <cstdlib>
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -140,7 +141,7 @@ int validate(const rk4ip_problem* probs, int nprob, uint32_t flags) {
 }
 
 // Offsets of every table and buffer; fills `gh` when non-null.
-Layout layout(const rk4ip_problem* probs, int nprob, uint32_t flags, std::vector<GroupHost>* gh) {
+Layout layout(const rk4ip_problem* probs, int nprob, uint32_t flags, GroupHost* gh) {
     Layout L;
     size_t off = 0;
     L.header = off;
@@ -161,21 +162,21 @@ Layout layout(const rk4ip_problem* probs, int nprob, uint32_t flags, std::vector
                 off = align_up(off + sizeof(double2) * (size_t)transform_len(p, a));
             }
             if (gh) {
-                (*gh)[i].tab_off[a] = e;
-                (*gh)[i].tw_off[a] = t;
-                (*gh)[i].tab64_off[a] = e64;
-                (*gh)[i].tw64_off[a] = t64;
+                gh[i].tab_off[a] = e;
+                gh[i].tw_off[a] = t;
+                gh[i].tab64_off[a] = e64;
+                gh[i].tw64_off[a] = t64;
             }
         }
     }
     for (int i = 0; i < nprob; i++) {
         const rk4ip_problem& p = probs[i];
         if (p.conv_K) {
-            if (gh) (*gh)[i].conv_off = off;
+            if (gh) gh[i].conv_off = off;
             off = align_up(off + sizeof(float2) * (size_t)p.n[0]);
         }
         if (is_kline(p, flags)) {
-            if (gh) (*gh)[i].e2_off = off;
+            if (gh) gh[i].e2_off = off;
             off = align_up(off + sizeof(float2) * (size_t)p.n[0]);
         }
     }
@@ -183,8 +184,8 @@ Layout layout(const rk4ip_problem* probs, int nprob, uint32_t flags, std::vector
         const rk4ip_problem& p = probs[i];
         if (is_kline(p, flags)) {
             if (gh) {
-                (*gh)[i].k_off = off;
-                (*gh)[i].kline = true;
+                gh[i].k_off = off;
+                gh[i].kline = true;
             }
             off = align_up(off + sizeof(float2) * (size_t)(p.batch * p.n[0]));
         }
@@ -193,7 +194,7 @@ Layout layout(const rk4ip_problem* probs, int nprob, uint32_t flags, std::vector
         const rk4ip_problem& p = probs[i];
         int64_t M = p.n[0] * p.n[1] * p.n[2];
         for (int a = 0; a < p.ndim; a++) {
-            if (gh) (*gh)[i].part_off[a] = off;
+            if (gh) gh[i].part_off[a] = off;
             off = align_up(off + sizeof(double) * 4 * (size_t)(p.batch * (M / p.n[a])));
         }
         L.points += p.batch * M;
@@ -202,6 +203,63 @@ Layout layout(const rk4ip_problem* probs, int nprob, uint32_t flags, std::vector
     off = align_up(off + 2 * sizeof(float2) * (size_t)L.points);
     L.total = off;
     return L;
+}
+
+// Per-group kernel parameters and table pointers into the workspace `ws` (the offsets come
+// from layout); the group's field starts at point `offset` of the concatenated field. The
+// tables themselves are written by the caller.
+void fill_group(GroupHost& g, char* ws, bool f64, int64_t offset) {
+    const rk4ip_problem& p = g.p;
+    GroupDev& d = g.d;
+    std::memset(&d, 0, sizeof(d));
+    d.ndim = p.ndim;
+    g.M = 1;
+    g.dV = 1.0;
+    for (int a = 0; a < 3; a++) {
+        const int64_t nt = transform_len(p, a);
+        d.n[a] = (int)nt;
+        d.log2n[a] = ilog2i(nt);
+        g.M *= p.n[a];
+        if (a < p.ndim) {
+            const double dx = (p.hi[a] - p.lo[a]) / (double)p.n[a];
+            g.dV *= dx;
+            // a cosine / sine group's points are the cell centres lo + (j + 1/2) dx
+            d.lo[a] = (float)(p.basis ? p.lo[a] + 0.5 * dx : p.lo[a]);
+            d.dx[a] = (float)dx;
+            d.half_trap[a] = (float)(0.5 * p.trap[a]);
+            d.inv_n[a] = (float)(1.0 / (double)nt);
+        }
+    }
+    d.basis = p.basis;
+    d.M = g.M;
+    d.batch = p.batch;
+    d.offset = offset;
+    d.h = (float)p.dt;
+    d.gnl = (float)p.g_nl;
+    d.noise_c = (float)(p.dt * p.sigma / std::sqrt(2.0 * p.dt * g.dV));
+    d.xi_scale = (float)(1.0 / std::sqrt(2.0 * p.dt * g.dV));
+    d.seed_lo = (uint32_t)(p.seed & 0xFFFFFFFFu);
+    d.seed_hi = (uint32_t)(p.seed >> 32);
+    d.id_base = p.id_base;
+    d.has_noise = (p.sigma != 0.0 || p.sigma_V != 0.0) ? 1 : 0;
+    d.has_vnoise = p.sigma_V != 0.0 ? 1 : 0;
+    d.vnoise_c = (float)(p.sigma_V / std::sqrt(p.dt * g.dV));
+    d.noise_sub = p.noise_substeps > 1 ? (int)p.noise_substeps : 1;
+    d.inv_sqrt_sub = (float)(1.0 / std::sqrt((double)d.noise_sub));  // a power of two or its root
+    d.Vgrid = p.V_grid;
+    for (int a = 0; a < p.ndim; a++) {
+        d.E[a] = reinterpret_cast<const float2*>(ws + g.tab_off[a]);
+        d.tw[a] = reinterpret_cast<const float2*>(ws + g.tw_off[a]);
+        if (f64) {
+            d.E64[a] = reinterpret_cast<const double2*>(ws + g.tab64_off[a]);
+            d.tw64[a] = reinterpret_cast<const double2*>(ws + g.tw64_off[a]);
+        }
+    }
+    if (g.kline) {
+        d.E2 = reinterpret_cast<const float2*>(ws + g.e2_off);
+        d.K = reinterpret_cast<float2*>(ws + g.k_off);
+    }
+    if (p.conv_K) d.convK = reinterpret_cast<const float2*>(ws + g.conv_off);
 }
 
 }  // namespace
@@ -852,6 +910,82 @@ int advance(rk4ip_plan_t plan, float2* psi, int64_t step, int64_t nsteps) {
     return RK4IP_OK;
 }
 
+// ---------------------------------------------------------------- the no-allocation step
+//
+// rk4ip_step_noalloc keeps its tables and work fields in `scratch`, a file-scope device
+// array that every GPU the library runs on holds for the life of the process. In host code
+// the array's name is not a device address: its address is taken once per device with
+// hipGetSymbolAddress (with that device current) and only that pointer is used.
+constexpr size_t kNoallocBytes = RK4IP_NOALLOC_SCRATCH_BYTES;
+constexpr int kNoallocMaxGroups = 16;
+constexpr int kNoallocMaxDevices = 64;
+
+static __device__ __align__(256) unsigned char scratch[kNoallocBytes];
+
+struct NoallocDevice {
+    std::once_flag once;
+    char* ptr = nullptr;
+    int status = RK4IP_ERR_NO_DEVICE;
+};
+NoallocDevice g_noalloc[kNoallocMaxDevices];
+
+// The scratch address of the current device (and whether it is a gfx950), looked up once.
+int noalloc_scratch(char** out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kNoallocMaxDevices) {
+        (void)hipGetLastError();
+        return RK4IP_ERR_NO_DEVICE;
+    }
+    NoallocDevice& nd = g_noalloc[dev];
+    std::call_once(nd.once, [&] {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) != hipSuccess || std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+            (void)hipGetLastError();
+            nd.status = RK4IP_ERR_NO_DEVICE;
+            return;
+        }
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            nd.status = RK4IP_ERR_HIP;
+            return;
+        }
+        nd.ptr = static_cast<char*>(ptr);
+        nd.status = RK4IP_OK;
+    });
+    *out = nd.ptr;
+    return nd.status;
+}
+
+// The tables of build_tables computed on the device in FP64 (the same expressions, in the
+// same order, without contraction), one thread per entry m: (E - 1)/n, the twiddles and,
+// when E2 is not null, (e^{L h} - 1)/n. kscale = 2 pi / L; gamma is the damping of this axis
+// (zero off axis 0).
+__global__ void k_noalloc_tables(float2* __restrict__ E, float2* __restrict__ tw, float2* __restrict__ E2, int n,
+                                 double kscale, double alpha, double h, double gamma) {
+#pragma clang fp contract(off)
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= n) return;
+    const double damp = exp(-gamma * h / 2.0);
+    const double em1 = expm1(-gamma * h / 2.0);
+    const double inv_n = 1.0 / (double)n;
+    const double k = kscale * (double)(m < n / 2 ? m : m - n);
+    const double theta = alpha * k * k * h / 2.0;
+    const double sh = sin(theta / 2.0);
+    const double c = em1 - 2.0 * damp * sh * sh;
+    const double sn = -damp * sin(theta);
+    E[m] = make_float2((float)(c * inv_n), (float)(sn * inv_n));
+    const double ang = 2.0 * kPi * (double)m / (double)n;
+    tw[m] = make_float2((float)cos(ang), (float)-sin(ang));
+    if (E2) {
+        const double d2 = damp * damp, em2 = expm1(-gamma * h), st = sin(theta);
+        const double c2 = em2 - 2.0 * d2 * st * st;
+        const double s2 = -d2 * sin(2.0 * theta);
+        E2[m] = make_float2((float)(c2 * inv_n), (float)(s2 * inv_n));
+    }
+}
+
 }  // namespace
 
 // ================================================================== C ABI
@@ -885,7 +1019,7 @@ int rk4ip_plan(const rk4ip_problem* probs, int nprob, void* workspace, size_t ws
     if (rc != RK4IP_OK) return rc;
     if (!workspace || (reinterpret_cast<uintptr_t>(workspace) % kAlign) != 0) return RK4IP_ERR_INVALID_ARG;
     std::vector<GroupHost> gh(nprob);
-    Layout L = layout(probs, nprob, flags, &gh);
+    Layout L = layout(probs, nprob, flags, gh.data());
     if (ws_bytes < L.total) return RK4IP_ERR_WORKSPACE_TOO_SMALL;
 
     rk4ip_plan_s* plan = new (std::nothrow) rk4ip_plan_s();
@@ -914,42 +1048,7 @@ int rk4ip_plan(const rk4ip_problem* probs, int nprob, void* workspace, size_t ws
         g.p = probs[i];
         const rk4ip_problem& p = g.p;
         GroupDev& d = g.d;
-        std::memset(&d, 0, sizeof(d));
-        d.ndim = p.ndim;
-        g.M = 1;
-        g.dV = 1.0;
-        for (int a = 0; a < 3; a++) {
-            const int64_t nt = transform_len(p, a);
-            d.n[a] = (int)nt;
-            d.log2n[a] = ilog2i(nt);
-            g.M *= p.n[a];
-            if (a < p.ndim) {
-                const double dx = (p.hi[a] - p.lo[a]) / (double)p.n[a];
-                g.dV *= dx;
-                // a cosine / sine group's points are the cell centres lo + (j + 1/2) dx
-                d.lo[a] = (float)(p.basis ? p.lo[a] + 0.5 * dx : p.lo[a]);
-                d.dx[a] = (float)dx;
-                d.half_trap[a] = (float)(0.5 * p.trap[a]);
-                d.inv_n[a] = (float)(1.0 / (double)nt);
-            }
-        }
-        d.basis = p.basis;
-        d.M = g.M;
-        d.batch = p.batch;
-        d.offset = offset;
-        d.h = (float)p.dt;
-        d.gnl = (float)p.g_nl;
-        d.noise_c = (float)(p.dt * p.sigma / std::sqrt(2.0 * p.dt * g.dV));
-        d.xi_scale = (float)(1.0 / std::sqrt(2.0 * p.dt * g.dV));
-        d.seed_lo = (uint32_t)(p.seed & 0xFFFFFFFFu);
-        d.seed_hi = (uint32_t)(p.seed >> 32);
-        d.id_base = p.id_base;
-        d.has_noise = (p.sigma != 0.0 || p.sigma_V != 0.0) ? 1 : 0;
-        d.has_vnoise = p.sigma_V != 0.0 ? 1 : 0;
-        d.vnoise_c = (float)(p.sigma_V / std::sqrt(p.dt * g.dV));
-        d.noise_sub = p.noise_substeps > 1 ? (int)p.noise_substeps : 1;
-        d.inv_sqrt_sub = (float)(1.0 / std::sqrt((double)d.noise_sub));  // a power of two or its root
-        d.Vgrid = p.V_grid;
+        fill_group(g, plan->ws, plan->f64, offset);
         for (int a = 0; a < p.ndim; a++) {
             std::vector<float2> E, tw, E2;
             std::vector<double2> E64, tw64;
@@ -958,10 +1057,8 @@ int rk4ip_plan(const rk4ip_problem* probs, int nprob, void* workspace, size_t ws
                          kline ? &E2 : nullptr);
             hipError_t e1 = hipMemcpy(plan->ws + g.tab_off[a], E.data(), sizeof(float2) * E.size(), hipMemcpyHostToDevice);
             hipError_t e2 = hipMemcpy(plan->ws + g.tw_off[a], tw.data(), sizeof(float2) * tw.size(), hipMemcpyHostToDevice);
-            if (e1 == hipSuccess && e2 == hipSuccess && kline) {
+            if (e1 == hipSuccess && e2 == hipSuccess && kline)
                 e1 = hipMemcpy(plan->ws + g.e2_off, E2.data(), sizeof(float2) * E2.size(), hipMemcpyHostToDevice);
-                d.E2 = reinterpret_cast<const float2*>(plan->ws + g.e2_off);
-            }
             if (e1 == hipSuccess && e2 == hipSuccess && plan->f64) {
                 e1 = hipMemcpy(plan->ws + g.tab64_off[a], E64.data(), sizeof(double2) * E64.size(),
                                hipMemcpyHostToDevice);
@@ -973,14 +1070,7 @@ int rk4ip_plan(const rk4ip_problem* probs, int nprob, void* workspace, size_t ws
                 release_plan(plan);
                 return rc;
             }
-            d.E[a] = reinterpret_cast<const float2*>(plan->ws + g.tab_off[a]);
-            d.tw[a] = reinterpret_cast<const float2*>(plan->ws + g.tw_off[a]);
-            if (plan->f64) {
-                d.E64[a] = reinterpret_cast<const double2*>(plan->ws + g.tab64_off[a]);
-                d.tw64[a] = reinterpret_cast<const double2*>(plan->ws + g.tw64_off[a]);
-            }
         }
-        if (g.kline) d.K = reinterpret_cast<float2*>(plan->ws + g.k_off);
         if (p.conv_K) {
             std::vector<float2> kh;
             build_conv_table(p, g.dV, kh);
@@ -991,8 +1081,8 @@ int rk4ip_plan(const rk4ip_problem* probs, int nprob, void* workspace, size_t ws
                 release_plan(plan);
                 return rc;
             }
-            d.convK = reinterpret_cast<const float2*>(plan->ws + g.conv_off);
         }
+        (void)d;
         g.first_inst = inst;
         offset += p.batch * g.M;
         inst += p.batch;
@@ -1365,6 +1455,65 @@ int rk4ip_debug_apply_D(rk4ip_plan_t plan, void* psi, int adjoint) {
             }
             HIPCHK(plan, rk4ip::launch_axis(g.d, a, rk4ip::PASS_D1, pa, plan->stream));
         }
+    return RK4IP_OK;
+}
+
+int rk4ip_step_noalloc(const rk4ip_problem* probs, int nprob, void* psi_v, int64_t step_index, void* stream_v) {
+    if (!psi_v || step_index < 0) return RK4IP_ERR_INVALID_ARG;
+    int rc = validate(probs, nprob, 0);
+    if (rc != RK4IP_OK) return rc;
+    if (nprob > kNoallocMaxGroups) return RK4IP_ERR_INVALID_ARG;
+    for (int i = 0; i < nprob; i++)
+        if (probs[i].conv_K) return RK4IP_ERR_INVALID_ARG;  // its table is a host-side DFT
+    GroupHost gh[kNoallocMaxGroups];
+    const Layout L = layout(probs, nprob, 0, gh);
+    if (L.total > kNoallocBytes) return RK4IP_ERR_WORKSPACE_TOO_SMALL;
+    char* ws = nullptr;
+    if ((rc = noalloc_scratch(&ws)) != RK4IP_OK) return rc;
+    hipStream_t st = static_cast<hipStream_t>(stream_v);
+    float2* psi = static_cast<float2*>(psi_v);
+    float2* A = reinterpret_cast<float2*>(ws + L.fields);
+    float2* B = A + L.points;
+    int64_t offset = 0;
+    for (int i = 0; i < nprob; i++) {
+        GroupHost& g = gh[i];
+        g.p = probs[i];
+        fill_group(g, ws, false, offset);
+        offset += g.p.batch * g.M;
+        const rk4ip_problem q = transform_problem(g.p);
+        for (int a = 0; a < g.p.ndim; a++) {
+            const int n = (int)q.n[a];
+            hipLaunchKernelGGL(k_noalloc_tables, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
+                               const_cast<float2*>(g.d.E[a]), const_cast<float2*>(g.d.tw[a]),
+                               g.kline ? const_cast<float2*>(g.d.E2) : nullptr, n, 2.0 * kPi / (q.hi[a] - q.lo[a]),
+                               q.alpha, q.dt, a == 0 ? q.gamma : 0.0);
+            if (hipGetLastError() != hipSuccess) return RK4IP_ERR_HIP;
+        }
+    }
+    // one step of every group with the default schedules: the launches rk4ip_step makes on
+    // a plan built without flags
+    for (int i = 0; i < nprob; i++) {
+        const GroupHost& g = gh[i];
+        if (g.p.ndim == 1) {
+            if (rk4ip::launch_line_step(g.d, psi, 1, step_index, nullptr, false, 0, false, st, 0) != hipSuccess)
+                return RK4IP_ERR_HIP;
+            continue;
+        }
+        PassDef defs[kMaxPasses];
+        const int np = pass_list(g.p.ndim, false, defs);
+        for (int role : {ROLE_OPEN, ROLE_MID, ROLE_CLOSE}) {
+            for (int k = 0; k < np; k++) {
+                if (defs[k].role != role) continue;
+                rk4ip::PassArgs pa{};
+                pa.psi = psi;
+                pa.A = A;
+                pa.B = B;
+                pa.step_off = step_index;
+                pa.twice = defs[k].twice;
+                if (rk4ip::launch_axis(g.d, defs[k].axis, defs[k].mode, pa, st) != hipSuccess) return RK4IP_ERR_HIP;
+            }
+        }
+    }
     return RK4IP_OK;
 }
 

@@ -41,7 +41,7 @@ EXPORTS = [
     "rk4ip_diagnostics", "rk4ip_overlap", "rk4ip_moments", "rk4ip_adjoint_workspace_bytes",
     "rk4ip_adjoint", "rk4ip_ark45", "rk4ip_status", "rk4ip_destroy", "rk4ip_strerror", "rk4ip_last_error",
     "rk4ip_schedule", "rk4ip_num_passes", "rk4ip_profile", "rk4ip_profile_read", "rk4ip_debug_philox", "rk4ip_debug_noise", "rk4ip_debug_fft",
-    "rk4ip_debug_apply_D",
+    "rk4ip_debug_apply_D", "rk4ip_step_noalloc",
 ]
 
 
@@ -100,6 +100,7 @@ def load(path: str = LIB_PATH):
         "rk4ip_debug_noise": (i32, [vp, i32, i64, vp]),
         "rk4ip_debug_fft": (i32, [vp, i32, i32, vp, vp, i64, i32]),
         "rk4ip_debug_apply_D": (i32, [vp, vp, i32]),
+        "rk4ip_step_noalloc": (i32, [P, i32, vp, i64, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -213,6 +214,18 @@ def rk4ip_debug_philox(seed: int, ctr, out) -> None:
     op = _buf(out, 4 * n, torch.int32, "out")
     _check(load().rk4ip_debug_philox(int(seed) & 0xFFFFFFFFFFFFFFFF, cp, n, op, _stream()),
            what="rk4ip_debug_philox")
+
+
+def step_noalloc(probs: List[rk4ip_problem], psi, step_index: int = 0):
+    """rk4ip_step_noalloc: one step of every instance of `probs` in place on psi (device
+    complex64, all points of all groups), without a plan or a workspace (the library's
+    static device buffer holds the tables and work fields)."""
+    import torch
+
+    arr = problems_array(list(probs))
+    points = sum(int(p.batch * p.n[0] * p.n[1] * p.n[2]) for p in probs)
+    _check(load().rk4ip_step_noalloc(arr, len(probs), _buf(psi, points, torch.complex64, "psi"), int(step_index),
+                                     _stream()), None, "rk4ip_step_noalloc")
 
 
 class Plan:

@@ -220,3 +220,24 @@ def test_instances_beyond_32bit_tile_offsets_are_refused(lib):
     arr = (rk4ip.rk4ip_problem * 1)(rk4ip.make_problem(n=(1024, 1024, 1024), **big))
     rc = lib.rk4ip_plan(arr, 1, ctypes.c_void_p(256), 1 << 40, None, 0, ctypes.byref(h))
     assert rc == rk4ip.RK4IP_ERR_UNSUPPORTED_SHAPE and not h.value
+
+
+def test_noalloc_step_refuses_before_touching_a_device(lib):
+    """rk4ip_step_noalloc checks its arguments before it looks for a device: more than 16
+    groups, a non-local kernel or a problem beyond its static buffer are refused with the
+    documented codes; a valid call on a host without a gfx950 says so."""
+    fake = ctypes.c_void_p(256)
+    small = rk4ip.make_problem((64,), (0,), (1,), 1e-3)
+    many = rk4ip.problems_array([small] * 17)
+    assert lib.rk4ip_step_noalloc(many, 17, fake, 0, None) == rk4ip.RK4IP_ERR_INVALID_ARG
+    conv = rk4ip.problems_array([rk4ip.make_problem((64,), (0,), (1,), 1e-3, conv_K=np.ones(64))])
+    assert lib.rk4ip_step_noalloc(conv, 1, fake, 0, None) == rk4ip.RK4IP_ERR_INVALID_ARG
+    big = rk4ip.problems_array([rk4ip.make_problem((256, 256, 128), (0, 0, 0), (1, 1, 1), 1e-3)])
+    assert lib.rk4ip_step_noalloc(big, 1, fake, 0, None) == rk4ip.RK4IP_ERR_WORKSPACE_TOO_SMALL
+    one = rk4ip.problems_array([small])
+    assert lib.rk4ip_step_noalloc(one, 1, None, 0, None) == rk4ip.RK4IP_ERR_INVALID_ARG
+    assert lib.rk4ip_step_noalloc(one, 1, fake, -1, None) == rk4ip.RK4IP_ERR_INVALID_ARG
+    import torch
+
+    if not torch.cuda.is_available():
+        assert lib.rk4ip_step_noalloc(one, 1, fake, 0, None) == rk4ip.RK4IP_ERR_NO_DEVICE
