@@ -130,6 +130,42 @@ __device__ __forceinline__ float2 noise_z(const GroupDev& g, int64_t j, uint32_t
     return make_float2(acc.x * g.inv_sqrt_sub, acc.y * g.inv_sqrt_sub);
 }
 
+// The unit complex normals of R points j(m) = j0 + m S (S even, m < R) of one lane, when
+// the partner lane (lane ^ 1) holds the points j(m) ^ 1: a Philox block feeds the pair of
+// points (2q, 2q + 1), so the even lane draws the blocks of m < R/2 and the odd lane those
+// of m >= R/2, and each hands the partner the two words it needs. The same integers and the
+// same arithmetic as noise_z with one draw per step (bitwise the same values), half the
+// Philox work. All lanes of the wavefront must call it together.
+template <int R>
+__device__ __forceinline__ void noise_z_pairs(const GroupDev& g, int64_t j0, int64_t S, uint32_t inst, int64_t step,
+                                              float2 (&z)[R]) {
+    static_assert(R % 2 == 0, "pairs of elements");
+    const bool odd = (j0 & 1) != 0;
+    const int64_t jb = j0 + (odd ? (int64_t)(R / 2) * S : 0);  // first element this lane draws for
+    uint32_t lo_w[R / 2][2], hi_w[R / 2][2];  // words of element k and of element k + R/2
+#pragma unroll
+    for (int k = 0; k < R / 2; k++) {
+        const U4 r = philox4x32_10(noise_counter(jb + k * S, inst, step), g.seed_lo, g.seed_hi);
+        // keep the words of this lane's own point, send the partner's
+        const uint32_t keep0 = odd ? r.z : r.x, keep1 = odd ? r.w : r.y;
+        const uint32_t send0 = odd ? r.x : r.z, send1 = odd ? r.y : r.w;
+        const uint32_t got0 = (uint32_t)__shfl_xor((int)send0, 1);
+        const uint32_t got1 = (uint32_t)__shfl_xor((int)send1, 1);
+        lo_w[k][0] = odd ? got0 : keep0;
+        lo_w[k][1] = odd ? got1 : keep1;
+        hi_w[k][0] = odd ? keep0 : got0;
+        hi_w[k][1] = odd ? keep1 : got1;
+    }
+#pragma unroll
+    for (int m = 0; m < R; m++) {
+        const uint32_t a = m < R / 2 ? lo_w[m % (R / 2)][0] : hi_w[m % (R / 2)][0];
+        const uint32_t b = m < R / 2 ? lo_w[m % (R / 2)][1] : hi_w[m % (R / 2)][1];
+        float rad, c, sn;
+        box_muller(a, b, rad, c, sn);
+        z[m] = make_float2(rad * c, rad * sn);
+    }
+}
+
 // The noise of the potential at point j (in units of the potential): sigma_V eta with
 // eta = Re(z)/sqrt(h dV), z the complex normal of counter tag 3, summed over the noise
 // substeps like noise_z (explicit FMAs for the same reason).

@@ -298,14 +298,19 @@ __global__ void __launch_bounds__((FFTShape<N, RR>::T * LPB))
     auto mulE = [&](c32 z, int j) { return cadd(z, cmul(z, cscale(E1[j], fn))); };
     for (int s = 0; s < nsteps; s++, step++) {
         c32 nz[R];
-#pragma unroll
-        for (int m = 0; m < R; m++) {
-            if constexpr (NOISE) {
-                const float2 z = noise_z(g, t + m * T, iid, step);
-                nz[m] = make_float2(g.noise_c * z.x, g.noise_c * z.y);
+        if constexpr (NOISE) {
+            if (T >= 2 && g.noise_sub == 1) {
+                // lanes t and t ^ 1 hold the pairs of points one Philox block feeds (uniform)
+                noise_z_pairs<R>(g, t, T, iid, step, nz);
             } else {
-                nz[m] = zero;
+#pragma unroll
+                for (int m = 0; m < R; m++) nz[m] = noise_z(g, t + m * T, iid, step);
             }
+#pragma unroll
+            for (int m = 0; m < R; m++) nz[m] = make_float2(g.noise_c * nz[m].x, g.noise_c * nz[m].y);
+        } else {
+#pragma unroll
+            for (int m = 0; m < R; m++) nz[m] = zero;
         }
         c32 inc[1][R];  // F of the step's increment, without E^2 P
         if constexpr (SI) {
