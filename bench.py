@@ -137,6 +137,12 @@ def form_uneven_batch(torch, rk4ip, workloads, steps: int = 100, sample: int = 2
     t = _timed(torch, lambda: (psi.copy_(psi0), plan.run(psi, steps)))
     batched = pts * steps / t
     plan.destroy()
+    # one launch per pass kind over both groups (work list), against the per-group launches
+    mplan = rk4ip.Plan(probs, flags=rk4ip.RK4IP_FLAG_GRAPH | rk4ip.RK4IP_FLAG_MERGE_GROUPS)
+    mpsi = psi0.clone()
+    tm = _timed(torch, lambda: (mpsi.copy_(psi0), mplan.run(mpsi, steps)))
+    merged_rel = float(torch.linalg.vector_norm(mpsi - psi) / torch.linalg.vector_norm(psi))
+    mplan.destroy()
     # plain path: `sample` instances of each size, one plan each, one after another
     tot_pts, tot_s = 0, 0.0
     same = True
@@ -157,9 +163,15 @@ def form_uneven_batch(torch, rk4ip, workloads, steps: int = 100, sample: int = 2
     # per-size throughputs weighted by the batch's point counts
     plain = tot_pts / tot_s
     return {"workload": f"adjoint2d shapes (32 x 128^2 + 32 x 256^2), forward, {steps} steps",
-            "batched_pt_steps_per_s": batched, "plain_pt_steps_per_s": plain,
+            "batched_pt_steps_per_s": batched, "batched_launches_per_step": 2 * len(w.groups),
+            "batched_us_per_step": t / steps * 1e6,
+            "merged_pt_steps_per_s": pts * steps / tm, "merged_launches_per_step": 2,
+            "merged_us_per_step": tm / steps * 1e6, "merged_vs_batched": t / tm,
+            "merged_rel_diff_to_batched": merged_rel,
+            "plain_pt_steps_per_s": plain,
             "plain_sample": f"{sample} instances of each size, one plan each, one after another",
-            "speedup_vs_plain": batched / plain, "matches_plain_within_1e-5": same}
+            "speedup_vs_plain": batched / plain, "merged_speedup_vs_plain": pts * steps / tm / plain,
+            "matches_plain_within_1e-5": same}
 
 
 def _torch_rk4ip(torch, w, psi0_list, V_list, steps):

@@ -103,6 +103,15 @@ enum {
  * Stratonovich draw as for RK4 (see noise_substeps). rk4ip_adjoint does not support it
  * (RK4IP_ERR_INVALID_ARG). */
 #define RK4IP_FLAG_SEMI_IMPLICIT 0x10u
+/* One launch per pass kind over every 2D/3D group of the plan (many instances of uneven
+ * lattice size, as in the multi-path runs of Sec. 4.6) instead of one per group: a work
+ * list divides the launch's workgroups among the groups. Every group's tiles use one fixed
+ * schedule (radix 8, 256 threads: 2048/n lines or columns), the same arithmetic as the
+ * per-group launches with that schedule. Takes RK4IP steps with FP32 transforms on 2D/3D
+ * groups whose axes all have 128 or 256 points, with n[0] >= 2048/n[a] for a >= 1, at most
+ * 64 groups (else RK4IP_ERR_UNSUPPORTED_SHAPE); 1D groups run as usual. The adjoint keeps
+ * per-group launches. */
+#define RK4IP_FLAG_MERGE_GROUPS 0x20u
 
 typedef struct rk4ip_plan_s* rk4ip_plan_t;
 

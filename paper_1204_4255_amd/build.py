@@ -12,7 +12,8 @@ LIB = os.path.join(HERE, "librk4ip.so")
 BUILD = os.path.join(HERE, "_build")
 SOURCES = [
     "kernels_fwd.hip", "kernels_pass_d.hip", "kernels_pass_first.hip", "kernels_pass_last.hip", "kernels_pass_xf.hip",
-    "kernels_pass_si.hip", "kernels_ark45.hip", "kernels_adj.hip", "kernels_aux.hip", "rk4ip.hip",
+    "kernels_pass_si.hip", "kernels_pass_merged.hip", "kernels_ark45.hip", "kernels_adj.hip", "kernels_aux.hip",
+    "rk4ip.hip",
 ]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -72,7 +72,7 @@ __global__ void __launch_bounds__(FFTShape<N>::T* LINES)
     stage_tables<F, c32>(tw, nullptr, g.tw[axis], nullptr);
     const int t = CONTIG ? (int)(threadIdx.x % T) : (int)(threadIdx.x / LINES);
     const int l = CONTIG ? (int)(threadIdx.x / T) : (int)(threadIdx.x % LINES);
-    const Tile<F, CONTIG, LINES> tile(g, axis, l, t);
+    const Tile<F, CONTIG, LINES> tile(g, axis, l, t, blockIdx.x, gridDim.x);
     const float2* ps = psi + g.offset + tile.base;
     c32 f[1][R];
     double s1 = 0.0, s2 = 0.0, s3 = 0.0;

@@ -67,11 +67,31 @@ struct DiagConst {
     double half_g;
 };
 
+// Work list of a pass launched once over several groups (kernels_pass_merged.hip): the
+// groups' kernel parameters live in device memory; workgroup b belongs to entry k with
+// block0[k] <= b < block0[k + 1] (each entry starts on a multiple of 8 blocks) and runs
+// tile b - block0[k] of its nblk[k].
+constexpr int kMaxMerged = 64;
+struct MergedList {
+    const GroupDev* groups;  // device, every group of the plan in plan order
+    int count;               // entries
+    int gid[kMaxMerged];     // plan-order group of each entry
+    uint32_t block0[kMaxMerged];
+    uint32_t nblk[kMaxMerged];
+};
+
 int axis_lines(int N, int axis, int n0);
 // Whether a (lines, seq) schedule of a pass is compiled for this length and axis.
 bool axis_schedule_ok(int N, int mode, int axis, int n0, int lines, int seq, int radix, bool f64, int occ = 1);
 
 hipError_t launch_axis(const GroupDev& g, int axis, int mode, const PassArgs& a, hipStream_t s);
+// The merged pass: lengths 128 and 256, forward-step kinds (FIRST, D2, LF, XF, LAST2),
+// FP32 transforms, 256-thread tiles of merged_tile_lines(N) lines or columns; smem =
+// the largest merged_lds_bytes of its entries.
+hipError_t launch_axis_merged(const MergedList& ml, int mode, int axis, bool noise, uint32_t blocks, size_t smem,
+                              const PassArgs& a, hipStream_t s);
+size_t merged_lds_bytes(int N, int mode, int axis);
+int merged_tile_lines(int N);
 hipError_t launch_axis_adjoint(const GroupDev& g, int axis, int mode, const PassArgs& a, hipStream_t s);
 hipError_t launch_axis_d(const GroupDev& g, int axis, int mode, const PassArgs& a, hipStream_t s);
 hipError_t launch_axis_first(const GroupDev& g, int axis, int mode, const PassArgs& a, hipStream_t s);

@@ -132,16 +132,17 @@ struct Tile {
     uint32_t jstride;  // in-instance index step per element along the axis
     bool active;
 
-    __device__ __forceinline__ Tile(const GroupDev& g, int axis, int l, int t) {
+    // bid: this workgroup's tile among the nblk tiles of the group's pass
+    __device__ __forceinline__ Tile(const GroupDev& g, int axis, int l, int t, uint32_t bid, uint32_t nblk) {
         constexpr int T = F::T;
         // every count below is a power of two: shifts and masks, no division
         if constexpr (CONTIG) {
             const int lpi = g.log2n[1] + g.log2n[2];  // log2 of the lines per instance
             const int64_t nlines = g.batch << lpi;
-            const int64_t line = (int64_t)blockIdx.x * LINES + l;
+            const int64_t line = (int64_t)bid * LINES + l;
             active = line < nlines;
             const int64_t ln = active ? line : 0;
-            base = (int64_t)blockIdx.x * LINES * N;
+            base = (int64_t)bid * LINES * N;
             off0 = (uint32_t)(l * N + t);
             dstep = T;
             inst = ln >> lpi;
@@ -151,7 +152,7 @@ struct Tile {
             const int xt_log = g.log2n[0] - ilog2(LINES);  // column tiles per row
             const int outer_log = (axis == 1) ? g.log2n[2] : g.log2n[1];
             // tiles whose rows are narrower than a 128-byte line share lines with a neighbour
-            uint32_t bid = (LINES * 8 < 128) ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x;
+            bid = (LINES * 8 < 128) ? xcd_tile(bid, nblk) : bid;
             const int xt = (int)(bid & ((1u << xt_log) - 1u));
             bid >>= xt_log;
             const int outer = (int)(bid & ((1u << outer_log) - 1u));
@@ -213,24 +214,38 @@ constexpr bool uses_rhs(int mode) {
 // OCC: the minimum waves per SIMD the register allocation must allow (1 = no constraint;
 // 4 is a tuned variant for the radix-8 passes, whose allocation otherwise lands just
 // above the 128 VGPRs that four waves need).
-template <int N, int MODE, bool CONTIG, int LINES, bool NOISE, int SEQ, int RR, bool P64, int OCC>
-__global__ void __launch_bounds__((FFTShape<N, RR>::T * LINES)) __attribute__((amdgpu_waves_per_eu(OCC)))
-k_axis(GroupDev g, int axis, PassArgs args) {
+// LDS of one workgroup of the pass: the exchange buffers, then the twiddles and the
+// propagator table (V entries).
+template <int N, int MODE, bool CONTIG, int LINES, int SEQ, int RR, bool P64>
+struct AxisLds {
+    using V = typename std::conditional<P64, c64, c32>::type;
+    using L = LdsLayout<N, LINES, CONTIG, FFTShape<N, RR>::R>;
+    static constexpr int BUF = (SEQ != 0 ? 1 : fields_of(MODE)) * L::SIZE;
+    static constexpr int ENTRIES = BUF + 2 * N;
+    static constexpr size_t BYTES = sizeof(V) * (size_t)ENTRIES;
+};
+
+// The pass on tile `bid` of the `nblk` tiles of group g (one workgroup of T x LINES
+// threads); smem holds AxisLds<...>::ENTRIES values of the working type.
+template <int N, int MODE, bool CONTIG, int LINES, bool NOISE, int SEQ, int RR, bool P64>
+__device__ __forceinline__ void axis_body(const GroupDev& g, int axis, const PassArgs& args, uint32_t bid, uint32_t nblk,
+                                          typename AxisLds<N, MODE, CONTIG, LINES, SEQ, RR, P64>::V* smem) {
     using F = FFTShape<N, RR>;
     using V = typename std::conditional<P64, c64, c32>::type;  // transform working type
     constexpr int R = F::R, T = F::T;
     constexpr int NF = fields_of(MODE);
     using L = LdsLayout<N, LINES, CONTIG, R>;
-    __shared__ V lds[(SEQ != 0 ? 1 : NF) * L::SIZE];
-    __shared__ V tw[N];
-    __shared__ V E[N];
+    using A = AxisLds<N, MODE, CONTIG, LINES, SEQ, RR, P64>;
+    V* lds = smem;
+    V* tw = smem + A::BUF;
+    V* E = tw + N;
     if constexpr (P64)
         stage_tables<F>(tw, E, g.tw64[axis], g.E64[axis]);
     else
         stage_tables<F>(tw, E, g.tw[axis], g.E[axis]);
     const int t = CONTIG ? (int)(threadIdx.x % T) : (int)(threadIdx.x / LINES);
     const int l = CONTIG ? (int)(threadIdx.x / T) : (int)(threadIdx.x % LINES);
-    const Tile<F, CONTIG, LINES> tile(g, axis, l, t);
+    const Tile<F, CONTIG, LINES> tile(g, axis, l, t, bid, nblk);
     const int64_t o = g.offset + tile.base;
     float2* __restrict__ ps = args.psi ? args.psi + o : nullptr;
     float2* __restrict__ pa = args.A ? args.A + o : nullptr;
@@ -434,6 +449,15 @@ k_axis(GroupDev g, int axis, PassArgs args) {
             st2(pb, tile.b8(m), f[1][m]);
         }
     }
+}
+
+// One group's pass: one workgroup per tile.
+template <int N, int MODE, bool CONTIG, int LINES, bool NOISE, int SEQ, int RR, bool P64, int OCC>
+__global__ void __launch_bounds__((FFTShape<N, RR>::T * LINES)) __attribute__((amdgpu_waves_per_eu(OCC)))
+k_axis(GroupDev g, int axis, PassArgs args) {
+    using A = AxisLds<N, MODE, CONTIG, LINES, SEQ, RR, P64>;
+    __shared__ typename A::V smem[A::ENTRIES];
+    axis_body<N, MODE, CONTIG, LINES, NOISE, SEQ, RR, P64>(g, axis, args, blockIdx.x, gridDim.x, smem);
 }
 
 // LDS of a strided tile of w columns and nf fields must fit the 160 KiB of a CU.

@@ -23,8 +23,8 @@ namespace {
 
 constexpr double kPi = 3.14159265358979323846;
 constexpr size_t kAlign = 256;
-constexpr uint32_t kKnownFlags =
-    RK4IP_FLAG_GRAPH | RK4IP_FLAG_AUTOTUNE | RK4IP_FLAG_FUSE_1D | RK4IP_FLAG_FP64_TRANSFORMS | RK4IP_FLAG_SEMI_IMPLICIT;
+constexpr uint32_t kKnownFlags = RK4IP_FLAG_GRAPH | RK4IP_FLAG_AUTOTUNE | RK4IP_FLAG_FUSE_1D |
+                                  RK4IP_FLAG_FP64_TRANSFORMS | RK4IP_FLAG_SEMI_IMPLICIT | RK4IP_FLAG_MERGE_GROUPS;
 constexpr uint32_t kMaxNoiseSubsteps = 1024;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
@@ -86,6 +86,7 @@ struct GroupHost {
 
 // Workspace layout computed identically by rk4ip_workspace_bytes and rk4ip_plan.
 struct Layout {
+    size_t gdev = 0;     // the groups' kernel parameters (merged launches)
     size_t header = 0;   // step counter + sticky flag
     size_t fields = 0;   // A and B
     size_t total = 0;
@@ -137,6 +138,20 @@ int validate(const rk4ip_problem* probs, int nprob, uint32_t flags) {
         ninst += p.batch;
     }
     if (ninst > (int64_t(1) << 31)) return RK4IP_ERR_INVALID_ARG;
+    if (flags & RK4IP_FLAG_MERGE_GROUPS) {
+        // the merged launches: RK4IP with FP32 transforms, lengths 128 and 256, tiles of
+        // 2048/n columns on the strided axes
+        if (flags & (RK4IP_FLAG_SEMI_IMPLICIT | RK4IP_FLAG_FP64_TRANSFORMS)) return RK4IP_ERR_UNSUPPORTED_SHAPE;
+        if (nprob > rk4ip::kMaxMerged) return RK4IP_ERR_UNSUPPORTED_SHAPE;
+        for (int i = 0; i < nprob; i++) {
+            const rk4ip_problem& p = probs[i];
+            if (p.ndim == 1) continue;
+            for (int a = 0; a < p.ndim; a++) {
+                if (p.n[a] != 128 && p.n[a] != 256) return RK4IP_ERR_UNSUPPORTED_SHAPE;
+                if (a > 0 && p.n[0] < 2048 / p.n[a]) return RK4IP_ERR_UNSUPPORTED_SHAPE;
+            }
+        }
+    }
     return RK4IP_OK;
 }
 
@@ -198,6 +213,10 @@ Layout layout(const rk4ip_problem* probs, int nprob, uint32_t flags, GroupHost* 
             off = align_up(off + sizeof(double) * 4 * (size_t)(p.batch * (M / p.n[a])));
         }
         L.points += p.batch * M;
+    }
+    if (flags & RK4IP_FLAG_MERGE_GROUPS) {
+        L.gdev = off;
+        off = align_up(off + sizeof(GroupDev) * (size_t)nprob);
     }
     L.fields = off;
     off = align_up(off + 2 * sizeof(float2) * (size_t)L.points);
@@ -279,6 +298,15 @@ struct rk4ip_plan_s {
     int* flag = nullptr;
     bool f64 = false;  // FP64 transforms in the forward step
     bool si = false;   // the semi-implicit integrator in place of RK4
+    // merged launches (RK4IP_FLAG_MERGE_GROUPS): one work list per (dimensionality, pass)
+    struct Merged {
+        int ndim, pass, mode, axis, role, twice;
+        bool noise;
+        uint32_t blocks;
+        size_t smem;
+        rk4ip::MergedList list;
+    };
+    std::vector<Merged> merged;
     std::string err;
     std::vector<std::vector<std::string>> sched_names;  // [group][pass]
     std::vector<std::vector<Sched>> sched;  // [group][pass]; zeros = default schedule
@@ -597,6 +625,62 @@ bool default_f64_sched(const GroupHost& g, int axis, int mode, Sched* out) {
     return false;
 }
 
+// Work lists of the merged launches (RK4IP_FLAG_MERGE_GROUPS): for every dimensionality
+// present and every pass of its list, the groups of that dimensionality in plan order, each
+// starting on a multiple of 8 workgroups (so the XCD-aware tile order of a group is the
+// one it has alone). The groups' kernel parameters are uploaded to the workspace at
+// `gdev`. Every group's schedule is set to the merged one (radix 8, 256 threads).
+int build_merged(rk4ip_plan_t plan, size_t gdev) {
+    const int ng = (int)plan->groups.size();
+    std::vector<GroupDev> devs(ng);
+    for (int i = 0; i < ng; i++) devs[i] = plan->groups[i].d;
+    GroupDev* dptr = reinterpret_cast<GroupDev*>(plan->ws + gdev);
+    HIPCHK(plan, hipMemcpy(dptr, devs.data(), sizeof(GroupDev) * (size_t)ng, hipMemcpyHostToDevice));
+    for (int nd = 2; nd <= 3; nd++) {
+        std::vector<int> members;
+        for (int i = 0; i < ng; i++)
+            if (plan->groups[i].p.ndim == nd) members.push_back(i);
+        if (members.empty()) continue;
+        PassDef defs[kMaxPasses];
+        const int np = pass_list(nd, false, defs);
+        for (int k = 0; k < np; k++) {
+            rk4ip_plan_s::Merged m{};
+            m.ndim = nd;
+            m.pass = k;
+            m.mode = defs[k].mode;
+            m.axis = defs[k].axis;
+            m.role = defs[k].role;
+            m.twice = defs[k].twice;
+            m.list.groups = dptr;
+            m.list.count = (int)members.size();
+            uint32_t b0 = 0;
+            for (size_t e = 0; e < members.size(); e++) {
+                GroupHost& g = plan->groups[members[e]];
+                const int N = (int)g.p.n[m.axis];
+                const int lines = rk4ip::merged_tile_lines(N);
+                const int64_t nl = g.p.batch * (g.M / g.p.n[m.axis]);  // lines along the axis
+                const int64_t nb = (nl + lines - 1) / lines;
+                if (nb > 0x7fffffffLL - b0) return fail(plan, RK4IP_ERR_UNSUPPORTED_SHAPE, "merged launch too large");
+                m.list.gid[e] = members[e];
+                m.list.block0[e] = b0;
+                m.list.nblk[e] = (uint32_t)nb;
+                b0 += (uint32_t)((nb + 7) / 8 * 8);
+                m.noise = m.noise || g.d.has_noise;
+                m.smem = std::max(m.smem, rk4ip::merged_lds_bytes(N, m.mode, m.axis));
+                Sched sc;
+                sc.lines = lines;
+                sc.seq = 0;
+                sc.radix = 8;
+                plan->sched[members[e]][k] = sc;
+            }
+            m.blocks = b0;
+            if (m.smem == 0) return fail(plan, RK4IP_ERR_UNSUPPORTED_SHAPE, "no merged kernel for this pass");
+            plan->merged.push_back(m);
+        }
+    }
+    return RK4IP_OK;
+}
+
 // Choose the fastest compiled schedule of every pass (RK4IP_FLAG_AUTOTUNE).
 int autotune(rk4ip_plan_t plan) {
     const char* path = std::getenv("RK4IP_TUNE_CACHE");
@@ -637,6 +721,7 @@ int autotune(rk4ip_plan_t plan) {
             fresh.push_back({tune_key(g, 0, plan->si), pick});
             continue;
         }
+        if (!plan->merged.empty()) continue;  // the merged launches have one fixed schedule
         PassDef defs[kMaxPasses];
         const int np = pass_list(g.p.ndim, plan->si, defs);
         for (int i = 0; i < np; i++) {
@@ -740,6 +825,25 @@ int enqueue_lattice(rk4ip_plan_t plan, hipStream_t stream, float2* psi, int64_t 
                     bool close, const int64_t* step_base) {
     const bool capturing = step_base != nullptr;
     auto launch_role = [&](int role, int64_t step) -> int {
+        if (!plan->merged.empty()) {
+            // one launch per pass over all groups of a dimensionality (timed under the
+            // first group of its work list)
+            for (const auto& m : plan->merged) {
+                if (m.role != role) continue;
+                rk4ip::PassArgs pa{};
+                pa.psi = psi;
+                pa.twice = m.twice;
+                pa.A = plan->A;
+                pa.B = plan->B;
+                pa.step_off = step;
+                pa.step_base = step_base;
+                int rc = timed_launch(plan, stream, m.list.gid[0], m.pass, capturing, [&] {
+                    return rk4ip::launch_axis_merged(m.list, m.mode, m.axis, m.noise, m.blocks, m.smem, pa, stream);
+                });
+                if (rc) return rc;
+            }
+            return RK4IP_OK;
+        }
         for (size_t gi = 0; gi < plan->groups.size(); gi++) {
             auto& g = plan->groups[gi];
             if (g.p.ndim == 1) continue;
@@ -1093,6 +1197,13 @@ int rk4ip_plan(const rk4ip_problem* probs, int nprob, void* workspace, size_t ws
     }
     plan->ninst = inst;
     plan->groups = std::move(gh);
+    if (flags & RK4IP_FLAG_MERGE_GROUPS) {
+        rc = build_merged(plan, L.gdev);
+        if (rc != RK4IP_OK) {
+            release_plan(plan);
+            return rc;
+        }
+    }
     if (plan->f64) {
         // FP64 transforms have no implicit default tile: take the first compiled candidate
         for (size_t gi = 0; gi < plan->groups.size(); gi++) {

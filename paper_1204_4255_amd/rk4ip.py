@@ -33,6 +33,7 @@ RK4IP_FLAG_AUTOTUNE = 0x2
 RK4IP_FLAG_FUSE_1D = 0x4
 RK4IP_FLAG_FP64_TRANSFORMS = 0x8
 RK4IP_FLAG_SEMI_IMPLICIT = 0x10
+RK4IP_FLAG_MERGE_GROUPS = 0x20
 BASIS_FOURIER, BASIS_COSINE, BASIS_SINE = 0, 1, 2
 
 # every symbol include/rk4ip.h declares

@@ -241,3 +241,20 @@ def test_noalloc_step_refuses_before_touching_a_device(lib):
 
     if not torch.cuda.is_available():
         assert lib.rk4ip_step_noalloc(one, 1, fake, 0, None) == rk4ip.RK4IP_ERR_NO_DEVICE
+
+
+def test_merge_groups_flag_limits(lib):
+    """RK4IP_FLAG_MERGE_GROUPS takes RK4IP with FP32 transforms on lattices whose axes have
+    128 or 256 points (and enough x columns for the strided tiles); it adds the groups'
+    kernel parameters to the workspace."""
+    M = rk4ip.RK4IP_FLAG_MERGE_GROUPS
+    ok = [rk4ip.make_problem((128, 128), (0, 0), (1, 1), 1e-3, batch=3),
+          rk4ip.make_problem((256, 256), (0, 0), (1, 1), 1e-3, batch=2),
+          rk4ip.make_problem((64,), (0,), (1,), 1e-3)]
+    assert rk4ip.rk4ip_workspace_bytes(ok, M) > rk4ip.rk4ip_workspace_bytes(ok, 0) > 0
+    for bad in ([rk4ip.make_problem((64, 64), (0, 0), (1, 1), 1e-3)],
+                [rk4ip.make_problem((512, 128), (0, 0), (1, 1), 1e-3)]):
+        assert rk4ip.rk4ip_workspace_bytes(bad, M) == 0
+        assert rk4ip.rk4ip_workspace_bytes(bad, 0) > 0
+    assert rk4ip.rk4ip_workspace_bytes(ok, M | rk4ip.RK4IP_FLAG_SEMI_IMPLICIT) == 0
+    assert rk4ip.rk4ip_workspace_bytes(ok, M | rk4ip.RK4IP_FLAG_FP64_TRANSFORMS) == 0
