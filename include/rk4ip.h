@@ -122,11 +122,14 @@ typedef struct {
                                 domain (Sec. 3.1: even / odd boundary conditions at both ends),
                                 on the cell centres x_j = lo + (j + 1/2)(hi - lo)/n with modes
                                 cos / sin(k_m (x - lo)), k_m = pi m / (hi - lo) (cosine,
-                                m = 0..n-1) or pi (m + 1) / (hi - lo) (sine). The step runs on
-                                the even / odd extension of the line (2n <= 4096, 2048 with
-                                FP64 transforms); not with conv_K. Plans holding such a group
-                                take rk4ip_step and rk4ip_run without samples; the other
-                                entry points return RK4IP_ERR_INVALID_ARG. */
+                                m = 0..n-1) or pi (m + 1) / (hi - lo) (sine). The step runs
+                                through the n-point transform of the reordered line (n <= 4096;
+                                Makhoul's cosine transform, the propagator pairing modes m and
+                                n - m); in the FP64-transform form or with sigma_V on the even /
+                                odd extension (2n points: 2n <= 2048 / 4096). Not with conv_K.
+                                Plans holding such a group take rk4ip_step and rk4ip_run
+                                without samples; the other entry points return
+                                RK4IP_ERR_INVALID_ARG. */
     int64_t n[3];            /* points per axis, axis 0 = x (contiguous); unused axes = 1 */
     double lo[3], hi[3];     /* periodic domain [lo, hi) per axis */
     int64_t batch;           /* instances in this group, >= 1 */

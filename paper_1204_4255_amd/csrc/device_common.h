@@ -44,6 +44,8 @@ struct GroupDev {
     const float2* convK;     // [n] (FFT of the non-local kernel) dV / n (1D groups), or null
     const float2* E2;        // [n] (e^{L h} - 1)/n of axis 0 (1D Fourier groups: the k-space line
                              // step), else null
+    const double2* pairT1;   // [n] cosine / sine line through its reordered transform: (A - 1)/n and
+    const double2* pairT2;   // B/n of the mode-pairing propagator, FP64 (else null)
     float2* K;               // [batch][n] the k-space state of a 1D group run by the k-space line
                              // step (kept between the launches of a run), else null
     int basis;               // 1D: 0 Fourier; 1 cosine, 2 sine (n[0] is then the length of the

@@ -234,6 +234,145 @@ __global__ void __launch_bounds__((FFTShape<N, RR>::T * LPB))
     }
 }
 
+// ------------------------------------------------ 1D step, cosine and sine bases
+
+// e^{L h/2} on NF reordered cosine / sine lines in delta form: with V = F v,
+// v <- v + F^-1[T1 V + T2 V_rev], V_rev[m] = V[(n - m) mod n], T1 = (A - 1)/n, T2 = B/n (see
+// the table builder: A pairs mode m with itself, B with n - m). The pairing is one LDS
+// round trip between the transforms; the two products and their sum, which nearly cancel
+// on the low modes, are formed in FP64 from FP64 tables and rounded once.
+template <class F, class L, int NF>
+__device__ __forceinline__ void propagate_pairs(c32 (&f)[NF][F::R], int t, int l, c32* lds, const c32* tw,
+                                                const double2* __restrict__ T1, const double2* __restrict__ T2) {
+    constexpr int R = F::R, T = F::T, N = F::NN;
+    c32 d[NF][R];
+#pragma unroll
+    for (int q = 0; q < NF; q++)
+#pragma unroll
+        for (int m = 0; m < R; m++) d[q][m] = f[q][m];
+    fft_line<F, -1, L, NF>(d, t, l, lds, tw);
+#pragma unroll
+    for (int q = 0; q < NF; q++)
+#pragma unroll
+        for (int m = 0; m < R; m++) lds[q * L::SIZE + L::addr(l, t + m * T)] = d[q][m];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NF; q++)
+#pragma unroll
+        for (int m = 0; m < R; m++) {
+            const int e = t + m * T;
+            const c32 rv = lds[q * L::SIZE + L::addr(l, (N - e) & (N - 1))];
+            const c64 s = cadd(cmul(widen(d[q][m], c64{}), T1[e]), cmul(widen(rv, c64{}), T2[e]));
+            d[q][m] = narrow(s);
+        }
+    __syncthreads();
+    fft_line<F, +1, L, NF>(d, t, l, lds, tw);
+#pragma unroll
+    for (int q = 0; q < NF; q++)
+#pragma unroll
+        for (int m = 0; m < R; m++) f[q][m] = cadd(f[q][m], d[q][m]);
+}
+
+// The RK4IP (or semi-implicit) step of whole cosine / sine lines of n = N stored points
+// through the n-point transform of the reordered line (half the transform length of the
+// even / odd extension): element e of a thread's registers is point j(e) = 2e (e < N/2) or
+// 2(N - 1 - e) + 1, negated on those odd points in the sine basis. G is pointwise, so the
+// stages act on the reordered line as they are; the potential and the noise are those of
+// point j(e) (the noise negated with the point in the sine basis). Same data flow as
+// k_line_step otherwise, so split runs equal whole runs bitwise.
+template <int N, int LPB, bool NOISE, int RR, bool SI>
+__global__ void __launch_bounds__((FFTShape<N, RR>::T * LPB))
+    k_line_basis(GroupDev g, float2* __restrict__ psi, int nsteps, int64_t step_off,
+                 const int64_t* __restrict__ step_base) {
+    using F = FFTShape<N, RR>;
+    using L = LdsLayout<N, LPB, true, F::R>;
+    constexpr int R = F::R, T = F::T;
+    __shared__ c32 lds[(SI ? 1 : 2) * L::SIZE];
+    __shared__ c32 tw[N];
+    stage_twiddles<F>(tw, g.tw[0]);
+    const double2* __restrict__ T1 = g.pairT1;
+    const double2* __restrict__ T2 = g.pairT2;
+    const int t = threadIdx.x % T;
+    const int l = threadIdx.x / T;
+    const int64_t inst = (int64_t)blockIdx.x * LPB + l;
+    const bool active = inst < g.batch;
+    float2* p = psi + g.offset + inst * N;
+    const float odd_sign = g.basis == 2 ? -1.0f : 1.0f;
+    auto point = [&](int e) { return e < N / 2 ? 2 * e : 2 * (N - 1 - e) + 1; };
+    auto sign = [&](int e) { return e < N / 2 ? 1.0f : odd_sign; };
+
+    c32 f[2][R];
+    float V[R];
+#pragma unroll
+    for (int m = 0; m < R; m++) {
+        const int e = t + m * T, j = point(e);
+        const float2 v0 = active ? p[j] : make_float2(0.f, 0.f);
+        f[0][m] = make_float2(sign(e) * v0.x, sign(e) * v0.y);
+        float v = trap_V(g, j, 0, 0);
+        if (g.Vgrid && active) v += g.Vgrid[inst * N + j];
+        V[m] = v;
+    }
+    const uint32_t iid = g.id_base + (uint32_t)inst;
+    int64_t step = read_step(step_off, step_base);
+    __syncthreads();  // twiddles staged
+    for (int s = 0; s < nsteps; s++, step++) {
+        c32 nz[R];
+#pragma unroll
+        for (int m = 0; m < R; m++) {
+            if constexpr (NOISE) {
+                const int e = t + m * T;
+                const float2 z = noise_z(g, point(e), iid, step);
+                nz[m] = make_float2(sign(e) * (g.noise_c * z.x), sign(e) * (g.noise_c * z.y));
+            } else {
+                nz[m] = make_float2(0.f, 0.f);
+            }
+        }
+        if constexpr (SI) {
+            c32(&f0)[1][R] = *reinterpret_cast<c32(*)[1][R]>(&f[0]);
+            propagate_pairs<F, L, 1>(f0, t, l, lds, tw, T1, T2);  // a = D psi
+#pragma unroll
+            for (int m = 0; m < R; m++) {
+                const c32 a = f[0][m];
+                c32 mid = a;
+#pragma unroll
+                for (int it = 0; it < 3; it++) {
+                    const c32 k = hG(g, mid, V[m], nz[m]);
+                    mid = make_float2(fmaf(0.5f, k.x, a.x), fmaf(0.5f, k.y, a.y));
+                }
+                f[0][m] = make_float2(fmaf(2.0f, mid.x, -a.x), fmaf(2.0f, mid.y, -a.y));
+            }
+            propagate_pairs<F, L, 1>(f0, t, l, lds, tw, T1, T2);  // psi' = D(2m - a)
+            continue;
+        }
+#pragma unroll
+        for (int m = 0; m < R; m++) f[1][m] = hG(g, f[0][m], V[m], nz[m]);
+        propagate_pairs<F, L, 2>(f, t, l, lds, tw, T1, T2);  // (a, k1)
+#pragma unroll
+        for (int m = 0; m < R; m++) {
+            const c32 a = f[0][m], k1 = f[1][m];
+            const c32 k2 = hG(g, make_float2(fmaf(0.5f, k1.x, a.x), fmaf(0.5f, k1.y, a.y)), V[m], nz[m]);
+            const c32 k3 = hG(g, make_float2(fmaf(0.5f, k2.x, a.x), fmaf(0.5f, k2.y, a.y)), V[m], nz[m]);
+            f[0][m] = cadd(a, k3);
+            const float sx = k1.x * (1.0f / 6.0f) + (k2.x + k3.x) * (1.0f / 3.0f);
+            const float sy = k1.y * (1.0f / 6.0f) + (k2.y + k3.y) * (1.0f / 3.0f);
+            f[1][m] = make_float2(a.x + sx, a.y + sy);
+        }
+        propagate_pairs<F, L, 2>(f, t, l, lds, tw, T1, T2);  // (D u, D acc)
+#pragma unroll
+        for (int m = 0; m < R; m++) {
+            const c32 k4 = hG(g, f[0][m], V[m], nz[m]);
+            f[0][m] = make_float2(fmaf(k4.x, 1.0f / 6.0f, f[1][m].x), fmaf(k4.y, 1.0f / 6.0f, f[1][m].y));
+        }
+    }
+    if (active) {
+#pragma unroll
+        for (int m = 0; m < R; m++) {
+            const int e = t + m * T;
+            p[point(e)] = make_float2(sign(e) * f[0][m].x, sign(e) * f[0][m].y);
+        }
+    }
+}
+
 // ------------------------------------------------------------- 1D step, k-space state
 
 // The same step on a whole 1D Fourier line with its state kept in k-space between the
@@ -463,9 +602,31 @@ static hipError_t go_kline(const GroupDev& g, float2* psi, int nsteps, int64_t s
     return hipGetLastError();
 }
 
+template <int N, int RR, bool SI>
+static hipError_t go_basis(const GroupDev& g, float2* psi, int nsteps, int64_t step_off, const int64_t* step_base,
+                           hipStream_t s) {
+    constexpr int T = FFTShape<N, RR>::T;
+    constexpr int LPB = T >= 64 ? 1 : 64 / T;
+    const int64_t blocks = (g.batch + LPB - 1) / LPB;
+    if (g.has_noise)
+        hipLaunchKernelGGL((k_line_basis<N, LPB, true, RR, SI>), dim3((unsigned)blocks), dim3(T * LPB), 0, s, g, psi,
+                           nsteps, step_off, step_base);
+    else
+        hipLaunchKernelGGL((k_line_basis<N, LPB, false, RR, SI>), dim3((unsigned)blocks), dim3(T * LPB), 0, s, g, psi,
+                           nsteps, step_off, step_base);
+    return hipGetLastError();
+}
+
 template <int N, bool SI>
 static hipError_t go_line_p(const GroupDev& g, float2* psi, int nsteps, int64_t step_off, const int64_t* step_base,
                             bool f64, int radix, int io, hipStream_t s) {
+    if (g.basis && g.pairT1) {
+        // a cosine / sine line through its reordered n-point transform
+        if (f64 || g.has_vnoise || io) return hipErrorInvalidValue;
+        if (radix == 8) return go_basis<N, 8, SI>(g, psi, nsteps, step_off, step_base, s);
+        if (radix == 0 || radix == 16) return go_basis<N, 16, SI>(g, psi, nsteps, step_off, step_base, s);
+        return hipErrorInvalidValue;
+    }
     if (g.K) {
         // Fourier lines with a k-space state buffer: the step with the state in k-space
         if (f64 || g.basis || g.has_vnoise || g.convK || !g.E2) return hipErrorInvalidValue;

@@ -31,15 +31,25 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
 
-// Length of the transform along axis a: a cosine / sine group runs the even / odd
-// extension of its half domain, twice the stored points.
-int64_t transform_len(const rk4ip_problem& p, int a) { return (p.basis && a == 0) ? 2 * p.n[0] : p.n[a]; }
+// A cosine / sine group runs through the n-point transform of its reordered line (FP32
+// transforms, no noise in the potential) or else through the even / odd extension of its
+// half domain, twice the stored points (the FP64-transform form, and the line kernel
+// variant that carries the potential's extra terms).
+bool basis_ext(const rk4ip_problem& p, uint32_t flags) {
+    return p.basis && ((flags & RK4IP_FLAG_FP64_TRANSFORMS) || p.sigma_V != 0.0);
+}
+bool basis_dct(const rk4ip_problem& p, uint32_t flags) { return p.basis && !basis_ext(p, flags); }
 
-// The problem seen by the transforms: for a cosine / sine group, the extension's length
-// and a domain twice as long (so k_m = pi m / L).
-rk4ip_problem transform_problem(const rk4ip_problem& p) {
+// Length of the transform along axis a.
+int64_t transform_len(const rk4ip_problem& p, int a, uint32_t flags) {
+    return (a == 0 && basis_ext(p, flags)) ? 2 * p.n[0] : p.n[a];
+}
+
+// The problem seen by the Fourier tables: for a group run on its extension, the
+// extension's length and a domain twice as long (so k_m = pi m / L).
+rk4ip_problem transform_problem(const rk4ip_problem& p, uint32_t flags) {
     rk4ip_problem q = p;
-    if (p.basis) {
+    if (basis_ext(p, flags)) {
         q.n[0] = 2 * p.n[0];
         q.hi[0] = p.hi[0] + (p.hi[0] - p.lo[0]);
     }
@@ -81,6 +91,7 @@ struct GroupHost {
     size_t e2_off = 0;               // (e^{L h} - 1)/n of a 1D Fourier group (its k-space line step)
     size_t k_off = 0;                // k-space state of a group run by the k-space line step
     bool kline = false;              // run by the k-space line step (state in the workspace)
+    bool dct = false;                // cosine / sine group run through its reordered n-point transform
     double dV = 1.0;
 };
 
@@ -123,7 +134,7 @@ int validate(const rk4ip_problem* probs, int nprob, uint32_t flags) {
         int64_t M = 1;
         for (int a = 0; a < 3; a++) {
             if (a < p.ndim) {
-                if (!is_pow2(p.n[a]) || p.n[a] < 8 || transform_len(p, a) > nmax) return RK4IP_ERR_UNSUPPORTED_SHAPE;
+                if (!is_pow2(p.n[a]) || p.n[a] < 8 || transform_len(p, a, flags) > nmax) return RK4IP_ERR_UNSUPPORTED_SHAPE;
                 if (!(p.hi[a] > p.lo[a]) || !std::isfinite(p.hi[a]) || !std::isfinite(p.lo[a]))
                     return RK4IP_ERR_INVALID_ARG;
                 if (!std::isfinite(p.trap[a])) return RK4IP_ERR_INVALID_ARG;
@@ -166,15 +177,15 @@ Layout layout(const rk4ip_problem* probs, int nprob, uint32_t flags, GroupHost* 
         const rk4ip_problem& p = probs[i];
         for (int a = 0; a < p.ndim; a++) {
             size_t e = off;
-            off = align_up(off + sizeof(float2) * (size_t)transform_len(p, a));
+            off = align_up(off + sizeof(float2) * (size_t)transform_len(p, a, flags));
             size_t t = off;
-            off = align_up(off + sizeof(float2) * (size_t)transform_len(p, a));
+            off = align_up(off + sizeof(float2) * (size_t)transform_len(p, a, flags));
             size_t e64 = 0, t64 = 0;
             if (f64) {
                 e64 = off;
-                off = align_up(off + sizeof(double2) * (size_t)transform_len(p, a));
+                off = align_up(off + sizeof(double2) * (size_t)transform_len(p, a, flags));
                 t64 = off;
-                off = align_up(off + sizeof(double2) * (size_t)transform_len(p, a));
+                off = align_up(off + sizeof(double2) * (size_t)transform_len(p, a, flags));
             }
             if (gh) {
                 gh[i].tab_off[a] = e;
@@ -191,8 +202,17 @@ Layout layout(const rk4ip_problem* probs, int nprob, uint32_t flags, GroupHost* 
             off = align_up(off + sizeof(float2) * (size_t)p.n[0]);
         }
         if (is_kline(p, flags)) {
+            // (e^{L h} - 1)/n of a k-space line
             if (gh) gh[i].e2_off = off;
             off = align_up(off + sizeof(float2) * (size_t)p.n[0]);
+        }
+        if (basis_dct(p, flags)) {
+            // the two FP64 mode-pairing tables of a cosine / sine line
+            if (gh) {
+                gh[i].e2_off = off;
+                gh[i].dct = true;
+            }
+            off = align_up(off + 2 * sizeof(double2) * (size_t)p.n[0]);
         }
     }
     for (int i = 0; i < nprob; i++) {
@@ -227,7 +247,8 @@ Layout layout(const rk4ip_problem* probs, int nprob, uint32_t flags, GroupHost* 
 // Per-group kernel parameters and table pointers into the workspace `ws` (the offsets come
 // from layout); the group's field starts at point `offset` of the concatenated field. The
 // tables themselves are written by the caller.
-void fill_group(GroupHost& g, char* ws, bool f64, int64_t offset) {
+void fill_group(GroupHost& g, char* ws, uint32_t flags, int64_t offset) {
+    const bool f64 = (flags & RK4IP_FLAG_FP64_TRANSFORMS) != 0;
     const rk4ip_problem& p = g.p;
     GroupDev& d = g.d;
     std::memset(&d, 0, sizeof(d));
@@ -235,7 +256,7 @@ void fill_group(GroupHost& g, char* ws, bool f64, int64_t offset) {
     g.M = 1;
     g.dV = 1.0;
     for (int a = 0; a < 3; a++) {
-        const int64_t nt = transform_len(p, a);
+        const int64_t nt = transform_len(p, a, flags);
         d.n[a] = (int)nt;
         d.log2n[a] = ilog2i(nt);
         g.M *= p.n[a];
@@ -274,10 +295,12 @@ void fill_group(GroupHost& g, char* ws, bool f64, int64_t offset) {
             d.tw64[a] = reinterpret_cast<const double2*>(ws + g.tw64_off[a]);
         }
     }
-    if (g.kline) {
-        d.E2 = reinterpret_cast<const float2*>(ws + g.e2_off);
-        d.K = reinterpret_cast<float2*>(ws + g.k_off);
+    if (g.kline) d.E2 = reinterpret_cast<const float2*>(ws + g.e2_off);
+    if (g.dct) {
+        d.pairT1 = reinterpret_cast<const double2*>(ws + g.e2_off);
+        d.pairT2 = d.pairT1 + p.n[0];
     }
+    if (g.kline) d.K = reinterpret_cast<float2*>(ws + g.k_off);
     if (p.conv_K) d.convK = reinterpret_cast<const float2*>(ws + g.conv_off);
 }
 
@@ -430,6 +453,52 @@ void build_conv_table(const rk4ip_problem& p, double dV, std::vector<float2>& kh
             im -= p.conv_K[d] * sn[q];
         }
         kh[m] = make_float2((float)(re * dV / (double)n), (float)(im * dV / (double)n));
+    }
+}
+
+// Tables of a cosine / sine line run through its reordered n-point transform (FP64
+// arithmetic, stored FP32). The line v_e = s_e f_{j(e)}, with j(e) = 2e for e < n/2 and
+// 2(n - 1 - e) + 1 above, s_e = -1 on the odd points in the sine basis, has V = F v with
+// cosine coefficients X_m = (W^m V_m + W^-m V_{n-m})/2, W = e^{-i pi/(2n)} (Makhoul's
+// algorithm). e^{L h/2} multiplies cosine coefficient m by E_m, which maps V to
+// A_m V_m + B_m V_{n-m} with A_m = (E_m + E_{n-m})/2, B_m = (E_m - E_{n-m}) e^{i pi m/n}/2
+// (A_0 = E_0, B_0 = 0). Cosine basis: E_m at k = pi m/L. Sine basis: the cosine coefficient m
+// of the sign-alternated line is the sine coefficient n - 1 - m, at k = pi (n - m)/L.
+// Stored: T1 = (A - 1)/n (without cancellation, from the expm1 form of E - 1), the FFT
+// twiddles, T2 = B/n. T1 and T2 stay in FP64: each pairs a low mode with a high one through
+// factors of order one whose sum nearly cancels, so their rounding would reach the field at
+// the size of the field, the same every step.
+void build_basis_tables(const rk4ip_problem& p, std::vector<double2>& T12, std::vector<float2>& tw) {
+    const int64_t n = p.n[0];
+    const double L = p.hi[0] - p.lo[0], h = p.dt;
+    const double damp = std::exp(-p.gamma * h / 2.0), em1 = std::expm1(-p.gamma * h / 2.0);
+    auto em1_of = [&](int64_t m, double& c, double& s) {  // E_m - 1
+        const double k = kPi / L * (double)(p.basis == 1 ? m : n - m);
+        const double theta = p.alpha * k * k * h / 2.0;
+        const double sh = std::sin(theta / 2.0);
+        c = em1 - 2.0 * damp * sh * sh;
+        s = -damp * std::sin(theta);
+    };
+    T12.resize(2 * n);  // T1 then T2
+    tw.resize(n);
+    const double inv_n = 1.0 / (double)n;
+    for (int64_t m = 0; m < n; m++) {
+        double ac, as;
+        em1_of(m, ac, as);
+        if (m == 0) {
+            T12[m] = make_double2(ac * inv_n, as * inv_n);
+            T12[n + m] = make_double2(0.0, 0.0);
+        } else {
+            double bc, bs;
+            em1_of(n - m, bc, bs);
+            const double dc = 0.5 * (ac - bc), ds = 0.5 * (as - bs);  // (E_m - E_{n-m})/2
+            const double ph = kPi * (double)m / (double)n;
+            const double cp = std::cos(ph), sp = std::sin(ph);
+            T12[m] = make_double2(0.5 * (ac + bc) * inv_n, 0.5 * (as + bs) * inv_n);
+            T12[n + m] = make_double2((dc * cp - ds * sp) * inv_n, (dc * sp + ds * cp) * inv_n);
+        }
+        const double ang = 2.0 * kPi * (double)m / (double)n;
+        tw[m] = make_float2((float)std::cos(ang), (float)-std::sin(ang));
     }
 }
 
@@ -1062,6 +1131,40 @@ int noalloc_scratch(char** out) {
     return nd.status;
 }
 
+// The tables of build_basis_tables computed on the device in FP64 (the same expressions, in
+// the same order, without contraction), one thread per entry m; kpl = pi / L.
+__global__ void k_noalloc_basis_tables(double2* __restrict__ T1, float2* __restrict__ tw, double2* __restrict__ T2, int n,
+                                       double kpl, double alpha, double h, double gamma, int basis) {
+#pragma clang fp contract(off)
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= n) return;
+    const double damp = exp(-gamma * h / 2.0), em1 = expm1(-gamma * h / 2.0);
+    const double inv_n = 1.0 / (double)n;
+    auto em1_of = [&](int mm, double& c, double& s) {
+        const double k = kpl * (double)(basis == 1 ? mm : n - mm);
+        const double theta = alpha * k * k * h / 2.0;
+        const double sh = sin(theta / 2.0);
+        c = em1 - 2.0 * damp * sh * sh;
+        s = -damp * sin(theta);
+    };
+    double ac, as;
+    em1_of(m, ac, as);
+    if (m == 0) {
+        T1[m] = make_double2(ac * inv_n, as * inv_n);
+        T2[m] = make_double2(0.0, 0.0);
+    } else {
+        double bc, bs;
+        em1_of(n - m, bc, bs);
+        const double dc = 0.5 * (ac - bc), ds = 0.5 * (as - bs);
+        const double ph = kPi * (double)m / (double)n;
+        const double cp = cos(ph), sp = sin(ph);
+        T1[m] = make_double2(0.5 * (ac + bc) * inv_n, 0.5 * (as + bs) * inv_n);
+        T2[m] = make_double2((dc * cp - ds * sp) * inv_n, (dc * sp + ds * cp) * inv_n);
+    }
+    const double ang = 2.0 * kPi * (double)m / (double)n;
+    tw[m] = make_float2((float)cos(ang), (float)-sin(ang));
+}
+
 // The tables of build_tables computed on the device in FP64 (the same expressions, in the
 // same order, without contraction), one thread per entry m: (E - 1)/n, the twiddles and,
 // when E2 is not null, (e^{L h} - 1)/n. kscale = 2 pi / L; gamma is the damping of this axis
@@ -1152,17 +1255,25 @@ int rk4ip_plan(const rk4ip_problem* probs, int nprob, void* workspace, size_t ws
         g.p = probs[i];
         const rk4ip_problem& p = g.p;
         GroupDev& d = g.d;
-        fill_group(g, plan->ws, plan->f64, offset);
+        fill_group(g, plan->ws, flags, offset);
         for (int a = 0; a < p.ndim; a++) {
             std::vector<float2> E, tw, E2;
             std::vector<double2> E64, tw64;
             const bool kline = g.kline;
-            build_tables(transform_problem(p), a, E, tw, plan->f64 ? &E64 : nullptr, plan->f64 ? &tw64 : nullptr,
-                         kline ? &E2 : nullptr);
+            std::vector<double2> T12;
+            if (g.dct) {
+                build_basis_tables(p, T12, tw);
+                E.assign(tw.size(), make_float2(0.f, 0.f));  // unused by the cosine / sine line
+            } else {
+                build_tables(transform_problem(p, flags), a, E, tw, plan->f64 ? &E64 : nullptr,
+                             plan->f64 ? &tw64 : nullptr, kline ? &E2 : nullptr);
+            }
             hipError_t e1 = hipMemcpy(plan->ws + g.tab_off[a], E.data(), sizeof(float2) * E.size(), hipMemcpyHostToDevice);
             hipError_t e2 = hipMemcpy(plan->ws + g.tw_off[a], tw.data(), sizeof(float2) * tw.size(), hipMemcpyHostToDevice);
             if (e1 == hipSuccess && e2 == hipSuccess && kline)
                 e1 = hipMemcpy(plan->ws + g.e2_off, E2.data(), sizeof(float2) * E2.size(), hipMemcpyHostToDevice);
+            if (e1 == hipSuccess && e2 == hipSuccess && g.dct)
+                e1 = hipMemcpy(plan->ws + g.e2_off, T12.data(), sizeof(double2) * T12.size(), hipMemcpyHostToDevice);
             if (e1 == hipSuccess && e2 == hipSuccess && plan->f64) {
                 e1 = hipMemcpy(plan->ws + g.tab64_off[a], E64.data(), sizeof(double2) * E64.size(),
                                hipMemcpyHostToDevice);
@@ -1589,9 +1700,18 @@ int rk4ip_step_noalloc(const rk4ip_problem* probs, int nprob, void* psi_v, int64
     for (int i = 0; i < nprob; i++) {
         GroupHost& g = gh[i];
         g.p = probs[i];
-        fill_group(g, ws, false, offset);
+        fill_group(g, ws, 0, offset);
         offset += g.p.batch * g.M;
-        const rk4ip_problem q = transform_problem(g.p);
+        if (g.dct) {
+            const int n = (int)g.p.n[0];
+            hipLaunchKernelGGL(k_noalloc_basis_tables, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
+                               const_cast<double2*>(g.d.pairT1), const_cast<float2*>(g.d.tw[0]),
+                               const_cast<double2*>(g.d.pairT2), n, kPi / (g.p.hi[0] - g.p.lo[0]), g.p.alpha, g.p.dt,
+                               g.p.gamma, g.p.basis);
+            if (hipGetLastError() != hipSuccess) return RK4IP_ERR_HIP;
+            continue;
+        }
+        const rk4ip_problem q = transform_problem(g.p, 0);
         for (int a = 0; a < g.p.ndim; a++) {
             const int n = (int)q.n[a];
             hipLaunchKernelGGL(k_noalloc_tables, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,

@@ -175,18 +175,23 @@ def test_potential_terms_sizes_and_limits(lib):
 
 
 def test_cosine_and_sine_bases_sizes_and_limits(lib):
-    """A cosine / sine group keeps transform tables of its extension (twice the stored
-    points) and is taken on 1D lattices whose extension fits the line kernel (compared
-    here with a Fourier line that also runs in x-space: one with noise in its potential)."""
+    """A cosine / sine group runs through the n-point transform of its reordered line: its
+    two mode-pairing tables of n FP64 entries besides the two tables every line keeps (a
+    Fourier line run in x-space, one with noise in its potential, keeps those two only),
+    and lines up to 4096 points. In the FP64-transform form, or with noise in its potential, it
+    runs on the even / odd extension (twice the stored points; its tables doubled)."""
     line = dict(lo=(0,), hi=(7,), dt=0.1)
     f = rk4ip.rk4ip_workspace_bytes([rk4ip.make_problem(n=(256,), sigma_V=0.1, **line)])
+    f64 = rk4ip.RK4IP_FLAG_FP64_TRANSFORMS
     for basis in (1, 2):
         c = rk4ip.rk4ip_workspace_bytes([rk4ip.make_problem(n=(256,), basis=basis, **line)])
-        assert c >= f + 2 * 256 * 8  # the two tables doubled
-        assert rk4ip.rk4ip_workspace_bytes([rk4ip.make_problem(n=(2048,), basis=basis, **line)]) > 0
-        assert rk4ip.rk4ip_workspace_bytes([rk4ip.make_problem(n=(4096,), basis=basis, **line)]) == 0
-        assert rk4ip.rk4ip_workspace_bytes([rk4ip.make_problem(n=(2048,), basis=basis, **line)],
-                                           rk4ip.RK4IP_FLAG_FP64_TRANSFORMS) == 0
+        assert c == f + 2 * 256 * 16
+        ext = rk4ip.rk4ip_workspace_bytes([rk4ip.make_problem(n=(256,), basis=basis, sigma_V=0.1, **line)])
+        assert ext == f + 2 * 256 * 8  # the two tables doubled
+        assert rk4ip.rk4ip_workspace_bytes([rk4ip.make_problem(n=(4096,), basis=basis, **line)]) > 0
+        assert rk4ip.rk4ip_workspace_bytes([rk4ip.make_problem(n=(4096,), basis=basis, sigma_V=0.1, **line)]) == 0
+        assert rk4ip.rk4ip_workspace_bytes([rk4ip.make_problem(n=(1024,), basis=basis, **line)], f64) > 0
+        assert rk4ip.rk4ip_workspace_bytes([rk4ip.make_problem(n=(2048,), basis=basis, **line)], f64) == 0
         assert rk4ip.rk4ip_workspace_bytes([_p(basis=basis)]) == 0
         assert rk4ip.rk4ip_workspace_bytes([rk4ip.make_problem(n=(64,), basis=basis, conv_K=np.ones(64),
                                                                **line)]) == 0
