@@ -217,7 +217,9 @@ def form_adjoint(torch, rk4ip, workloads, steps: int = 50, ckpt: int = 10):
 
     w = workloads.adjoint2d(nsteps=steps, ckpt_every=ckpt)
     probs, _k = rk4ip.problems_from_workload(w)
-    solver = RK4IPSolver(probs, steps, ckpt)
+    # graph-replayed forward run and adjoint segments; the eager solver beside it
+    solver = RK4IPSolver(probs, steps, ckpt, flags=rk4ip.RK4IP_FLAG_GRAPH)
+    eager = RK4IPSolver(probs, steps, ckpt)
     psi0 = rk4ip.field_to_device(w)
     Vall = torch.tensor(np.concatenate([g.Vgrid.reshape(-1) for g in w.groups]).astype(np.float32), device="cuda")
     phis = [torch.tensor(p.astype(np.complex64).reshape(-1), device="cuda") for p in w.target]
@@ -243,8 +245,19 @@ def form_adjoint(torch, rk4ip, workloads, steps: int = 50, ckpt: int = 10):
         with torch.no_grad():
             solver(psi0, Vall)
 
+    def ours_eager():
+        p = psi0.clone().requires_grad_(True)
+        V = Vall.clone().requires_grad_(True)
+        loss_flat(eager(p, V)).backward()
+
+    def fwd_eager():
+        with torch.no_grad():
+            eager(psi0, Vall)
+
     t_ours = _timed(torch, ours)
     t_fwd = _timed(torch, fwd_only)
+    t_ours_eager = _timed(torch, ours_eager)
+    t_fwd_eager = _timed(torch, fwd_eager)
 
     def plain_autograd():
         p = psi0.clone().requires_grad_(True)
@@ -265,6 +278,9 @@ def form_adjoint(torch, rk4ip, workloads, steps: int = 50, ckpt: int = 10):
     return {"workload": f"adjoint2d shapes (32 x 128^2 + 32 x 256^2), {steps} steps, checkpoint every {ckpt}",
             "forward_plus_adjoint_s": t_ours, "forward_only_s": t_fwd,
             "gradient_cost_in_forward_runs": t_ours / t_fwd,
+            "launch": "hipGraph replays (forward run and whole adjoint segments)",
+            "eager_forward_plus_adjoint_s": t_ours_eager, "eager_forward_only_s": t_fwd_eager,
+            "eager_gradient_cost_in_forward_runs": t_ours_eager / t_fwd_eager,
             "torch_autograd_s": t_torch, "speedup_vs_torch_autograd": t_torch / t_ours,
             "rel_diff_vs_torch_autograd": {"grad_psi0": rel(gp, tp), "grad_V": rel(gv, tv)}}
 

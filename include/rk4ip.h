@@ -250,8 +250,12 @@ int rk4ip_ark45(rk4ip_plan_t plan, void* psi, double t_span, double tol, int64_t
  * grad_psi0 (device complex64, same convention) and, if grad_V != NULL, adds nothing
  * but overwrites grad_V (device float [ninst][M]) with dLoss/dV_grid. Each segment of
  * ckpt_every steps is recomputed from its checkpoint into adj_ws and walked
- * backwards; V gradients accumulate in FP64. Plans made with RK4IP_FLAG_SEMI_IMPLICIT
- * return RK4IP_ERR_INVALID_ARG (the adjoint is that of the RK4IP step). */
+ * backwards; V gradients accumulate in FP64. The recomputed states go straight into
+ * their slots of adj_ws (one copy per segment, of its checkpoint). With RK4IP_FLAG_GRAPH a
+ * whole segment is replayed from two hipGraphs (recompute, backward walk), recorded once
+ * per adj_ws address and ckpt_every, so callers that reuse adj_ws replay them. Plans made
+ * with RK4IP_FLAG_SEMI_IMPLICIT return RK4IP_ERR_INVALID_ARG (the adjoint is that of the
+ * RK4IP step). */
 int rk4ip_adjoint(rk4ip_plan_t plan, const void* ckpt, int64_t step0, int64_t nsteps, int64_t ckpt_every,
                   const void* lambda_T, void* grad_psi0, float* grad_V, void* adj_ws, size_t adj_ws_bytes);
 

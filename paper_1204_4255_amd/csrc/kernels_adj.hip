@@ -12,7 +12,8 @@ namespace rk4ip {
 template <int N, int LPB>
 __global__ void __launch_bounds__(FFTShape<N>::T* LPB)
     k_line_adjoint(GroupDev g, const float2* __restrict__ psi_n, float2* __restrict__ lam, double* __restrict__ vbar,
-                   int64_t step) {
+                   int64_t step_off, const int64_t* __restrict__ step_base) {
+    const int64_t step = read_step(step_off, step_base);
     using F = FFTShape<N>;
     using L = LdsLayout<N, LPB, true, F::R>;
     constexpr int R = F::R, T = F::T;
@@ -119,28 +120,28 @@ hipError_t launch_axis_adjoint(const GroupDev& g, int axis, int mode, const Pass
 
 template <int N>
 static hipError_t go_line_adj(const GroupDev& g, const float2* psi_n, float2* lam, double* vbar, int64_t step,
-                              hipStream_t s) {
+                              const int64_t* step_base, hipStream_t s) {
     constexpr int T = FFTShape<N>::T;
     constexpr int LPB = T >= 64 ? 1 : 64 / T;
     const int64_t blocks = (g.batch + LPB - 1) / LPB;
     hipLaunchKernelGGL((k_line_adjoint<N, LPB>), dim3((unsigned)blocks), dim3(T * LPB), 0, s, g, psi_n, lam, vbar,
-                       step);
+                       step, step_base);
     return hipGetLastError();
 }
 
 hipError_t launch_line_adjoint(const GroupDev& g, const float2* psi_n, float2* lam, double* vbar, int64_t step,
-                               hipStream_t s) {
+                               const int64_t* step_base, hipStream_t s) {
     switch (g.n[0]) {
-        case 8: return go_line_adj<8>(g, psi_n, lam, vbar, step, s);
-        case 16: return go_line_adj<16>(g, psi_n, lam, vbar, step, s);
-        case 32: return go_line_adj<32>(g, psi_n, lam, vbar, step, s);
-        case 64: return go_line_adj<64>(g, psi_n, lam, vbar, step, s);
-        case 128: return go_line_adj<128>(g, psi_n, lam, vbar, step, s);
-        case 256: return go_line_adj<256>(g, psi_n, lam, vbar, step, s);
-        case 512: return go_line_adj<512>(g, psi_n, lam, vbar, step, s);
-        case 1024: return go_line_adj<1024>(g, psi_n, lam, vbar, step, s);
-        case 2048: return go_line_adj<2048>(g, psi_n, lam, vbar, step, s);
-        case 4096: return go_line_adj<4096>(g, psi_n, lam, vbar, step, s);
+        case 8: return go_line_adj<8>(g, psi_n, lam, vbar, step, step_base, s);
+        case 16: return go_line_adj<16>(g, psi_n, lam, vbar, step, step_base, s);
+        case 32: return go_line_adj<32>(g, psi_n, lam, vbar, step, step_base, s);
+        case 64: return go_line_adj<64>(g, psi_n, lam, vbar, step, step_base, s);
+        case 128: return go_line_adj<128>(g, psi_n, lam, vbar, step, step_base, s);
+        case 256: return go_line_adj<256>(g, psi_n, lam, vbar, step, step_base, s);
+        case 512: return go_line_adj<512>(g, psi_n, lam, vbar, step, step_base, s);
+        case 1024: return go_line_adj<1024>(g, psi_n, lam, vbar, step, step_base, s);
+        case 2048: return go_line_adj<2048>(g, psi_n, lam, vbar, step, step_base, s);
+        case 4096: return go_line_adj<4096>(g, psi_n, lam, vbar, step, step_base, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -17,8 +17,8 @@ namespace rk4ip {
 // transform pair per G evaluation) instead of point by point.
 template <int N, int LPB, bool NOISE, bool P64, int RR, bool SI, bool EXTRA>
 __global__ void __launch_bounds__((FFTShape<N, RR>::T * LPB))
-    k_line_step(GroupDev g, float2* __restrict__ psi, int nsteps, int64_t step_off,
-                const int64_t* __restrict__ step_base) {
+    k_line_step(GroupDev g, float2* psi, int nsteps, int64_t step_off,
+                const int64_t* __restrict__ step_base, float2* out) {
     using F = FFTShape<N, RR>;
     using L = LdsLayout<N, LPB, true, F::R>;
     using W = typename std::conditional<P64, c64, c32>::type;  // transform working type
@@ -226,10 +226,11 @@ __global__ void __launch_bounds__((FFTShape<N, RR>::T * LPB))
         }
     }
     if (active) {
+        float2* q = out + g.offset + inst * NM;
 #pragma unroll
         for (int m = 0; m < R; m++) {
             const int e = t + m * T;
-            if (g.basis == 0 || e >= NM) p[g.basis ? e - NM : e] = f[0][m];  // the half domain
+            if (g.basis == 0 || e >= NM) q[g.basis ? e - NM : e] = f[0][m];  // the half domain
         }
     }
 }
@@ -282,8 +283,8 @@ __device__ __forceinline__ void propagate_pairs(c32 (&f)[NF][F::R], int t, int l
 // k_line_step otherwise, so split runs equal whole runs bitwise.
 template <int N, int LPB, bool NOISE, int RR, bool SI>
 __global__ void __launch_bounds__((FFTShape<N, RR>::T * LPB))
-    k_line_basis(GroupDev g, float2* __restrict__ psi, int nsteps, int64_t step_off,
-                 const int64_t* __restrict__ step_base) {
+    k_line_basis(GroupDev g, float2* psi, int nsteps, int64_t step_off,
+                 const int64_t* __restrict__ step_base, float2* out) {
     using F = FFTShape<N, RR>;
     using L = LdsLayout<N, LPB, true, F::R>;
     constexpr int R = F::R, T = F::T;
@@ -365,10 +366,11 @@ __global__ void __launch_bounds__((FFTShape<N, RR>::T * LPB))
         }
     }
     if (active) {
+        float2* q = out + g.offset + inst * N;
 #pragma unroll
         for (int m = 0; m < R; m++) {
             const int e = t + m * T;
-            p[point(e)] = make_float2(sign(e) * f[0][m].x, sign(e) * f[0][m].y);
+            q[point(e)] = make_float2(sign(e) * f[0][m].x, sign(e) * f[0][m].y);
         }
     }
 }
@@ -400,8 +402,8 @@ __global__ void __launch_bounds__((FFTShape<N, RR>::T * LPB))
 // exchange buffers only.
 template <int N, int LPB, bool NOISE, int RR, bool SI>
 __global__ void __launch_bounds__((FFTShape<N, RR>::T * LPB))
-    k_line_kstep(GroupDev g, float2* __restrict__ psi, int nsteps, int64_t step_off,
-                 const int64_t* __restrict__ step_base, int io) {
+    k_line_kstep(GroupDev g, float2* psi, int nsteps, int64_t step_off,
+                 const int64_t* __restrict__ step_base, int io, float2* out) {
     using F = FFTShape<N, RR>;
     using L = LdsLayout<N, LPB, true, F::R>;
     constexpr int R = F::R, T = F::T;
@@ -530,8 +532,9 @@ __global__ void __launch_bounds__((FFTShape<N, RR>::T * LPB))
     }
     fft_line<F, +1, L, 1>(P, t, l, lds, tw);  // back to x-space
     if (active) {
+        float2* q = out + g.offset + inst * N;
 #pragma unroll
-        for (int m = 0; m < R; m++) p[t + m * T] = cscale(P[0][m], inv_n);
+        for (int m = 0; m < R; m++) q[t + m * T] = cscale(P[0][m], inv_n);
     }
 }
 
@@ -574,104 +577,106 @@ hipError_t launch_axis(const GroupDev& g, int axis, int mode, const PassArgs& a,
 
 template <int N, bool P64, int RR, bool SI, bool EXTRA = false>
 static hipError_t go_line(const GroupDev& g, float2* psi, int nsteps, int64_t step_off, const int64_t* step_base,
-                          hipStream_t s) {
+                          float2* out, hipStream_t s) {
     constexpr int T = FFTShape<N, RR>::T;
     constexpr int LPB = T >= 64 ? 1 : 64 / T;
     const int64_t blocks = (g.batch + LPB - 1) / LPB;
     if (g.has_noise)
         hipLaunchKernelGGL((k_line_step<N, LPB, true, P64, RR, SI, EXTRA>), dim3((unsigned)blocks), dim3(T * LPB), 0, s,
-                           g, psi, nsteps, step_off, step_base);
+                           g, psi, nsteps, step_off, step_base, out);
     else
         hipLaunchKernelGGL((k_line_step<N, LPB, false, P64, RR, SI, EXTRA>), dim3((unsigned)blocks), dim3(T * LPB), 0,
-                           s, g, psi, nsteps, step_off, step_base);
+                           s, g, psi, nsteps, step_off, step_base, out);
     return hipGetLastError();
 }
 
 template <int N, int RR, bool SI>
 static hipError_t go_kline(const GroupDev& g, float2* psi, int nsteps, int64_t step_off, const int64_t* step_base,
-                           int io, hipStream_t s) {
+                           int io, float2* out, hipStream_t s) {
     constexpr int T = FFTShape<N, RR>::T;
     constexpr int LPB = T >= 64 ? 1 : 64 / T;
     const int64_t blocks = (g.batch + LPB - 1) / LPB;
     if (g.has_noise)
         hipLaunchKernelGGL((k_line_kstep<N, LPB, true, RR, SI>), dim3((unsigned)blocks), dim3(T * LPB), 0, s, g, psi,
-                           nsteps, step_off, step_base, io);
+                           nsteps, step_off, step_base, io, out);
     else
         hipLaunchKernelGGL((k_line_kstep<N, LPB, false, RR, SI>), dim3((unsigned)blocks), dim3(T * LPB), 0, s, g, psi,
-                           nsteps, step_off, step_base, io);
+                           nsteps, step_off, step_base, io, out);
     return hipGetLastError();
 }
 
 template <int N, int RR, bool SI>
 static hipError_t go_basis(const GroupDev& g, float2* psi, int nsteps, int64_t step_off, const int64_t* step_base,
-                           hipStream_t s) {
+                           float2* out, hipStream_t s) {
     constexpr int T = FFTShape<N, RR>::T;
     constexpr int LPB = T >= 64 ? 1 : 64 / T;
     const int64_t blocks = (g.batch + LPB - 1) / LPB;
     if (g.has_noise)
         hipLaunchKernelGGL((k_line_basis<N, LPB, true, RR, SI>), dim3((unsigned)blocks), dim3(T * LPB), 0, s, g, psi,
-                           nsteps, step_off, step_base);
+                           nsteps, step_off, step_base, out);
     else
         hipLaunchKernelGGL((k_line_basis<N, LPB, false, RR, SI>), dim3((unsigned)blocks), dim3(T * LPB), 0, s, g, psi,
-                           nsteps, step_off, step_base);
+                           nsteps, step_off, step_base, out);
     return hipGetLastError();
 }
 
 template <int N, bool SI>
 static hipError_t go_line_p(const GroupDev& g, float2* psi, int nsteps, int64_t step_off, const int64_t* step_base,
-                            bool f64, int radix, int io, hipStream_t s) {
+                            bool f64, int radix, int io, float2* out, hipStream_t s) {
     if (g.basis && g.pairT1) {
         // a cosine / sine line through its reordered n-point transform
         if (f64 || g.has_vnoise || io) return hipErrorInvalidValue;
-        if (radix == 8) return go_basis<N, 8, SI>(g, psi, nsteps, step_off, step_base, s);
-        if (radix == 0 || radix == 16) return go_basis<N, 16, SI>(g, psi, nsteps, step_off, step_base, s);
+        if (radix == 8) return go_basis<N, 8, SI>(g, psi, nsteps, step_off, step_base, out, s);
+        if (radix == 0 || radix == 16) return go_basis<N, 16, SI>(g, psi, nsteps, step_off, step_base, out, s);
         return hipErrorInvalidValue;
     }
     if (g.K) {
         // Fourier lines with a k-space state buffer: the step with the state in k-space
         if (f64 || g.basis || g.has_vnoise || g.convK || !g.E2) return hipErrorInvalidValue;
-        if (radix == 8) return go_kline<N, 8, SI>(g, psi, nsteps, step_off, step_base, io, s);
-        if (radix == 0 || radix == 16) return go_kline<N, 16, SI>(g, psi, nsteps, step_off, step_base, io, s);
+        if (radix == 8) return go_kline<N, 8, SI>(g, psi, nsteps, step_off, step_base, io, out, s);
+        if (radix == 0 || radix == 16) return go_kline<N, 16, SI>(g, psi, nsteps, step_off, step_base, io, out, s);
         return hipErrorInvalidValue;
     }
     if (io) return hipErrorInvalidValue;  // no k-space state to read or keep
     if (g.has_vnoise || g.convK) {
         // the potential's extra terms: 8 values per thread
         if (f64) {
-            if constexpr (N <= 2048) return go_line<N, true, 8, SI, true>(g, psi, nsteps, step_off, step_base, s);
+            if constexpr (N <= 2048) return go_line<N, true, 8, SI, true>(g, psi, nsteps, step_off, step_base, out, s);
             return hipErrorInvalidValue;
         }
-        return go_line<N, false, 8, SI, true>(g, psi, nsteps, step_off, step_base, s);
+        return go_line<N, false, 8, SI, true>(g, psi, nsteps, step_off, step_base, out, s);
     }
     if (f64) {
-        if constexpr (N <= 2048) return go_line<N, true, 8, SI>(g, psi, nsteps, step_off, step_base, s);
+        if constexpr (N <= 2048) return go_line<N, true, 8, SI>(g, psi, nsteps, step_off, step_base, out, s);
         return hipErrorInvalidValue;  // FP64 tables and exchange buffers exceed the LDS
     }
-    if (radix == 8) return go_line<N, false, 8, SI>(g, psi, nsteps, step_off, step_base, s);
-    if (radix == 0 || radix == 16) return go_line<N, false, 16, SI>(g, psi, nsteps, step_off, step_base, s);
+    if (radix == 8) return go_line<N, false, 8, SI>(g, psi, nsteps, step_off, step_base, out, s);
+    if (radix == 0 || radix == 16) return go_line<N, false, 16, SI>(g, psi, nsteps, step_off, step_base, out, s);
     return hipErrorInvalidValue;
 }
 
 template <int N>
 static hipError_t go_line_n(const GroupDev& g, float2* psi, int nsteps, int64_t step_off, const int64_t* step_base,
-                            bool f64, int radix, bool si, int io, hipStream_t s) {
-    if (si) return go_line_p<N, true>(g, psi, nsteps, step_off, step_base, f64, radix, io, s);
-    return go_line_p<N, false>(g, psi, nsteps, step_off, step_base, f64, radix, io, s);
+                            bool f64, int radix, bool si, int io, float2* out, hipStream_t s) {
+    if (si) return go_line_p<N, true>(g, psi, nsteps, step_off, step_base, f64, radix, io, out, s);
+    return go_line_p<N, false>(g, psi, nsteps, step_off, step_base, f64, radix, io, out, s);
 }
 
 hipError_t launch_line_step(const GroupDev& g, float2* psi, int nsteps, int64_t step_off, const int64_t* step_base,
-                            bool f64, int radix, bool semi_implicit, hipStream_t s, int io) {
+                            bool f64, int radix, bool semi_implicit, hipStream_t s, int io, float2* out) {
+    if (!out) out = psi;
+    if (out != psi && (io & 2)) return hipErrorInvalidValue;  // the state stays in K
     switch (g.n[0]) {
-        case 8: return go_line_n<8>(g, psi, nsteps, step_off, step_base, f64, radix, semi_implicit, io, s);
-        case 16: return go_line_n<16>(g, psi, nsteps, step_off, step_base, f64, radix, semi_implicit, io, s);
-        case 32: return go_line_n<32>(g, psi, nsteps, step_off, step_base, f64, radix, semi_implicit, io, s);
-        case 64: return go_line_n<64>(g, psi, nsteps, step_off, step_base, f64, radix, semi_implicit, io, s);
-        case 128: return go_line_n<128>(g, psi, nsteps, step_off, step_base, f64, radix, semi_implicit, io, s);
-        case 256: return go_line_n<256>(g, psi, nsteps, step_off, step_base, f64, radix, semi_implicit, io, s);
-        case 512: return go_line_n<512>(g, psi, nsteps, step_off, step_base, f64, radix, semi_implicit, io, s);
-        case 1024: return go_line_n<1024>(g, psi, nsteps, step_off, step_base, f64, radix, semi_implicit, io, s);
-        case 2048: return go_line_n<2048>(g, psi, nsteps, step_off, step_base, f64, radix, semi_implicit, io, s);
-        case 4096: return go_line_n<4096>(g, psi, nsteps, step_off, step_base, f64, radix, semi_implicit, io, s);
+        case 8: return go_line_n<8>(g, psi, nsteps, step_off, step_base, f64, radix, semi_implicit, io, out, s);
+        case 16: return go_line_n<16>(g, psi, nsteps, step_off, step_base, f64, radix, semi_implicit, io, out, s);
+        case 32: return go_line_n<32>(g, psi, nsteps, step_off, step_base, f64, radix, semi_implicit, io, out, s);
+        case 64: return go_line_n<64>(g, psi, nsteps, step_off, step_base, f64, radix, semi_implicit, io, out, s);
+        case 128: return go_line_n<128>(g, psi, nsteps, step_off, step_base, f64, radix, semi_implicit, io, out, s);
+        case 256: return go_line_n<256>(g, psi, nsteps, step_off, step_base, f64, radix, semi_implicit, io, out, s);
+        case 512: return go_line_n<512>(g, psi, nsteps, step_off, step_base, f64, radix, semi_implicit, io, out, s);
+        case 1024: return go_line_n<1024>(g, psi, nsteps, step_off, step_base, f64, radix, semi_implicit, io, out, s);
+        case 2048: return go_line_n<2048>(g, psi, nsteps, step_off, step_base, f64, radix, semi_implicit, io, out, s);
+        case 4096: return go_line_n<4096>(g, psi, nsteps, step_off, step_base, f64, radix, semi_implicit, io, out, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -27,6 +27,7 @@ enum PassMode {
 // groups (the kernel adds the group offset).
 struct PassArgs {
     float2* psi;              // single field: D1 in/out, FIRST in, LAST2/AF/U out, AW in (lambda)
+    float2* psi_out;          // LAST2: write psi' here instead of psi (a step out of place), or null
     float2* A;                // field pair in/out
     float2* B;
     const float2* aux0;       // extra pointwise inputs: U (a, k1), AW (w), AS (a, k1), AF (psi_n)
@@ -99,12 +100,13 @@ hipError_t launch_axis_xf(const GroupDev& g, int axis, const PassArgs& a, hipStr
 hipError_t launch_axis_si(const GroupDev& g, int axis, const PassArgs& a, hipStream_t s);
 hipError_t launch_axis_last(const GroupDev& g, int axis, int mode, const PassArgs& a, hipStream_t s);
 hipError_t launch_line_adjoint(const GroupDev& g, const float2* psi_n, float2* lam, double* vbar, int64_t step,
-                               hipStream_t s);
+                               const int64_t* step_base, hipStream_t s);
 hipError_t launch_vbar_to_float(const double* vbar, float* out, int64_t n, hipStream_t s);
 // io (groups with a k-space state buffer, GroupDev::K, only): bit 0 reads the state from K
 // instead of transforming psi, bit 1 leaves it in K instead of transforming it back into psi.
+// out: where the lines are written (null: back into psi).
 hipError_t launch_line_step(const GroupDev& g, float2* psi, int nsteps, int64_t step_off, const int64_t* step_base, bool f64,
-                            int radix, bool semi_implicit, hipStream_t s, int io = 0);
+                            int radix, bool semi_implicit, hipStream_t s, int io = 0, float2* out = nullptr);
 hipError_t launch_line_ark45(const GroupDev& g, float2* psi, const ArkArgs& x, hipStream_t s);
 hipError_t launch_diag_axis(const GroupDev& g, int axis, const float2* psi, double kscale, double* part,
                             hipStream_t s);

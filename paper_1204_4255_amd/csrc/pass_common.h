@@ -406,10 +406,11 @@ __device__ __forceinline__ void axis_body(const GroupDev& g, int axis, const Pas
 #pragma unroll
         for (int m = 0; m < R; m++) st2(ps, tile.b8(m), f[0][m]);
     } else if constexpr (MODE == PASS_LAST2) {
+        float2* __restrict__ po = args.psi_out ? args.psi_out + o : ps;
 #pragma unroll
         for (int m = 0; m < R; m++) {
             const c32 k4 = hG(g, f[0][m], pot_at(m, step), noise_at(m, step));
-            st2(ps, tile.b8(m), make_float2(fmaf(k4.x, 1.0f / 6.0f, f[1][m].x), fmaf(k4.y, 1.0f / 6.0f, f[1][m].y)));
+            st2(po, tile.b8(m), make_float2(fmaf(k4.x, 1.0f / 6.0f, f[1][m].x), fmaf(k4.y, 1.0f / 6.0f, f[1][m].y)));
         }
     } else if constexpr (MODE == PASS_AS) {
         // transposes of the stage combinations: (accbar, ubar) -> (abar, k1bar)

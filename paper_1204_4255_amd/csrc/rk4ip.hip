@@ -339,6 +339,11 @@ struct rk4ip_plan_s {
     void* graph_psi = nullptr;
     int graph_steps = 0;
     hipStream_t capture_stream = nullptr;  // private stream the graph is recorded on
+    // graphs of one adjoint segment (recompute, backward walk) for the buffers they were
+    // recorded on
+    hipGraphExec_t adj_fwd = nullptr, adj_bwd = nullptr;
+    const void* adj_key[3] = {nullptr, nullptr, nullptr};  // store, lambda, vbar
+    int64_t adj_M = 0;
     int sticky = RK4IP_OK;
     // per-pass event timing
     bool profiling = false;
@@ -380,6 +385,10 @@ void drop_graph(rk4ip_plan_t plan) {
     plan->graph_src = nullptr;
     plan->graph_psi = nullptr;
     plan->graph_steps = 0;
+    if (plan->adj_fwd) (void)hipGraphExecDestroy(plan->adj_fwd);
+    if (plan->adj_bwd) (void)hipGraphExecDestroy(plan->adj_bwd);
+    plan->adj_fwd = plan->adj_bwd = nullptr;
+    plan->adj_M = 0;
 }
 
 // Waits for the plan's stream, frees the HIP objects the plan created (graph, capture
@@ -1193,6 +1202,128 @@ __global__ void k_noalloc_tables(float2* __restrict__ E, float2* __restrict__ tw
     }
 }
 
+// One step of every group from src into dst (the adjoint's recompute: the states of a
+// segment go straight into their slots). Per-group launches with the plan's schedules;
+// step_base != null: the step index is *step_base + step_off.
+int enqueue_step_to(rk4ip_plan_t plan, hipStream_t st, const float2* src, float2* dst, int64_t step_off,
+                    const int64_t* step_base) {
+    for (size_t gi = 0; gi < plan->groups.size(); gi++) {
+        auto& g = plan->groups[gi];
+        if (g.p.ndim == 1) {
+            HIPCHK(plan, rk4ip::launch_line_step(g.d, const_cast<float2*>(src), 1, step_off, step_base, plan->f64,
+                                                 plan->sched[gi][0].radix, plan->si, st, 0, dst));
+            continue;
+        }
+        PassDef defs[kMaxPasses];
+        const int np = pass_list(g.p.ndim, plan->si, defs);
+        for (int role : {ROLE_OPEN, ROLE_MID, ROLE_CLOSE}) {
+            for (int i = 0; i < np; i++) {
+                if (defs[i].role != role) continue;
+                rk4ip::PassArgs pa{};
+                pa.psi = const_cast<float2*>(src);
+                pa.psi_out = dst;
+                pa.A = plan->A;
+                pa.B = plan->B;
+                pa.step_off = step_off;
+                pa.step_base = step_base;
+                pa.twice = defs[i].twice;
+                pa.f64 = plan->f64 ? 1 : 0;
+                pa.occ = plan->sched[gi][i].occ;
+                pa.lines = plan->sched[gi][i].lines;
+                pa.seq = plan->sched[gi][i].seq;
+                pa.radix = plan->sched[gi][i].radix;
+                HIPCHK(plan, rk4ip::launch_axis(g.d, defs[i].axis, defs[i].mode, pa, st));
+            }
+        }
+    }
+    return RK4IP_OK;
+}
+
+// The adjoint of one step at state pn (psi_n) for every group: lam <- (d step)^T lam, and
+// the potential gradient accumulated into vbar. W, X, Y: work fields.
+int enqueue_adjoint_step(rk4ip_plan_t plan, hipStream_t st, const float2* pn, float2* lam, double* vbar, float2* W,
+                         float2* X, float2* Y, int64_t step_off, const int64_t* step_base) {
+    for (auto& g : plan->groups) {
+        if (g.p.ndim == 1) {
+            HIPCHK(plan, rk4ip::launch_line_adjoint(g.d, pn, lam, vbar, step_off, step_base, st));
+            continue;
+        }
+        const int last = g.p.ndim - 1;
+        rk4ip::PassArgs pa{};
+        pa.step_off = step_off;
+        pa.step_base = step_base;
+        // forward: (A, B) = D (psi_n, hG(psi_n)) = (a, k1)
+        pa.psi = const_cast<float2*>(pn);
+        pa.A = plan->A;
+        pa.B = plan->B;
+        HIPCHK(plan, rk4ip::launch_axis(g.d, 0, rk4ip::PASS_FIRST, pa, st));
+        for (int a = 1; a <= last; a++) HIPCHK(plan, rk4ip::launch_axis(g.d, a, rk4ip::PASS_D2, pa, st));
+        // forward: W = D (a + k3)
+        rk4ip::PassArgs pu{};
+        pu.step_off = step_off;
+        pu.step_base = step_base;
+        pu.psi = W;
+        pu.aux0 = plan->A;
+        pu.aux1 = plan->B;
+        HIPCHK(plan, rk4ip::launch_axis(g.d, 0, rk4ip::PASS_U, pu, st));
+        for (int a = 1; a <= last; a++) HIPCHK(plan, rk4ip::launch_axis(g.d, a, rk4ip::PASS_D1, pu, st));
+        // adjoint: (X, Y) = D^T (lam, h J(w)^T lam/6), then the stage transposes
+        rk4ip::PassArgs pw{};
+        pw.step_off = step_off;
+        pw.step_base = step_base;
+        pw.adj = 1;
+        pw.psi = lam;
+        pw.aux0 = W;
+        pw.A = X;
+        pw.B = Y;
+        pw.vbar = vbar;
+        HIPCHK(plan, rk4ip::launch_axis(g.d, 0, rk4ip::PASS_AW, pw, st));
+        for (int a = 1; a < last; a++) HIPCHK(plan, rk4ip::launch_axis(g.d, a, rk4ip::PASS_D2, pw, st));
+        pw.aux0 = plan->A;
+        pw.aux1 = plan->B;
+        HIPCHK(plan, rk4ip::launch_axis(g.d, last, rk4ip::PASS_AS, pw, st));
+        // adjoint: lam = D^T abar + h J(psi_n)^T D^T k1bar
+        rk4ip::PassArgs pf{};
+        pf.step_off = step_off;
+        pf.step_base = step_base;
+        pf.adj = 1;
+        pf.A = X;
+        pf.B = Y;
+        pf.psi = lam;
+        pf.aux0 = pn;
+        pf.vbar = vbar;
+        for (int a = 0; a < last; a++) HIPCHK(plan, rk4ip::launch_axis(g.d, a, rk4ip::PASS_D2, pf, st));
+        HIPCHK(plan, rk4ip::launch_axis(g.d, last, rk4ip::PASS_AF, pf, st));
+    }
+    return RK4IP_OK;
+}
+
+// Record `body` (enqueueing on the given stream) as a graph on the plan's private stream.
+template <class Fn>
+int record_graph(rk4ip_plan_t plan, hipGraphExec_t* out, Fn&& body) {
+    if (!plan->capture_stream) HIPCHK(plan, hipStreamCreateWithFlags(&plan->capture_stream, hipStreamNonBlocking));
+    hipStream_t s = plan->capture_stream;
+    hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return fail_hip(plan, e, "hipStreamBeginCapture");
+    const int rc = body(s);
+    hipGraph_t gr = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(s, &gr);
+    if (rc != RK4IP_OK || e2 != hipSuccess || !gr) {
+        if (gr) (void)hipGraphDestroy(gr);
+        plan->err = "graph capture failed";
+        return RK4IP_ERR_NOT_CAPTURABLE;
+    }
+    hipGraphExec_t ex = nullptr;
+    e = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(gr);
+    if (e != hipSuccess) {
+        plan->err = std::string("hipGraphInstantiate: ") + hipGetErrorString(e);
+        return RK4IP_ERR_NOT_CAPTURABLE;
+    }
+    *out = ex;
+    return RK4IP_OK;
+}
+
 }  // namespace
 
 // ================================================================== C ABI
@@ -1472,8 +1603,8 @@ int rk4ip_ark45(rk4ip_plan_t plan, void* psi_v, double t_span, double tol, int64
 
 size_t rk4ip_adjoint_workspace_bytes(rk4ip_plan_t plan, int64_t ckpt_every) {
     if (!plan || ckpt_every < 1) return 0;
-    // segment states, the recompute buffer, three work fields (w, and the adjoint pair)
-    // and the FP64 potential-gradient accumulator
+    // segment states, the adjoint state, three work fields (w, and the adjoint pair) and
+    // the FP64 potential-gradient accumulator
     const size_t field = align_up(sizeof(float2) * (size_t)plan->points);
     return (size_t)(ckpt_every + 4) * field + align_up(sizeof(double) * (size_t)plan->points);
 }
@@ -1491,87 +1622,74 @@ int rk4ip_adjoint(rk4ip_plan_t plan, const void* ckpt_v, int64_t step0, int64_t 
     if (adj_ws_bytes < rk4ip_adjoint_workspace_bytes(plan, ckpt_every)) return RK4IP_ERR_WORKSPACE_TOO_SMALL;
     hipStream_t st = plan->stream;
     const size_t field = align_up(sizeof(float2) * (size_t)plan->points);
+    const int64_t fstride = (int64_t)(field / sizeof(float2));
     char* w = static_cast<char*>(adj_ws);
-    float2* store = reinterpret_cast<float2*>(w);
-    float2* cur = reinterpret_cast<float2*>(w + (size_t)ckpt_every * field);
-    float2* W = reinterpret_cast<float2*>(w + (size_t)(ckpt_every + 1) * field);
-    float2* X = reinterpret_cast<float2*>(w + (size_t)(ckpt_every + 2) * field);
-    float2* Y = reinterpret_cast<float2*>(w + (size_t)(ckpt_every + 3) * field);
+    float2* store = reinterpret_cast<float2*>(w);  // the states of a segment, slot i = step i
+    float2* W = reinterpret_cast<float2*>(w + (size_t)ckpt_every * field);
+    float2* X = reinterpret_cast<float2*>(w + (size_t)(ckpt_every + 1) * field);
+    float2* Y = reinterpret_cast<float2*>(w + (size_t)(ckpt_every + 2) * field);
+    float2* lam = reinterpret_cast<float2*>(w + (size_t)(ckpt_every + 3) * field);  // the adjoint state
     double* vbar = reinterpret_cast<double*>(w + (size_t)(ckpt_every + 4) * field);
     const float2* ckpt = static_cast<const float2*>(ckpt_v);
-    float2* lam = static_cast<float2*>(grad_psi0);
     const size_t fbytes = sizeof(float2) * (size_t)plan->points;
-    if (lam != lambda_T) HIPCHK(plan, hipMemcpyAsync(lam, lambda_T, fbytes, hipMemcpyDeviceToDevice, st));
+    HIPCHK(plan, hipMemcpyAsync(lam, lambda_T, fbytes, hipMemcpyDeviceToDevice, st));
     HIPCHK(plan, hipMemsetAsync(vbar, 0, sizeof(double) * (size_t)plan->points, st));
 
-    const int64_t nseg = (nsteps + ckpt_every - 1) / ckpt_every;
-    for (int64_t seg = nseg - 1; seg >= 0; seg--) {
-        const int64_t s0 = seg * ckpt_every;
-        const int64_t len = std::min(ckpt_every, nsteps - s0);
-        // recompute and keep the states of this segment
-        HIPCHK(plan, hipMemcpyAsync(cur, ckpt + seg * plan->points, fbytes, hipMemcpyDeviceToDevice, st));
-        for (int64_t i = 0; i < len; i++) {
-            HIPCHK(plan, hipMemcpyAsync(store + i * (int64_t)(field / sizeof(float2)), cur, fbytes,
-                                        hipMemcpyDeviceToDevice, st));
-            if (i + 1 < len) {
-                int rc = enqueue_steps(plan, st, cur, step0 + s0 + i, 1, false);
-                if (rc) return rc;
-            }
-        }
-        // walk the segment backwards
-        for (int64_t i = len - 1; i >= 0; i--) {
-            const float2* pn = store + i * (int64_t)(field / sizeof(float2));
-            const int64_t step = step0 + s0 + i;
-            for (auto& g : plan->groups) {
-                if (g.p.ndim == 1) {
-                    HIPCHK(plan, rk4ip::launch_line_adjoint(g.d, pn, lam, vbar, step, st));
-                    continue;
+    // With RK4IP_FLAG_GRAPH a whole segment (ckpt_every steps) is two graph replays: the
+    // recompute from slot 0 and the backward walk, with step indices read from the device
+    // counter. Recorded once per workspace (every buffer they touch lives in it).
+    const int64_t M = ckpt_every;
+    const bool graphs = (plan->flags & RK4IP_FLAG_GRAPH) != 0 && nsteps >= M;
+    if (graphs && (plan->adj_M != M || plan->adj_key[0] != store || plan->adj_key[1] != lam || plan->adj_key[2] != vbar)) {
+        if (plan->adj_fwd) (void)hipGraphExecDestroy(plan->adj_fwd);
+        if (plan->adj_bwd) (void)hipGraphExecDestroy(plan->adj_bwd);
+        plan->adj_fwd = plan->adj_bwd = nullptr;
+        plan->adj_M = 0;
+        int rc = RK4IP_OK;
+        if (M > 1)
+            rc = record_graph(plan, &plan->adj_fwd, [&](hipStream_t s) {
+                for (int64_t i = 0; i + 1 < M; i++) {
+                    const int r = enqueue_step_to(plan, s, store + i * fstride, store + (i + 1) * fstride, i, plan->counter);
+                    if (r) return r;
                 }
-                const int last = g.p.ndim - 1;
-                rk4ip::PassArgs pa{};
-                pa.step_off = step;
-                // forward: (A, B) = D (psi_n, hG(psi_n)) = (a, k1)
-                pa.psi = const_cast<float2*>(pn);
-                pa.A = plan->A;
-                pa.B = plan->B;
-                HIPCHK(plan, rk4ip::launch_axis(g.d, 0, rk4ip::PASS_FIRST, pa, st));
-                for (int a = 1; a <= last; a++) HIPCHK(plan, rk4ip::launch_axis(g.d, a, rk4ip::PASS_D2, pa, st));
-                // forward: W = D (a + k3)
-                rk4ip::PassArgs pu{};
-                pu.step_off = step;
-                pu.psi = W;
-                pu.aux0 = plan->A;
-                pu.aux1 = plan->B;
-                HIPCHK(plan, rk4ip::launch_axis(g.d, 0, rk4ip::PASS_U, pu, st));
-                for (int a = 1; a <= last; a++) HIPCHK(plan, rk4ip::launch_axis(g.d, a, rk4ip::PASS_D1, pu, st));
-                // adjoint: (X, Y) = D^T (lam, h J(w)^T lam/6), then the stage transposes
-                rk4ip::PassArgs pw{};
-                pw.step_off = step;
-                pw.adj = 1;
-                pw.psi = lam;
-                pw.aux0 = W;
-                pw.A = X;
-                pw.B = Y;
-                pw.vbar = vbar;
-                HIPCHK(plan, rk4ip::launch_axis(g.d, 0, rk4ip::PASS_AW, pw, st));
-                for (int a = 1; a < last; a++) HIPCHK(plan, rk4ip::launch_axis(g.d, a, rk4ip::PASS_D2, pw, st));
-                pw.aux0 = plan->A;
-                pw.aux1 = plan->B;
-                HIPCHK(plan, rk4ip::launch_axis(g.d, last, rk4ip::PASS_AS, pw, st));
-                // adjoint: lam = D^T abar + h J(psi_n)^T D^T k1bar
-                rk4ip::PassArgs pf{};
-                pf.step_off = step;
-                pf.adj = 1;
-                pf.A = X;
-                pf.B = Y;
-                pf.psi = lam;
-                pf.aux0 = pn;
-                pf.vbar = vbar;
-                for (int a = 0; a < last; a++) HIPCHK(plan, rk4ip::launch_axis(g.d, a, rk4ip::PASS_D2, pf, st));
-                HIPCHK(plan, rk4ip::launch_axis(g.d, last, rk4ip::PASS_AF, pf, st));
-            }
-        }
+                return (int)RK4IP_OK;
+            });
+        if (rc == RK4IP_OK)
+            rc = record_graph(plan, &plan->adj_bwd, [&](hipStream_t s) {
+                for (int64_t i = M - 1; i >= 0; i--) {
+                    const int r = enqueue_adjoint_step(plan, s, store + i * fstride, lam, vbar, W, X, Y, i, plan->counter);
+                    if (r) return r;
+                }
+                return (int)RK4IP_OK;
+            });
+        if (rc != RK4IP_OK) return rc;
+        plan->adj_M = M;
+        plan->adj_key[0] = store;
+        plan->adj_key[1] = lam;
+        plan->adj_key[2] = vbar;
     }
+
+    const int64_t nseg = (nsteps + M - 1) / M;
+    for (int64_t seg = nseg - 1; seg >= 0; seg--) {
+        const int64_t s0 = seg * M;
+        const int64_t len = std::min(M, nsteps - s0);
+        HIPCHK(plan, hipMemcpyAsync(store, ckpt + seg * plan->points, fbytes, hipMemcpyDeviceToDevice, st));
+        if (graphs && len == M) {
+            HIPCHK(plan, rk4ip::launch_counter(plan->counter, step0 + s0, 0, st));
+            if (plan->adj_fwd) HIPCHK(plan, hipGraphLaunch(plan->adj_fwd, st));
+            HIPCHK(plan, hipGraphLaunch(plan->adj_bwd, st));
+            continue;
+        }
+        // recompute the segment's states into their slots, then walk it backwards
+        int rc;
+        for (int64_t i = 0; i + 1 < len; i++)
+            if ((rc = enqueue_step_to(plan, st, store + i * fstride, store + (i + 1) * fstride, step0 + s0 + i, nullptr)))
+                return rc;
+        for (int64_t i = len - 1; i >= 0; i--)
+            if ((rc = enqueue_adjoint_step(plan, st, store + i * fstride, lam, vbar, W, X, Y, step0 + s0 + i, nullptr)))
+                return rc;
+    }
+    HIPCHK(plan, hipMemcpyAsync(grad_psi0, lam, fbytes, hipMemcpyDeviceToDevice, st));
     if (grad_V) HIPCHK(plan, rk4ip::launch_vbar_to_float(vbar, grad_V, plan->points, st));
     return RK4IP_OK;
 }

@@ -339,7 +339,11 @@ class Plan:
 
         self._sync_stream()
         nb = self.adjoint_workspace_bytes(ckpt_every)
-        ws = torch.empty(nb + 256, dtype=torch.uint8, device=lambda_T.device)
+        # kept between calls (stream-ordered reuse), so that the segment graphs recorded on
+        # it are replayed by later calls
+        ws = getattr(self, "_keep_adj_ws", None)
+        if ws is None or ws.numel() < nb + 256 or ws.device != lambda_T.device:
+            ws = torch.empty(nb + 256, dtype=torch.uint8, device=lambda_T.device)
         aligned = (ws.data_ptr() + 255) // 256 * 256
         g = torch.empty_like(lambda_T)
         gV = torch.zeros(self.points, dtype=torch.float32, device=lambda_T.device) if want_V else None

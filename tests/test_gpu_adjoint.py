@@ -203,3 +203,37 @@ def test_solver_called_twice_before_backward(torch):
     log(f"  grad_psi0 diff {float((g_both - g_alone).abs().max()):.3e}, grad_V diff "
         f"{float((gv_both - gv_alone).abs().max()):.3e}")
     assert torch.equal(g_both, g_alone) and torch.equal(gv_both, gv_alone)
+
+
+def test_adjoint_graph_segments_equal_eager(torch):
+    """With RK4IP_FLAG_GRAPH the forward run and each whole checkpoint segment of the adjoint
+    (recompute into the segment's slots, backward walk) replay hipGraphs: the gradients equal
+    the eager ones bitwise, on two calls in a row (the second replays the graphs recorded on
+    the solver's kept workspace), with a last partial segment run eagerly."""
+    from paper_1204_4255_amd.autograd import RK4IPSolver
+
+    gs = _groups([((64,), 3), ((16, 16), 2), ((16, 8, 8), 1)])
+    nsteps, M, h = 11, 4, 2e-3
+    fields = [quantised(random_field(g, 17 + i)) for i, g in enumerate(gs)]
+    w = W.Workload("adjg", gs, h, nsteps, fields)
+    probs, _ = rk4ip.problems_from_workload(w)
+    V0 = torch.tensor(np.concatenate([g.Vgrid.reshape(-1) for g in gs]), device="cuda")
+    rng = np.random.Generator(np.random.PCG64(3))
+    base = rk4ip.field_to_device(w)
+    lam = torch.tensor((rng.standard_normal(base.numel()) + 1j * rng.standard_normal(base.numel()))
+                       .astype(np.complex64), device="cuda")
+
+    def grads(solver, scale):
+        p = (base * scale).requires_grad_(True)
+        V = V0.clone().requires_grad_(True)
+        torch.sum((torch.conj(lam) * solver(p, V)).real).backward()
+        return p.grad.clone(), V.grad.clone()
+
+    eager = RK4IPSolver(probs, nsteps, M, step0=3)
+    graph = RK4IPSolver(probs, nsteps, M, step0=3, flags=rk4ip.RK4IP_FLAG_GRAPH)
+    for scale in (1.0, 0.8):
+        ge, gve = grads(eager, scale)
+        gg, gvg = grads(graph, scale)
+        log(f"  scale {scale}: grad_psi0 max diff {float((gg - ge).abs().max()):.3e}, "
+            f"grad_V max diff {float((gvg - gve).abs().max()):.3e}")
+        assert torch.equal(gg, ge) and torch.equal(gvg, gve)
