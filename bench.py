@@ -31,6 +31,7 @@ PASS_BYTES = {"FIRST": 24, "D2": 32, "LF": 32, "XF": 32, "LAST2": 24, "line_step
               # the semi-implicit step works on psi in place: every pass reads and writes it once
               "D1": 16, "D1x2": 16, "SI": 16, "line_si": 16}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_gpe3d_256.json")
+LINE_COUNTERS_FILE = os.path.join(ROOT, "profiles", "counters_line_kernels.json")
 TRAFFIC_FILE_SI = os.path.join(ROOT, "profiles", "traffic_gpe3d_256_semi_implicit.json")
 
 
@@ -57,6 +58,20 @@ def measured_traffic(kernel: str, path: str = TRAFFIC_FILE):
     """HBM bytes per launch of `kernel` (scaled FETCH_SIZE + WRITE_SIZE), or None."""
     rec = measured_counters(kernel, path)
     return rec.get("bytes_per_launch") if rec else None
+
+def line_kernel_counters(kernel: str):
+    """Counter record of a whole-line kernel (short name, e.g. k_line_kstep<1024, 1, true, 8,
+    false>) from the committed rocprofv3 summary of the forms, or None when it is missing or
+    the kernels changed since."""
+    try:
+        with open(LINE_COUNTERS_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_hash") != kernel_source_hash():
+        return None
+    return t.get("kernels", {}).get(kernel)
+
 
 def _timed(torch, fn, reps: int = 1) -> float:
     """Seconds per call of fn (events on the current stream, after one untimed call)."""
@@ -123,6 +138,12 @@ def form_batched_paths(torch, rk4ip, workloads, steps: int = 200, sample_paths: 
         "one_launch_per_step_pt_steps_per_s"]
     out["bitwise_equal_to_plain"] = same  # when both picked the same line kernel
     out["max_rel_diff_to_plain"] = worst
+    # VALU issue of the fused kernel from the committed counter run (k-space line step)
+    rr = out["fused_steps_schedule"].split(":r")[-1]
+    kname = f"k_line_kstep<{g.n[0]}, 1, true, {rr}, false>"
+    rec = line_kernel_counters(kname) or {}
+    out["kernel"] = kname
+    out["valu_issue_frac_profiled"] = rec.get("valu_issue_frac")
     return out
 
 
@@ -536,12 +557,17 @@ def progress(msg: str) -> None:
     print(f"bench: {msg}", file=sys.stderr, flush=True)
 
 
-def measure_forms(torch, rk4ip, workloads):
+FORMS = (("other_workloads", other_workloads), ("batched_paths", form_batched_paths),
+         ("uneven_batch", form_uneven_batch), ("adjoint", form_adjoint),
+         ("fp64_transforms", form_fp64_transforms), ("semi_implicit", form_semi_implicit),
+         ("ark45", form_ark45), ("potential_terms", form_potential_terms), ("bases", form_bases))
+
+
+def measure_forms(torch, rk4ip, workloads, only=None):
     out = {}
-    for name, fn in (("other_workloads", other_workloads), ("batched_paths", form_batched_paths),
-                     ("uneven_batch", form_uneven_batch), ("adjoint", form_adjoint),
-                     ("fp64_transforms", form_fp64_transforms), ("semi_implicit", form_semi_implicit),
-                     ("ark45", form_ark45), ("potential_terms", form_potential_terms), ("bases", form_bases)):
+    for name, fn in FORMS:
+        if only is not None and name not in only:
+            continue
         t0 = time.perf_counter()
         out[name] = fn(torch, rk4ip, workloads)
         progress(f"form {name} done ({time.perf_counter() - t0:.1f} s)")
@@ -562,10 +588,18 @@ def main() -> int:
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the batched and adjoint forms (each timed against the plain path)")
     ap.add_argument("--forms-only", action="store_true", help="measure only the batched and adjoint forms")
+    ap.add_argument("--forms", default=None,
+                    help="comma-separated subset of the forms to measure (default: all of them)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one elementwise copy kernel of 256 MiB in + 256 MiB out (a reference for "
                          "rocprofv3 FETCH_SIZE/WRITE_SIZE counters)")
     args = ap.parse_args()
+    only = None
+    if args.forms is not None:
+        only = [f.strip() for f in args.forms.split(",") if f.strip()]
+        unknown = sorted(set(only) - {name for name, _ in FORMS})
+        if unknown:
+            ap.error(f"unknown forms {unknown}; known: {[name for name, _ in FORMS]}")
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; the multi-GPU path is a design "
                           "(slab decomposition with RCCL all-to-all), not implemented", "n_gpus": args.gpus}))
@@ -578,7 +612,7 @@ def main() -> int:
 
     torch.cuda.set_device(0)
     if args.forms_only:
-        print(json.dumps({"forms": measure_forms(torch, rk4ip, workloads)}))
+        print(json.dumps({"forms": measure_forms(torch, rk4ip, workloads, only)}))
         return 0
     if args.calibrate_copy:
         src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
@@ -708,7 +742,7 @@ def main() -> int:
         result[f"parity_{cpu_steps}step_rel_l2"] = err
         progress(f"cpu baseline done ({cpu_s:.1f} s)")
     if not args.no_forms:
-        result["forms"] = measure_forms(torch, rk4ip, workloads)
+        result["forms"] = measure_forms(torch, rk4ip, workloads, only)
     print(json.dumps(result))
     plan.destroy()
     prof_plan.destroy()
