@@ -226,6 +226,7 @@ struct FFTShape {
 //    passes, so there is none.
 template <int N, int LINES, bool ROWMAJOR, int R = 16>
 struct LdsLayout {
+    static constexpr bool ROWS = ROWMAJOR;
     static constexpr bool SWZ = ROWMAJOR && R == 8 && N >= 16;
     static constexpr int ROW = SWZ ? N + 1 : N + (N >= 16 ? N / 16 : 0);
     static constexpr int SIZE = ROWMAJOR ? LINES * ROW : LINES * N;
@@ -290,6 +291,28 @@ __device__ __forceinline__ void fft_stage(V (&v)[F::R], int t, const V* __restri
     }
 }
 
+// Order this wave's LDS accesses on either side: the wave's LDS instructions execute in
+// order, so what its lanes wrote before is what its lanes read after, with no workgroup
+// barrier (the fences keep the compiler from moving LDS accesses across).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// The exchange of a line whose threads are consecutive lanes of one wave (row-major
+// buffer, at most 64 threads per line; every kernel with a row-major buffer gives thread
+// t of line l the index l T + t) touches LDS that only that wave uses: a wave-level sync
+// suffices. Otherwise the line spans waves and needs the workgroup barrier.
+template <class F, class L>
+__device__ __forceinline__ void exchange_sync() {
+    if constexpr (L::ROWS && F::T <= 64) {
+        wave_lds_sync();
+    } else {
+        __syncthreads();
+    }
+}
+
 // Write the outputs of stage STAGE to LDS and read the inputs of stage STAGE+1.
 template <class F, int STAGE, class L, int NF, class V>
 __device__ __forceinline__ void fft_exchange(V (&v)[NF][F::R], int t, int line, V* lds) {
@@ -309,7 +332,7 @@ __device__ __forceinline__ void fft_exchange(V (&v)[NF][F::R], int t, int line, 
             for (int k = 0; k < r; k++) lds[f * L::SIZE + L::addr(line, base + k * ns)] = v[f][u * r + k];
         }
     }
-    __syncthreads();
+    exchange_sync<F, L>();
 #pragma unroll
     for (int f = 0; f < NF; f++) {
 #pragma unroll
@@ -319,7 +342,7 @@ __device__ __forceinline__ void fft_exchange(V (&v)[NF][F::R], int t, int line, 
             for (int k = 0; k < r2; k++) v[f][u * r2 + k] = lds[f * L::SIZE + L::addr(line, b + k * (N / r2))];
         }
     }
-    __syncthreads();
+    exchange_sync<F, L>();
 }
 
 // After the last stage, register u*Q + k holds element t + T (u + k R/Q); put element
@@ -355,7 +378,7 @@ __device__ __forceinline__ void fft_stages_from(V (&v)[NF][F::R], int t, int lin
 // Full transform of NF lines (one per field) owned by this thread group. On entry and
 // on exit thread t holds element t + T m in v[f][m]. S = -1 forward, +1 inverse. F is the
 // FFTShape (length and values per thread). All threads of the block must call this
-// together (it contains barriers).
+// together (it contains barriers, workgroup-wide unless the line sits in one wave).
 template <class F, int S, class L, int NF, class V>
 __device__ __forceinline__ void fft_line(V (&v)[NF][F::R], int t, int line, V* lds,
                                          const V* __restrict__ tw) {
