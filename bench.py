@@ -143,7 +143,10 @@ def form_batched_paths(torch, rk4ip, workloads, steps: int = 200, sample_paths: 
     kname = f"k_line_kstep<{g.n[0]}, 1, true, {rr}, false>"
     rec = line_kernel_counters(kname) or {}
     out["kernel"] = kname
-    out["valu_issue_frac_profiled"] = rec.get("valu_issue_frac")
+    # the issue of its longest launch (many steps over the whole batch, as in the fused
+    # form), and the duration-weighted average over every launch of the forms
+    out["valu_issue_frac_profiled"] = rec.get("valu_issue_longest_dispatch")
+    out["valu_issue_frac_profiled_all_launches"] = rec.get("valu_issue_frac")
     return out
 
 

@@ -76,6 +76,9 @@ def summarise(src: str) -> dict:
         for c in ("SQ_INSTS_VALU", "SQ_INSTS_LDS", "SQ_LDS_BANK_CONFLICT", "SQ_WAVES"):
             a[c] += d.get(c, 0.0)
         a["n"] += 1
+        if d["dur"] > a["longest_dur"]:
+            a["longest_dur"] = d["dur"]
+            a["longest_issue"] = d["SQ_INSTS_VALU"] / (CUS * CLOCK * d["dur"])
     kernels = {}
     for name, st in stats.items():
         rec = dict(st)
@@ -85,6 +88,8 @@ def summarise(src: str) -> dict:
             rec["lds_per_valu"] = a["SQ_INSTS_LDS"] / a["SQ_INSTS_VALU"] if a["SQ_INSTS_VALU"] else None
             rec["lds_bank_conflict_cycles_per_dispatch"] = a["SQ_LDS_BANK_CONFLICT"] / a["n"]
             rec["counter_dispatches"] = int(a["n"])
+            rec["valu_issue_longest_dispatch"] = a["longest_issue"]
+            rec["longest_dispatch_us"] = a["longest_dur"] * 1e6
         kernels[name] = rec
     return {"source_hash": source_hash(), "kernels": kernels}
 
@@ -108,11 +113,15 @@ def report(out: dict) -> str:
         "Columns: calls and durations from the kernel trace (they mix every form that launches a",
         "kernel, and several steps run per launch where a form fuses them, so a launch is not a",
         "step; the forms' own event timings are in `bench.py`'s JSON). VALU issue = SQ_INSTS_VALU /",
-        "(256 CUs x 2.4 GHz x duration) over the counter run's dispatches, weighted by duration.",
+        "(256 CUs x 2.4 GHz x duration) over the counter run's dispatches, weighted by duration;",
+        "that average mixes full launches with the forms' small ones (a plan of one line, a",
+        "conversion-only launch), so the issue of each kernel's longest dispatch (for the line",
+        "kernels, a launch of many steps over the whole batch) is given beside it. Integer",
+        "multiplies (Philox) and transcendentals issue at a quarter of the rate and count once.",
         "Rows: the 30 kernels of most GPU time, then every other whole-line and merged kernel.",
         "",
-        "| kernel | calls | average us | total ms | % GPU time | VALU issue | LDS / VALU instr | bank-conflict cycles per dispatch |",
-        "|---|---|---|---|---|---|---|---|",
+        "| kernel | calls | average us | total ms | % GPU time | VALU issue | VALU issue, longest dispatch (us) | LDS / VALU instr | bank-conflict cycles per dispatch |",
+        "|---|---|---|---|---|---|---|---|---|",
     ]
     rows = sorted(out["kernels"].items(), key=lambda kv: -kv[1]["total_ms"])
     for i, (name, r) in enumerate(rows):
@@ -121,9 +130,10 @@ def report(out: dict) -> str:
         iss = r.get("valu_issue_frac")
         lpv = r.get("lds_per_valu")
         bc = r.get("lds_bank_conflict_cycles_per_dispatch")
+        li, ld = r.get("valu_issue_longest_dispatch"), r.get("longest_dispatch_us")
         lines.append(f"| `{name}` | {r['calls']} | {r['average_us']:.1f} | {r['total_ms']:.2f} | {r['percent']:.2f} | "
-                     f"{'' if iss is None else f'{iss:.2f}'} | {'' if lpv is None else f'{lpv:.3f}'} | "
-                     f"{'' if bc is None else f'{bc:.3g}'} |")
+                     f"{'' if iss is None else f'{iss:.2f}'} | {'' if li is None else f'{li:.2f} ({ld:.0f})'} | "
+                     f"{'' if lpv is None else f'{lpv:.3f}'} | {'' if bc is None else f'{bc:.3g}'} |")
     lines += ["", "Template arguments:"]
     lines += [f"* `{k}`: {v}." for k, v in LEGEND.items()]
     return "\n".join(lines) + "\n"
