@@ -37,7 +37,8 @@ struct PassArgs {
     int lines;                // tile schedule: lines (contiguous axis) or columns (strided) per
                               // workgroup, 0 = default
     int seq;                  // 0: fields transformed together; 1: one after the other (half the
-                              // LDS); 2: as 1 with the second field loaded after the first
+                              // LDS); 2: as 1 with the second field loaded after the first;
+                              // 3: one thread per field (twice the threads)
     int radix;                // values per thread in the transform: 16 (0 = default) or 8
     int f64;                  // transforms, propagator multiply and delta add in FP64 (radix 8)
     int occ;                  // minimum waves per SIMD the kernel is compiled for (0/1 = none, 4)

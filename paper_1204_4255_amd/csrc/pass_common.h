@@ -209,6 +209,11 @@ constexpr bool uses_rhs(int mode) {
 //          lower register peak, twice the barriers).
 // SEQ = 2: as 1, and the second field is only loaded once the first is transformed
 //          (lowest register peak, fewer loads in flight per wave).
+// SEQ = 3: one thread per field: the workgroup has twice the threads, its first half
+//          carries field 0 and its second half field 1 of the same lines, each through its
+//          own exchange buffer; where a pass combines the two fields pointwise, the halves
+//          swap values through LDS. Twice the threads per line for lattices with few lines,
+//          and half the registers per thread (forward passes with two fields, radix 8).
 // RR: values per thread in the transform (16, or 8 for half the registers and one more
 // LDS exchange per transform).
 // OCC: the minimum waves per SIMD the register allocation must allow (1 = no constraint;
@@ -220,7 +225,7 @@ template <int N, int MODE, bool CONTIG, int LINES, int SEQ, int RR, bool P64>
 struct AxisLds {
     using V = typename std::conditional<P64, c64, c32>::type;
     using L = LdsLayout<N, LINES, CONTIG, FFTShape<N, RR>::R>;
-    static constexpr int BUF = (SEQ != 0 ? 1 : fields_of(MODE)) * L::SIZE;
+    static constexpr int BUF = ((SEQ == 1 || SEQ == 2) ? 1 : fields_of(MODE)) * L::SIZE;
     static constexpr int ENTRIES = BUF + 2 * N;
     static constexpr size_t BYTES = sizeof(V) * (size_t)ENTRIES;
 };
@@ -452,13 +457,160 @@ __device__ __forceinline__ void axis_body(const GroupDev& g, int axis, const Pas
     }
 }
 
+// Passes with one thread per field (SEQ = 3): FIRST, D2, LF, XF, LAST2.
+constexpr bool split_mode(int mode) {
+    return mode == PASS_FIRST || mode == PASS_D2 || mode == PASS_LF || mode == PASS_XF || mode == PASS_LAST2;
+}
+
+// The pass on tile `bid` with one thread per field (SEQ = 3; 2 x T x LINES threads): the
+// same arithmetic as axis_body with both fields at once, each field in its own half of
+// the workgroup.
+template <int N, int MODE, bool CONTIG, int LINES, bool NOISE, int RR, bool P64>
+__device__ __forceinline__ void axis_body_split(const GroupDev& g, int axis, const PassArgs& args, uint32_t bid,
+                                                uint32_t nblk,
+                                                typename AxisLds<N, MODE, CONTIG, LINES, 3, RR, P64>::V* smem) {
+    static_assert(split_mode(MODE), "a forward pass with two fields");
+    using F = FFTShape<N, RR>;
+    using V = typename std::conditional<P64, c64, c32>::type;
+    constexpr int R = F::R, T = F::T;
+    using L = LdsLayout<N, LINES, CONTIG, R>;
+    using A = AxisLds<N, MODE, CONTIG, LINES, 3, RR, P64>;
+    V* tw = smem + A::BUF;
+    V* E = tw + N;
+    if constexpr (P64)
+        stage_tables<F>(tw, E, g.tw64[axis], g.E64[axis]);
+    else
+        stage_tables<F>(tw, E, g.tw[axis], g.E[axis]);
+    const int tid = (int)(threadIdx.x % (unsigned)(T * LINES));
+    const int q = (int)(threadIdx.x / (unsigned)(T * LINES));  // the field this thread carries
+    V* lds = smem + q * L::SIZE;                                // its exchange buffer
+    const V* partner = smem + (1 - q) * L::SIZE;                // the other field's
+    const int t = CONTIG ? tid % T : tid / LINES;
+    const int l = CONTIG ? tid / T : tid % LINES;
+    const Tile<F, CONTIG, LINES> tile(g, axis, l, t, bid, nblk);
+    const int64_t o = g.offset + tile.base;
+    float2* __restrict__ ps = args.psi ? args.psi + o : nullptr;
+    float2* __restrict__ pa = args.A ? args.A + o : nullptr;
+    float2* __restrict__ pb = args.B ? args.B + o : nullptr;
+    const int64_t step = read_step(args.step_off, args.step_base);
+    const uint32_t iid = g.id_base + (uint32_t)tile.inst;
+    const float* __restrict__ Vg = g.Vgrid ? g.Vgrid + tile.inst * g.M : nullptr;
+    float V_other = 0.0f;
+    {
+        int x, y, z;
+        unflatten(g, tile.j(0), x, y, z);
+        const int c[3] = {x, y, z};
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            if (a == axis || a >= g.ndim) continue;
+            const float xa = fmaf((float)c[a], g.dx[a], g.lo[a]);
+            V_other = fmaf(g.half_trap[a] * xa, xa, V_other);
+        }
+    }
+    const float ht_axis = g.half_trap[axis], lo_axis = g.lo[axis], dx_axis = g.dx[axis];
+    auto pot_at = [&](int m, int64_t st) {
+        const float xa = fmaf((float)(t + m * T), dx_axis, lo_axis);
+        float Vp = fmaf(ht_axis * xa, xa, V_other);
+        if (Vg) Vp += Vg[tile.j(m)];
+        if constexpr (NOISE) {
+            if (g.has_vnoise) Vp += vnoise(g, tile.j(m), iid, st);  // uniform
+        }
+        return Vp;
+    };
+    auto noise_at = [&](int m, int64_t st) {
+        if constexpr (!NOISE) {
+            return make_float2(0.f, 0.f);
+        } else {
+            const float2 zz = noise_z(g, tile.j(m), iid, st);
+            return make_float2(g.noise_c * zz.x, g.noise_c * zz.y);
+        }
+    };
+    const c32 zero = make_float2(0.f, 0.f);
+    // the other half's field at this thread's elements, after this half's transform (the
+    // buffers are free: the transforms' last exchanges are done)
+    auto swap_in = [&](const c32 (&mine)[R], c32 (&theirs)[R]) {
+#pragma unroll
+        for (int m = 0; m < R; m++) lds[L::addr(l, t + m * T)] = widen(mine[m], V{});
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < R; m++) theirs[m] = narrow(partner[L::addr(l, t + m * T)]);
+        __syncthreads();  // both halves have read before the next transform reuses the buffers
+    };
+
+    c32 f[1][R];
+    if constexpr (MODE == PASS_FIRST) {
+#pragma unroll
+        for (int m = 0; m < R; m++) {
+            const c32 psi = tile.active ? ld2(ps, tile.b8(m)) : zero;
+            f[0][m] = q ? hG(g, psi, pot_at(m, step), noise_at(m, step)) : psi;
+        }
+    } else {
+        const float2* src = q ? pb : pa;
+#pragma unroll
+        for (int m = 0; m < R; m++) f[0][m] = tile.active ? ld2(src, tile.b8(m)) : zero;
+    }
+    __syncthreads();  // tables staged
+    propagate<F, L, 1>(f, t, l, lds, tw, E, false);
+
+    if constexpr (MODE == PASS_LF || MODE == PASS_XF || MODE == PASS_LAST2) {
+        c32 other[R];
+        swap_in(f[0], other);
+#pragma unroll
+        for (int m = 0; m < R; m++) {
+            const c32 f0 = q ? other[m] : f[0][m], f1 = q ? f[0][m] : other[m];
+            if constexpr (MODE == PASS_LF) {
+                // RK4 stages at the midpoint picture: (a, k1) -> (u, acc)
+                const float Vp = pot_at(m, step);
+                const c32 nz = noise_at(m, step);
+                const c32 a = f0, k1 = f1;
+                const c32 k2 = hG(g, make_float2(fmaf(0.5f, k1.x, a.x), fmaf(0.5f, k1.y, a.y)), Vp, nz);
+                const c32 k3 = hG(g, make_float2(fmaf(0.5f, k2.x, a.x), fmaf(0.5f, k2.y, a.y)), Vp, nz);
+                const float sx = k1.x * (1.0f / 6.0f) + (k2.x + k3.x) * (1.0f / 3.0f);
+                const float sy = k1.y * (1.0f / 6.0f) + (k2.y + k3.y) * (1.0f / 3.0f);
+                f[0][m] = q ? make_float2(a.x + sx, a.y + sy) : cadd(a, k3);
+            } else if constexpr (MODE == PASS_XF) {
+                // end of step n-1: psi_n = D acc + hG(D u)/6, then (psi_n, h G(psi_n))
+                const c32 k4 = hG(g, f0, pot_at(m, step - 1), noise_at(m, step - 1));
+                const c32 psi_n = make_float2(fmaf(k4.x, 1.0f / 6.0f, f1.x), fmaf(k4.y, 1.0f / 6.0f, f1.y));
+                f[0][m] = q ? hG(g, psi_n, pot_at(m, step), noise_at(m, step)) : psi_n;
+            } else {
+                // LAST2: psi' = D acc + hG(D u)/6 (stored by the first half)
+                const c32 k4 = hG(g, f0, pot_at(m, step), noise_at(m, step));
+                f[0][m] = make_float2(fmaf(k4.x, 1.0f / 6.0f, f1.x), fmaf(k4.y, 1.0f / 6.0f, f1.y));
+            }
+        }
+        if constexpr (MODE != PASS_LAST2) propagate<F, L, 1>(f, t, l, lds, tw, E, false);
+    }
+
+    if (!tile.active) return;  // after the last barrier
+    if constexpr (MODE == PASS_LAST2) {
+        if (q) return;
+        float2* __restrict__ po = args.psi_out ? args.psi_out + o : ps;
+#pragma unroll
+        for (int m = 0; m < R; m++) st2(po, tile.b8(m), f[0][m]);
+    } else {
+        float2* dst = q ? pb : pa;
+#pragma unroll
+        for (int m = 0; m < R; m++) st2(dst, tile.b8(m), f[0][m]);
+    }
+}
+
+// Threads of a workgroup of the pass.
+template <int N, int LINES, int SEQ, int RR>
+constexpr int pass_threads() { return FFTShape<N, RR>::T * LINES * (SEQ == 3 ? 2 : 1); }
+
 // One group's pass: one workgroup per tile.
 template <int N, int MODE, bool CONTIG, int LINES, bool NOISE, int SEQ, int RR, bool P64, int OCC>
-__global__ void __launch_bounds__((FFTShape<N, RR>::T * LINES)) __attribute__((amdgpu_waves_per_eu(OCC)))
+__global__ void __launch_bounds__((pass_threads<N, LINES, SEQ, RR>())) __attribute__((amdgpu_waves_per_eu(OCC)))
 k_axis(GroupDev g, int axis, PassArgs args) {
     using A = AxisLds<N, MODE, CONTIG, LINES, SEQ, RR, P64>;
     __shared__ typename A::V smem[A::ENTRIES];
-    axis_body<N, MODE, CONTIG, LINES, NOISE, SEQ, RR, P64>(g, axis, args, blockIdx.x, gridDim.x, smem);
+    if constexpr (SEQ == 3) {
+        if constexpr (split_mode(MODE))
+            axis_body_split<N, MODE, CONTIG, LINES, NOISE, RR, P64>(g, axis, args, blockIdx.x, gridDim.x, smem);
+    } else {
+        axis_body<N, MODE, CONTIG, LINES, NOISE, SEQ, RR, P64>(g, axis, args, blockIdx.x, gridDim.x, smem);
+    }
 }
 
 // LDS of a strided tile of w columns and nf fields must fit the 160 KiB of a CU.
@@ -484,7 +636,7 @@ static hipError_t go_axis(const GroupDev& g, int axis, const PassArgs& a, hipStr
         blocks = (g.batch * (g.M >> g.log2n[0]) + LINES - 1) / LINES;
     else
         blocks = g.batch * (g.M >> g.log2n[axis]) / LINES;
-    const dim3 grid((unsigned)blocks), block(FFTShape<N, RR>::T * LINES);
+    const dim3 grid((unsigned)blocks), block(pass_threads<N, LINES, SEQ, RR>());
     if constexpr (uses_rhs(MODE)) {
         if (g.has_noise) {
             hipLaunchKernelGGL((k_axis<N, MODE, CONTIG, LINES, true, SEQ, RR, P64, OCC>), grid, block, 0, s, g, axis, a);
@@ -547,7 +699,19 @@ template <int N, int MODE>
 constexpr bool schedule_compiled(bool contig, int lines, int seq, int rr, bool p64, int occ = 1) {
     constexpr int NF = fields_of(MODE);
     const bool tuned = tuned_length(N) && tuned_mode(MODE);
-    if (seq < 0 || seq > 2) return false;
+    if (seq < 0 || seq > 3) return false;
+    if (seq == 3) {
+        // one thread per field: radix 8, no occupancy hint, at most 1024 threads
+        if (!split_mode(MODE) || !tuned || rr != 8 || occ != 1) return false;
+        const int T = N / 8;
+        if (T * lines * 2 > 1024) return false;
+        if (p64 ? !fits_lds64(N, lines, 2, contig) : (!contig && !fits_lds(N, lines, 2))) return false;
+        if (contig) {
+            const int dl = default_contig_lines(N);
+            return lines >= 1 && (lines == dl / 2 || lines == dl / 4 || (lines == dl / 8 && narrow_tile<N>(true, lines)));
+        }
+        return lines == 1 || lines == 2 || lines == 4 || lines == 8;
+    }
     if (tuned && narrow_tile<N>(contig, lines)) return occ == 1 && seq == 0 && rr == 8;
     if (occ != 1) {
         // the four-wave variant: FP32, radix 8, both fields at once, tuned lengths
@@ -593,6 +757,9 @@ static hipError_t go_axis_sched_rr(const GroupDev& g, int axis, const PassArgs& 
         if (a.occ == 4 && a.seq == 0) return go_axis<N, MODE, CONTIG, LINES, 0, RR, P64, 4>(g, axis, a, s);
     }
     if (a.occ != 0 && a.occ != 1) return hipErrorInvalidValue;
+    if constexpr (schedule_compiled<N, MODE>(CONTIG, LINES, 3, RR, P64)) {
+        if (a.seq == 3) return go_axis<N, MODE, CONTIG, LINES, 3, RR, P64>(g, axis, a, s);
+    }
     if constexpr (schedule_compiled<N, MODE>(CONTIG, LINES, 2, RR, P64)) {
         if (a.seq == 2) return go_axis<N, MODE, CONTIG, LINES, 2, RR, P64>(g, axis, a, s);
     }

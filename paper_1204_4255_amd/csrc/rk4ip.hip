@@ -68,8 +68,8 @@ int ilog2i(int64_t v) {
     return r;
 }
 
-// Tile schedule of one pass (see PassArgs): lines or columns per workgroup, joint or
-// sequential field transforms, values per thread in the transform.
+// Tile schedule of one pass (see PassArgs): lines or columns per workgroup, joint,
+// sequential or split field transforms, values per thread in the transform.
 struct Sched {
     int occ = 0;    // 4: the variant compiled for four waves per SIMD
     int lines = 0;
@@ -817,7 +817,7 @@ int autotune(rk4ip_plan_t plan) {
             const int cand_radix[] = {16, 8};
             for (int rr : cand_radix)
                 for (int lines : cand_lines)
-                    for (int sq = 0; sq < 3; sq++)
+                    for (int sq = 0; sq < 4; sq++)
                         for (int occ : {0, 4}) {
                         if (!rk4ip::axis_schedule_ok(N, mode, axis, n0, lines, sq, rr, plan->f64, occ ? occ : 1)) continue;
                         Sched cand;
@@ -1487,7 +1487,7 @@ int rk4ip_plan(const rk4ip_problem* probs, int nprob, void* workspace, size_t ws
                 const int lines = sc.lines ? sc.lines : rk4ip::axis_lines((int)p.n[a], a, (int)p.n[0]);
                 std::snprintf(name, sizeof(name), "%s%s:axis%d:n%lld:%s:lines%d:%s:r%d%s%s", mode_name(defs[k].mode),
                               defs[k].twice ? "x2" : "", a, (long long)p.n[a], a == 0 ? "contig" : "strided", lines,
-                              sc.seq == 2 ? "seq-deferred" : (sc.seq ? "seq" : "joint"), sc.radix ? sc.radix : 16,
+                              sc.seq == 3 ? "split" : (sc.seq == 2 ? "seq-deferred" : (sc.seq ? "seq" : "joint")), sc.radix ? sc.radix : 16,
                               sc.occ == 4 ? ":o4" : "", plan->f64 ? ":f64" : "");
                 names.push_back(name);
             }
