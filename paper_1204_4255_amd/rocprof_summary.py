@@ -197,7 +197,8 @@ def report(out: dict, tune: str = "") -> str:
         "",
         "Template arguments of `k_axis`: (length, pass kind, contiguous axis, lines or columns per",
         "workgroup, noise drawn, field order 0 joint / 1 one after the other / 2 the same with the",
-        "second load deferred, values per thread, FP64 transforms, minimum waves per SIMD). Pass",
+        "second load deferred / 3 one thread per field, values per thread, FP64 transforms, minimum",
+        "waves per SIMD). Pass",
         "kinds: 0 = D1 (once, or twice where two semi-implicit steps meet), 1 = D2, 2 = FIRST,",
         "4 = LAST2, 9 = LF, 10 = XF, 11 = SI.",
         "",
