@@ -1,5 +1,5 @@
-// kernels_adj.hip -- adjoint-step kernels (not in the paper): the per-axis passes U, AW,
-// AS, AF and the 1D whole-line adjoint step.
+// kernels_adj.hip -- adjoint-step kernels (not in the paper): the per-axis passes D2U,
+// XAW, AS, AF and the 1D whole-line adjoint step.
 #include "pass_common.h"
 
 namespace rk4ip {
@@ -110,10 +110,10 @@ __global__ void k_vbar_to_float(const double* __restrict__ v, float* __restrict_
 
 hipError_t launch_axis_adjoint(const GroupDev& g, int axis, int mode, const PassArgs& a, hipStream_t s) {
     switch (mode) {
-        case PASS_U: return go_axis_mode<PASS_U>(g, axis, a, s);
-        case PASS_AW: return go_axis_mode<PASS_AW>(g, axis, a, s);
         case PASS_AS: return go_axis_mode<PASS_AS>(g, axis, a, s);
         case PASS_AF: return go_axis_mode<PASS_AF>(g, axis, a, s);
+        case PASS_D2U: return go_axis_mode<PASS_D2U>(g, axis, a, s);
+        case PASS_XAW: return go_axis_mode<PASS_XAW>(g, axis, a, s);
         default: return hipErrorInvalidValue;
     }
 }

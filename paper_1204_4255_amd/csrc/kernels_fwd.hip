@@ -567,10 +567,10 @@ hipError_t launch_axis(const GroupDev& g, int axis, int mode, const PassArgs& a,
         case PASS_LF: return launch_axis_last(g, axis, mode, a, s);
         case PASS_SI: return launch_axis_si(g, axis, a, s);
         case PASS_XF: return launch_axis_xf(g, axis, a, s);
-        case PASS_U:
-        case PASS_AW:
         case PASS_AS:
-        case PASS_AF: return launch_axis_adjoint(g, axis, mode, a, s);
+        case PASS_AF:
+        case PASS_D2U:
+        case PASS_XAW: return launch_axis_adjoint(g, axis, mode, a, s);
         default: return hipErrorInvalidValue;
     }
 }

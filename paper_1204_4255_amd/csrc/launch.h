@@ -8,31 +8,31 @@ namespace rk4ip {
 struct GroupDev;
 
 // Kinds of axis pass (see pass_common.h for the data flow of each). FIRST, D2, LF, XF and
-// LAST2 make the forward step; U, AW, AS and AF are the extra passes of the adjoint step.
+// LAST2 make the forward step; D2U, XAW, AS and AF are the extra passes of the adjoint step.
 enum PassMode {
     PASS_D1 = 0,
     PASS_D2 = 1,
     PASS_FIRST = 2,
     PASS_LAST2 = 4,
-    PASS_U = 5,
-    PASS_AW = 6,
     PASS_AS = 7,
     PASS_AF = 8,
     PASS_LF = 9,   // last axis: D, the RK4 stage epilogue, D again
     PASS_XF = 10,  // axis 0: D, the end of one step, the start of the next, D again
-    PASS_SI = 11   // last axis, semi-implicit step: D, the midpoint iteration, D again
+    PASS_SI = 11,  // last axis, semi-implicit step: D, the midpoint iteration, D again
+    PASS_D2U = 12, // adjoint recompute, last axis: (A, B) -> D (a, k1), then u = a + k3 -> D u
+    PASS_XAW = 13  // adjoint, axis 0: w = D W', then D^T (lam, h J(w)^T lam / 6)
 };
 
 // Pointers of one pass; every field pointer addresses the concatenated field of all
 // groups (the kernel adds the group offset).
 struct PassArgs {
-    float2* psi;              // single field: D1 in/out, FIRST in, LAST2/AF/U out, AW in (lambda)
+    float2* psi;              // single field: D1 in/out, FIRST in, LAST2/AF/D2U out, XAW in (lambda)
     float2* psi_out;          // LAST2: write psi' here instead of psi (a step out of place), or null
     float2* A;                // field pair in/out
     float2* B;
-    const float2* aux0;       // extra pointwise inputs: U (a, k1), AW (w), AS (a, k1), AF (psi_n)
+    const float2* aux0;       // extra inputs: XAW (W before its axis-0 propagator), AS (a, k1), AF (psi_n)
     const float2* aux1;
-    double* vbar;             // FP64 potential-gradient accumulator (concatenated), AW/AS/AF
+    double* vbar;             // FP64 potential-gradient accumulator (concatenated), XAW/AS/AF
     int adj;                  // apply the transpose of D
     int lines;                // tile schedule: lines (contiguous axis) or columns (strided) per
                               // workgroup, 0 = default

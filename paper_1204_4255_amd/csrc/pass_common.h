@@ -196,12 +196,15 @@ __device__ __forceinline__ void unflatten(const GroupDev& g, int64_t j, int& x, 
     z = (int)(j >> (g.log2n[0] + g.log2n[1]));
 }
 
-constexpr int fields_of(int mode) { return (mode == PASS_D1 || mode == PASS_U || mode == PASS_SI) ? 1 : 2; }
+constexpr int fields_of(int mode) { return (mode == PASS_D1 || mode == PASS_SI) ? 1 : 2; }
+
+// The fused adjoint passes (own bodies below).
+constexpr bool adj_fused(int mode) { return mode == PASS_D2U || mode == PASS_XAW; }
 
 // passes whose pointwise work evaluates G (and so may draw noise)
 constexpr bool uses_rhs(int mode) {
-    return mode == PASS_FIRST || mode == PASS_LAST2 || mode == PASS_U || mode == PASS_AS ||
-           mode == PASS_LF || mode == PASS_XF || mode == PASS_SI;
+    return mode == PASS_FIRST || mode == PASS_LAST2 || mode == PASS_AS ||
+           mode == PASS_LF || mode == PASS_XF || mode == PASS_SI || mode == PASS_D2U;
 }
 
 // SEQ = 0: both fields go through the transform together (one exchange buffer each).
@@ -321,26 +324,6 @@ __device__ __forceinline__ void axis_body(const GroupDev& g, int axis, const Pas
 #pragma unroll
             for (int m = 0; m < R; m++) f[1][m] = hG(g, f[0][m], pot_at(m, step), noise_at(m, step));
         }
-    } else if constexpr (MODE == PASS_U) {
-        // u = a + k3 from (a, k1)
-#pragma unroll
-        for (int m = 0; m < R; m++) {
-            c32 a = tile.active ? ld2(x0, tile.b8(m)) : zero;
-            c32 k1 = tile.active ? ld2(x1, tile.b8(m)) : zero;
-            stages(a, k1, potential_at(m), noise_at(m, step));
-            f[0][m] = a;
-        }
-    } else if constexpr (MODE == PASS_AW) {
-        // adjoint of psi' = D acc + k4/6, k4 = h G(w): (lam, wbar = h J(w)^T lam/6)
-#pragma unroll
-        for (int m = 0; m < R; m++) {
-            const c32 lam = tile.active ? ld2(ps, tile.b8(m)) : zero;
-            const c32 w = tile.active ? ld2(x0, tile.b8(m)) : zero;
-            const c32 k4b = cscale(lam, 1.0f / 6.0f);
-            f[0][m] = lam;
-            f[1][m] = hJT(g, w, potential_at(m), k4b);
-            if (vb && tile.active) std_(vb, tile.b8(m), ldd(vb, tile.b8(m)) + (double)hImconj(g, k4b, w));
-        }
     } else {
 #pragma unroll
         for (int m = 0; m < R; m++) f[0][m] = tile.active ? ld2(pa, tile.b8(m)) : zero;
@@ -407,7 +390,7 @@ __device__ __forceinline__ void axis_body(const GroupDev& g, int axis, const Pas
     }
 
     if (!tile.active) return;  // after the last barrier
-    if constexpr (MODE == PASS_D1 || MODE == PASS_U || MODE == PASS_SI) {
+    if constexpr (MODE == PASS_D1 || MODE == PASS_SI) {
 #pragma unroll
         for (int m = 0; m < R; m++) st2(ps, tile.b8(m), f[0][m]);
     } else if constexpr (MODE == PASS_LAST2) {
@@ -448,7 +431,114 @@ __device__ __forceinline__ void axis_body(const GroupDev& g, int axis, const Pas
             if (vb) std_(vb, tile.b8(m), ldd(vb, tile.b8(m)) + (double)hImconj(g, g0b, pn));
             st2(ps, tile.b8(m), cadd(f[0][m], r));
         }
-    } else {  // FIRST, D2, AW, LF, XF
+    } else {  // FIRST, D2, LF, XF
+#pragma unroll
+        for (int m = 0; m < R; m++) {
+            st2(pa, tile.b8(m), f[0][m]);
+            st2(pb, tile.b8(m), f[1][m]);
+        }
+    }
+}
+
+// The fused passes of the adjoint step (default schedule: both fields at once).
+// D2U, last axis: (A, B) -> D_last (A, B) = (a, k1) once the other axes are done; stored;
+//   then u = a + k3 (the RK4 stages) and W' = D_last u, stored in psi.
+// XAW, axis 0, once W' has been through every other axis: w = D_0 W' (the stage-4 input
+//   D(a + k3)); then (A, B) = D_0^T (lam, h J(w)^T lam / 6), with V-bar += its term.
+template <int N, int MODE, bool CONTIG, int LINES, bool NOISE, int RR>
+__device__ __forceinline__ void axis_body_adjf(const GroupDev& g, int axis, const PassArgs& args, uint32_t bid,
+                                               uint32_t nblk, c32* smem) {
+    static_assert(adj_fused(MODE), "a fused adjoint pass");
+    using F = FFTShape<N, RR>;
+    constexpr int R = F::R, T = F::T;
+    using L = LdsLayout<N, LINES, CONTIG, R>;
+    using A = AxisLds<N, MODE, CONTIG, LINES, 0, RR, false>;
+    c32* lds = smem;
+    c32* tw = smem + A::BUF;
+    c32* E = tw + N;
+    stage_tables<F>(tw, E, g.tw[axis], g.E[axis]);
+    const int t = CONTIG ? (int)(threadIdx.x % T) : (int)(threadIdx.x / LINES);
+    const int l = CONTIG ? (int)(threadIdx.x / T) : (int)(threadIdx.x % LINES);
+    const Tile<F, CONTIG, LINES> tile(g, axis, l, t, bid, nblk);
+    const int64_t o = g.offset + tile.base;
+    float2* __restrict__ ps = args.psi ? args.psi + o : nullptr;
+    float2* __restrict__ pa = args.A ? args.A + o : nullptr;
+    float2* __restrict__ pb = args.B ? args.B + o : nullptr;
+    const float2* __restrict__ x0 = args.aux0 ? args.aux0 + o : nullptr;
+    double* __restrict__ vb = args.vbar ? args.vbar + o : nullptr;
+    const int64_t step = MODE == PASS_D2U ? read_step(args.step_off, args.step_base) : 0;
+    const uint32_t iid = g.id_base + (uint32_t)tile.inst;
+    const float* __restrict__ Vg = g.Vgrid ? g.Vgrid + tile.inst * g.M : nullptr;
+    float V_other = 0.0f;
+    {
+        int x, y, z;
+        unflatten(g, tile.j(0), x, y, z);
+        const int c[3] = {x, y, z};
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            if (a == axis || a >= g.ndim) continue;
+            const float xa = fmaf((float)c[a], g.dx[a], g.lo[a]);
+            V_other = fmaf(g.half_trap[a] * xa, xa, V_other);
+        }
+    }
+    const float ht_axis = g.half_trap[axis], lo_axis = g.lo[axis], dx_axis = g.dx[axis];
+    auto potential_at = [&](int m) {
+        const float xa = fmaf((float)(t + m * T), dx_axis, lo_axis);
+        float Vp = fmaf(ht_axis * xa, xa, V_other);
+        if (Vg) Vp += Vg[tile.j(m)];
+        return Vp;
+    };
+    const c32 zero = make_float2(0.f, 0.f);
+    c32 f[2][R];
+    if constexpr (MODE == PASS_D2U) {
+#pragma unroll
+        for (int m = 0; m < R; m++) {
+            f[0][m] = tile.active ? ld2(pa, tile.b8(m)) : zero;
+            f[1][m] = tile.active ? ld2(pb, tile.b8(m)) : zero;
+        }
+        __syncthreads();  // tables staged
+        propagate<F, L, 2>(f, t, l, lds, tw, E, false);
+        c32(&u)[1][R] = *reinterpret_cast<c32(*)[1][R]>(&f[0]);
+#pragma unroll
+        for (int m = 0; m < R; m++) {
+            if (tile.active) {
+                st2(pa, tile.b8(m), f[0][m]);
+                st2(pb, tile.b8(m), f[1][m]);
+            }
+            // u = a + k3 (the same arithmetic as the forward stages)
+            c32 nz = zero;
+            if constexpr (NOISE) {
+                const float2 zz = noise_z(g, tile.j(m), iid, step);
+                nz = make_float2(g.noise_c * zz.x, g.noise_c * zz.y);
+            }
+            const float Vp = potential_at(m);
+            const c32 a = f[0][m], k1 = f[1][m];
+            const c32 k2 = hG(g, make_float2(fmaf(0.5f, k1.x, a.x), fmaf(0.5f, k1.y, a.y)), Vp, nz);
+            const c32 k3 = hG(g, make_float2(fmaf(0.5f, k2.x, a.x), fmaf(0.5f, k2.y, a.y)), Vp, nz);
+            u[0][m] = cadd(a, k3);
+        }
+        propagate<F, L, 1>(u, t, l, lds, tw, E, false);
+        if (!tile.active) return;  // after the last barrier
+#pragma unroll
+        for (int m = 0; m < R; m++) st2(ps, tile.b8(m), u[0][m]);
+    } else {
+        c32(&w)[1][R] = *reinterpret_cast<c32(*)[1][R]>(&f[1]);
+#pragma unroll
+        for (int m = 0; m < R; m++) w[0][m] = tile.active ? ld2(x0, tile.b8(m)) : zero;
+        __syncthreads();  // tables staged
+        propagate<F, L, 1>(w, t, l, lds, tw, E, false);
+        // adjoint of psi' = D acc + k4/6, k4 = h G(w): (lam, wbar = h J(w)^T lam/6)
+#pragma unroll
+        for (int m = 0; m < R; m++) {
+            const c32 lam = tile.active ? ld2(ps, tile.b8(m)) : zero;
+            const c32 k4b = cscale(lam, 1.0f / 6.0f);
+            const c32 wm = w[0][m];
+            f[0][m] = lam;
+            f[1][m] = hJT(g, wm, potential_at(m), k4b);
+            if (vb && tile.active) std_(vb, tile.b8(m), ldd(vb, tile.b8(m)) + (double)hImconj(g, k4b, wm));
+        }
+        propagate<F, L, 2>(f, t, l, lds, tw, E, true);
+        if (!tile.active) return;  // after the last barrier
 #pragma unroll
         for (int m = 0; m < R; m++) {
             st2(pa, tile.b8(m), f[0][m]);
@@ -608,6 +698,9 @@ k_axis(GroupDev g, int axis, PassArgs args) {
     if constexpr (SEQ == 3) {
         if constexpr (split_mode(MODE))
             axis_body_split<N, MODE, CONTIG, LINES, NOISE, RR, P64>(g, axis, args, blockIdx.x, gridDim.x, smem);
+    } else if constexpr (adj_fused(MODE)) {
+        if constexpr (!P64 && SEQ == 0)
+            axis_body_adjf<N, MODE, CONTIG, LINES, NOISE, RR>(g, axis, args, blockIdx.x, gridDim.x, smem);
     } else {
         axis_body<N, MODE, CONTIG, LINES, NOISE, SEQ, RR, P64>(g, axis, args, blockIdx.x, gridDim.x, smem);
     }
@@ -649,10 +742,10 @@ static hipError_t go_axis(const GroupDev& g, int axis, const PassArgs& a, hipStr
 
 // passes that run only on axis 0 / only on the last (strided) axis
 constexpr bool contig_only(int mode) {
-    return mode == PASS_FIRST || mode == PASS_U || mode == PASS_AW || mode == PASS_XF || mode == PASS_LAST2;
+    return mode == PASS_FIRST || mode == PASS_XF || mode == PASS_LAST2 || mode == PASS_XAW;
 }
 constexpr bool strided_only(int mode) {
-    return mode == PASS_AS || mode == PASS_AF || mode == PASS_LF || mode == PASS_SI;
+    return mode == PASS_AS || mode == PASS_AF || mode == PASS_LF || mode == PASS_SI || mode == PASS_D2U;
 }
 // lengths with more than the default schedule compiled (the ones the workloads use)
 constexpr bool tuned_length(int N) { return N >= 128 && N <= 512; }

@@ -1252,22 +1252,23 @@ int enqueue_adjoint_step(rk4ip_plan_t plan, hipStream_t st, const float2* pn, fl
         rk4ip::PassArgs pa{};
         pa.step_off = step_off;
         pa.step_base = step_base;
-        // forward: (A, B) = D (psi_n, hG(psi_n)) = (a, k1)
+        // forward: (A, B) = D (psi_n, hG(psi_n)) = (a, k1); the last axis's pass also forms
+        // u = a + k3 and W = D_last u
         pa.psi = const_cast<float2*>(pn);
         pa.A = plan->A;
         pa.B = plan->B;
         HIPCHK(plan, rk4ip::launch_axis(g.d, 0, rk4ip::PASS_FIRST, pa, st));
-        for (int a = 1; a <= last; a++) HIPCHK(plan, rk4ip::launch_axis(g.d, a, rk4ip::PASS_D2, pa, st));
-        // forward: W = D (a + k3)
+        for (int a = 1; a < last; a++) HIPCHK(plan, rk4ip::launch_axis(g.d, a, rk4ip::PASS_D2, pa, st));
+        rk4ip::PassArgs pd = pa;
+        pd.psi = W;
+        HIPCHK(plan, rk4ip::launch_axis_adjoint(g.d, last, rk4ip::PASS_D2U, pd, st));
+        // forward: W = D (a + k3) on the middle axes; axis 0 is applied in the next pass
         rk4ip::PassArgs pu{};
         pu.step_off = step_off;
         pu.step_base = step_base;
         pu.psi = W;
-        pu.aux0 = plan->A;
-        pu.aux1 = plan->B;
-        HIPCHK(plan, rk4ip::launch_axis(g.d, 0, rk4ip::PASS_U, pu, st));
-        for (int a = 1; a <= last; a++) HIPCHK(plan, rk4ip::launch_axis(g.d, a, rk4ip::PASS_D1, pu, st));
-        // adjoint: (X, Y) = D^T (lam, h J(w)^T lam/6), then the stage transposes
+        for (int a = last - 1; a >= 1; a--) HIPCHK(plan, rk4ip::launch_axis(g.d, a, rk4ip::PASS_D1, pu, st));
+        // adjoint: w = D_0 W, (X, Y) = D^T (lam, h J(w)^T lam/6), then the stage transposes
         rk4ip::PassArgs pw{};
         pw.step_off = step_off;
         pw.step_base = step_base;
@@ -1277,7 +1278,7 @@ int enqueue_adjoint_step(rk4ip_plan_t plan, hipStream_t st, const float2* pn, fl
         pw.A = X;
         pw.B = Y;
         pw.vbar = vbar;
-        HIPCHK(plan, rk4ip::launch_axis(g.d, 0, rk4ip::PASS_AW, pw, st));
+        HIPCHK(plan, rk4ip::launch_axis_adjoint(g.d, 0, rk4ip::PASS_XAW, pw, st));
         for (int a = 1; a < last; a++) HIPCHK(plan, rk4ip::launch_axis(g.d, a, rk4ip::PASS_D2, pw, st));
         pw.aux0 = plan->A;
         pw.aux1 = plan->B;
