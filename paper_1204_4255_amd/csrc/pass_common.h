@@ -358,6 +358,32 @@ __device__ __forceinline__ void axis_body(const GroupDev& g, int axis, const Pas
         if (args.twice) transform(false);  // uniform over the grid
     }
 
+    if constexpr (MODE == PASS_AS) {
+        // transposes of the stage combinations: (accbar, ubar) -> (abar, k1bar), then the
+        // transposed propagator of this axis on both (the pass runs on the last axis, whose
+        // share of D^T (abar, k1bar) is applied here rather than in a pass of its own)
+#pragma unroll
+        for (int m = 0; m < R; m++) {
+            const float V = potential_at(m);
+            const c32 nz = noise_at(m, step);
+            const c32 a = ld2(x0, tile.b8(m)), k1 = ld2(x1, tile.b8(m));
+            const c32 p2 = make_float2(fmaf(0.5f, k1.x, a.x), fmaf(0.5f, k1.y, a.y));
+            const c32 k2 = hG(g, p2, V, nz);
+            const c32 p3 = make_float2(fmaf(0.5f, k2.x, a.x), fmaf(0.5f, k2.y, a.y));
+            const c32 accb = f[0][m], ub = f[1][m];
+            const c32 k3b = make_float2(fmaf(accb.x, 1.0f / 3.0f, ub.x), fmaf(accb.y, 1.0f / 3.0f, ub.y));
+            const c32 p3b = hJT(g, p3, V, k3b);
+            const c32 k2b = make_float2(fmaf(accb.x, 1.0f / 3.0f, 0.5f * p3b.x), fmaf(accb.y, 1.0f / 3.0f, 0.5f * p3b.y));
+            const c32 p2b = hJT(g, p2, V, k2b);
+            const c32 k1b = make_float2(fmaf(accb.x, 1.0f / 6.0f, 0.5f * p2b.x), fmaf(accb.y, 1.0f / 6.0f, 0.5f * p2b.y));
+            const c32 ab = make_float2(accb.x + ub.x + p3b.x + p2b.x, accb.y + ub.y + p3b.y + p2b.y);
+            if (vb) std_(vb, tile.b8(m), ldd(vb, tile.b8(m)) + (double)hImconj(g, k3b, p3) + (double)hImconj(g, k2b, p2));
+            f[0][m] = ab;
+            f[1][m] = k1b;
+        }
+        transform(false);
+    }
+
     if constexpr (MODE == PASS_LF || MODE == PASS_XF || MODE == PASS_SI) {
         // the work between the two transforms of a fused pass (every thread takes part in
         // the second transform's barriers, active or not)
@@ -400,29 +426,8 @@ __device__ __forceinline__ void axis_body(const GroupDev& g, int axis, const Pas
             const c32 k4 = hG(g, f[0][m], pot_at(m, step), noise_at(m, step));
             st2(po, tile.b8(m), make_float2(fmaf(k4.x, 1.0f / 6.0f, f[1][m].x), fmaf(k4.y, 1.0f / 6.0f, f[1][m].y)));
         }
-    } else if constexpr (MODE == PASS_AS) {
-        // transposes of the stage combinations: (accbar, ubar) -> (abar, k1bar)
-#pragma unroll
-        for (int m = 0; m < R; m++) {
-            const float V = potential_at(m);
-            const c32 nz = noise_at(m, step);
-            const c32 a = ld2(x0, tile.b8(m)), k1 = ld2(x1, tile.b8(m));
-            const c32 p2 = make_float2(fmaf(0.5f, k1.x, a.x), fmaf(0.5f, k1.y, a.y));
-            const c32 k2 = hG(g, p2, V, nz);
-            const c32 p3 = make_float2(fmaf(0.5f, k2.x, a.x), fmaf(0.5f, k2.y, a.y));
-            const c32 accb = f[0][m], ub = f[1][m];
-            const c32 k3b = make_float2(fmaf(accb.x, 1.0f / 3.0f, ub.x), fmaf(accb.y, 1.0f / 3.0f, ub.y));
-            const c32 p3b = hJT(g, p3, V, k3b);
-            const c32 k2b = make_float2(fmaf(accb.x, 1.0f / 3.0f, 0.5f * p3b.x), fmaf(accb.y, 1.0f / 3.0f, 0.5f * p3b.y));
-            const c32 p2b = hJT(g, p2, V, k2b);
-            const c32 k1b = make_float2(fmaf(accb.x, 1.0f / 6.0f, 0.5f * p2b.x), fmaf(accb.y, 1.0f / 6.0f, 0.5f * p2b.y));
-            const c32 ab = make_float2(accb.x + ub.x + p3b.x + p2b.x, accb.y + ub.y + p3b.y + p2b.y);
-            if (vb) std_(vb, tile.b8(m), ldd(vb, tile.b8(m)) + (double)hImconj(g, k3b, p3) + (double)hImconj(g, k2b, p2));
-            st2(pa, tile.b8(m), ab);
-            st2(pb, tile.b8(m), k1b);
-        }
     } else if constexpr (MODE == PASS_AF) {
-        // psibar = D^T abar + h J(psi_n)^T (D^T k1bar)
+        // psibar = D^T abar + h J(psi_n)^T (D^T k1bar) (axis 0, after every other axis)
 #pragma unroll
         for (int m = 0; m < R; m++) {
             const c32 pn = ld2(x0, tile.b8(m));
@@ -431,7 +436,7 @@ __device__ __forceinline__ void axis_body(const GroupDev& g, int axis, const Pas
             if (vb) std_(vb, tile.b8(m), ldd(vb, tile.b8(m)) + (double)hImconj(g, g0b, pn));
             st2(ps, tile.b8(m), cadd(f[0][m], r));
         }
-    } else {  // FIRST, D2, LF, XF
+    } else {  // FIRST, D2, LF, XF, AS
 #pragma unroll
         for (int m = 0; m < R; m++) {
             st2(pa, tile.b8(m), f[0][m]);
@@ -742,10 +747,10 @@ static hipError_t go_axis(const GroupDev& g, int axis, const PassArgs& a, hipStr
 
 // passes that run only on axis 0 / only on the last (strided) axis
 constexpr bool contig_only(int mode) {
-    return mode == PASS_FIRST || mode == PASS_XF || mode == PASS_LAST2 || mode == PASS_XAW;
+    return mode == PASS_FIRST || mode == PASS_XF || mode == PASS_LAST2 || mode == PASS_XAW || mode == PASS_AF;
 }
 constexpr bool strided_only(int mode) {
-    return mode == PASS_AS || mode == PASS_AF || mode == PASS_LF || mode == PASS_SI || mode == PASS_D2U;
+    return mode == PASS_AS || mode == PASS_LF || mode == PASS_SI || mode == PASS_D2U;
 }
 // lengths with more than the default schedule compiled (the ones the workloads use)
 constexpr bool tuned_length(int N) { return N >= 128 && N <= 512; }

@@ -1283,7 +1283,8 @@ int enqueue_adjoint_step(rk4ip_plan_t plan, hipStream_t st, const float2* pn, fl
         pw.aux0 = plan->A;
         pw.aux1 = plan->B;
         HIPCHK(plan, rk4ip::launch_axis(g.d, last, rk4ip::PASS_AS, pw, st));
-        // adjoint: lam = D^T abar + h J(psi_n)^T D^T k1bar
+        // adjoint: lam = D^T abar + h J(psi_n)^T D^T k1bar (AS applied the last axis's
+        // share, AF applies axis 0's)
         rk4ip::PassArgs pf{};
         pf.step_off = step_off;
         pf.step_base = step_base;
@@ -1293,8 +1294,8 @@ int enqueue_adjoint_step(rk4ip_plan_t plan, hipStream_t st, const float2* pn, fl
         pf.psi = lam;
         pf.aux0 = pn;
         pf.vbar = vbar;
-        for (int a = 0; a < last; a++) HIPCHK(plan, rk4ip::launch_axis(g.d, a, rk4ip::PASS_D2, pf, st));
-        HIPCHK(plan, rk4ip::launch_axis(g.d, last, rk4ip::PASS_AF, pf, st));
+        for (int a = 1; a < last; a++) HIPCHK(plan, rk4ip::launch_axis(g.d, a, rk4ip::PASS_D2, pf, st));
+        HIPCHK(plan, rk4ip::launch_axis(g.d, 0, rk4ip::PASS_AF, pf, st));
     }
     return RK4IP_OK;
 }
