@@ -28,15 +28,15 @@ def torch():
     return t
 
 
-def _forced(probs, g, seq, f64, flags, path):
+def _forced(probs, g, seq, f64, flags, path, slines=4):
     """A plan whose passes all take radix 8 with `seq` (0 joint, 3 split): half the default
-    lines on the contiguous axis, 4 columns on the strided ones (compiled for both)."""
+    lines on the contiguous axis, `slines` columns on the strided ones."""
     n3 = tuple(g.n) + (1,) * (3 - len(g.n))
     base = f"gfx950|n={n3[0]},{n3[1]},{n3[2]}|b={g.batch}"
     cache = {}
     for i, ax in enumerate(PASS_AXES[len(g.n)]):
         N = g.n[ax]
-        lines = (4096 // N) // 2 if ax == 0 else 4
+        lines = (4096 // N) // 2 if ax == 0 else slines
         cache[f"{base}|pass={i}{'|f64' if f64 else ''}"] = [lines, seq, 8, 0]
     with open(path, "w") as fh:
         json.dump(cache, fh)
@@ -56,6 +56,22 @@ def _forced(probs, g, seq, f64, flags, path):
 @pytest.mark.parametrize("f64", [False, True])
 def test_split_schedule_equals_joint_and_oracle(torch, tmp_path, n, batch, f64):
     log(f"split schedule: n={n} batch={batch} f64={f64}")
+    _compare(torch, tmp_path, n, batch, f64, [(0, 4), (3, 4)])
+
+
+@pytest.mark.parametrize("n,batch", [((128, 256), 2), ((128, 256, 256), 1)])
+@pytest.mark.parametrize("f64", [False, True])
+def test_narrow_strided_tiles_equal_wide_and_oracle(torch, tmp_path, n, batch, f64):
+    """Strided tiles of two columns (the narrow schedules of lattices with few lines) must
+    equal four-column tiles bitwise, with both fields at once and split."""
+    log(f"narrow strided tiles: n={n} batch={batch} f64={f64}")
+    _compare(torch, tmp_path, n, batch, f64, [(0, 4), (0, 2), (3, 2)])
+
+
+def _compare(torch, tmp_path, n, batch, f64, schedules):
+    """Runs of one noisy problem (potential grid, noise in the potential) under each forced
+    (field order, strided columns) schedule: bitwise equal, one of them graph-replayed, and
+    within 2e-6 of the oracle."""
     nd = len(n)
     g = W.Group(n=n, lo=(-6.0,) * nd, hi=(6.0,) * nd, batch=batch, gnl=3.0, trap=(1.0, 1.3, 0.7), gamma=0.02,
                 sigma=0.01, seed=41, id_base=2)
@@ -72,20 +88,25 @@ def test_split_schedule_equals_joint_and_oracle(torch, tmp_path, n, batch, f64):
                         trap=g.trap, Vgrid=Vg.astype(np.float64), sigma=g.sigma, seed=g.seed, id_base=g.id_base,
                         sigma_V=sv)
     flags = rk4ip.RK4IP_FLAG_FP64_TRANSFORMS if f64 else 0
-    joint = _forced([p], g, 0, f64, flags, tmp_path / "joint.json")
-    split = _forced([p], g, 3, f64, flags, tmp_path / "split.json")
-    splitg = _forced([p], g, 3, f64, flags | rk4ip.RK4IP_FLAG_GRAPH, tmp_path / "split.json")
-    assert all(":split:" in split.schedule(0, i) for i in range(split.num_passes(0)))
-    assert all(":joint:" in joint.schedule(0, i) for i in range(joint.num_passes(0)))
+    plans = []
+    for k, (seq, sl) in enumerate(schedules):
+        plans.append(_forced([p], g, seq, f64, flags, tmp_path / f"s{k}.json", sl))
+        want = ":split:" if seq == 3 else ":joint:"
+        assert all(want in plans[-1].schedule(0, i) for i in range(plans[-1].num_passes(0)))
+        strided = [plans[-1].schedule(0, i) for i in range(plans[-1].num_passes(0)) if ":strided:" in
+                   plans[-1].schedule(0, i)]
+        assert all(f":lines{sl}:" in x for x in strided), strided
+    seq, sl = schedules[-1]
+    plans.append(_forced([p], g, seq, f64, flags | rk4ip.RK4IP_FLAG_GRAPH, tmp_path / "g.json", sl))
     nsteps = 6
     fields = []
-    for plan in (joint, split, splitg):
+    for plan in plans:
         d = torch.tensor(f0.astype(np.complex64).reshape(-1), device="cuda")
         plan.run(d, nsteps, step0=5)
         fields.append(d)
     torch.cuda.synchronize()
-    assert torch.equal(fields[0], fields[1]) and torch.equal(fields[1], fields[2])
+    assert all(torch.equal(fields[0], x) for x in fields[1:])
     ref, _, _ = oracle.run(op, f0, nsteps, step0=5)
-    err = rel(fields[1].cpu().numpy().astype(np.complex128).reshape(g.shape), ref)
-    log(f"  {nsteps} steps: split == joint bitwise, rel L2 vs oracle {err:.2e}")
+    err = rel(fields[-1].cpu().numpy().astype(np.complex128).reshape(g.shape), ref)
+    log(f"  {nsteps} steps: schedules {schedules} bitwise equal, rel L2 vs oracle {err:.2e}")
     assert err < 2e-6
