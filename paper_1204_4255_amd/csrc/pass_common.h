@@ -799,9 +799,11 @@ constexpr bool schedule_compiled(bool contig, int lines, int seq, int rr, bool p
     const bool tuned = tuned_length(N) && tuned_mode(MODE);
     if (seq < 0 || seq > 3) return false;
     if (seq == 3) {
-        // one thread per field: radix 8, no occupancy hint, at most 1024 threads
-        if (!split_mode(MODE) || !tuned || rr != 8 || occ != 1) return false;
-        const int T = N / 8;
+        // one thread per field: radix 8 (LF and XF in FP32 also radix 16: with one field
+        // per thread it fits four waves per SIMD), no occupancy hint, at most 1024 threads
+        const bool r16 = rr == 16 && !p64 && (MODE == PASS_LF || MODE == PASS_XF);
+        if (!split_mode(MODE) || !tuned || (rr != 8 && !r16) || occ != 1) return false;
+        const int T = N / rr;
         if (T * lines * 2 > 1024) return false;
         if (p64 ? !fits_lds64(N, lines, 2, contig) : (!contig && !fits_lds(N, lines, 2))) return false;
         if (contig) {

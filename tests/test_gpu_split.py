@@ -17,6 +17,8 @@ pytestmark = pytest.mark.gpu
 
 # axis of each pass: FIRST, LF, XF, LAST2 (2D); FIRST, D2, LF, D2, XF, LAST2 (3D)
 PASS_AXES = {2: [0, 1, 0, 0], 3: [0, 1, 2, 1, 0, 0]}
+# the LF and XF passes (split also at radix 16)
+PASS_LFXF = {2: [1, 2], 3: [2, 4]}
 
 
 @pytest.fixture(scope="module")
@@ -28,16 +30,18 @@ def torch():
     return t
 
 
-def _forced(probs, g, seq, f64, flags, path, slines=4):
-    """A plan whose passes all take radix 8 with `seq` (0 joint, 3 split): half the default
-    lines on the contiguous axis, `slines` columns on the strided ones."""
+def _forced(probs, g, seq, f64, flags, path, slines=4, rr=8):
+    """A plan whose passes all take radix `rr` with `seq` (0 joint, 3 split): half the
+    default lines on the contiguous axis, `slines` columns on the strided ones. At radix 16
+    only LF and XF take the split schedule (the others stay joint)."""
     n3 = tuple(g.n) + (1,) * (3 - len(g.n))
     base = f"gfx950|n={n3[0]},{n3[1]},{n3[2]}|b={g.batch}"
     cache = {}
     for i, ax in enumerate(PASS_AXES[len(g.n)]):
         N = g.n[ax]
         lines = (4096 // N) // 2 if ax == 0 else slines
-        cache[f"{base}|pass={i}{'|f64' if f64 else ''}"] = [lines, seq, 8, 0]
+        sq = seq if (rr == 8 or i in PASS_LFXF[len(g.n)]) else 0
+        cache[f"{base}|pass={i}{'|f64' if f64 else ''}"] = [lines, sq, rr, 0]
     with open(path, "w") as fh:
         json.dump(cache, fh)
     old = os.environ.get("RK4IP_TUNE_CACHE")
@@ -68,7 +72,14 @@ def test_narrow_strided_tiles_equal_wide_and_oracle(torch, tmp_path, n, batch, f
     _compare(torch, tmp_path, n, batch, f64, [(0, 4), (0, 2), (3, 2)])
 
 
-def _compare(torch, tmp_path, n, batch, f64, schedules):
+@pytest.mark.parametrize("n,batch", [((256, 128), 2), ((128, 256, 256), 1)])
+def test_radix16_split_equals_joint_and_oracle(torch, tmp_path, n, batch):
+    """LF and XF split at radix 16 (complex64 only) equal the joint radix-16 schedule."""
+    log(f"radix-16 split: n={n} batch={batch}")
+    _compare(torch, tmp_path, n, batch, False, [(0, 4), (3, 4)], rr=16)
+
+
+def _compare(torch, tmp_path, n, batch, f64, schedules, rr=8):
     """Runs of one noisy problem (potential grid, noise in the potential) under each forced
     (field order, strided columns) schedule: bitwise equal, one of them graph-replayed, and
     within 2e-6 of the oracle."""
@@ -90,14 +101,16 @@ def _compare(torch, tmp_path, n, batch, f64, schedules):
     flags = rk4ip.RK4IP_FLAG_FP64_TRANSFORMS if f64 else 0
     plans = []
     for k, (seq, sl) in enumerate(schedules):
-        plans.append(_forced([p], g, seq, f64, flags, tmp_path / f"s{k}.json", sl))
-        want = ":split:" if seq == 3 else ":joint:"
-        assert all(want in plans[-1].schedule(0, i) for i in range(plans[-1].num_passes(0)))
+        plans.append(_forced([p], g, seq, f64, flags, tmp_path / f"s{k}.json", sl, rr))
+        for i in range(plans[-1].num_passes(0)):
+            sq = seq if (rr == 8 or i in PASS_LFXF[nd]) else 0
+            assert (":split:" if sq == 3 else ":joint:") in plans[-1].schedule(0, i)
+            assert f":r{rr}" in plans[-1].schedule(0, i)
         strided = [plans[-1].schedule(0, i) for i in range(plans[-1].num_passes(0)) if ":strided:" in
                    plans[-1].schedule(0, i)]
         assert all(f":lines{sl}:" in x for x in strided), strided
     seq, sl = schedules[-1]
-    plans.append(_forced([p], g, seq, f64, flags | rk4ip.RK4IP_FLAG_GRAPH, tmp_path / "g.json", sl))
+    plans.append(_forced([p], g, seq, f64, flags | rk4ip.RK4IP_FLAG_GRAPH, tmp_path / "g.json", sl, rr))
     nsteps = 6
     fields = []
     for plan in plans:
