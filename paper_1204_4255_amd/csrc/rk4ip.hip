@@ -333,11 +333,11 @@ struct rk4ip_plan_s {
     std::string err;
     std::vector<std::vector<std::string>> sched_names;  // [group][pass]
     std::vector<std::vector<Sched>> sched;  // [group][pass]; zeros = default schedule
-    // cached graph of `graph_steps` steps on `graph_psi`
-    hipGraphExec_t graph = nullptr;
-    hipGraph_t graph_src = nullptr;
+    // cached graphs of 1, 2, 4, ..., 32 steady-state steps on `graph_psi` (recorded when a
+    // run first needs them)
+    hipGraphExec_t graph[6] = {};
+    hipGraph_t graph_src[6] = {};
     void* graph_psi = nullptr;
-    int graph_steps = 0;
     hipStream_t capture_stream = nullptr;  // private stream the graph is recorded on
     // graphs of one adjoint segment (recompute, backward walk) for the buffers they were
     // recorded on
@@ -378,13 +378,18 @@ int fail_hip(rk4ip_plan_t plan, hipError_t e, const char* what) {
         if (e_ != hipSuccess) return fail_hip((plan), e_, #expr);    \
     } while (0)
 
-void drop_graph(rk4ip_plan_t plan) {
-    if (plan->graph) (void)hipGraphExecDestroy(plan->graph);
-    if (plan->graph_src) (void)hipGraphDestroy(plan->graph_src);
-    plan->graph = nullptr;
-    plan->graph_src = nullptr;
+void drop_step_graphs(rk4ip_plan_t plan) {
+    for (int i = 0; i < 6; i++) {
+        if (plan->graph[i]) (void)hipGraphExecDestroy(plan->graph[i]);
+        if (plan->graph_src[i]) (void)hipGraphDestroy(plan->graph_src[i]);
+        plan->graph[i] = nullptr;
+        plan->graph_src[i] = nullptr;
+    }
     plan->graph_psi = nullptr;
-    plan->graph_steps = 0;
+}
+
+void drop_graph(rk4ip_plan_t plan) {
+    drop_step_graphs(plan);
     if (plan->adj_fwd) (void)hipGraphExecDestroy(plan->adj_fwd);
     if (plan->adj_bwd) (void)hipGraphExecDestroy(plan->adj_bwd);
     plan->adj_fwd = plan->adj_bwd = nullptr;
@@ -1022,15 +1027,18 @@ int do_diagnostics(rk4ip_plan_t plan, const float2* psi, double* out) {
     return RK4IP_OK;
 }
 
-// Steps per replayed graph.
-constexpr int kGraphSteps = 32;
+// Replayed graphs hold 2^level steady-state steps, level < kGraphLevels (at most 32).
+constexpr int kGraphLevels = 6;
 
-// Build (or reuse) a graph of `gsteps` steady-state steps whose step index s is read from
-// the device counter: the 1D groups' steps s ... s + gsteps - 1 and the 2D/3D groups'
-// units (MID of step s + u, NEXT into s + u + 1), followed by counter += gsteps.
-int ensure_graph(rk4ip_plan_t plan, float2* psi, int gsteps) {
-    if (plan->graph && plan->graph_psi == psi && plan->graph_steps == gsteps) return RK4IP_OK;
-    drop_graph(plan);
+// Build (or reuse) the graph of gsteps = 2^level steady-state steps whose step index s is
+// read from the device counter: the 1D groups' steps s ... s + gsteps - 1 and the 2D/3D
+// groups' units (MID of step s + u, NEXT into s + u + 1), followed by counter += gsteps.
+// A run of any length replays the binary decomposition of its units, so runs of
+// different lengths share the recorded graphs.
+int ensure_graph(rk4ip_plan_t plan, float2* psi, int level) {
+    if (plan->graph_psi != psi) drop_step_graphs(plan);
+    if (plan->graph[level]) return RK4IP_OK;
+    const int gsteps = 1 << level;
     // record on a private stream (the caller's may be the legacy default stream, which
     // cannot be captured); the instantiated graph is then launched on the plan's stream
     if (!plan->capture_stream) HIPCHK(plan, hipStreamCreateWithFlags(&plan->capture_stream, hipStreamNonBlocking));
@@ -1054,10 +1062,9 @@ int ensure_graph(rk4ip_plan_t plan, float2* psi, int gsteps) {
         plan->err = std::string("hipGraphInstantiate: ") + hipGetErrorString(e);
         return RK4IP_ERR_NOT_CAPTURABLE;
     }
-    plan->graph = ex;
-    plan->graph_src = gr;
+    plan->graph[level] = ex;
+    plan->graph_src[level] = gr;
     plan->graph_psi = psi;
-    plan->graph_steps = gsteps;
     return RK4IP_OK;
 }
 
@@ -1072,18 +1079,24 @@ int advance(rk4ip_plan_t plan, float2* psi, int64_t step, int64_t nsteps) {
     if (lattice && (rc = enqueue_lattice(plan, plan->stream, psi, step, 0, true, false, nullptr))) return rc;
     int64_t done = 0;
     if (units >= 1) {
-        const int gsteps = (int)(units < kGraphSteps ? units : kGraphSteps);
-        if ((rc = ensure_graph(plan, psi, gsteps))) return rc;
+        // every level is recorded on the first replayed run of a field, before that run's
+        // first replay, so that a later run of another length records nothing
+        if (plan->graph_psi != psi)
+            for (int level = 0; level < kGraphLevels; level++)
+                if ((rc = ensure_graph(plan, psi, level))) return rc;
         HIPCHK(plan, rk4ip::launch_counter(plan->counter, step, 0, plan->stream));
         // the replays step the k-space lines' states in the workspace
         if ((rc = enqueue_lines(plan, plan->stream, psi, step, 0, nullptr, true, false, true))) return rc;
-        while (units - done >= gsteps) {
-            hipError_t e = hipGraphLaunch(plan->graph, plan->stream);
+        while (done < units) {
+            int level = kGraphLevels - 1;
+            while ((int64_t(1) << level) > units - done) level--;
+            if ((rc = ensure_graph(plan, psi, level))) return rc;
+            hipError_t e = hipGraphLaunch(plan->graph[level], plan->stream);
             if (e != hipSuccess) {
                 plan->err = std::string("hipGraphLaunch: ") + hipGetErrorString(e);
                 return RK4IP_ERR_NOT_CAPTURABLE;
             }
-            done += gsteps;
+            done += int64_t(1) << level;
         }
     }
     if ((rc = enqueue_lines(plan, plan->stream, psi, step + done, nsteps - done, nullptr, true, done > 0, false)))
