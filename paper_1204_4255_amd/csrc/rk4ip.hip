@@ -1065,6 +1065,10 @@ int ensure_graph(rk4ip_plan_t plan, float2* psi, int level) {
     plan->graph[level] = ex;
     plan->graph_src[level] = gr;
     plan->graph_psi = psi;
+    // upload it now (on the plan's stream, ahead of the run's work) rather than at its first
+    // launch, which may fall inside a timed run
+    e = hipGraphUpload(ex, plan->stream);
+    if (e != hipSuccess) return fail_hip(plan, e, "hipGraphUpload");
     return RK4IP_OK;
 }
 
