@@ -22,3 +22,10 @@ def test_help_lists_the_switches():
     assert r.returncode == 0
     for sw in ("--steps", "--warmup", "--gpus", "--semi-implicit", "--no-cpu-baseline"):
         assert sw in r.stdout
+
+
+def test_unknown_forms_are_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--forms-only", "--forms", "batched_paths,nope"],
+                       capture_output=True, text=True, timeout=120, cwd=ROOT)
+    assert r.returncode == 2
+    assert "unknown forms ['nope']" in r.stderr and "batched_paths" in r.stderr
